@@ -1,0 +1,281 @@
+"""Plain FP64 CPU oracle (test infrastructure only).
+
+This package wraps ``oracle.c``: a slow, obviously-correct implementation of
+the nodal DG operator, SSP-RK3 stepper and conservative-to-primitive
+recovery of Kidder et al. (arXiv:1609.00098), plus the FP64 reference of the
+pressure-guess MLP (``oracle/mlp.py``).  It shares no code with the GPU
+library and must only be used by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.
+
+Every function states the passage of the paper it follows in ``oracle.c``.
+Parity status: every function is pinned by ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NE, SR, MHD = 0, 1, 2
+NVARS = {NE: 5, SR: 5, MHD: 9}
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain -O2, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+             "-std=c11", "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("sys", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("deg", ctypes.c_int32 * 3), ("pad", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), kappa=0.0):
+    """Periodic box of nelem=(nx,ny,nz) affine elements.  degree is an int or a
+    per-direction triple; a 0 entry collapses that direction."""
+    if isinstance(degree, int):
+        degree = (degree, degree, degree)
+    m = Mesh()
+    m.sys = system
+    m.nx, m.ny, m.nz = nelem
+    m.deg[:] = list(degree)
+    m.gamma = gamma
+    m.kappa = kappa
+    m.lo[:] = list(lo)
+    m.hi[:] = list(hi)
+    return m
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    D = ctypes.POINTER(ctypes.c_double)
+    I64 = ctypes.c_int64
+    U8 = ctypes.POINTER(ctypes.c_uint8)
+    MP = ctypes.POINTER(Mesh)
+    sig = {
+        "ora_gll": (ctypes.c_int, [ctypes.c_int, D, D]),
+        "ora_legendre": (ctypes.c_double, [ctypes.c_int, ctypes.c_double]),
+        "ora_diff_matrix": (ctypes.c_int, [ctypes.c_int, D, D]),
+        "ora_lagrange_matrix": (ctypes.c_int, [ctypes.c_int, D, ctypes.c_int, D, D]),
+        "ora_prim2cons": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, I64, D, D, D]),
+        "ora_cons2prim": (I64, [ctypes.c_int, ctypes.c_double, I64, D, D, U8]),
+        "ora_c2p_pressure_function": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, D, I64, D, D, U8]),
+        "ora_backward_residual": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, I64, D, D, D]),
+        "ora_flux": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, I64, D, D, D]),
+        "ora_max_speed": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, I64, D, D, D]),
+        "ora_llf": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, D, D, D, D, D]),
+        "ora_num_nodes": (I64, [MP]),
+        "ora_node_coords": (ctypes.c_int, [MP, D]),
+        "ora_rhs": (I64, [MP, D, D, D]),
+        "ora_rhs_elements": (ctypes.c_int, [MP, D, D, I64, ctypes.POINTER(I64), D]),
+        "ora_rhs_weak": (I64, [MP, D, D]),
+        "ora_rk3_combine": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, I64, D, D, D, D]),
+        "ora_step": (I64, [MP, D, ctypes.c_double]),
+        "ora_evolve": (I64, [MP, D, ctypes.c_double, I64]),
+        "ora_l1_error": (ctypes.c_double, [MP, ctypes.c_int, D, D]),
+        "ora_integrate": (ctypes.c_int, [MP, ctypes.c_int, D, D]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c(a, dtype=np.float64):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ----------------------------------------------------------------- tables
+def gll(N):
+    x = np.zeros(N + 1)
+    w = np.zeros(N + 1)
+    if _load().ora_gll(N, _p(x), _p(w)) != 0:
+        raise ValueError("bad degree")
+    return x, w
+
+
+def legendre(N, x):
+    return _load().ora_legendre(N, float(x))
+
+
+def diff_matrix(N):
+    x, _ = gll(N)
+    D = np.zeros((N + 1) * (N + 1))
+    _load().ora_diff_matrix(N, _p(x), _p(D))
+    return D.reshape(N + 1, N + 1)
+
+
+def lagrange_matrix(xfrom, yto):
+    xfrom = _c(xfrom)
+    yto = _c(yto)
+    out = np.zeros(len(yto) * len(xfrom))
+    _load().ora_lagrange_matrix(len(xfrom), _p(xfrom), len(yto), _p(yto), _p(out))
+    return out.reshape(len(yto), len(xfrom))
+
+
+# --------------------------------------------------------------- pointwise
+def prim2cons(system, gamma, prim, mag=None):
+    prim = _c(prim)
+    n = prim.shape[1]
+    nv = NVARS[system]
+    U = np.zeros((nv, n))
+    magp = None
+    if system == MHD:
+        mag = _c(mag)
+        magp = _p(mag)
+    _load().ora_prim2cons(system, gamma, n, _p(prim), magp, _p(U))
+    return U
+
+
+def cons2prim(system, gamma, U):
+    U = _c(U)
+    n = U.shape[1]
+    prim = np.zeros((5, n))
+    fail = np.zeros(n, dtype=np.uint8)
+    nf = _load().ora_cons2prim(system, gamma, n, _p(U), _p(prim),
+                               fail.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return prim, fail, nf
+
+
+def pressure_function(system, gamma, u1, p):
+    u1 = _c(u1)
+    p = _c(p)
+    f = np.zeros_like(p)
+    valid = np.zeros(len(p), dtype=np.uint8)
+    _load().ora_c2p_pressure_function(system, gamma, _p(u1), len(p), _p(p), _p(f),
+                                      valid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return f, valid.astype(bool)
+
+
+def backward_residual(system, gamma, U, prim):
+    U = _c(U)
+    prim = _c(prim)
+    r = np.zeros(U.shape[1])
+    _load().ora_backward_residual(system, gamma, U.shape[1], _p(U), _p(prim), _p(r))
+    return r
+
+
+def flux(system, gamma, d, U, prim):
+    U = _c(U)
+    prim = _c(prim)
+    F = np.zeros_like(U)
+    _load().ora_flux(system, gamma, d, U.shape[1], _p(U), _p(prim), _p(F))
+    return F
+
+
+def max_speed(system, gamma, d, U, prim):
+    U = _c(U)
+    prim = _c(prim)
+    a = np.zeros_like(U)
+    _load().ora_max_speed(system, gamma, d, U.shape[1], _p(U), _p(prim), _p(a))
+    return a
+
+
+def llf(system, gamma, d, sgn, ui, pi, ue, pe):
+    out = np.zeros(NVARS[system])
+    _load().ora_llf(system, gamma, d, sgn, _p(_c(ui)), _p(_c(pi)), _p(_c(ue)), _p(_c(pe)), _p(out))
+    return out
+
+
+# -------------------------------------------------------------------- mesh
+def num_nodes(m):
+    return int(_load().ora_num_nodes(ctypes.byref(m)))
+
+
+def node_coords(m):
+    n = num_nodes(m)
+    xyz = np.zeros((3, n))
+    _load().ora_node_coords(ctypes.byref(m), _p(xyz))
+    return xyz
+
+
+def rhs(m, U):
+    """Returns (dUdt, prims, n_failed)."""
+    U = _c(U)
+    n = U.shape[1]
+    prim = np.zeros((5, n))
+    dU = np.zeros_like(U)
+    nf = _load().ora_rhs(ctypes.byref(m), _p(U), _p(prim), _p(dU))
+    if nf < 0:
+        raise ValueError("bad mesh")
+    return dU, prim, int(nf)
+
+
+def rhs_elements(m, U, prim, elems):
+    U = _c(U)
+    prim = _c(prim)
+    elems = _c(elems, np.int64)
+    npe = num_nodes(m) // (m.nx * m.ny * m.nz)
+    out = np.zeros((U.shape[0], len(elems) * npe))
+    rc = _load().ora_rhs_elements(ctypes.byref(m), _p(U), _p(prim), len(elems),
+                                  elems.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(out))
+    if rc != 0:
+        raise ValueError("bad element list")
+    return out
+
+
+def rhs_weak(m, U):
+    U = _c(U)
+    dU = np.zeros_like(U)
+    _load().ora_rhs_weak(ctypes.byref(m), _p(U), _p(dU))
+    return dU
+
+
+def rk3_combine(stage, dt, Un, Uprev, L):
+    Un, Uprev, L = _c(Un), _c(Uprev), _c(L)
+    out = np.zeros_like(Un)
+    if _load().ora_rk3_combine(stage, dt, Un.size, _p(Un), _p(Uprev), _p(L), _p(out)) != 0:
+        raise ValueError("bad stage")
+    return out
+
+
+def step(m, U, dt):
+    U = _c(U).copy()
+    nf = _load().ora_step(ctypes.byref(m), _p(U), dt)
+    return U, int(nf)
+
+
+def evolve(m, U, dt, nsteps):
+    U = _c(U).copy()
+    nf = _load().ora_evolve(ctypes.byref(m), _p(U), dt, nsteps)
+    return U, int(nf)
+
+
+def l1_error(m, a, b):
+    a, b = _c(a), _c(b)
+    return float(_load().ora_l1_error(ctypes.byref(m), a.shape[0], _p(a), _p(b)))
+
+
+def integrate(m, q):
+    q = _c(q)
+    out = np.zeros(q.shape[0])
+    _load().ora_integrate(ctypes.byref(m), q.shape[0], _p(q), _p(out))
+    return out

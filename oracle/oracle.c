@@ -1,0 +1,862 @@
+/*
+ * Plain FP64 CPU oracle for the nodal discontinuous Galerkin right-hand side
+ * and conservative-to-primitive recovery of Kidder et al., "SpECTRE: a
+ * task-based discontinuous Galerkin code for relativistic astrophysics"
+ * (arXiv:1609.00098).
+ *
+ * THIS IS TEST INFRASTRUCTURE.  It is slow on purpose, written to be checked
+ * against the paper by eye, and shares no code, header, table or constant
+ * generator with the GPU library.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared oracle.c -lm
+ *
+ * Conventions (stated once, used everywhere below)
+ *   systems:   0 = Newtonian Euler (5 vars: rho, m_x, m_y, m_z, E)
+ *              1 = special-relativistic hydro (5 vars: D, S_x, S_y, S_z, tau)
+ *              2 = special-relativistic MHD with divergence cleaning
+ *                  (9 vars: D, S_x, S_y, S_z, tau, B_x, B_y, B_z, Phi)
+ *   primitives: 5 per point (rho, v_x, v_y, v_z, p); for MHD, B and Phi are
+ *              read from the conserved array.
+ *   arrays are structure-of-arrays: A[var * npts + point].
+ *   element e = ex + nx*(ey + ny*ez); node inside an element
+ *              i + n1*(j + n2*k), n_d = deg_d + 1, i along x fastest;
+ *   a direction with deg_d = 0 is collapsed (one node, no derivative, no
+ *   faces), which turns the 3D operator into its 1D/2D analogue.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORA_OK 0
+#define ORA_EINVAL (-1)
+
+static int nvars_of(int sys) { return sys == 2 ? 9 : 5; }
+
+/* ------------------------------------------------------------------------ */
+/* Legendre polynomials and Gauss-Legendre-Lobatto quadrature               */
+/* (the nodal basis of the algorithm section: Lagrange polynomials on GLL   */
+/*  nodes; weights of the GLL rule used for the diagonal mass matrix and    */
+/*  the L1 norm).                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* P_N(x) and P_N'(x) by the three-term recurrence
+ * (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}, P'_{k+1} = P'_{k-1} + (2k+1) P_k. */
+static void legendre(int N, double x, double *PN, double *dPN) {
+  double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+  if (N == 0) { *PN = 1.0; *dPN = 0.0; return; }
+  for (int k = 1; k < N; ++k) {
+    double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+    double d2 = d0 + (2.0 * k + 1.0) * p1;
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+  }
+  *PN = p1; *dPN = d1;
+}
+
+double ora_legendre(int N, double x) { double p, d; legendre(N, x, &p, &d); return p; }
+
+/* GLL nodes: -1, +1 and the N-1 roots of P_N' in (-1,1).  The interior roots
+ * are found by scanning for sign changes on a fine uniform grid and then
+ * bisecting each bracket until it cannot shrink further.  Weights:
+ * w_i = 2 / (N (N+1) P_N(x_i)^2).                                          */
+int ora_gll(int N, double *x, double *w) {
+  if (N < 1 || N > 32) return ORA_EINVAL;
+  x[0] = -1.0; x[N] = 1.0;
+  int found = 1;
+  const int G = 20000;
+  double xa = -1.0, pa, da;
+  legendre(N, -1.0 + 1e-12, &pa, &da);
+  xa = -1.0 + 1e-12;
+  for (int g = 1; g <= G && found < N; ++g) {
+    double xb = -1.0 + 2.0 * g / G;
+    if (g == G) xb = 1.0 - 1e-12;
+    double pb, db;
+    legendre(N, xb, &pb, &db);
+    if ((da < 0) != (db < 0)) {
+      double lo = xa, hi = xb, dlo = da;
+      for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double pm, dm;
+        legendre(N, mid, &pm, &dm);
+        if ((dm < 0) == (dlo < 0)) { lo = mid; dlo = dm; } else { hi = mid; }
+      }
+      x[found++] = 0.5 * (lo + hi);
+    }
+    xa = xb; da = db;
+  }
+  if (found != N) return ORA_EINVAL;
+  for (int i = 0; i <= N; ++i) {
+    double p, d;
+    legendre(N, x[i], &p, &d);
+    w[i] = 2.0 / (N * (N + 1.0) * p * p);
+  }
+  return ORA_OK;
+}
+
+/* Differentiation matrix D_il = d ell_l / dxbar at x_i (eq. for D^{1bar}):
+ * the classical closed form on GLL nodes,
+ *   D_il = P_N(x_i) / (P_N(x_l) (x_i - x_l)),  i != l,
+ *   D_00 = -N(N+1)/4,  D_NN = +N(N+1)/4,  other diagonal entries 0.
+ * Row-major: D[i*(N+1)+l].                                                 */
+int ora_diff_matrix(int N, const double *x, double *D) {
+  if (N < 1) return ORA_EINVAL;
+  for (int i = 0; i <= N; ++i) {
+    for (int l = 0; l <= N; ++l) {
+      double v;
+      if (i != l) {
+        v = ora_legendre(N, x[i]) / (ora_legendre(N, x[l]) * (x[i] - x[l]));
+      } else if (i == 0) {
+        v = -N * (N + 1.0) / 4.0;
+      } else if (i == N) {
+        v = N * (N + 1.0) / 4.0;
+      } else {
+        v = 0.0;
+      }
+      D[i * (N + 1) + l] = v;
+    }
+  }
+  return ORA_OK;
+}
+
+/* Lagrange interpolation matrix I[m*(nfrom)+i] = ell_i(y_m) for the
+ * nodes xfrom[0..nfrom-1]; ell_i is the product formula of the paper.     */
+int ora_lagrange_matrix(int nfrom, const double *xfrom, int nto, const double *yto, double *I) {
+  for (int m = 0; m < nto; ++m)
+    for (int i = 0; i < nfrom; ++i) {
+      double v = 1.0;
+      for (int j = 0; j < nfrom; ++j)
+        if (j != i) v *= (yto[m] - xfrom[j]) / (xfrom[i] - xfrom[j]);
+      I[m * nfrom + i] = v;
+    }
+  return ORA_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pointwise physics (conservation-laws section; flat space, alpha=1,       */
+/* beta=0, gamma_ij = delta_ij, so sqrt(gamma)=1 and all tildes drop).      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double u[9]; } cons_t;
+typedef struct { double rho, v[3], p; } prim_t;
+
+/* Newtonian Euler: U = [rho, rho v_i, E], E = rho eps + rho v^2/2, ideal gas
+ * p = (gamma-1) rho eps.                                                    */
+static void ne_p2c(double g, const prim_t *P, cons_t *C) {
+  double v2 = P->v[0] * P->v[0] + P->v[1] * P->v[1] + P->v[2] * P->v[2];
+  double rho_eps = P->p / (g - 1.0);
+  C->u[0] = P->rho;
+  for (int i = 0; i < 3; ++i) C->u[1 + i] = P->rho * P->v[i];
+  C->u[4] = rho_eps + 0.5 * P->rho * v2;
+}
+
+/* Relativistic Euler (flat): D = rho W, S_i = rho h W^2 v_i,
+ * tau = rho h W^2 - p - rho W, h = 1 + eps + p/rho, W = 1/sqrt(1 - v^2).  */
+static void sr_p2c(double g, const prim_t *P, cons_t *C) {
+  double v2 = P->v[0] * P->v[0] + P->v[1] * P->v[1] + P->v[2] * P->v[2];
+  double W = 1.0 / sqrt(1.0 - v2);
+  double eps = P->p / ((g - 1.0) * P->rho);
+  double h = 1.0 + eps + P->p / P->rho;
+  C->u[0] = P->rho * W;
+  for (int i = 0; i < 3; ++i) C->u[1 + i] = P->rho * h * W * W * P->v[i];
+  C->u[4] = P->rho * h * W * W - P->p - P->rho * W;
+}
+
+/* Comoving field of the MHD subsection: alpha b^0 = W B.v,
+ * b_i = B_i/W + v_i alpha b^0, b^2 = b^mu b_mu = B^2/W^2 + (B.v)^2.        */
+static void mhd_b(const prim_t *P, const double B[3], double W, double *b0, double b[3], double *b2) {
+  double Bv = B[0] * P->v[0] + B[1] * P->v[1] + B[2] * P->v[2];
+  double BB = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  *b0 = W * Bv;
+  for (int i = 0; i < 3; ++i) b[i] = B[i] / W + P->v[i] * (*b0);
+  *b2 = BB / (W * W) + Bv * Bv;
+}
+
+/* Evolved variables of the MHD system (flat):
+ * D = rho W, S_i = (rho h)* W^2 v_i - b^0 b_i,
+ * tau = (rho h)* W^2 - p* - (b^0)^2 - rho W, B^i, Phi.                    */
+static void mhd_p2c(double g, const prim_t *P, const double B[3], double Phi, cons_t *C) {
+  double v2 = P->v[0] * P->v[0] + P->v[1] * P->v[1] + P->v[2] * P->v[2];
+  double W = 1.0 / sqrt(1.0 - v2);
+  double eps = P->p / ((g - 1.0) * P->rho);
+  double h = 1.0 + eps + P->p / P->rho;
+  double b0, b[3], b2;
+  mhd_b(P, B, W, &b0, b, &b2);
+  double rhohs = P->rho * h + b2;
+  double ps = P->p + 0.5 * b2;
+  C->u[0] = P->rho * W;
+  for (int i = 0; i < 3; ++i) C->u[1 + i] = rhohs * W * W * P->v[i] - b0 * b[i];
+  C->u[4] = rhohs * W * W - ps - b0 * b0 - P->rho * W;
+  for (int i = 0; i < 3; ++i) C->u[5 + i] = B[i];
+  C->u[8] = Phi;
+}
+
+/* Pressure function of the recovery, f(p) = (gamma-1) rho eps(p) - p, where
+ * rho eps(p) is the internal energy the conserved state implies for a trial
+ * pressure p.  For relativistic hydro: z = rho h W^2 = tau + D + p,
+ * v_i = S_i / z, W = 1/sqrt(1-v^2), rho = D/W, rho eps = z/W^2 - rho - p.
+ * For MHD the same chain holds after the magnetic terms are removed: with
+ * T = S.B, d = (B^2 S^2 - T^2)/2 and e = tau + D + p + B^2/2, the quantity
+ * eps_m = z + B^2 is the largest root of eps_m^3 - e eps_m^2 + d = 0, and
+ * v^2 = (S^2 z^2 + T^2 (z + eps_m)) / (z^2 eps_m^2),
+ * v_i = (S_i + (T/z) B_i) / eps_m.
+ * Returns 0 if p lies outside the domain where the map is defined (no real
+ * root of the cubic above its double-root region, z <= 0 or v^2 >= 1).     */
+static int c2p_eval(int sys, double g, const cons_t *C, double p, double *f, prim_t *P) {
+  double D = C->u[0], tau = C->u[4];
+  const double *S = &C->u[1];
+  double S2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
+  double z, v[3];
+  if (sys == 1) {
+    z = tau + D + p;
+    if (!(z > 0.0)) return 0;
+    for (int i = 0; i < 3; ++i) v[i] = S[i] / z;
+  } else {
+    const double *B = &C->u[5];
+    double BB = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+    double T = S[0] * B[0] + S[1] * B[1] + S[2] * B[2];
+    double d = 0.5 * (BB * S2 - T * T);
+    if (d < 0.0) d = 0.0;
+    double e = tau + D + p + 0.5 * BB;
+    if (!(e > 0.0)) return 0;
+    /* largest root by the trigonometric (Viete) form of the cubic */
+    double c = 1.0 - 27.0 * d / (2.0 * e * e * e);
+    if (!(c >= -1.0)) return 0;
+    if (c > 1.0) c = 1.0;
+    double phi = acos(c);
+    double em = (e / 3.0) * (1.0 + 2.0 * cos(phi / 3.0));
+    z = em - BB;
+    if (!(z > 0.0)) return 0;
+    for (int i = 0; i < 3; ++i) v[i] = (S[i] + (T / z) * B[i]) / em;
+  }
+  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  if (!(v2 < 1.0)) return 0;
+  double W = 1.0 / sqrt(1.0 - v2);
+  double rho = D / W;
+  double rho_eps = z / (W * W) - rho - p;
+  *f = (g - 1.0) * rho_eps - p;
+  if (P) { P->rho = rho; P->v[0] = v[0]; P->v[1] = v[1]; P->v[2] = v[2]; P->p = p; }
+  return 1;
+}
+
+/* Recovery.  Newtonian Euler: algebraic.  Relativistic systems: the unique
+ * physical pressure, i.e. the root of f in [0, p_hi] with
+ * p_hi = (gamma-1) tau (hydro) or (gamma-1)(tau - B^2/2) (MHD), found by
+ * plain bisection until the bracket cannot shrink.  f is defined and
+ * positive at p = 0 and non-positive at p_hi for every physical state;
+ * anything else is reported as a failure (return 0).                       */
+static int c2p_point(int sys, double g, const cons_t *C, prim_t *P) {
+  if (sys == 0) {
+    double rho = C->u[0];
+    if (!(rho > 0.0)) return 0;
+    double m2 = 0.0;
+    for (int i = 0; i < 3; ++i) { P->v[i] = C->u[1 + i] / rho; m2 += C->u[1 + i] * C->u[1 + i]; }
+    P->rho = rho;
+    P->p = (g - 1.0) * (C->u[4] - 0.5 * m2 / rho);
+    return P->p > 0.0;
+  }
+  double D = C->u[0], tau = C->u[4];
+  if (!(D > 0.0) || !(tau > 0.0)) return 0;
+  double hi = (g - 1.0) * tau;
+  if (sys == 2) {
+    double BB = C->u[5] * C->u[5] + C->u[6] * C->u[6] + C->u[7] * C->u[7];
+    hi = (g - 1.0) * (tau - 0.5 * BB);
+  }
+  if (!(hi > 0.0)) return 0;
+  double lo = 0.0, flo, fhi;
+  if (!c2p_eval(sys, g, C, lo, &flo, NULL) || !(flo > 0.0)) return 0;
+  if (!c2p_eval(sys, g, C, hi, &fhi, NULL)) return 0;
+  /* mathematically f(p_hi) <= 0 with equality at rest (W = 1); a positive
+   * value at rounding level means the root is p_hi itself */
+  if (fhi > 0.0) {
+    if (fhi > 1e-12 * hi) return 0;
+    return c2p_eval(sys, g, C, hi, &fhi, P);
+  }
+  for (int it = 0; it < 4000; ++it) {
+    double mid = lo + 0.5 * (hi - lo);
+    if (!(mid > lo && mid < hi)) break;
+    double fm;
+    if (!c2p_eval(sys, g, C, mid, &fm, NULL) || fm > 0.0) lo = mid; else hi = mid;
+  }
+  double p = lo + 0.5 * (hi - lo), f;
+  if (!c2p_eval(sys, g, C, p, &f, P)) return 0;
+  return 1;
+}
+
+/* Physical fluxes in direction d (flat space, v_tr = v):
+ * NE:  [rho v^d, rho v_i v^d + p delta, (E + p) v^d]
+ * SR:  [D v^d, S_i v^d + p delta, tau v^d + p v^d]
+ * MHD: [D v^d, S_i v^d + p* delta - B^d b_i / W, tau v^d + p* v^d - b^0 B^d / W,
+ *       v^d B^i - v^i B^d + delta Phi, B^d]                                 */
+static void flux(int sys, double g, int d, const cons_t *C, const prim_t *P, double *F) {
+  const double *v = P->v;
+  if (sys == 0) {
+    F[0] = C->u[1 + d];
+    for (int i = 0; i < 3; ++i) F[1 + i] = C->u[1 + i] * v[d] + (i == d ? P->p : 0.0);
+    F[4] = (C->u[4] + P->p) * v[d];
+    return;
+  }
+  if (sys == 1) {
+    F[0] = C->u[0] * v[d];
+    for (int i = 0; i < 3; ++i) F[1 + i] = C->u[1 + i] * v[d] + (i == d ? P->p : 0.0);
+    F[4] = C->u[4] * v[d] + P->p * v[d];
+    return;
+  }
+  const double *B = &C->u[5];
+  double Phi = C->u[8];
+  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  double W = 1.0 / sqrt(1.0 - v2);
+  double b0, b[3], b2;
+  mhd_b(P, B, W, &b0, b, &b2);
+  double ps = P->p + 0.5 * b2;
+  F[0] = C->u[0] * v[d];
+  for (int i = 0; i < 3; ++i) F[1 + i] = C->u[1 + i] * v[d] + (i == d ? ps : 0.0) - B[d] * b[i] / W;
+  F[4] = C->u[4] * v[d] + ps * v[d] - b0 * B[d] / W;
+  for (int i = 0; i < 3; ++i) F[5 + i] = v[d] * B[i] - v[i] * B[d] + (i == d ? Phi : 0.0);
+  F[8] = B[d];
+}
+
+/* Largest characteristic speed |lambda| along +/- e_d, per component
+ * (the LLF alpha of eq. LLF is the max of this over both sides).
+ * NE: |v_n| + c_s, c_s^2 = gamma p / rho.
+ * SR: the two acoustic speeds
+ *   lambda_pm = [v_n (1 - c^2) pm c sqrt((1-v^2)(1 - v^2 c^2 - v_n^2 (1-c^2)))]
+ *               / (1 - v^2 c^2),  c^2 = gamma p / (rho h);
+ * MHD: the same expression with the fast-speed bound
+ *   c^2 = v_A^2 + c_s^2 (1 - v_A^2),  v_A^2 = b^2 / (rho h + b^2)
+ * for the 7-variable sub-system, and 1 (speed of light) for the
+ * (B_n, Phi) sub-system, per the split of the MHD wave-speed subsection.  */
+static void max_speed(int sys, double g, int d, const cons_t *C, const prim_t *P, double *alpha) {
+  const double *v = P->v;
+  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  int nv = nvars_of(sys);
+  if (sys == 0) {
+    double cs = sqrt(g * P->p / P->rho);
+    double a = fabs(v[d]) + cs;
+    for (int c = 0; c < nv; ++c) alpha[c] = a;
+    return;
+  }
+  double h = 1.0 + P->p / ((g - 1.0) * P->rho) + P->p / P->rho;
+  double c2 = g * P->p / (P->rho * h);
+  if (sys == 2) {
+    double W = 1.0 / sqrt(1.0 - v2);
+    double b0, b[3], b2;
+    mhd_b(P, &C->u[5], W, &b0, b, &b2);
+    double vA2 = b2 / (P->rho * h + b2);
+    c2 = vA2 + c2 * (1.0 - vA2);
+  }
+  double vn = v[d];
+  double disc = (1.0 - v2) * (1.0 - v2 * c2 - vn * vn * (1.0 - c2));
+  if (disc < 0.0) disc = 0.0;
+  double c = sqrt(c2);
+  double lp = (vn * (1.0 - c2) + c * sqrt(disc)) / (1.0 - v2 * c2);
+  double lm = (vn * (1.0 - c2) - c * sqrt(disc)) / (1.0 - v2 * c2);
+  double a = fmax(fabs(lp), fabs(lm));
+  for (int c_ = 0; c_ < nv; ++c_) alpha[c_] = a;
+  if (sys == 2) {
+    alpha[5 + d] = 1.0; /* normal field component */
+    alpha[8] = 1.0;     /* cleaning scalar */
+  }
+}
+
+static void load_cons(int nv, int64_t n, const double *U, int64_t idx, cons_t *C) {
+  for (int v = 0; v < nv; ++v) C->u[v] = U[(int64_t)v * n + idx];
+}
+static void load_prim(int64_t n, const double *Pr, int64_t idx, prim_t *P) {
+  P->rho = Pr[idx];
+  P->v[0] = Pr[n + idx]; P->v[1] = Pr[2 * n + idx]; P->v[2] = Pr[3 * n + idx];
+  P->p = Pr[4 * n + idx];
+}
+
+/* -------------------------- pointwise entry points ---------------------- */
+
+/* prim [5][n]; mag [4][n] = (B_x, B_y, B_z, Phi) for MHD (ignored otherwise) */
+int ora_prim2cons(int sys, double g, int64_t n, const double *prim, const double *mag, double *U) {
+  int nv = nvars_of(sys);
+#pragma omp parallel for schedule(static) if (n > 65536)
+  for (int64_t q = 0; q < n; ++q) {
+    prim_t P; cons_t C;
+    load_prim(n, prim, q, &P);
+    if (sys == 0) ne_p2c(g, &P, &C);
+    else if (sys == 1) sr_p2c(g, &P, &C);
+    else {
+      double B[3] = {mag[q], mag[n + q], mag[2 * n + q]};
+      mhd_p2c(g, &P, B, mag[3 * n + q], &C);
+    }
+    for (int v = 0; v < nv; ++v) U[(int64_t)v * n + q] = C.u[v];
+  }
+  return ORA_OK;
+}
+
+/* fail[n] (nullable): 1 where no physical primitive state exists.  Returns
+ * the number of failed points.                                             */
+int64_t ora_cons2prim(int sys, double g, int64_t n, const double *U, double *prim, uint8_t *fail) {
+  int nv = nvars_of(sys);
+  int64_t nfail = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nfail) if (n > 4096)
+  for (int64_t q = 0; q < n; ++q) {
+    cons_t C; prim_t P = {0};
+    load_cons(nv, n, U, q, &C);
+    int ok = c2p_point(sys, g, &C, &P);
+    prim[q] = P.rho; prim[n + q] = P.v[0]; prim[2 * n + q] = P.v[1];
+    prim[3 * n + q] = P.v[2]; prim[4 * n + q] = P.p;
+    if (fail) fail[q] = ok ? 0 : 1;
+    nfail += ok ? 0 : 1;
+  }
+  return nfail;
+}
+
+/* The pressure function at one point for a list of trial pressures (used by
+ * the root-uniqueness scan).  valid[k] = 0 where the map is undefined.     */
+int ora_c2p_pressure_function(int sys, double g, const double *u1, int64_t m, const double *p, double *f,
+                              uint8_t *valid) {
+  cons_t C;
+  for (int v = 0; v < nvars_of(sys); ++v) C.u[v] = u1[v];
+  for (int64_t k = 0; k < m; ++k) {
+    double fk = 0.0;
+    valid[k] = (uint8_t)c2p_eval(sys, g, &C, p[k], &fk, NULL);
+    f[k] = fk;
+  }
+  return ORA_OK;
+}
+
+/* Backward residual of a recovery: with U' = cons(prim) (magnetic field and
+ * Phi taken from U), r = max(|D'-D|/D, max_i |S'_i - S_i|/E, |tau'-tau|/E),
+ * E = tau + D.                                                              */
+int ora_backward_residual(int sys, double g, int64_t n, const double *U, const double *prim, double *r) {
+  int nv = nvars_of(sys);
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < n; ++q) {
+    cons_t C, C2; prim_t P;
+    load_cons(nv, n, U, q, &C);
+    load_prim(n, prim, q, &P);
+    if (sys == 0) ne_p2c(g, &P, &C2);
+    else if (sys == 1) sr_p2c(g, &P, &C2);
+    else mhd_p2c(g, &P, &C.u[5], C.u[8], &C2);
+    double E = C.u[4] + C.u[0];
+    double rr = fabs(C2.u[0] - C.u[0]) / C.u[0];
+    for (int i = 0; i < 3; ++i) rr = fmax(rr, fabs(C2.u[1 + i] - C.u[1 + i]) / E);
+    rr = fmax(rr, fabs(C2.u[4] - C.u[4]) / E);
+    r[q] = rr;
+  }
+  return ORA_OK;
+}
+
+/* F[nv][n] for direction d. */
+int ora_flux(int sys, double g, int d, int64_t n, const double *U, const double *prim, double *F) {
+  int nv = nvars_of(sys);
+  for (int64_t q = 0; q < n; ++q) {
+    cons_t C; prim_t P; double f[9];
+    load_cons(nv, n, U, q, &C);
+    load_prim(n, prim, q, &P);
+    flux(sys, g, d, &C, &P, f);
+    for (int v = 0; v < nv; ++v) F[(int64_t)v * n + q] = f[v];
+  }
+  return ORA_OK;
+}
+
+/* alpha[nv][n] for direction d. */
+int ora_max_speed(int sys, double g, int d, int64_t n, const double *U, const double *prim, double *alpha) {
+  int nv = nvars_of(sys);
+  for (int64_t q = 0; q < n; ++q) {
+    cons_t C; prim_t P; double a[9];
+    load_cons(nv, n, U, q, &C);
+    load_prim(n, prim, q, &P);
+    max_speed(sys, g, d, &C, &P, a);
+    for (int v = 0; v < nv; ++v) alpha[(int64_t)v * n + q] = a[v];
+  }
+  return ORA_OK;
+}
+
+/* Local Lax-Friedrichs numerical flux (eq. LLF) for one face point, written
+ * with the element's outward unit normal n = sgn e_d:
+ *   F*.n = (F(U_int).n + F(U_ext).n)/2 - alpha/2 (U_ext - U_int),
+ * alpha = max of the largest speeds of the two sides (pointwise).          */
+static void llf(int sys, double g, int d, double sgn, const cons_t *Ci, const prim_t *Pi, const cons_t *Ce,
+                const prim_t *Pe, double *Fstar_n, double *Fint_n) {
+  int nv = nvars_of(sys);
+  double fi[9], fe[9], ai[9], ae[9];
+  flux(sys, g, d, Ci, Pi, fi);
+  flux(sys, g, d, Ce, Pe, fe);
+  max_speed(sys, g, d, Ci, Pi, ai);
+  max_speed(sys, g, d, Ce, Pe, ae);
+  for (int c = 0; c < nv; ++c) {
+    double alpha = fmax(ai[c], ae[c]);
+    Fint_n[c] = sgn * fi[c];
+    Fstar_n[c] = 0.5 * (sgn * fi[c] + sgn * fe[c]) - 0.5 * alpha * (Ce->u[c] - Ci->u[c]);
+  }
+}
+
+int ora_llf(int sys, double g, int d, double sgn, const double *ui, const double *pi_, const double *ue,
+            const double *pe, double *fstar_n) {
+  cons_t Ci, Ce; prim_t Pi, Pe; double fin[9];
+  int nv = nvars_of(sys);
+  for (int v = 0; v < nv; ++v) { Ci.u[v] = ui[v]; Ce.u[v] = ue[v]; }
+  Pi.rho = pi_[0]; Pi.v[0] = pi_[1]; Pi.v[1] = pi_[2]; Pi.v[2] = pi_[3]; Pi.p = pi_[4];
+  Pe.rho = pe[0]; Pe.v[0] = pe[1]; Pe.v[1] = pe[2]; Pe.v[2] = pe[3]; Pe.p = pe[4];
+  llf(sys, g, d, sgn, &Ci, &Pi, &Ce, &Pe, fstar_n, fin);
+  return ORA_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The semi-discrete DG operator on a periodic box of affine elements.      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t sys;
+  int32_t nx, ny, nz;
+  int32_t deg[3];
+  int32_t pad;
+  double gamma, kappa;
+  double lo[3], hi[3];
+} ora_mesh;
+
+typedef struct {
+  int n[3], npe;
+  int64_t nelem, nnodes;
+  double dx[3];
+  double x[3][33], w[3][33], D[3][33 * 33];
+} geom_t;
+
+static int make_geom(const ora_mesh *m, geom_t *G) {
+  if (m->nx < 1 || m->ny < 1 || m->nz < 1) return ORA_EINVAL;
+  int ne[3] = {m->nx, m->ny, m->nz};
+  for (int d = 0; d < 3; ++d) {
+    if (m->deg[d] < 0 || m->deg[d] > 32) return ORA_EINVAL;
+    G->n[d] = m->deg[d] + 1;
+    G->dx[d] = (m->hi[d] - m->lo[d]) / ne[d];
+    if (m->deg[d] >= 1) {
+      if (ora_gll(m->deg[d], G->x[d], G->w[d]) != ORA_OK) return ORA_EINVAL;
+      ora_diff_matrix(m->deg[d], G->x[d], G->D[d]);
+    } else {
+      G->x[d][0] = 0.0; G->w[d][0] = 2.0; G->D[d][0] = 0.0;
+    }
+  }
+  G->npe = G->n[0] * G->n[1] * G->n[2];
+  G->nelem = (int64_t)m->nx * m->ny * m->nz;
+  G->nnodes = G->nelem * G->npe;
+  return ORA_OK;
+}
+
+int64_t ora_num_nodes(const ora_mesh *m) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return -1;
+  return G.nnodes;
+}
+
+/* Physical coordinates of every node through the affine map
+ * x = a + (1 + xbar)(b - a)/2 (eq. AffineMap).  xyz[3][nnodes].            */
+int ora_node_coords(const ora_mesh *m, double *xyz) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
+  int64_t n = G.nnodes;
+  for (int64_t e = 0; e < G.nelem; ++e) {
+    int64_t ex = e % m->nx, ey = (e / m->nx) % m->ny, ez = e / ((int64_t)m->nx * m->ny);
+    int64_t ec[3] = {ex, ey, ez};
+    for (int k = 0; k < G.n[2]; ++k)
+      for (int j = 0; j < G.n[1]; ++j)
+        for (int i = 0; i < G.n[0]; ++i) {
+          int ijk[3] = {i, j, k};
+          int64_t q = e * G.npe + i + G.n[0] * (j + G.n[1] * k);
+          for (int d = 0; d < 3; ++d) {
+            double a = m->lo[d] + ec[d] * G.dx[d];
+            xyz[d * n + q] = a + 0.5 * (1.0 + G.x[d][ijk[d]]) * G.dx[d];
+          }
+        }
+  }
+  return ORA_OK;
+}
+
+/* Neighbouring element across face (d, side) with periodic wrap. */
+static int64_t neighbour(const ora_mesh *m, int64_t e, int d, int side) {
+  int64_t c[3] = {e % m->nx, (e / m->nx) % m->ny, e / ((int64_t)m->nx * m->ny)};
+  int64_t ne[3] = {m->nx, m->ny, m->nz};
+  c[d] = (c[d] + (side ? 1 : ne[d] - 1)) % ne[d];
+  return c[0] + ne[0] * (c[1] + ne[1] * c[2]);
+}
+
+/* Strong-form semi-discrete operator (eq. 411) for the elements listed in
+ * elems (or all elements when elems == NULL), written into dUdt[nv][nsel*npe]
+ * in list order.  prim must hold the primitives of every node.
+ * For each element and each node ijk:
+ *   L = S - sum_d (2/dx_d) sum_l D_{i_d l} F^d(..l..)
+ *       - sum_{faces through ijk} (2/dx_d)(1/w_end)(F*.n - F.n),
+ * with the unit outward normal n = +-e_d; 2/dx_d is the affine inverse
+ * Jacobian, and the ratio sqrt(2gamma)/J of the surface to the volume scale
+ * factor of an affine map is also 2/dx_d.                                  */
+static int rhs_strong(const ora_mesh *m, const geom_t *G, const double *U, const double *prim, int64_t nsel,
+                      const int64_t *elems, double *dUdt) {
+  int sys = m->sys, nv = nvars_of(sys);
+  double g = m->gamma;
+  int64_t N = G->nnodes, npe = G->npe;
+  int n0 = G->n[0], n1 = G->n[1];
+  int64_t nout = nsel * npe;
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) if (nsel * npe > 4096)
+  for (int64_t s = 0; s < nsel; ++s) {
+    int64_t e = elems ? elems[s] : s;
+    double *F = (double *)malloc(sizeof(double) * 3 * nv * npe);
+    if (!F) { err = 1; continue; }
+    /* nodal fluxes */
+    for (int64_t a = 0; a < npe; ++a) {
+      cons_t C; prim_t P; double f[9];
+      load_cons(nv, N, U, e * npe + a, &C);
+      load_prim(N, prim, e * npe + a, &P);
+      for (int d = 0; d < 3; ++d) {
+        flux(sys, g, d, &C, &P, f);
+        for (int v = 0; v < nv; ++v) F[(d * nv + v) * npe + a] = f[v];
+      }
+    }
+    for (int k = 0; k < G->n[2]; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n0; ++i) {
+          int ijk[3] = {i, j, k};
+          int64_t a = i + n0 * (j + n1 * k);
+          double L[9];
+          /* source: only the damping of the cleaning scalar survives in flat space */
+          for (int v = 0; v < nv; ++v) L[v] = 0.0;
+          if (sys == 2) L[8] = -m->kappa * U[(int64_t)8 * N + e * npe + a];
+          /* volume term */
+          for (int d = 0; d < 3; ++d) {
+            if (G->n[d] < 2) continue;
+            double sc = 2.0 / G->dx[d];
+            int nd = G->n[d];
+            for (int v = 0; v < nv; ++v) {
+              double acc = 0.0;
+              for (int l = 0; l < nd; ++l) {
+                int c[3] = {i, j, k};
+                c[d] = l;
+                int64_t b = c[0] + n0 * (c[1] + n1 * c[2]);
+                acc += G->D[d][ijk[d] * nd + l] * F[(d * nv + v) * npe + b];
+              }
+              L[v] -= sc * acc;
+            }
+          }
+          /* surface terms of every face through this node */
+          for (int d = 0; d < 3; ++d) {
+            if (G->n[d] < 2) continue;
+            int Nd = G->n[d] - 1;
+            for (int side = 0; side < 2; ++side) {
+              if (ijk[d] != (side ? Nd : 0)) continue;
+              int64_t en = neighbour(m, e, d, side);
+              int c[3] = {i, j, k};
+              c[d] = side ? 0 : Nd;
+              int64_t b = c[0] + n0 * (c[1] + n1 * c[2]);
+              cons_t Ci, Ce; prim_t Pi, Pe;
+              load_cons(nv, N, U, e * npe + a, &Ci);
+              load_prim(N, prim, e * npe + a, &Pi);
+              load_cons(nv, N, U, en * npe + b, &Ce);
+              load_prim(N, prim, en * npe + b, &Pe);
+              double Fs[9], Fi[9];
+              llf(sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
+              double wend = G->w[d][side ? Nd : 0];
+              double sc = 2.0 / G->dx[d];
+              for (int v = 0; v < nv; ++v) L[v] -= sc * (1.0 / wend) * (Fs[v] - Fi[v]);
+            }
+          }
+          for (int v = 0; v < nv; ++v) dUdt[(int64_t)v * nout + s * npe + a] = L[v];
+        }
+    free(F);
+  }
+  return err ? ORA_EINVAL : ORA_OK;
+}
+
+/* Weak-form operator, an independent route to the same semi-discrete
+ * equation (before integration by parts is undone, eq. 4):
+ *   L_ijk = S + sum_d (2/dx_d) (1/w_{i_d}) sum_l D_{l i_d} w_l F^d(..l..)
+ *           - sum_{faces through ijk} (2/dx_d)(1/w_end) F*.n
+ * GLL quadrature makes it algebraically equal to the strong form.          */
+static int rhs_weak(const ora_mesh *m, const geom_t *G, const double *U, const double *prim, double *dUdt) {
+  int sys = m->sys, nv = nvars_of(sys);
+  double g = m->gamma;
+  int64_t N = G->nnodes, npe = G->npe;
+  int n0 = G->n[0], n1 = G->n[1];
+#pragma omp parallel for schedule(dynamic, 1) if (G->nnodes > 4096)
+  for (int64_t e = 0; e < G->nelem; ++e) {
+    double *F = (double *)malloc(sizeof(double) * 3 * nv * npe);
+    for (int64_t a = 0; a < npe; ++a) {
+      cons_t C; prim_t P; double f[9];
+      load_cons(nv, N, U, e * npe + a, &C);
+      load_prim(N, prim, e * npe + a, &P);
+      for (int d = 0; d < 3; ++d) {
+        flux(sys, g, d, &C, &P, f);
+        for (int v = 0; v < nv; ++v) F[(d * nv + v) * npe + a] = f[v];
+      }
+    }
+    for (int k = 0; k < G->n[2]; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n0; ++i) {
+          int ijk[3] = {i, j, k};
+          int64_t a = i + n0 * (j + n1 * k);
+          double L[9];
+          for (int v = 0; v < nv; ++v) L[v] = 0.0;
+          if (sys == 2) L[8] = -m->kappa * U[(int64_t)8 * N + e * npe + a];
+          for (int d = 0; d < 3; ++d) {
+            if (G->n[d] < 2) continue;
+            double sc = 2.0 / G->dx[d];
+            int nd = G->n[d];
+            for (int v = 0; v < nv; ++v) {
+              double acc = 0.0;
+              for (int l = 0; l < nd; ++l) {
+                int c[3] = {i, j, k};
+                c[d] = l;
+                int64_t b = c[0] + n0 * (c[1] + n1 * c[2]);
+                acc += G->D[d][l * nd + ijk[d]] * G->w[d][l] * F[(d * nv + v) * npe + b];
+              }
+              L[v] += sc * acc / G->w[d][ijk[d]];
+            }
+          }
+          for (int d = 0; d < 3; ++d) {
+            if (G->n[d] < 2) continue;
+            int Nd = G->n[d] - 1;
+            for (int side = 0; side < 2; ++side) {
+              if (ijk[d] != (side ? Nd : 0)) continue;
+              int64_t en = neighbour(m, e, d, side);
+              int c[3] = {i, j, k};
+              c[d] = side ? 0 : Nd;
+              int64_t b = c[0] + n0 * (c[1] + n1 * c[2]);
+              cons_t Ci, Ce; prim_t Pi, Pe;
+              load_cons(nv, N, U, e * npe + a, &Ci);
+              load_prim(N, prim, e * npe + a, &Pi);
+              load_cons(nv, N, U, en * npe + b, &Ce);
+              load_prim(N, prim, en * npe + b, &Pe);
+              double Fs[9], Fi[9];
+              llf(sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
+              double sc = 2.0 / G->dx[d];
+              for (int v = 0; v < nv; ++v) L[v] -= sc * Fs[v] / G->w[d][side ? Nd : 0];
+            }
+          }
+          for (int v = 0; v < nv; ++v) dUdt[(int64_t)v * N + e * npe + a] = L[v];
+        }
+    free(F);
+  }
+  return ORA_OK;
+}
+
+/* L(U): recover the primitives of every node (written to prim_out, may be
+ * NULL), then apply the strong-form operator.  Returns the number of nodes
+ * whose recovery failed (their dUdt is still written), or <0 on bad input. */
+int64_t ora_rhs(const ora_mesh *m, const double *U, double *prim_out, double *dUdt) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
+  double *prim = prim_out ? prim_out : (double *)malloc(sizeof(double) * 5 * G.nnodes);
+  int64_t nf = ora_cons2prim(m->sys, m->gamma, G.nnodes, U, prim, NULL);
+  int rc = rhs_strong(m, &G, U, prim, G.nelem, NULL, dUdt);
+  if (!prim_out) free(prim);
+  return rc == ORA_OK ? nf : rc;
+}
+
+/* Same operator, given primitives, for a subset of elements (for sampled
+ * checks on large meshes).  dUdt_sel[nv][nsel*npe].                        */
+int ora_rhs_elements(const ora_mesh *m, const double *U, const double *prim, int64_t nsel, const int64_t *elems,
+                     double *dUdt_sel) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
+  for (int64_t s = 0; s < nsel; ++s)
+    if (elems[s] < 0 || elems[s] >= G.nelem) return ORA_EINVAL;
+  return rhs_strong(m, &G, U, prim, nsel, elems, dUdt_sel);
+}
+
+int64_t ora_rhs_weak(const ora_mesh *m, const double *U, double *dUdt) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
+  double *prim = (double *)malloc(sizeof(double) * 5 * G.nnodes);
+  int64_t nf = ora_cons2prim(m->sys, m->gamma, G.nnodes, U, prim, NULL);
+  rhs_weak(m, &G, U, prim, dUdt);
+  free(prim);
+  return nf;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Third-order strong-stability-preserving Runge-Kutta (Shu-Osher form):     */
+/*   U1 = Un + dt L(Un)                                                      */
+/*   U2 = 3/4 Un + 1/4 (U1 + dt L(U1))                                       */
+/*   Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2))                                     */
+/* ------------------------------------------------------------------------ */
+int ora_rk3_combine(int stage, double dt, int64_t n, const double *Un, const double *Uprev, const double *L,
+                    double *Uout) {
+  double a, b;
+  if (stage == 1) { a = 0.0; b = 1.0; }
+  else if (stage == 2) { a = 0.75; b = 0.25; }
+  else if (stage == 3) { a = 1.0 / 3.0; b = 2.0 / 3.0; }
+  else return ORA_EINVAL;
+#pragma omp parallel for schedule(static) if (n > 65536)
+  for (int64_t q = 0; q < n; ++q) Uout[q] = a * Un[q] + b * (Uprev[q] + dt * L[q]);
+  return ORA_OK;
+}
+
+/* One SSP-RK3 step in place; primitives recovered afresh for every stage.
+ * Returns the number of failed recoveries summed over the three stages.   */
+int64_t ora_step(const ora_mesh *m, double *U, double dt) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
+  int nv = nvars_of(m->sys);
+  int64_t n = (int64_t)nv * G.nnodes;
+  double *L = (double *)malloc(sizeof(double) * n);
+  double *U1 = (double *)malloc(sizeof(double) * n);
+  double *U2 = (double *)malloc(sizeof(double) * n);
+  int64_t nf = 0;
+  nf += ora_rhs(m, U, NULL, L);
+  ora_rk3_combine(1, dt, n, U, U, L, U1);
+  nf += ora_rhs(m, U1, NULL, L);
+  ora_rk3_combine(2, dt, n, U, U1, L, U2);
+  nf += ora_rhs(m, U2, NULL, L);
+  ora_rk3_combine(3, dt, n, U, U2, L, U);
+  free(L); free(U1); free(U2);
+  return nf;
+}
+
+int64_t ora_evolve(const ora_mesh *m, double *U, double dt, int64_t nsteps) {
+  int64_t nf = 0;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    int64_t r = ora_step(m, U, dt);
+    if (r < 0) return r;
+    nf += r;
+  }
+  return nf;
+}
+
+/* L1 norm of eq. L1 with the GLL rule of each element:
+ * sum over components of sum_e sum_ijk w_i w_j w_k (dx dy dz / 8) |a - b|.
+ * (collapsed directions contribute weight 2 and length dx, i.e. unit
+ *  measure per element in that direction when dx = 1.)                     */
+double ora_l1_error(const ora_mesh *m, int ncomp, const double *a, const double *b) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return -1.0;
+  int64_t N = G.nnodes;
+  double vol = 1.0;
+  for (int d = 0; d < 3; ++d) vol *= G.dx[d] / 2.0;
+  double total = 0.0;
+  for (int c = 0; c < ncomp; ++c)
+    for (int64_t e = 0; e < G.nelem; ++e)
+      for (int k = 0; k < G.n[2]; ++k)
+        for (int j = 0; j < G.n[1]; ++j)
+          for (int i = 0; i < G.n[0]; ++i) {
+            int64_t q = e * G.npe + i + G.n[0] * (j + G.n[1] * k);
+            double w = G.w[0][i] * G.w[1][j] * G.w[2][k];
+            total += w * vol * fabs(a[(int64_t)c * N + q] - b[(int64_t)c * N + q]);
+          }
+  return total;
+}
+
+/* Weighted sum sum_e sum_ijk w_i w_j w_k (dx dy dz/8) q[c] for each component:
+ * the discrete integral of a nodal field (conservation check).             */
+int ora_integrate(const ora_mesh *m, int ncomp, const double *q, double *out) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
+  int64_t N = G.nnodes;
+  double vol = (G.dx[0] / 2.0) * (G.dx[1] / 2.0) * (G.dx[2] / 2.0);
+  for (int c = 0; c < ncomp; ++c) {
+    double total = 0.0;
+    for (int64_t e = 0; e < G.nelem; ++e)
+      for (int k = 0; k < G.n[2]; ++k)
+        for (int j = 0; j < G.n[1]; ++j)
+          for (int i = 0; i < G.n[0]; ++i) {
+            int64_t a = e * G.npe + i + G.n[0] * (j + G.n[1] * k);
+            total += G.w[0][i] * G.w[1][j] * G.w[2][k] * vol * q[(int64_t)c * N + a];
+          }
+    out[c] = total;
+  }
+  return ORA_OK;
+}
