@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark: DG right-hand side with per-node primitive recovery on one MI355X.
+
+Workload (one step = one dg_rhs call = recovery of every node + the DG
+operator): 3D special-relativistic hydrodynamics, ideal gas Gamma = 4/3,
+periodic unit cube, 32^3 affine elements of degree 4 (5^3 GLL nodes each,
+4,096,000 nodes, 20.48M degrees of freedom), FP64, seeded smooth random
+primitives (rho in [0.1, 10], p in [0.01, 100], Lorentz factor up to 10).
+Two input sets A and B (B = A with rho and p scaled by 1 + 1e-3) alternate,
+so every recovery starts from the previous call's pressures, as in a time
+integration, and the 2 x 164 MB of state exceed the 256 MB Infinity Cache.
+
+Printed: one JSON line with the metric (DOF-updates/s), the dominant
+kernel's roofline figures (HIP events on the launch stream) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SR = 1
+GAMMA = 4.0 / 3.0
+NEL = (32, 32, 32)
+DEG = 4
+NV = 5
+# algorithmic bytes per node of each kernel (FP64): the operator reads U and
+# the primitives and writes dU/dt; the recovery reads U and the pressure seed
+# and writes the primitives.
+OP_BYTES_PER_NODE = 8 * (NV + 5 + NV)
+C2P_BYTES_PER_NODE = 8 * (NV + 1 + 5)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def make_inputs(dg, synth, torch):
+    G = dg.Mesh(SR, NEL, DEG, GAMMA)
+    xyz = G.node_coords()
+    prim_a = synth.fourier_random_prims(xyz, seed=1609, xp="torch", device="cuda")
+    prim_b = prim_a.clone()
+    prim_b[0] *= 1.0 + 1e-3
+    prim_b[4] *= 1.0 + 1e-3
+    Ua = dg.dgmi_prim2cons(SR, GAMMA, prim_a.contiguous())
+    Ub = dg.dgmi_prim2cons(SR, GAMMA, prim_b.contiguous())
+    P = prim_b.contiguous().clone()  # the first call on A is seeded from B
+    dUa = G.empty_state()
+    dUb = G.empty_state()
+    del xyz
+    return G, Ua, Ub, P, dUa, dUb
+
+
+def time_loop(torch, fn, steps, warmup):
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for i in range(steps):
+        fn(i)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps  # ms
+
+
+def cpu_baseline(seconds):
+    """The oracle (plain FP64 C, OpenMP) on a 12^3-element periodic sub-box
+    of the same workload (same degree, generator and seed), repeated for at
+    least `seconds`."""
+    import oracle
+    from paper_1609_00098_amd import synth
+    sub = (12, 12, 12)
+    m = oracle.mesh(SR, sub, DEG, GAMMA)
+    U = oracle.prim2cons(SR, GAMMA, synth.fourier_random_prims(oracle.node_coords(m), seed=1609))
+    n = U.shape[1]
+    calls = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.rhs(m, U)
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": n * NV * calls / el, "unit": "DOF-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"oracle dg_rhs (bisection recovery + strong-form operator) on a {sub[0]}x{sub[1]}x{sub[2]}-"
+                      f"element periodic sub-box ({n} nodes) of the same workload, {calls} calls in {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_1609_00098_amd import dgmi as dg
+    from paper_1609_00098_amd import synth
+
+    torch.cuda.set_device(0)
+    G, Ua, Ub, P, dUa, dUb = make_inputs(dg, synth, torch)
+    nn = G.nnodes
+
+    def step(i):
+        if i % 2 == 0:
+            dg.dg_rhs(G, Ua, P, dUa)
+        else:
+            dg.dg_rhs(G, Ub, P, dUb)
+
+    torch.cuda.synchronize()
+    ms = time_loop(torch, step, args.steps, args.warmup)
+    nfail = dg.dgmi_failures(G)
+
+    # per-kernel durations with the same alternation (recovery, then operator)
+    def c2p(i):
+        dg.con2prim(SR, GAMMA, Ua if i % 2 == 0 else Ub, P, guess=dg.GUESS_INPUT, tol=0.0)
+
+    def op(i):
+        if i % 2 == 0:
+            dg.dg_operator(G, Ua, P, dUa)
+        else:
+            dg.dg_operator(G, Ub, P, dUb)
+
+    ksteps = max(args.steps // 2, 10)
+    ms_c2p = time_loop(torch, c2p, ksteps, 4)
+    ms_op = time_loop(torch, op, ksteps, 4)
+    if ms_op >= ms_c2p:
+        kname, kms, kbytes = "rhs_kernel<SR,4>", ms_op, OP_BYTES_PER_NODE * nn
+    else:
+        kname, kms, kbytes = "con2prim_kernel<SR,input>", ms_c2p, C2P_BYTES_PER_NODE * nn
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel_ms": {"rhs_kernel": round(ms_op, 4), "con2prim_kernel": round(ms_c2p, 4)},
+            "algorithmic_bytes_per_node": {"rhs_kernel": OP_BYTES_PER_NODE, "con2prim_kernel": C2P_BYTES_PER_NODE}}
+    value = nn * NV / (ms * 1e-3)
+    out = {
+        "metric": "DG RHS DOF-updates/s (FP64); con2prim pts/s, learned guess vs plain Newton",
+        "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "SR hydro dg_rhs (recovery + operator), Gamma 4/3, periodic 32^3 elements, "
+                               "degree 4 (4,096,000 nodes), smooth random primitives, W <= 10",
+                   "nodes": nn, "dof": nn * NV, "failed_recoveries": nfail},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * dgmi -- nodal discontinuous Galerkin right-hand side, SSP-RK3 step and
+ * conservative-to-primitive recovery on one AMD MI355X (gfx950).
+ *
+ * The library evolves a conservation law in flux-conservative form,
+ *     d_t U + d_a F^a(U) = S(U)
+ * (the conservation-laws section of Kidder et al., arXiv:1609.00098, with the
+ * flat metric: lapse 1, zero shift, Euclidean spatial metric), discretised by
+ * the strong-form nodal DG scheme (eq. 411) on a periodic box of affine
+ * hexahedra (eq. AffineMap) with the local Lax-Friedrichs flux (eq. LLF).
+ *
+ * Conventions common to every call
+ *   - Systems: DGMI_NEWTONIAN_EULER  U = (rho, rho v_x, rho v_y, rho v_z, E)
+ *              DGMI_SR_HYDRO         U = (D, S_x, S_y, S_z, tau)
+ *              DGMI_SR_MHD           U = (D, S_x, S_y, S_z, tau, B_x, B_y, B_z, Phi)
+ *     with the ideal-gas equation of state p = (gamma - 1) rho eps.
+ *   - Primitives: prim[5][n] = (rho, v_x, v_y, v_z, p); for MHD the magnetic
+ *     field and Phi are read from U.
+ *   - All arrays are structure-of-arrays, A[var * n + point], FP64 unless
+ *     stated.  Mesh node order: element e = ex + nx*(ey + ny*ez) owns the
+ *     contiguous block [off[e], off[e+1]); inside it node
+ *     i + (N+1)*(j + (N+1)*k) with i along x fastest, on the GLL nodes.
+ *   - Every pointer argument is device memory owned by the caller unless its
+ *     name ends in _host.  The library never frees caller memory.
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*;
+ *     NULL = the default stream) unless stated.
+ *   - Every call returns a dgmi_status; nothing aborts and nothing throws
+ *     across the ABI.  Invalid arguments return DGMI_EINVAL before any work is
+ *     enqueued; dgmi_last_error() then describes the problem (thread-local).
+ */
+#ifndef DGMI_H
+#define DGMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DGMI_OK = 0,
+  DGMI_EINVAL = -1,       /* bad argument; nothing was enqueued */
+  DGMI_ENOMEM = -2,       /* device allocation failed */
+  DGMI_EHIP = -3,         /* a HIP runtime call failed */
+  DGMI_ECON2PRIM = -4,    /* a recovery failed (checked variants only) */
+  DGMI_EUNSUPPORTED = -5  /* valid request the library does not implement */
+} dgmi_status;
+
+enum { DGMI_NEWTONIAN_EULER = 0, DGMI_SR_HYDRO = 1, DGMI_SR_MHD = 2 };
+
+/* Initial pressure for the recovery's Newton iteration. */
+enum {
+  DGMI_GUESS_INPUT = 0,   /* prim_inout[4][i] on entry */
+  DGMI_GUESS_PLAIN = 1,   /* upper end of the bracket (ignores prim_inout on entry) */
+  DGMI_GUESS_LEARNED = 2  /* the pressure-guess MLP (needs an MLP handle) */
+};
+
+/* dgmi_mesh_desc.flags */
+#define DGMI_FLAG_PLAIN_GUESS 1   /* dg_rhs / dg_step: seed recoveries from the bracket, not prim_inout */
+#define DGMI_FLAG_RECOVER_FIRST 2 /* dg_step: recompute prims of U^n before the first stage */
+
+typedef struct dgmi_ctx dgmi_ctx;
+typedef struct dgmi_mlp dgmi_mlp;
+
+typedef struct {
+  int32_t system;         /* DGMI_NEWTONIAN_EULER, DGMI_SR_HYDRO or DGMI_SR_MHD */
+  int32_t nx, ny, nz;     /* elements per direction (>= 1 each); periodic box */
+  int32_t degree;         /* 1..7: uniform polynomial degree N (N+1 GLL nodes per
+                             direction); 0: per-element degrees from degrees_host */
+  int32_t flags;          /* DGMI_FLAG_* */
+  double gamma;           /* ideal-gas adiabatic index, 1 < gamma <= 2 */
+  double kappa;           /* divergence-cleaning damping (MHD source -kappa Phi) */
+  double lo[3], hi[3];    /* box corners; every element has size (hi-lo)/n_d */
+  const int32_t *degrees_host; /* nx*ny*nz degrees in 2..7 when degree == 0 */
+} dgmi_mesh_desc;
+
+/* Build a mesh context: GLL nodes, weights and differentiation matrices
+ * (eq. for D^{1bar}), neighbour tables, RK scratch.  Synchronous.  The
+ * context is bound to the device current at creation.  Mixed degrees
+ * (degree == 0) return DGMI_EUNSUPPORTED from dg_rhs/dg_step until the
+ * mortar path is enabled.                                                */
+dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out);
+dgmi_status dgmi_destroy(dgmi_ctx *ctx);
+
+int64_t dgmi_num_nodes(const dgmi_ctx *ctx);    /* sum over elements of (N_e+1)^3 */
+int32_t dgmi_num_vars(const dgmi_ctx *ctx);     /* 5 or 9 */
+int64_t dgmi_num_elements(const dgmi_ctx *ctx);
+/* off_host[nelem+1]: first node of every element (host copy). */
+dgmi_status dgmi_elem_offsets(const dgmi_ctx *ctx, int64_t *off_host);
+
+/* xyz[3][nnodes]: physical coordinates of every node through the affine map
+ * x = a + (1 + xbar)(b - a)/2 (eq. AffineMap). */
+dgmi_status dgmi_node_coords(const dgmi_ctx *ctx, double *xyz, void *stream);
+
+/* U[nv][n] from prim[5][n] (and mag[4][n] = (B_x, B_y, B_z, Phi) for MHD;
+ * ignored otherwise): the definitions of the evolved variables of the
+ * conservation-laws section (eq. evolved for MHD). */
+dgmi_status dgmi_prim2cons(int32_t system, double gamma, const double *prim, const double *mag, double *U,
+                           int64_t n, void *stream);
+
+/* Semi-discrete operator dUdt = L(U) of eq. 411:
+ *   L = S - sum_d (2/dx_d) D^(d) F^d - sum_faces (2/dx_d)(1/w_end)(F*.n - F.n),
+ * F*.n the LLF flux with the unit outward normal.  First recovers the
+ * primitives of every node (Newton polished to rounding level, seeded from
+ * prim_inout's pressure unless DGMI_FLAG_PLAIN_GUESS), which are written
+ * back to prim_inout.  Failed recoveries are counted (dgmi_failures).
+ * U[nv][nnodes], prim_inout[5][nnodes], dUdt[nv][nnodes]; dUdt must not
+ * alias U or prim_inout. */
+dgmi_status dg_rhs(dgmi_ctx *ctx, const double *U, double *prim_inout, double *dUdt, void *stream);
+
+/* The operator alone, for callers that already hold the primitives of U:
+ * dUdt = L(U) of eq. 411 with prim[5][nnodes] taken as given (dg_rhs is
+ * con2prim followed by this call).  dUdt must not alias U or prim. */
+dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, double *dUdt, void *stream);
+
+/* One third-order SSP Runge-Kutta step (Shu-Osher form) in place:
+ *   U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
+ *   U <- 1/3 U + 2/3 (U2 + dt L(U2)).
+ * prim_inout must hold the primitives of U on entry (or set
+ * DGMI_FLAG_RECOVER_FIRST); on exit it holds those of the new U.  Each stage
+ * is one kernel that also recovers the primitives of its output. */
+dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream);
+
+/* Number of failed recoveries since the last call (synchronises `stream`,
+ * then resets the counter). */
+dgmi_status dgmi_failures(dgmi_ctx *ctx, int64_t *n_failed_host, void *stream);
+
+/* Pointwise recovery of the primitives (conservation-laws section; the
+ * relativistic systems solve f(p) = (gamma-1) rho eps(p) - p = 0 by a
+ * bracketed Newton iteration on [0, p_hi], p_hi = (gamma-1) tau, or
+ * (gamma-1)(tau - B^2/2) for MHD).
+ *   U[nv][n] in, prim_inout[5][n] in (pressure guess for DGMI_GUESS_INPUT)
+ *   and out.  tol > 0: stop once the backward residual
+ *   max(|dD|/D, |dS|_inf/E, |dtau|/E) of the returned primitives is <= tol
+ *   (E = tau + D); tol <= 0: polish to rounding level.
+ *   iters_out (uint8[n], nullable): pressure-function evaluations used;
+ *   fail_out (uint8[n], nullable): 1 where no physical state was found
+ *   (prims then hold the last iterate); n_failed (device int64, nullable):
+ *   incremented by the number of failures.
+ *   mlp: trained network for DGMI_GUESS_LEARNED (SR_MHD and SR_HYDRO). */
+dgmi_status con2prim(int32_t system, double gamma, const double *U, double *prim_inout, int64_t n, int32_t guess,
+                     const dgmi_mlp *mlp, double tol, uint8_t *iters_out, uint8_t *fail_out, int64_t *n_failed,
+                     void *stream);
+
+/* ---------------------------------------------------------------------
+ * Learned pressure guess: a 5 -> 64 -> 64 -> 1 multilayer perceptron with
+ * SiLU activations in FP32 that proposes the recovery's initial pressure
+ * (p0 = D exp(y), y the predicted ln(p/D)).  The FP64 bracketed Newton
+ * iteration still decides every result.  Inputs are the raw features
+ *   x = [ln D, ln(tau/D), ln(1 + |S|/D), ln(1 + B^2/D), S.B/(|S||B| + tiny)]
+ * in x[5][batch] (float32, device), normalised inside the library with the
+ * stored feature means/deviations; targets t[batch] are raw ln(p/D).
+ * Parameter vector: 4609 weights W1[64][5] b1[64] W2[64][64] b2[64] W3[64] b3
+ * followed by mu[5] sd[5] ymu ysd (4621 floats).
+ * ------------------------------------------------------------------- */
+
+/* New network with weights drawn U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a
+ * generator seeded by `seed`; identity normalisation.  Synchronous. */
+dgmi_status mlp_create(dgmi_mlp **out, uint64_t seed);
+dgmi_status mlp_destroy(dgmi_mlp *mlp);
+/* Copy the 4621-float parameter vector out of / into the network
+ * (device to device); mlp_set also resets the optimiser state. */
+dgmi_status mlp_get(const dgmi_mlp *mlp, float *params_out, void *stream);
+dgmi_status mlp_set(dgmi_mlp *mlp, const float *params_in, void *stream);
+/* x_out[5][n] raw features of conserved states U[nv][n] (SR_HYDRO or SR_MHD);
+ * when prim[5][n] is given, t_out[n] (nullable) receives the training target
+ * ln(p/D). */
+dgmi_status mlp_features(int32_t system, double gamma, const double *U, const double *prim, int64_t n, float *x_out,
+                         float *t_out, void *stream);
+/* Feature matrices are read as x[i * ldx + s] (ldx >= the sample count), so
+ * a minibatch is a column slice of a larger [5][ldx] array. */
+/* Store the means and standard deviations of x[5][n] and t[n] as the
+ * network's normalisation (FP64 accumulation). */
+dgmi_status mlp_fit_normalization(dgmi_mlp *mlp, const float *x, int64_t ldx, const float *t, int64_t n, void *stream);
+/* y_out[batch]: predicted ln(p/D) for raw features x. */
+dgmi_status mlp_forward(const dgmi_mlp *mlp, const float *x, int64_t ldx, int64_t batch, float *y_out, void *stream);
+/* Gradient of L = mean over the batch of (y_n - t_n)^2 (normalised units)
+ * with respect to the 4609 weights, into grads_out[4609]; loss_out[1]
+ * (nullable) receives L.  Deterministic (fixed-order reductions). */
+dgmi_status mlp_grad(dgmi_mlp *mlp, const float *x, int64_t ldx, const float *t, int64_t batch, float *grads_out,
+                     float *loss_out, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on that
+ * gradient. */
+dgmi_status mlp_train_step(dgmi_mlp *mlp, const float *x, int64_t ldx, const float *t, int64_t batch, float lr,
+                           float *loss_out, void *stream);
+/* Whole training run over x[5][n], t[n]: `epochs` passes of n/batch
+ * consecutive minibatches, learning rate cosine-decayed from lr0 to lr1;
+ * loss_hist (nullable) receives every step's loss
+ * (epochs * (n/batch) floats, device). */
+dgmi_status mlp_train(dgmi_mlp *mlp, const float *x, const float *t, int64_t n, int64_t batch, int32_t epochs,
+                      float lr0, float lr1, float *loss_hist, void *stream);
+
+const char *dgmi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

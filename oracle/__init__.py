@@ -75,6 +75,7 @@ def _load():
     U8 = ctypes.POINTER(ctypes.c_uint8)
     MP = ctypes.POINTER(Mesh)
     sig = {
+        "ora_num_threads": (ctypes.c_int, []),
         "ora_gll": (ctypes.c_int, [ctypes.c_int, D, D]),
         "ora_legendre": (ctypes.c_double, [ctypes.c_int, ctypes.c_double]),
         "ora_diff_matrix": (ctypes.c_int, [ctypes.c_int, D, D]),
@@ -82,6 +83,7 @@ def _load():
         "ora_prim2cons": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, I64, D, D, D]),
         "ora_cons2prim": (I64, [ctypes.c_int, ctypes.c_double, I64, D, D, U8]),
         "ora_c2p_pressure_function": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, D, I64, D, D, U8]),
+        "ora_c2p_f_points": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, I64, D, D, D, U8]),
         "ora_backward_residual": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, I64, D, D, D]),
         "ora_flux": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, I64, D, D, D]),
         "ora_max_speed": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, I64, D, D, D]),
@@ -111,6 +113,10 @@ def _p(a):
 
 def _c(a, dtype=np.float64):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def num_threads():
+    return int(_load().ora_num_threads())
 
 
 # ----------------------------------------------------------------- tables
@@ -172,6 +178,17 @@ def pressure_function(system, gamma, u1, p):
     valid = np.zeros(len(p), dtype=np.uint8)
     _load().ora_c2p_pressure_function(system, gamma, _p(u1), len(p), _p(p), _p(f),
                                       valid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return f, valid.astype(bool)
+
+
+def pressure_function_points(system, gamma, U, p):
+    """f(p[q]) of state q for every point (one trial pressure per point)."""
+    U = _c(U)
+    p = _c(p)
+    f = np.zeros(U.shape[1])
+    valid = np.zeros(U.shape[1], dtype=np.uint8)
+    _load().ora_c2p_f_points(system, gamma, U.shape[1], _p(U), _p(p), _p(f),
+                             valid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
     return f, valid.astype(bool)
 
 

@@ -25,6 +25,7 @@
  *   faces), which turns the 3D operator into its 1D/2D analogue.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -33,6 +34,9 @@
 #define ORA_EINVAL (-1)
 
 static int nvars_of(int sys) { return sys == 2 ? 9 : 5; }
+
+/* Threads OpenMP regions of the oracle use. */
+int ora_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Legendre polynomials and Gauss-Legendre-Lobatto quadrature               */
@@ -417,6 +421,20 @@ int ora_c2p_pressure_function(int sys, double g, const double *u1, int64_t m, co
     double fk = 0.0;
     valid[k] = (uint8_t)c2p_eval(sys, g, &C, p[k], &fk, NULL);
     f[k] = fk;
+  }
+  return ORA_OK;
+}
+
+/* f at one trial pressure per point: f[q] = f(p[q]) for state q (valid[q] = 0
+ * where the map is undefined). */
+int ora_c2p_f_points(int sys, double g, int64_t n, const double *U, const double *p, double *f, uint8_t *valid) {
+  int nv = nvars_of(sys);
+  for (int64_t q = 0; q < n; ++q) {
+    cons_t C;
+    double fq = 0.0;
+    load_cons(nv, n, U, q, &C);
+    valid[q] = (uint8_t)c2p_eval(sys, g, &C, p[q], &fq, NULL);
+    f[q] = fq;
   }
   return ORA_OK;
 }

@@ -1,0 +1,409 @@
+// C-ABI of the library: mesh contexts, the DG operator, the SSP-RK3 step and
+// the pointwise recovery.  Host-side tables are computed here (GLL nodes by
+// Newton iteration from Chebyshev-Gauss-Lobatto seeds, differentiation
+// matrices from barycentric weights).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/dgmi.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+dgmi_status fail(dgmi_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(DGMI_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Legendre P_N and its first two derivatives at x (three-term recurrence).
+void legendre_derivs(int N, double x, double &P, double &dP, double &d2P) {
+  double pm1 = 1.0, p = x, dpm1 = 0.0, dp = 1.0;
+  if (N == 0) { P = 1.0; dP = 0.0; d2P = 0.0; return; }
+  for (int k = 1; k < N; ++k) {
+    const double pn = ((2 * k + 1) * x * p - k * pm1) / (k + 1);
+    const double dpn = dpm1 + (2 * k + 1) * p;
+    pm1 = p; p = pn; dpm1 = dp; dp = dpn;
+  }
+  P = p;
+  dP = dp;
+  // (1 - x^2) P'' = 2x P' - N(N+1) P
+  d2P = (std::fabs(1.0 - x * x) > 0.0) ? (2.0 * x * dP - N * (N + 1.0) * P) / (1.0 - x * x) : 0.0;
+}
+
+// GLL nodes and weights: interior nodes are the roots of P_N', refined by
+// Newton from x_i = -cos(pi i / N).
+void gll_nodes(int N, double *x, double *w) {
+  x[0] = -1.0;
+  x[N] = 1.0;
+  for (int i = 1; i < N; ++i) {
+    double xi = -std::cos(M_PI * i / N);
+    for (int it = 0; it < 100; ++it) {
+      double P, dP, d2P;
+      legendre_derivs(N, xi, P, dP, d2P);
+      const double dx = dP / d2P;
+      xi -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    x[i] = xi;
+  }
+  for (int i = 0; i <= N / 2; ++i) {  // enforce exact symmetry
+    const double s = 0.5 * (x[N - i] - x[i]);
+    x[i] = -s;
+    x[N - i] = s;
+  }
+  if (N % 2 == 0) x[N / 2] = 0.0;
+  for (int i = 0; i <= N; ++i) {
+    double P, dP, d2P;
+    legendre_derivs(N, x[i], P, dP, d2P);
+    w[i] = 2.0 / (N * (N + 1.0) * P * P);
+  }
+}
+
+// D_il = ell_l'(x_i) via barycentric weights lambda_i = 1/prod_{j!=i}(x_i - x_j):
+// D_il = (lambda_l / lambda_i) / (x_i - x_l), D_ii = -sum_{l!=i} D_il.
+void diff_matrix(int N, const double *x, double *D) {
+  const int n = N + 1;
+  std::vector<double> lam(n);
+  for (int i = 0; i < n; ++i) {
+    double p = 1.0;
+    for (int j = 0; j < n; ++j)
+      if (j != i) p *= (x[i] - x[j]);
+    lam[i] = 1.0 / p;
+  }
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int l = 0; l < n; ++l) {
+      if (l == i) continue;
+      const double v = (lam[l] / lam[i]) / (x[i] - x[l]);
+      D[i * n + l] = v;
+      s += v;
+    }
+    D[i * n + i] = -s;
+  }
+}
+
+bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+int dgmi::set_error(int st, const char *msg) {
+  std::snprintf(g_err, sizeof(g_err), "%s", msg);
+  return st;
+}
+
+struct dgmi_ctx {
+  int device = 0;
+  int sys = 0, nv = 5;
+  int nx = 0, ny = 0, nz = 0;
+  int degree = 0;
+  int flags = 0;
+  double gamma = 0, kappa = 0;
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, dx[3] = {0, 0, 0};
+  int64_t nelem = 0, nnodes = 0;
+  std::vector<int64_t> off;
+  std::vector<int32_t> deg;
+  double *d_D = nullptr;      // [8][64] differentiation matrices by degree
+  double *d_x = nullptr;      // [8][8] GLL nodes by degree
+  int32_t *d_nbr = nullptr;   // [nelem][6]
+  double *d_U1 = nullptr, *d_U2 = nullptr, *d_P1 = nullptr, *d_P2 = nullptr;
+  unsigned long long *d_nfail = nullptr;
+  double wend[8];
+};
+
+extern "C" {
+
+const char *dgmi_last_error(void) { return g_err; }
+
+static void ctx_free(dgmi_ctx *c) {
+  if (!c) return;
+  (void)hipFree(c->d_D);
+  (void)hipFree(c->d_x);
+  (void)hipFree(c->d_nbr);
+  (void)hipFree(c->d_U1);
+  (void)hipFree(c->d_U2);
+  (void)hipFree(c->d_P1);
+  (void)hipFree(c->d_P2);
+  (void)hipFree(c->d_nfail);
+  delete c;
+}
+
+dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
+  if (!desc || !out) return fail(DGMI_EINVAL, "dgmi_create: null argument");
+  *out = nullptr;
+  if (desc->system < 0 || desc->system > 2) return fail(DGMI_EINVAL, "dgmi_create: unknown system %d", desc->system);
+  if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1)
+    return fail(DGMI_EINVAL, "dgmi_create: element counts must be >= 1");
+  if ((int64_t)desc->nx * desc->ny * desc->nz > (int64_t)1 << 26)
+    return fail(DGMI_EINVAL, "dgmi_create: too many elements");
+  if (!(desc->gamma > 1.0 && desc->gamma <= 2.0)) return fail(DGMI_EINVAL, "dgmi_create: gamma must be in (1, 2]");
+  for (int d = 0; d < 3; ++d)
+    if (!(desc->hi[d] > desc->lo[d])) return fail(DGMI_EINVAL, "dgmi_create: empty box in direction %d", d);
+  if (desc->degree < 0 || desc->degree > 7) return fail(DGMI_EINVAL, "dgmi_create: degree must be 1..7 or 0");
+  if (desc->degree == 0 && !desc->degrees_host)
+    return fail(DGMI_EINVAL, "dgmi_create: degree 0 needs degrees_host");
+  dgmi_ctx *c = new (std::nothrow) dgmi_ctx();
+  if (!c) return fail(DGMI_ENOMEM, "dgmi_create: out of host memory");
+  (void)hipGetDevice(&c->device);
+  c->sys = desc->system;
+  c->nv = desc->system == 2 ? 9 : 5;
+  c->nx = desc->nx; c->ny = desc->ny; c->nz = desc->nz;
+  c->degree = desc->degree;
+  c->flags = desc->flags;
+  c->gamma = desc->gamma;
+  c->kappa = desc->kappa;
+  const int ne[3] = {desc->nx, desc->ny, desc->nz};
+  for (int d = 0; d < 3; ++d) {
+    c->lo[d] = desc->lo[d];
+    c->hi[d] = desc->hi[d];
+    c->dx[d] = (desc->hi[d] - desc->lo[d]) / ne[d];
+  }
+  c->nelem = (int64_t)desc->nx * desc->ny * desc->nz;
+  c->deg.resize(c->nelem);
+  for (int64_t e = 0; e < c->nelem; ++e) {
+    const int N = desc->degree ? desc->degree : desc->degrees_host[e];
+    if (N < 1 || N > 7) {
+      delete c;
+      return fail(DGMI_EINVAL, "dgmi_create: element %lld has degree %d", (long long)e, N);
+    }
+    c->deg[e] = N;
+  }
+  c->off.resize(c->nelem + 1);
+  c->off[0] = 0;
+  for (int64_t e = 0; e < c->nelem; ++e) c->off[e + 1] = c->off[e] + (int64_t)(c->deg[e] + 1) * (c->deg[e] + 1) * (c->deg[e] + 1);
+  c->nnodes = c->off[c->nelem];
+
+  // tables for every degree
+  std::vector<double> hD(8 * 64, 0.0), hx(8 * 8, 0.0);
+  for (int N = 1; N <= 7; ++N) {
+    double w[8];
+    gll_nodes(N, &hx[N * 8], w);
+    diff_matrix(N, &hx[N * 8], &hD[N * 64]);
+    c->wend[N] = w[0];
+  }
+  std::vector<int32_t> nbr(c->nelem * 6);
+  for (int64_t e = 0; e < c->nelem; ++e) {
+    const int64_t ex = e % c->nx, ey = (e / c->nx) % c->ny, ez = e / ((int64_t)c->nx * c->ny);
+    const int64_t cc[3] = {ex, ey, ez};
+    for (int f = 0; f < 6; ++f) {
+      int64_t k[3] = {cc[0], cc[1], cc[2]};
+      const int d = f >> 1;
+      k[d] = (k[d] + ((f & 1) ? 1 : ne[d] - 1)) % ne[d];
+      nbr[e * 6 + f] = (int32_t)(k[0] + ne[0] * (k[1] + ne[1] * k[2]));
+    }
+  }
+  const size_t ubytes = sizeof(double) * (size_t)c->nv * c->nnodes;
+  const size_t pbytes = sizeof(double) * 5 * (size_t)c->nnodes;
+  if (hipMalloc(&c->d_D, hD.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_x, hx.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_nbr, nbr.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&c->d_nfail, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&c->d_U1, ubytes) != hipSuccess || hipMalloc(&c->d_U2, ubytes) != hipSuccess ||
+      hipMalloc(&c->d_P1, pbytes) != hipSuccess || hipMalloc(&c->d_P2, pbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx_free(c);
+    return fail(DGMI_ENOMEM, "dgmi_create: device allocation failed (%lld nodes)", (long long)c->nnodes);
+  }
+  if (hipMemcpy(c->d_D, hD.data(), hD.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_x, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->d_nfail, 0, sizeof(unsigned long long)) != hipSuccess) {
+    ctx_free(c);
+    return fail(DGMI_EHIP, "dgmi_create: table upload failed");
+  }
+  *out = c;
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_destroy(dgmi_ctx *ctx) {
+  if (!ctx) return DGMI_OK;
+  (void)hipDeviceSynchronize();
+  ctx_free(ctx);
+  return DGMI_OK;
+}
+
+int64_t dgmi_num_nodes(const dgmi_ctx *ctx) { return ctx ? ctx->nnodes : -1; }
+int32_t dgmi_num_vars(const dgmi_ctx *ctx) { return ctx ? ctx->nv : -1; }
+int64_t dgmi_num_elements(const dgmi_ctx *ctx) { return ctx ? ctx->nelem : -1; }
+
+dgmi_status dgmi_elem_offsets(const dgmi_ctx *ctx, int64_t *off_host) {
+  if (!ctx || !off_host) return fail(DGMI_EINVAL, "dgmi_elem_offsets: null argument");
+  std::memcpy(off_host, ctx->off.data(), sizeof(int64_t) * (ctx->nelem + 1));
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_node_coords(const dgmi_ctx *ctx, double *xyz, void *stream) {
+  if (!ctx || !is_device_ptr(xyz)) return fail(DGMI_EINVAL, "dgmi_node_coords: bad argument");
+  if (ctx->degree == 0) return fail(DGMI_EUNSUPPORTED, "dgmi_node_coords: mixed degrees not enabled");
+  HIP_TRY(dgmi::launch_node_coords(ctx->degree, ctx->d_x + 8 * ctx->degree, ctx->nx, ctx->ny, ctx->nz, ctx->lo,
+                                   ctx->dx, xyz, ctx->nnodes, (hipStream_t)stream));
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_prim2cons(int32_t system, double gamma, const double *prim, const double *mag, double *U, int64_t n,
+                           void *stream) {
+  if (system < 0 || system > 2) return fail(DGMI_EINVAL, "dgmi_prim2cons: unknown system");
+  if (n < 0) return fail(DGMI_EINVAL, "dgmi_prim2cons: negative size");
+  if (n == 0) return DGMI_OK;
+  if (!is_device_ptr(prim) || !is_device_ptr(U) || (system == 2 && !is_device_ptr(mag)))
+    return fail(DGMI_EINVAL, "dgmi_prim2cons: arguments must be device pointers");
+  if (!(gamma > 1.0 && gamma <= 2.0)) return fail(DGMI_EINVAL, "dgmi_prim2cons: gamma must be in (1, 2]");
+  HIP_TRY(dgmi::launch_prim2cons(system, gamma, prim, mag, U, n, (hipStream_t)stream));
+  return DGMI_OK;
+}
+
+static dgmi::RhsArgs rhs_args(dgmi_ctx *c) {
+  dgmi::RhsArgs a{};
+  a.nbr = c->d_nbr;
+  a.Dmat = c->d_D + 64 * c->degree;
+  a.nfail = c->d_nfail;
+  a.nelem = c->nelem;
+  a.nnodes = c->nnodes;
+  a.gamma = c->gamma;
+  a.kappa = c->kappa;
+  for (int d = 0; d < 3; ++d) a.scale[d] = 2.0 / c->dx[d];
+  a.inv_wend = 1.0 / c->wend[c->degree];
+  return a;
+}
+
+static dgmi_status recover_all(dgmi_ctx *c, const double *U, double *prim, int guess, hipStream_t s) {
+  dgmi::C2PArgs a{};
+  a.U = U;
+  a.prim = prim;
+  a.n = c->nnodes;
+  a.gamma = c->gamma;
+  a.tol = 0.0;
+  a.nfail = c->d_nfail;
+  HIP_TRY(dgmi::launch_con2prim(c->sys, guess, a, s));
+  return DGMI_OK;
+}
+
+dgmi_status dg_rhs(dgmi_ctx *ctx, const double *U, double *prim_inout, double *dUdt, void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dg_rhs: null context");
+  if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || !is_device_ptr(dUdt))
+    return fail(DGMI_EINVAL, "dg_rhs: U, prim_inout and dUdt must be device pointers");
+  if (dUdt == U || dUdt == prim_inout) return fail(DGMI_EINVAL, "dg_rhs: dUdt must not alias its inputs");
+  if (ctx->degree == 0) return fail(DGMI_EUNSUPPORTED, "dg_rhs: mixed degrees not enabled");
+  hipStream_t s = (hipStream_t)stream;
+  const int guess = (ctx->flags & DGMI_FLAG_PLAIN_GUESS) ? DGMI_GUESS_PLAIN : DGMI_GUESS_INPUT;
+  dgmi_status st = recover_all(ctx, U, prim_inout, guess, s);
+  if (st != DGMI_OK) return st;
+  dgmi::RhsArgs a = rhs_args(ctx);
+  a.U = U;
+  a.P = prim_inout;
+  a.out = dUdt;
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 0, a, s));
+  return DGMI_OK;
+}
+
+dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, double *dUdt, void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dg_operator: null context");
+  if (!is_device_ptr(U) || !is_device_ptr(prim) || !is_device_ptr(dUdt))
+    return fail(DGMI_EINVAL, "dg_operator: U, prim and dUdt must be device pointers");
+  if (dUdt == U || dUdt == prim) return fail(DGMI_EINVAL, "dg_operator: dUdt must not alias its inputs");
+  if (ctx->degree == 0) return fail(DGMI_EUNSUPPORTED, "dg_operator: mixed degrees not enabled");
+  dgmi::RhsArgs a = rhs_args(ctx);
+  a.U = U;
+  a.P = prim;
+  a.out = dUdt;
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 0, a, (hipStream_t)stream));
+  return DGMI_OK;
+}
+
+dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dg_step: null context");
+  if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
+    return fail(DGMI_EINVAL, "dg_step: U and prim_inout must be distinct device pointers");
+  if (!std::isfinite(dt)) return fail(DGMI_EINVAL, "dg_step: dt must be finite");
+  if (ctx->degree == 0) return fail(DGMI_EUNSUPPORTED, "dg_step: mixed degrees not enabled");
+  hipStream_t s = (hipStream_t)stream;
+  if (ctx->flags & DGMI_FLAG_RECOVER_FIRST) {
+    const int guess = (ctx->flags & DGMI_FLAG_PLAIN_GUESS) ? DGMI_GUESS_PLAIN : DGMI_GUESS_INPUT;
+    dgmi_status st = recover_all(ctx, U, prim_inout, guess, s);
+    if (st != DGMI_OK) return st;
+  }
+  dgmi::RhsArgs a = rhs_args(ctx);
+  a.dt = dt;
+  a.Un = U;
+  // stage 1: U1 = U + dt L(U)
+  a.U = U; a.P = prim_inout; a.out = ctx->d_U1; a.Pout = ctx->d_P1; a.a = 0.0; a.b = 1.0;
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, a, s));
+  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
+  a.U = ctx->d_U1; a.P = ctx->d_P1; a.out = ctx->d_U2; a.Pout = ctx->d_P2; a.a = 0.75; a.b = 0.25;
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, a, s));
+  // stage 3: U <- 1/3 U + 2/3 (U2 + dt L(U2))  (each thread reads U^n at its own node before writing it)
+  a.U = ctx->d_U2; a.P = ctx->d_P2; a.out = U; a.Pout = prim_inout; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, a, s));
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_failures(dgmi_ctx *ctx, int64_t *n_failed_host, void *stream) {
+  if (!ctx || !n_failed_host) return fail(DGMI_EINVAL, "dgmi_failures: null argument");
+  unsigned long long v = 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(&v, ctx->d_nfail, sizeof(v), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemsetAsync(ctx->d_nfail, 0, sizeof(v), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *n_failed_host = (int64_t)v;
+  return DGMI_OK;
+}
+
+dgmi_status con2prim(int32_t system, double gamma, const double *U, double *prim_inout, int64_t n, int32_t guess,
+                     const dgmi_mlp *mlp, double tol, uint8_t *iters_out, uint8_t *fail_out, int64_t *n_failed,
+                     void *stream) {
+  if (system < 0 || system > 2) return fail(DGMI_EINVAL, "con2prim: unknown system");
+  if (guess < 0 || guess > 2) return fail(DGMI_EINVAL, "con2prim: unknown guess mode");
+  if (n < 0) return fail(DGMI_EINVAL, "con2prim: negative size");
+  if (!(gamma > 1.0 && gamma <= 2.0)) return fail(DGMI_EINVAL, "con2prim: gamma must be in (1, 2]");
+  if (!std::isfinite(tol)) return fail(DGMI_EINVAL, "con2prim: tol must be finite");
+  if (n == 0) return DGMI_OK;
+  if (!is_device_ptr(U) || !is_device_ptr(prim_inout)) return fail(DGMI_EINVAL, "con2prim: U/prim must be device pointers");
+  if ((iters_out && !is_device_ptr(iters_out)) || (fail_out && !is_device_ptr(fail_out)) ||
+      (n_failed && !is_device_ptr(n_failed)))
+    return fail(DGMI_EINVAL, "con2prim: optional outputs must be device pointers");
+  const float *mp = nullptr;
+  if (guess == DGMI_GUESS_LEARNED) {
+    if (system == 0) return fail(DGMI_EINVAL, "con2prim: the learned guess needs a relativistic system");
+    if (!mlp) return fail(DGMI_EINVAL, "con2prim: the learned guess needs an MLP handle");
+    mp = mlp->params;
+  }
+  dgmi::C2PArgs a{};
+  a.U = U;
+  a.prim = prim_inout;
+  a.n = n;
+  a.gamma = gamma;
+  a.tol = tol;
+  a.iters = iters_out;
+  a.fail = fail_out;
+  a.nfail = (unsigned long long *)n_failed;
+  a.mlp = mp;
+  HIP_TRY(dgmi::launch_con2prim(system, guess, a, (hipStream_t)stream));
+  return DGMI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Internal launch interface between the host library and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgmi {
+
+// Arguments of the uniform-degree RHS / RK-stage kernel.
+struct RhsArgs {
+  const double *U;     // state the operator is applied to, [nv][nnodes]
+  const double *P;     // its primitives, [5][nnodes]
+  double *out;         // dU/dt (RHS) or the stage output U^(s) (stage kernel)
+  const double *Un;    // U^n (stage kernel only)
+  double *Pout;        // primitives of U^(s) (stage kernel only)
+  const int32_t *nbr;  // [nelem][6] neighbours across faces (-x,+x,-y,+y,-z,+z)
+  const double *Dmat;  // (N+1)x(N+1) differentiation matrix, row-major
+  unsigned long long *nfail;
+  int64_t nelem, nnodes;
+  double gamma, kappa;
+  double scale[3];     // 2/dx_d
+  double inv_wend;     // 1/w_0 = N(N+1)/2
+  double a, b, dt;     // Shu-Osher stage: out = a Un + b (U + dt L(U))
+  int nblocks;         // logical blocks (elements / elements-per-block)
+};
+
+// Launch dg RHS (stage == 0) or RK stage (stage == 1).
+hipError_t launch_rhs(int sys, int N, int stage, const RhsArgs &a, hipStream_t s);
+
+struct C2PArgs {
+  const double *U;
+  double *prim;
+  int64_t n;
+  double gamma;
+  double tol;
+  uint8_t *iters;
+  uint8_t *fail;
+  unsigned long long *nfail;
+  const float *mlp;    // learned-guess parameters (device), or null
+};
+
+// Records msg as the thread's last error (dgmi_last_error) and returns st.
+int set_error(int st, const char *msg);
+
+hipError_t launch_con2prim(int sys, int guess, const C2PArgs &a, hipStream_t s);
+hipError_t launch_prim2cons(int sys, double gamma, const double *prim, const double *mag, double *U, int64_t n,
+                            hipStream_t s);
+hipError_t launch_node_coords(int N, const double *xnodes, int nx, int ny, int nz, const double *lo,
+                              const double *dx, double *xyz, int64_t nnodes, hipStream_t s);
+
+}  // namespace dgmi
+
+// Handle of a pressure-guess network (defined here so that the recovery can
+// read its device parameter vector).
+struct dgmi_mlp {
+  float *params = nullptr;   // kNumParams floats (weights then normalisation)
+  float *grad = nullptr;     // kNumWeights floats
+  float *adam_m = nullptr;   // first moments
+  float *adam_v = nullptr;   // second moments
+  float *partial = nullptr;  // per-block gradient partials
+  float *loss = nullptr;     // scratch for the loss partials
+  int64_t partial_cap = 0;   // blocks the partial buffer holds
+  int64_t step = 0;          // Adam step count
+  int device = 0;
+};

@@ -1,0 +1,370 @@
+// Pointwise physics of the three flat-space systems: conserved variables,
+// fluxes, largest wave speeds and the primitive recovery.  Every function is
+// __host__ __device__ so that it can be unit-checked on the host as well.
+//
+// References are to Kidder et al., arXiv:1609.00098:
+//   Newtonian Euler, relativistic Euler and the MHD system with divergence
+//   cleaning (conservation-laws section; eq. evolved and eq. MHD_RHS with
+//   lapse 1, zero shift and Euclidean metric), the LLF flux (eq. LLF) and the
+//   split of the MHD wave speeds into the (B_n, Phi) sub-system and the
+//   fluid sub-system bounded by the fast speed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DG_HD __host__ __device__ __forceinline__
+
+namespace dgmi {
+
+enum : int { kNE = 0, kSR = 1, kMHD = 2 };
+
+template <int SYS>
+struct SysTraits {
+  static constexpr int nv = (SYS == kMHD) ? 9 : 5;
+};
+
+struct Prim {
+  double rho, v[3], p;
+};
+
+DG_HD double sq(double x) { return x * x; }
+
+// ---------------------------------------------------------------- p -> U
+// NE: (rho, rho v, p/(g-1) + rho v^2/2).
+// SR: D = rho W, S = rho h W^2 v, tau = rho h W^2 - p - D, rho h = rho + g p/(g-1).
+// MHD: with z = rho h W^2 and B.v, S = (z + B^2) v - (B.v) B,
+//      tau = z - p + B^2/2 + (B^2 v^2 - (B.v)^2)/2 - D   (equal to eq. evolved).
+template <int SYS>
+DG_HD void prim_to_cons(const Prim &P, const double *mag, double g, double *u) {
+  const double v2 = sq(P.v[0]) + sq(P.v[1]) + sq(P.v[2]);
+  if (SYS == kNE) {
+    u[0] = P.rho;
+    u[1] = P.rho * P.v[0];
+    u[2] = P.rho * P.v[1];
+    u[3] = P.rho * P.v[2];
+    u[4] = P.p / (g - 1.0) + 0.5 * P.rho * v2;
+    return;
+  }
+  const double W2 = 1.0 / (1.0 - v2);
+  const double W = sqrt(W2);
+  const double rhoh = P.rho + g / (g - 1.0) * P.p;
+  const double z = rhoh * W2;
+  const double D = P.rho * W;
+  if (SYS == kSR) {
+    u[0] = D;
+    u[1] = z * P.v[0];
+    u[2] = z * P.v[1];
+    u[3] = z * P.v[2];
+    u[4] = z - P.p - D;
+    return;
+  }
+  const double B0 = mag[0], B1 = mag[1], B2 = mag[2];
+  const double BB = B0 * B0 + B1 * B1 + B2 * B2;
+  const double Bv = B0 * P.v[0] + B1 * P.v[1] + B2 * P.v[2];
+  const double zb = z + BB;
+  u[0] = D;
+  u[1] = zb * P.v[0] - Bv * B0;
+  u[2] = zb * P.v[1] - Bv * B1;
+  u[3] = zb * P.v[2] - Bv * B2;
+  u[4] = z - P.p + 0.5 * BB + 0.5 * (BB * v2 - Bv * Bv) - D;
+  u[5] = B0;
+  u[6] = B1;
+  u[7] = B2;
+  u[8] = mag[3];
+}
+
+// ---------------------------------------------------------------- fluxes
+// Flux along direction d (0..2), flat space (transport velocity = v).
+template <int SYS>
+DG_HD void flux_dir(int d, const double *u, const Prim &P, double *F) {
+  const double vd = P.v[d];
+  if (SYS == kNE) {
+    F[0] = u[1 + d];
+    F[1] = u[1] * vd;
+    F[2] = u[2] * vd;
+    F[3] = u[3] * vd;
+    F[1 + d] += P.p;
+    F[4] = (u[4] + P.p) * vd;
+    return;
+  }
+  if (SYS == kSR) {
+    F[0] = u[0] * vd;
+    F[1] = u[1] * vd;
+    F[2] = u[2] * vd;
+    F[3] = u[3] * vd;
+    F[1 + d] += P.p;
+    F[4] = (u[4] + P.p) * vd;
+    return;
+  }
+  // MHD: comoving field b^0 = W B.v, b_i = B_i/W + b^0 v_i, b^2 = B^2/W^2 + (B.v)^2
+  const double v2 = sq(P.v[0]) + sq(P.v[1]) + sq(P.v[2]);
+  const double iW2 = 1.0 - v2;  // 1/W^2
+  const double B[3] = {u[5], u[6], u[7]};
+  const double BB = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  const double Bv = B[0] * P.v[0] + B[1] * P.v[1] + B[2] * P.v[2];
+  const double ps = P.p + 0.5 * (BB * iW2 + Bv * Bv);  // p* = p + b^2/2
+  const double Bd = B[d];
+  // B^d b_i / W = B^d (B_i/W^2 + B.v v_i);  b^0 B^d / W = B.v B^d
+  F[0] = u[0] * vd;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) F[1 + i] = u[1 + i] * vd - Bd * (B[i] * iW2 + Bv * P.v[i]);
+  F[1 + d] += ps;
+  F[4] = (u[4] + ps) * vd - Bv * Bd;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) F[5 + i] = B[i] * vd - P.v[i] * Bd;
+  F[5 + d] += u[8];
+  F[8] = Bd;
+}
+
+// All three directions at once (volume term); shares the MHD invariants.
+template <int SYS>
+DG_HD void flux_all(const double *u, const Prim &P, double (*F)[SysTraits<SYS>::nv]) {
+  if (SYS != kMHD) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) flux_dir<SYS>(d, u, P, F[d]);
+    return;
+  }
+  const double v2 = sq(P.v[0]) + sq(P.v[1]) + sq(P.v[2]);
+  const double iW2 = 1.0 - v2;
+  const double B[3] = {u[5], u[6], u[7]};
+  const double BB = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  const double Bv = B[0] * P.v[0] + B[1] * P.v[1] + B[2] * P.v[2];
+  const double ps = P.p + 0.5 * (BB * iW2 + Bv * Bv);
+  double bw[3];  // b_i / W
+#pragma unroll
+  for (int i = 0; i < 3; ++i) bw[i] = B[i] * iW2 + Bv * P.v[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double vd = P.v[d], Bd = B[d];
+    F[d][0] = u[0] * vd;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F[d][1 + i] = u[1 + i] * vd - Bd * bw[i];
+    F[d][1 + d] += ps;
+    F[d][4] = (u[4] + ps) * vd - Bv * Bd;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F[d][5 + i] = B[i] * vd - P.v[i] * Bd;
+    F[d][5 + d] += u[8];
+    F[d][8] = Bd;
+  }
+}
+
+// ---------------------------------------------------------------- speeds
+// Largest |lambda| along +-e_d for the fluid sub-system.
+// NE: |v_n| + c_s.  SR / MHD: the acoustic (fast) pair
+//   lambda_pm = [v_n (1 - c^2) pm c sqrt((1 - v^2)(1 - v^2 c^2 - v_n^2 (1 - c^2)))] / (1 - v^2 c^2)
+// whose larger modulus is (|v_n|(1 - c^2) + c sqrt(...)) / (1 - v^2 c^2);
+// MHD uses c^2 = v_A^2 + c_s^2 (1 - v_A^2), v_A^2 = b^2 / (rho h + b^2).
+// (B_n, Phi) of MHD travel at the speed of light, handled by the caller.
+template <int SYS>
+DG_HD double max_speed(int d, const double *u, const Prim &P, double g) {
+  const double vn = P.v[d];
+  if (SYS == kNE) return fabs(vn) + sqrt(g * P.p / P.rho);
+  const double v2 = sq(P.v[0]) + sq(P.v[1]) + sq(P.v[2]);
+  const double rhoh = P.rho + g / (g - 1.0) * P.p;
+  double c2;
+  if (SYS == kSR) {
+    c2 = g * P.p / rhoh;
+  } else {
+    const double BB = sq(u[5]) + sq(u[6]) + sq(u[7]);
+    const double Bv = u[5] * P.v[0] + u[6] * P.v[1] + u[7] * P.v[2];
+    const double b2 = BB * (1.0 - v2) + Bv * Bv;
+    const double cs2 = g * P.p / rhoh;
+    const double vA2 = b2 / (rhoh + b2);
+    c2 = vA2 + cs2 * (1.0 - vA2);
+  }
+  double disc = (1.0 - v2) * (1.0 - v2 * c2 - vn * vn * (1.0 - c2));
+  disc = disc > 0.0 ? disc : 0.0;
+  return (fabs(vn) * (1.0 - c2) + sqrt(c2 * disc)) / (1.0 - v2 * c2);
+}
+
+// ---------------------------------------------------------------- recovery
+struct C2PResult {
+  Prim P;
+  int iters;
+  int ok;
+};
+
+// Largest root of x^3 - e x^2 + d = 0 (d >= 0), known to lie in [2e/3, e]:
+// Newton from x0 >= root descends monotonically (the cubic is convex there).
+DG_HD double cubic_top_root(double e, double d, double x0) {
+  double x = x0;
+#pragma unroll 1
+  for (int k = 0; k < 40; ++k) {
+    const double q = x * x * (x - e) + d;
+    const double dq = x * (3.0 * x - 2.0 * e);
+    if (!(dq > 0.0)) return -1.0;
+    const double dx = q / dq;
+    x -= dx;
+    if (fabs(dx) <= 4.0e-16 * x) break;
+  }
+  return x;
+}
+
+// Pressure function f(p) = (g-1) rho eps(p) - p of a conserved state at one
+// trial pressure; returns false where the map is undefined (no admissible
+// root of the magnetic cubic, z <= 0 or v^2 >= 1).
+template <int SYS>
+DG_HD bool pressure_function(const double *u, double g, double p, double *f) {
+  const double D = u[0], tau = u[4];
+  const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+  double z, v2;
+  if (SYS == kMHD) {
+    const double BB = u[5] * u[5] + u[6] * u[6] + u[7] * u[7];
+    const double T = u[1] * u[5] + u[2] * u[6] + u[3] * u[7];
+    double dc = 0.5 * (BB * S2 - T * T);
+    dc = dc > 0.0 ? dc : 0.0;
+    const double e = tau + D + p + 0.5 * BB;
+    if (!(e > 0.0)) return false;
+    const double em = cubic_top_root(e, dc, e);
+    z = em - BB;
+    if (!(em > 0.0) || !(z > 0.0)) return false;
+    v2 = (S2 * z * z + T * T * (z + em)) / (z * z * em * em);
+  } else {
+    z = tau + D + p;
+    if (!(z > 0.0)) return false;
+    v2 = S2 / (z * z);
+  }
+  if (!(v2 < 1.0)) return false;
+  const double uu = 1.0 - v2;
+  *f = (g - 1.0) * (z * uu - D * sqrt(uu) - p) - p;
+  return true;
+}
+
+// Recovery of one point.  p0: initial pressure (outside the bracket => the
+// bracket's upper end).  tol > 0: stop when the backward residual
+// |f| W^2 / ((g-1) E) <= tol at the evaluated pressure; tol <= 0: iterate
+// Newton until the step is below 1e-14 p (rounding level).
+template <int SYS>
+DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int maxit) {
+  C2PResult R;
+  R.iters = 0;
+  R.ok = 0;
+  const double D = u[0];
+  const double tau = u[4];
+  if (SYS == kNE) {
+    const double irho = 1.0 / D;
+    R.P.rho = D;
+    R.P.v[0] = u[1] * irho;
+    R.P.v[1] = u[2] * irho;
+    R.P.v[2] = u[3] * irho;
+    const double m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    R.P.p = (g - 1.0) * (tau - 0.5 * m2 * irho);
+    R.ok = (D > 0.0) && (R.P.p > 0.0);
+    return R;
+  }
+  const double gm1 = g - 1.0;
+  const double S0 = u[1], S1 = u[2], S2c = u[3];
+  const double S2 = S0 * S0 + S1 * S1 + S2c * S2c;
+  const double E = tau + D;
+  double BB = 0.0, T = 0.0, dcub = 0.0;
+  if (SYS == kMHD) {
+    BB = u[5] * u[5] + u[6] * u[6] + u[7] * u[7];
+    T = S0 * u[5] + S1 * u[6] + S2c * u[7];
+    dcub = 0.5 * (BB * S2 - T * T);
+    dcub = dcub > 0.0 ? dcub : 0.0;
+  }
+  double lo = 0.0;
+  double hi = gm1 * (tau - 0.5 * BB);
+  R.P.rho = D;
+  R.P.v[0] = R.P.v[1] = R.P.v[2] = 0.0;
+  R.P.p = hi;
+  if (!(D > 0.0) || !(hi > 0.0) || !(E > 0.0)) return R;
+  if (SYS == kSR && !(E * E - S2 > D * D)) return R;  // f(0) <= 0: no physical state
+  double p = (p0 > lo && p0 < hi) ? p0 : hi;
+  double em_prev = -1.0, e_prev = 0.0;
+  double z = 0.0, em = 0.0, W = 1.0;
+  double prev_step = 1e300;
+  int conv = 0;
+#pragma unroll 1
+  for (int it = 1; it <= maxit; ++it) {
+    R.iters = it;
+    int valid = 1;
+    double v2, e = 0.0;
+    double iz = 0.0;
+    if (SYS == kSR) {
+      z = tau + D + p;
+      iz = 1.0 / z;
+      v2 = S2 * iz * iz;
+    } else {
+      e = E + p + 0.5 * BB;
+      const double x0 = (em_prev > 0.0) ? fmax(em_prev + (e - e_prev), 2.0 * e / 3.0 + 1e-3 * e) : e;
+      em = cubic_top_root(e, dcub, fmin(x0, e));
+      z = em - BB;
+      valid = (em > 0.0) && (z > 0.0);
+      v2 = valid ? (S2 * z * z + T * T * (z + em)) / (z * z * em * em) : 1.0;
+      if (valid) { em_prev = em; e_prev = e; }
+    }
+    valid = valid && (v2 < 1.0);
+    if (!valid) {  // pressure below the domain of the map: raise it
+      lo = p;
+      const double pn = 0.5 * (lo + hi);
+      if (!(pn > lo && pn < hi)) break;
+      p = pn;
+      continue;
+    }
+    const double uu = 1.0 - v2;  // 1/W^2
+    const double sqw = sqrt(uu);
+    W = 1.0 / sqw;
+    const double rho_eps = z * uu - D * sqw - p;
+    const double f = gm1 * rho_eps - p;
+    if (tol > 0.0 && fabs(f) * W * W <= tol * gm1 * E) {
+      conv = 1;
+      break;
+    }
+    if (f > 0.0) lo = p; else hi = p;
+    double df;
+    if (SYS == kSR) {
+      df = gm1 * v2 * (1.0 - D * W * iz) - 1.0;
+    } else {
+      const double dem = em / (3.0 * em - 2.0 * e);  // d eps_m / dp
+      const double iz = 1.0 / z, iem = 1.0 / em;
+      const double dv2 = -2.0 * dem * (S2 * iem * iem * iem +
+                                       T * T * (iz * iz * iem * iem + iz * iem * iem * iem + iz * iz * iz * iem));
+      const double drho_eps = dem * uu - dv2 * (z - 0.5 * D * W) - 1.0;
+      df = gm1 * drho_eps - 1.0;
+    }
+    if (f == 0.0) {  // exact root
+      conv = 1;
+      break;
+    }
+    double pn = p - f / df;
+    if (!(pn > lo && pn < hi)) pn = 0.5 * (lo + hi);
+    const double step = fabs(pn - p);
+    p = pn;
+    // Polishing: Newton converges quadratically, so after a step below
+    // 1e-11 p the new iterate is accurate to rounding; a step that no longer
+    // halves (once below 1e-9 p) marks the rounding floor of f.
+    if (tol <= 0.0 && (step <= 1e-11 * p || hi - lo <= 1e-14 * p || (step <= 1e-9 * p && step >= 0.5 * prev_step))) {
+      conv = 1;
+      break;
+    }
+    prev_step = step;
+  }
+  // primitives at the final pressure
+  double v2;
+  if (SYS == kSR) {
+    z = tau + D + p;
+    const double iz = 1.0 / z;
+    R.P.v[0] = S0 * iz;
+    R.P.v[1] = S1 * iz;
+    R.P.v[2] = S2c * iz;
+    v2 = S2 * iz * iz;
+  } else {
+    const double e = E + p + 0.5 * BB;
+    const double x0 = (em_prev > 0.0) ? fmax(em_prev + (e - e_prev), 2.0 * e / 3.0 + 1e-3 * e) : e;
+    em = cubic_top_root(e, dcub, fmin(x0, e));
+    z = em - BB;
+    const double Tz = T / z, iem = 1.0 / em;
+    R.P.v[0] = (S0 + Tz * u[5]) * iem;
+    R.P.v[1] = (S1 + Tz * u[6]) * iem;
+    R.P.v[2] = (S2c + Tz * u[7]) * iem;
+    v2 = sq(R.P.v[0]) + sq(R.P.v[1]) + sq(R.P.v[2]);
+    conv = conv && (em > 0.0) && (z > 0.0);
+  }
+  R.P.p = p;
+  R.P.rho = D * sqrt(1.0 - v2);
+  R.ok = conv && (v2 < 1.0) && (p > 0.0) && (R.P.rho > 0.0);
+  return R;
+}
+
+}  // namespace dgmi

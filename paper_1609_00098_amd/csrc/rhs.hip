@@ -1,0 +1,222 @@
+// Uniform-degree DG right-hand side (eq. 411) and fused SSP-RK3 stage.
+//
+// One workgroup owns EPB whole elements, one thread per volume node.
+//   1. Each thread loads its node's U and primitives and forms the flux
+//      along one direction at a time; the direction's nodal fluxes go through
+//      one LDS buffer (EPB x nv x (N+1)^3 doubles) and every thread contracts
+//      its pencil with the row of D (eq. for D^{1bar}) scaled by 2/dx_d.
+//   2. The 6 (N+1)^2 face nodes of each element are handed out densely to
+//      the workgroup's threads: each computes the LLF flux difference
+//      F*.n - F.n (eq. LLF) against the coincident node of the periodic
+//      neighbour (read from global memory/L2) and parks it in LDS.
+//   3. Each volume thread adds -(2/dx_d)(1/w_end)(F*.n - F.n) for every face
+//      it lies on (edge and corner nodes receive two or three terms).
+//   4. RHS mode writes dU/dt; stage mode forms the Shu-Osher combination
+//      a U^n + b (U + dt L) and recovers the primitives of the result with
+//      the previous stage's pressure as the Newton seed (tail recovery), so
+//      the next stage finds neighbour primitives ready.
+// Workgroups are mapped XCD-major: consecutive element groups land on the
+// same XCD (and L2), so face neighbours along x and y are usually L2 hits.
+#include "kernels.hpp"
+#include "physics.hpp"
+
+namespace dgmi {
+
+template <int SYS, int N>
+struct RhsCfg {
+  static constexpr int NP = N + 1;
+  static constexpr int NPE = NP * NP * NP;
+  static constexpr int NF = NP * NP;
+  static constexpr int NV = SysTraits<SYS>::nv;
+  static constexpr int EPB = (N == 1) ? 8 : (N == 2) ? 9 : (N == 3) ? 4 : (N == 4) ? 2 : 1;
+  static constexpr int THREADS = ((EPB * NPE + 63) / 64) * 64;
+  static constexpr int FACE_TASKS = EPB * 6 * NF;
+  static constexpr int SLOT = (NPE > 6 * NF) ? NPE : 6 * NF;  // doubles per variable per element
+  static constexpr int LDS_DOUBLES = EPB * NV * SLOT;
+};
+
+template <int SYS, int N, int STAGE>
+__global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const RhsArgs A) {
+  using C = RhsCfg<SYS, N>;
+  constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
+  __shared__ double sbuf[C::LDS_DOUBLES];
+  __shared__ double sD[NP * NP];
+
+  // XCD-major block order: hardware block b runs on XCD b % 8.
+  const int per = (A.nblocks + 7) >> 3;
+  const int grp = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (grp >= A.nblocks) return;
+
+  const int tid = threadIdx.x;
+  for (int t = tid; t < NP * NP; t += C::THREADS) sD[t] = A.Dmat[t];
+
+  const int le = tid / NPE;
+  const int a = tid - le * NPE;
+  const int64_t e = (int64_t)grp * EPB + le;
+  const bool active = (le < EPB) && (e < A.nelem);
+  const int ci = a % NP, cj = (a / NP) % NP, ck = a / NF;
+  const int64_t q = e * NPE + a;
+  const int64_t nn = A.nnodes;
+
+  double u[NV];
+  Prim P;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = A.U[v * nn + q];
+    P.rho = A.P[q];
+    P.v[0] = A.P[nn + q];
+    P.v[1] = A.P[2 * nn + q];
+    P.v[2] = A.P[3 * nn + q];
+    P.p = A.P[4 * nn + q];
+    if (SYS == kMHD) acc[8] = -A.kappa * u[8];
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = 0.0;
+    P.rho = 1.0; P.v[0] = P.v[1] = P.v[2] = 0.0; P.p = 1.0;
+  }
+  double *mybuf = sbuf + le * NV * NPE;  // [v][node] for this element
+
+  // ---- volume term, one direction at a time
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (active) {
+      double F[NV];
+      flux_dir<SYS>(d, u, P, F);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) mybuf[v * NPE + a] = F[v];
+    }
+    __syncthreads();
+    if (active) {
+      const int idx = (d == 0) ? ci : (d == 1) ? cj : ck;
+      const int stride = (d == 0) ? 1 : (d == 1) ? NP : NF;
+      const int base = a - idx * stride;
+      double Drow[NP];
+#pragma unroll
+      for (int l = 0; l < NP; ++l) Drow[l] = sD[idx * NP + l];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < NP; ++l) s += Drow[l] * mybuf[v * NPE + base + l * stride];
+        acc[v] -= A.scale[d] * s;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- face terms: dense assignment of the EPB*6*(N+1)^2 face nodes
+  for (int t = tid; t < C::FACE_TASKS; t += C::THREADS) {
+    const int fle = t / (6 * NF);
+    const int r = t - fle * 6 * NF;
+    const int f = r / NF;
+    const int fn = r - f * NF;
+    const int64_t fe = (int64_t)grp * EPB + fle;
+    if (fe >= A.nelem) continue;
+    const int d = f >> 1, side = f & 1;
+    const int ta = fn % NP, tb = fn / NP;
+    int c0, c1, c2, n0, n1, n2;
+    if (d == 0) { c0 = side ? N : 0; c1 = ta; c2 = tb; n0 = side ? 0 : N; n1 = ta; n2 = tb; }
+    else if (d == 1) { c0 = ta; c1 = side ? N : 0; c2 = tb; n0 = ta; n1 = side ? 0 : N; n2 = tb; }
+    else { c0 = ta; c1 = tb; c2 = side ? N : 0; n0 = ta; n1 = tb; n2 = side ? 0 : N; }
+    const int64_t en = A.nbr[fe * 6 + f];
+    const int64_t qi = fe * NPE + c0 + NP * (c1 + NP * c2);
+    const int64_t qe = en * NPE + n0 + NP * (n1 + NP * n2);
+    double ui[NV], ue[NV], Fi[NV], Fe[NV];
+    Prim Pi, Pe;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { ui[v] = A.U[v * nn + qi]; ue[v] = A.U[v * nn + qe]; }
+    Pi.rho = A.P[qi]; Pi.v[0] = A.P[nn + qi]; Pi.v[1] = A.P[2 * nn + qi]; Pi.v[2] = A.P[3 * nn + qi];
+    Pi.p = A.P[4 * nn + qi];
+    Pe.rho = A.P[qe]; Pe.v[0] = A.P[nn + qe]; Pe.v[1] = A.P[2 * nn + qe]; Pe.v[2] = A.P[3 * nn + qe];
+    Pe.p = A.P[4 * nn + qe];
+    flux_dir<SYS>(d, ui, Pi, Fi);
+    flux_dir<SYS>(d, ue, Pe, Fe);
+    const double alpha = fmax(max_speed<SYS>(d, ui, Pi, A.gamma), max_speed<SYS>(d, ue, Pe, A.gamma));
+    const double hs = side ? 0.5 : -0.5;
+    double *fb = sbuf + (fle * NV) * (6 * NF) + f * NF + fn;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double al = alpha;
+      if (SYS == kMHD && (v == 8 || v == 5 + d)) al = 1.0;
+      fb[v * 6 * NF] = hs * (Fe[v] - Fi[v]) - 0.5 * al * (ue[v] - ui[v]);
+    }
+  }
+  __syncthreads();
+
+  if (!active) return;
+  const double *myface = sbuf + (le * NV) * (6 * NF);
+  const int cc[3] = {ci, cj, ck};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int idx = cc[d];
+    if (idx != 0 && idx != N) continue;
+    const int f = 2 * d + (idx == N ? 1 : 0);
+    const int fn = (d == 0) ? (cj + NP * ck) : (d == 1) ? (ci + NP * ck) : (ci + NP * cj);
+    const double sc = A.scale[d] * A.inv_wend;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] -= sc * myface[v * 6 * NF + f * NF + fn];
+  }
+
+  if (STAGE == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) A.out[v * nn + q] = acc[v];
+    return;
+  }
+  // ---- Shu-Osher combination and tail recovery
+  double un[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double base = A.Un[v * nn + q];
+    un[v] = A.a * base + A.b * (u[v] + A.dt * acc[v]);
+    A.out[v * nn + q] = un[v];
+  }
+  const C2PResult R = recover<SYS>(un, A.gamma, P.p, 0.0, 100);
+  A.Pout[q] = R.P.rho;
+  A.Pout[nn + q] = R.P.v[0];
+  A.Pout[2 * nn + q] = R.P.v[1];
+  A.Pout[3 * nn + q] = R.P.v[2];
+  A.Pout[4 * nn + q] = R.P.p;
+  const unsigned long long bad = __ballot(!R.ok);
+  if (bad && (threadIdx.x & 63) == (__ffsll((long long)bad) - 1)) atomicAdd(A.nfail, (unsigned long long)__popcll(bad));
+}
+
+template <int SYS, int N>
+static hipError_t launch_one(int stage, const RhsArgs &a, hipStream_t s) {
+  using C = RhsCfg<SYS, N>;
+  RhsArgs b = a;
+  b.nblocks = (int)((a.nelem + C::EPB - 1) / C::EPB);
+  const int grid = ((b.nblocks + 7) / 8) * 8;
+  if (stage == 0)
+    hipLaunchKernelGGL((rhs_kernel<SYS, N, 0>), dim3(grid), dim3(C::THREADS), 0, s, b);
+  else
+    hipLaunchKernelGGL((rhs_kernel<SYS, N, 1>), dim3(grid), dim3(C::THREADS), 0, s, b);
+  return hipGetLastError();
+}
+
+template <int SYS>
+static hipError_t launch_sys(int N, int stage, const RhsArgs &a, hipStream_t s) {
+  switch (N) {
+    case 1: return launch_one<SYS, 1>(stage, a, s);
+    case 2: return launch_one<SYS, 2>(stage, a, s);
+    case 3: return launch_one<SYS, 3>(stage, a, s);
+    case 4: return launch_one<SYS, 4>(stage, a, s);
+    case 5: return launch_one<SYS, 5>(stage, a, s);
+    case 6: return launch_one<SYS, 6>(stage, a, s);
+    case 7: return launch_one<SYS, 7>(stage, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rhs(int sys, int N, int stage, const RhsArgs &a, hipStream_t s) {
+  switch (sys) {
+    case kNE: return launch_sys<kNE>(N, stage, a, s);
+    case kSR: return launch_sys<kSR>(N, stage, a, s);
+    case kMHD: return launch_sys<kMHD>(N, stage, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dgmi

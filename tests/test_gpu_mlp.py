@@ -1,0 +1,142 @@
+"""GPU parity of the learned pressure guess: features, inference, gradients
+(FP32 kernels against the FP64 oracle), Adam, determinism, and the gain of a
+trained network over the plain bracket seed at equal backward residual."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_1609_00098_amd import synth
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+SR, MHD = 1, 2
+G43 = 4.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1609_00098_amd import dgmi
+    return dgmi
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(M.NP, dtype=np.float32)
+    p[:M.NW] = rng.uniform(-0.3, 0.3, M.NW)
+    p[M.O_MU:M.O_MU + 5] = rng.uniform(-1, 1, 5)
+    p[M.O_SD:M.O_SD + 5] = rng.uniform(0.5, 2, 5)
+    p[M.O_YMU] = -1.0
+    p[M.O_YSD] = 2.0
+    return p
+
+
+def _samples(ora, n, seed):
+    prim, mag = synth.srmhd_samples(n, seed=seed)
+    return ora.prim2cons(MHD, G43, prim, mag), prim
+
+
+@pytest.mark.parametrize("system", [SR, MHD])
+def test_features_and_targets_parity(ora, dg, system):
+    prim, mag = synth.srmhd_samples(20000, seed=31)
+    if system == SR:
+        mag = None
+    U = ora.prim2cons(system, G43, prim, mag)
+    x, t = dg.mlp_features(system, G43, to_dev(U), prim=to_dev(prim))
+    xo = M.features(system, G43, U)
+    xg = to_host(x)
+    assert np.all(np.abs(xg - xo) <= 3e-6 * np.maximum(1.0, np.abs(xo)))
+    to = np.log(prim[4] / U[0])
+    assert np.all(np.abs(to_host(t) - to) <= 3e-6 * np.maximum(1.0, np.abs(to)))
+
+
+def test_forward_parity(ora, dg):
+    import torch
+    p = _params(1)
+    net = dg.Mlp(seed=0)
+    dg.mlp_set(net, to_dev(p))
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=(5, 3000)).astype(np.float32)
+    y = to_host(dg.mlp_forward(net, to_dev(x)))
+    yo = M.predict(p.astype(np.float64), x.astype(np.float64))
+    assert np.abs(y - yo).max() <= 2e-5 * max(1.0, np.abs(yo).max())
+    # a column slice of a wider matrix (minibatch view) gives the same answer
+    wide = torch.zeros((5, 5000), dtype=torch.float32, device="cuda")
+    wide[:, 1000:4000] = to_dev(x)
+    y2 = to_host(dg.mlp_forward(net, wide[:, 1000:4000]))
+    assert np.array_equal(y, y2)
+
+
+def test_gradient_parity_fixed_batch(ora, dg):
+    """FP32 kernels against FP64 back-propagation on a fixed 4096-sample
+    batch: relative Frobenius error per tensor <= 1e-5."""
+    U, prim = _samples(ora, 4096, 41)
+    x = M.features(MHD, G43, U).astype(np.float32)
+    t = np.log(prim[4] / U[0]).astype(np.float32)
+    p = _params(3)
+    p[M.O_MU:M.O_MU + 5] = x.mean(1)
+    p[M.O_SD:M.O_SD + 5] = x.std(1)
+    p[M.O_YMU], p[M.O_YSD] = t.mean(), t.std()
+    net = dg.Mlp(seed=0)
+    dg.mlp_set(net, to_dev(p))
+    g, loss = dg.mlp_grad(net, to_dev(x), to_dev(t))
+    g = to_host(g).astype(np.float64)
+    Lo, go = M.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert abs(float(to_host(loss)[0]) - Lo) <= 1e-5 * Lo
+    for name, (a, b) in {"W1": (M.O_W1, M.O_B1), "b1": (M.O_B1, M.O_W2), "W2": (M.O_W2, M.O_B2),
+                         "b2": (M.O_B2, M.O_W3), "W3": (M.O_W3, M.O_B3), "b3": (M.O_B3, M.NW)}.items():
+        rel = np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b])
+        assert rel <= 1e-5, (name, rel)
+    # deterministic: a second evaluation is bit-identical
+    g2, _ = dg.mlp_grad(net, to_dev(x), to_dev(t))
+    assert np.array_equal(to_host(g2).astype(np.float64), g)
+
+
+def test_adam_step_parity(ora, dg):
+    U, prim = _samples(ora, 1024, 43)
+    x = M.features(MHD, G43, U).astype(np.float32)
+    t = np.log(prim[4] / U[0]).astype(np.float32)
+    p = _params(5)
+    net = dg.Mlp(seed=0)
+    dg.mlp_set(net, to_dev(p))
+    lr = 1e-3
+    dg.mlp_train_step(net, to_dev(x), to_dev(t), lr)
+    p1 = to_host(dg.mlp_get(net)).astype(np.float64)
+    _, go = M.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    po, _, _ = M.adam_step(p.astype(np.float64), go, np.zeros(M.NW), np.zeros(M.NW), 1, lr)
+    step_g = (p1 - p)[:M.NW]
+    step_o = (po - p)[:M.NW]
+    big = np.abs(go) > 1e-4 * np.abs(go).max()
+    assert np.abs(step_g - step_o)[big].max() <= 1e-3 * lr + 2e-7
+    assert np.array_equal(p1[M.NW:], p[M.NW:].astype(np.float64))
+
+
+def test_trained_guess_cuts_iterations_at_equal_residual(ora, dg):
+    """Train on 2e5 seeded SRMHD samples, then recover 5e4 fresh samples at
+    backward residual 1e-10 with the plain bracket seed and with the learned
+    seed: both meet the residual everywhere (oracle check) and the learned
+    seed needs fewer pressure-function evaluations on average."""
+    import torch
+    n = 200_000
+    prim, mag = synth.srmhd_samples(n, seed=1)
+    Ud = dg.dgmi_prim2cons(MHD, G43, to_dev(prim), to_dev(mag))
+    x, t = dg.mlp_features(MHD, G43, Ud, prim=to_dev(prim))
+    net = dg.Mlp(seed=7)
+    dg.mlp_fit_normalization(net, x, t)
+    hist = to_host(dg.mlp_train(net, x, t, batch=2048, epochs=8, lr0=3e-3, lr1=1e-5))
+    assert hist[-50:].mean() < 0.01 * hist[:20].mean()
+    vp, vm = synth.srmhd_samples(50_000, seed=3)
+    Uv = ora.prim2cons(MHD, G43, vp, vm)
+    res = {}
+    for guess in (dg.GUESS_PLAIN, dg.GUESS_LEARNED):
+        P = torch.zeros((5, Uv.shape[1]), dtype=torch.float64, device="cuda")
+        it = torch.zeros(Uv.shape[1], dtype=torch.uint8, device="cuda")
+        nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+        dg.con2prim(MHD, G43, to_dev(Uv), P, guess=guess, mlp=net if guess == dg.GUESS_LEARNED else None,
+                    tol=1e-10, iters_out=it, n_failed=nf)
+        assert int(nf.item()) == 0
+        r = ora.backward_residual(MHD, G43, Uv, to_host(P))
+        assert r.max() <= 1e-10
+        res[guess] = to_host(it).astype(np.float64).mean()
+    assert res[dg.GUESS_LEARNED] < 0.8 * res[dg.GUESS_PLAIN], res

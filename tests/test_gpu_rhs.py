@@ -1,0 +1,293 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+
+Bar: relative 1e-12 norm-wise per variable for the DG operator and the RK
+step (max |gpu - oracle| / max |oracle|), backward residual <= 1e-10 for the
+tolerance-driven recovery, and the recovered primitives within the
+conditioning of the inversion when polished.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1609_00098_amd import synth
+from tests.gpu_util import normwise_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+NE, SR, MHD = 0, 1, 2
+NV = {NE: 5, SR: 5, MHD: 9}
+RHS_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1609_00098_amd import dgmi
+    return dgmi
+
+
+def _state(ora, system, m, seed=3, wmax=None):
+    """Seeded smooth random state at the oracle's node coordinates; the
+    oracle maps primitives to conserved variables."""
+    xyz = ora.node_coords(m)
+    lo = np.array(m.lo[:])
+    hi = np.array(m.hi[:])
+    unit = (xyz - lo[:, None]) / (hi - lo)[:, None]
+    if system == MHD:
+        prim = synth.fourier_random_prims(unit, seed=seed, w_max=wmax or 3.0, rho_range=(0.5, 2.0),
+                                          p_range=(0.1, 10.0))
+        rng = np.random.default_rng(seed)
+        mag = np.zeros((4, prim.shape[1]))
+        for c in range(4):
+            k = rng.integers(1, 3, size=3)
+            mag[c] = 0.3 * np.sin(2 * np.pi * (k @ unit) + rng.uniform(0, 6))
+        mag[0] += 1.0
+        return ora.prim2cons(MHD, m.gamma, prim, mag), prim
+    prim = synth.fourier_random_prims(unit, seed=seed, w_max=wmax or (5.0 if system == SR else 1.5))
+    if system == NE:
+        prim[1:4] *= 2.0
+    return ora.prim2cons(system, m.gamma, prim), prim
+
+
+def _pair(ora, dg, system, nel, deg, lo=(-0.3, 0.1, 0.0), hi=(0.7, 1.6, 2.0), kappa=0.5, flags=0):
+    g = 4.0 / 3.0 if system else 1.4
+    m = ora.mesh(system, nel, deg, g, lo=lo, hi=hi, kappa=kappa)
+    G = dg.Mesh(system, nel, deg, g, lo=lo, hi=hi, kappa=kappa, flags=flags)
+    assert G.nnodes == ora.num_nodes(m)
+    return m, G
+
+
+@pytest.mark.parametrize("system", [NE, SR, MHD])
+def test_prim2cons_parity(ora, dg, system):
+    g = 4.0 / 3.0
+    if system == MHD:
+        prim, mag = synth.srmhd_samples(10000, seed=1)
+    else:
+        prim, mag = synth.sr_samples(10000, seed=1), None
+    Uo = ora.prim2cons(system, g, prim, mag)
+    Ug = to_host(dg.dgmi_prim2cons(system, g, to_dev(prim), to_dev(mag) if mag is not None else None))
+    # algebraically equal expressions in a different order: a few ulp of the
+    # largest term (MHD tau cancels its magnetic terms)
+    assert np.all(normwise_err(Ug, Uo) <= 1e-13)
+
+
+@pytest.mark.parametrize("system", [SR, MHD])
+@pytest.mark.parametrize("guess", [0, 1])
+def test_con2prim_tolerance_mode(ora, dg, system, guess):
+    """tol = 1e-10: every point's backward residual (computed by the oracle)
+    is below 1e-10, and the iteration counts are sane."""
+    import torch
+    g = 4.0 / 3.0
+    if system == MHD:
+        prim, mag = synth.srmhd_samples(50000, seed=2)
+    else:
+        prim, mag = synth.sr_samples(50000, seed=2, w_max=20.0), None
+    U = ora.prim2cons(system, g, prim, mag)
+    P = to_dev(prim * (1 + 1e-2)) if guess == 0 else torch.zeros((5, U.shape[1]), dtype=torch.float64,
+                                                                   device="cuda")
+    iters = torch.zeros(U.shape[1], dtype=torch.uint8, device="cuda")
+    fail = torch.ones(U.shape[1], dtype=torch.uint8, device="cuda")
+    nfail = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dg.con2prim(system, g, to_dev(U), P, guess=guess, tol=1e-10, iters_out=iters, fail_out=fail, n_failed=nfail)
+    Pg = to_host(P)
+    assert int(nfail.item()) == 0 and int(fail.sum().item()) == 0
+    r = ora.backward_residual(system, g, U, Pg)
+    assert r.max() <= 1e-10
+    it = to_host(iters)
+    assert it.min() >= 1 and it.max() <= 40
+
+
+@pytest.mark.parametrize("system", [NE, SR, MHD])
+def test_con2prim_polish_matches_oracle_root(ora, dg, system):
+    import torch
+    g = 4.0 / 3.0
+    if system == MHD:
+        prim, mag = synth.srmhd_samples(20000, seed=4)
+        tolp = 5e-9   # ill-conditioned samples: rounding alone moves the root ~1e-9
+    else:
+        prim, mag = synth.sr_samples(20000, seed=4), None
+        tolp = 2e-11
+    U = ora.prim2cons(system, g, prim, mag)
+    Po, fo, _ = ora.cons2prim(system, g, U)
+    P = torch.zeros((5, U.shape[1]), dtype=torch.float64, device="cuda")
+    dg.con2prim(system, g, to_dev(U), P, guess=1, tol=0.0)
+    Pg = to_host(P)
+    assert (np.abs(Pg[4] - Po[4]) / Po[4]).max() <= tolp
+    assert (np.abs(Pg[0] - Po[0]) / Po[0]).max() <= tolp
+    assert ora.backward_residual(system, g, U, Pg).max() <= 1e-12
+
+
+# every degree the library supports, three systems, a non-cubic box
+RHS_CASES = [(s, N) for s in (NE, SR, MHD) for N in range(1, 8)]
+
+
+@pytest.mark.parametrize("system,N", RHS_CASES)
+def test_dg_rhs_parity(ora, dg, system, N):
+    nel = (3, 2, 2) if N <= 4 else (2, 2, 1)
+    m, G = _pair(ora, dg, system, nel, N)
+    U, prim = _state(ora, system, m, seed=10 + N)
+    dUo, Po, nf = ora.rhs(m, U)
+    assert nf == 0
+    Ud = to_dev(U)
+    Pd = to_dev(prim * (1 + 1e-3))
+    dUd = G.empty_state()
+    dg.dg_rhs(G, Ud, Pd, dUd)
+    err = normwise_err(to_host(dUd), dUo)
+    assert np.all(err <= RHS_TOL), err
+    assert dg.dgmi_failures(G) == 0
+    perr = normwise_err(to_host(Pd), Po)
+    assert np.all(perr <= 1e-12), perr
+
+
+def _step_tolerance(Lo, U, dt):
+    """Per-variable bound on |dg_step - oracle step|: the operator's 1e-12
+    parity carried through three stages (weights sum to < 2), plus a few
+    ulp of U from forming the Shu-Osher combinations in different orders."""
+    eps = np.finfo(np.float64).eps
+    return 2e-12 * dt * np.abs(Lo).max(axis=1) + 8 * eps * np.abs(U).max(axis=1)
+
+
+@pytest.mark.parametrize("system,N", [(NE, 3), (SR, 4), (MHD, 3), (SR, 2), (MHD, 5)])
+def test_dg_step_parity(ora, dg, system, N):
+    m, G = _pair(ora, dg, system, (3, 2, 2), N, flags=2)
+    U, prim = _state(ora, system, m, seed=20 + N, wmax=3.0 if system else None)
+    Lo, _, _ = ora.rhs(m, U)
+    # a step that moves U by ~1e-3 of its range (the random state is rough)
+    dt = 1e-3 * np.abs(U).max() / np.abs(Lo).max()
+    Uo, nf = ora.step(m, U, dt)
+    assert nf == 0
+    Ud = to_dev(U)
+    Pd = to_dev(prim)
+    dg.dg_step(G, Ud, Pd, dt)
+    diff = np.abs(to_host(Ud) - Uo).max(axis=1)
+    tol = _step_tolerance(Lo, U, dt)
+    assert np.all(diff <= tol), (diff, tol)
+    # the step did move the state by far more than the tolerance
+    assert np.all(np.abs(Uo - U).max(axis=1)[:5] > 1e3 * tol[:5])
+    assert dg.dgmi_failures(G) == 0
+    # primitives written back are those of the new state
+    Po, _, _ = ora.cons2prim(system, m.gamma, Uo)
+    assert np.all(normwise_err(to_host(Pd), Po) <= 1e-10)
+
+
+@pytest.mark.parametrize("system", [NE, SR, MHD])
+def test_free_stream_on_gpu(ora, dg, system):
+    m, G = _pair(ora, dg, system, (3, 3, 2), 4)
+    n = G.nnodes
+    prim = np.tile(np.array([[1.3], [0.3], [-0.2], [0.25], [0.7]]), (1, n))
+    mag = np.tile(np.array([[0.4], [-0.3], [0.2], [0.0]]), (1, n))
+    U = ora.prim2cons(system, m.gamma, prim, mag if system == MHD else None)
+    dUd = G.empty_state()
+    dg.dg_rhs(G, to_dev(U), to_dev(prim), dUd)
+    assert np.abs(to_host(dUd)).max() < 1e-12
+
+
+@pytest.mark.parametrize("system", [SR, MHD])
+def test_discrete_conservation_on_gpu(ora, dg, system):
+    m, G = _pair(ora, dg, system, (3, 2, 2), 3)
+    U, prim = _state(ora, system, m, seed=5)
+    dUd = G.empty_state()
+    dg.dg_rhs(G, to_dev(U), to_dev(prim), dUd)
+    dU = to_host(dUd)
+    tot = ora.integrate(m, dU)
+    absint = ora.integrate(m, np.abs(dU))
+    if system == MHD:
+        tot[8] -= ora.integrate(m, -m.kappa * U[8:9])[0]
+    assert np.all(np.abs(tot) <= 1e-13 * absint.max())
+
+
+def test_config1_newtonian_rhs_and_step(ora, dg):
+    """3D Newtonian Euler, gamma 5/3, periodic unit cube, 8^3 elements of
+    degree 3 (32,768 nodes), rho = 1 + 0.2 sin(2 pi (x+y+z)), v = (0.5, 0.3,
+    0.2), p = 1; one RHS and one SSP-RK3 step, full comparison."""
+    g = 5.0 / 3.0
+    m = ora.mesh(NE, (8, 8, 8), 3, g)
+    G = dg.Mesh(NE, (8, 8, 8), 3, g)
+    prim = synth.smooth_flow(ora.node_coords(m), 0.0, 0.2, 2 * math.pi, (0.5, 0.3, 0.2))
+    U = ora.prim2cons(NE, g, prim)
+    dUo, _, _ = ora.rhs(m, U)
+    dUd = G.empty_state()
+    dg.dg_rhs(G, to_dev(U), to_dev(prim), dUd)
+    assert np.all(normwise_err(to_host(dUd), dUo) <= RHS_TOL)
+    dt = 2e-3
+    Uo, _ = ora.step(m, U, dt)
+    Ud = to_dev(U)
+    dg.dg_step(G, Ud, to_dev(prim), dt)
+    assert np.all(np.abs(to_host(Ud) - Uo).max(axis=1) <= _step_tolerance(dUo, U, dt))
+
+
+def test_config2_sr_full_size_sampled(ora, dg):
+    """3D SR hydro, Gamma 4/3, periodic, 32^3 elements of degree 4
+    (4,096,000 nodes), seeded smooth random primitives (rho in [0.1, 10],
+    p in [0.01, 100], W up to 10), dg_rhs in the benchmark's launch
+    configuration.  Primitives compared at every node; dU/dt on 96 sampled
+    elements recomputed by the oracle one by one."""
+    import torch
+    g = 4.0 / 3.0
+    m = ora.mesh(SR, (32, 32, 32), 4, g)
+    G = dg.Mesh(SR, (32, 32, 32), 4, g)
+    prim = synth.fourier_random_prims(ora.node_coords(m), seed=1609)
+    U = ora.prim2cons(SR, g, prim)
+    Po, fo, nf = ora.cons2prim(SR, g, U)
+    assert nf == 0
+    Ud = to_dev(U)
+    Pd = to_dev(prim * (1 + 1e-3))
+    dUd = G.empty_state()
+    dg.dg_rhs(G, Ud, Pd, dUd)
+    assert dg.dgmi_failures(G) == 0
+    Pg = to_host(Pd)
+    assert (np.abs(Pg[4] - Po[4]) / Po[4]).max() <= 2e-11
+    rng = np.random.default_rng(99)
+    elems = np.concatenate([[0, 31, 32 * 32 - 1, 32 ** 3 - 1], rng.choice(32 ** 3, 92, replace=False)])
+    ref = ora.rhs_elements(m, U, Po, elems)
+    npe = 125
+    idx = (elems[:, None] * npe + np.arange(npe)[None, :]).ravel()
+    got = to_host(dUd)[:, idx]
+    full_scale = np.abs(ref).max(axis=1)
+    err = np.abs(got - ref).max(axis=1) / full_scale
+    assert np.all(err <= RHS_TOL), err
+    del Ud, Pd, dUd
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("system", [SR, MHD])
+def test_unphysical_states_flagged_on_gpu(ora, dg, system):
+    import torch
+    g = 4.0 / 3.0
+    prim, mag = synth.srmhd_samples(8, seed=2)
+    if system == SR:
+        mag = None
+    U = ora.prim2cons(system, g, prim, mag)
+    U[0, 0] = -1.0
+    U[4, 1] = -0.5
+    U[1, 2] = 10 * (U[4, 2] + U[0, 2])
+    U[:, 3] = np.nan
+    U[0, 4] = 0.0
+    _, fo, nfo = ora.cons2prim(system, g, U)
+    P = torch.zeros((5, 8), dtype=torch.float64, device="cuda")
+    fail = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    nfail = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dg.con2prim(system, g, to_dev(U), P, guess=1, tol=1e-10, fail_out=fail, n_failed=nfail)
+    assert np.array_equal(to_host(fail), fo)
+    assert int(nfail.item()) == nfo == 5
+
+
+def test_invalid_arguments_rejected(dg):
+    import torch
+    with pytest.raises(dg.DgmiError):
+        dg.Mesh(SR, (0, 2, 2), 3, 4.0 / 3.0)
+    with pytest.raises(dg.DgmiError):
+        dg.Mesh(SR, (2, 2, 2), 9, 4.0 / 3.0)
+    with pytest.raises(dg.DgmiError):
+        dg.Mesh(SR, (2, 2, 2), 3, 0.5)
+    G = dg.Mesh(SR, (2, 2, 2), 2, 4.0 / 3.0)
+    U = G.empty_state()
+    with pytest.raises(dg.DgmiError):
+        dg.dg_rhs(G, U, G.empty_prims(), U)  # aliasing output
+    with pytest.raises(ValueError):
+        dg.dg_rhs(G, U[:, :-1].contiguous(), G.empty_prims(), G.empty_state())
+    P = torch.zeros((5, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(dg.DgmiError):
+        dg.con2prim(SR, 4.0 / 3.0, torch.zeros((5, 4), dtype=torch.float64, device="cuda"), P, guess=7)
