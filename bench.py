@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -139,6 +141,14 @@ def main():
             dg.dg_operator(G, Ua, P, dUa)
         else:
             dg.dg_operator(G, Ub, P, dUb)
+
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ksteps = max(args.steps // 2, 10)
     ms_c2p = time_loop(torch, c2p, ksteps, 4)

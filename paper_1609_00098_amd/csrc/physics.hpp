@@ -116,6 +116,52 @@ DG_HD void flux_dir(int d, const double *u, const Prim &P, double *F) {
   F[8] = Bd;
 }
 
+// Flux along a direction d known only at run time (face terms): the same
+// formulas as flux_dir, with the direction picked by selects so that no
+// private array is indexed dynamically (that would live in scratch memory)
+// and lanes working on different faces do not diverge.
+template <int SYS>
+DG_HD void flux_normal(int d, const double *u, const Prim P, double *F) {
+  const bool dx = (d == 0), dy = (d == 1), dz = (d == 2);
+  // scalar copies: a select between struct fields in memory is folded into a
+  // load from a computed address, which forces the struct into scratch
+  const double v0 = P.v[0], v1 = P.v[1], v2s = P.v[2];
+  const double vd = dx ? v0 : (dy ? v1 : v2s);
+  if (SYS == kNE) {
+    const double m0 = u[1], m1 = u[2], m2 = u[3];
+    F[0] = dx ? m0 : (dy ? m1 : m2);
+    F[1] = m0 * vd + (dx ? P.p : 0.0);
+    F[2] = m1 * vd + (dy ? P.p : 0.0);
+    F[3] = m2 * vd + (dz ? P.p : 0.0);
+    F[4] = (u[4] + P.p) * vd;
+    return;
+  }
+  if (SYS == kSR) {
+    F[0] = u[0] * vd;
+    F[1] = u[1] * vd + (dx ? P.p : 0.0);
+    F[2] = u[2] * vd + (dy ? P.p : 0.0);
+    F[3] = u[3] * vd + (dz ? P.p : 0.0);
+    F[4] = (u[4] + P.p) * vd;
+    return;
+  }
+  const double v2 = v0 * v0 + v1 * v1 + v2s * v2s;
+  const double iW2 = 1.0 - v2;
+  const double B0 = u[5], B1 = u[6], B2 = u[7];
+  const double BB = B0 * B0 + B1 * B1 + B2 * B2;
+  const double Bv = B0 * v0 + B1 * v1 + B2 * v2s;
+  const double ps = P.p + 0.5 * (BB * iW2 + Bv * Bv);
+  const double Bd = dx ? B0 : (dy ? B1 : B2);
+  F[0] = u[0] * vd;
+  F[1] = u[1] * vd - Bd * (B0 * iW2 + Bv * v0) + (dx ? ps : 0.0);
+  F[2] = u[2] * vd - Bd * (B1 * iW2 + Bv * v1) + (dy ? ps : 0.0);
+  F[3] = u[3] * vd - Bd * (B2 * iW2 + Bv * v2s) + (dz ? ps : 0.0);
+  F[4] = (u[4] + ps) * vd - Bv * Bd;
+  F[5] = B0 * vd - v0 * Bd + (dx ? u[8] : 0.0);
+  F[6] = B1 * vd - v1 * Bd + (dy ? u[8] : 0.0);
+  F[7] = B2 * vd - v2s * Bd + (dz ? u[8] : 0.0);
+  F[8] = Bd;
+}
+
 // All three directions at once (volume term); shares the MHD invariants.
 template <int SYS>
 DG_HD void flux_all(const double *u, const Prim &P, double (*F)[SysTraits<SYS>::nv]) {
@@ -156,17 +202,18 @@ DG_HD void flux_all(const double *u, const Prim &P, double (*F)[SysTraits<SYS>::
 // MHD uses c^2 = v_A^2 + c_s^2 (1 - v_A^2), v_A^2 = b^2 / (rho h + b^2).
 // (B_n, Phi) of MHD travel at the speed of light, handled by the caller.
 template <int SYS>
-DG_HD double max_speed(int d, const double *u, const Prim &P, double g) {
-  const double vn = P.v[d];
+DG_HD double max_speed(int d, const double *u, const Prim P, double g) {
+  const double v0 = P.v[0], v1 = P.v[1], v2s = P.v[2];
+  const double vn = (d == 0) ? v0 : ((d == 1) ? v1 : v2s);
   if (SYS == kNE) return fabs(vn) + sqrt(g * P.p / P.rho);
-  const double v2 = sq(P.v[0]) + sq(P.v[1]) + sq(P.v[2]);
+  const double v2 = v0 * v0 + v1 * v1 + v2s * v2s;
   const double rhoh = P.rho + g / (g - 1.0) * P.p;
   double c2;
   if (SYS == kSR) {
     c2 = g * P.p / rhoh;
   } else {
     const double BB = sq(u[5]) + sq(u[6]) + sq(u[7]);
-    const double Bv = u[5] * P.v[0] + u[6] * P.v[1] + u[7] * P.v[2];
+    const double Bv = u[5] * v0 + u[6] * v1 + u[7] * v2s;
     const double b2 = BB * (1.0 - v2) + Bv * Bv;
     const double cs2 = g * P.p / rhoh;
     const double vA2 = b2 / (rhoh + b2);
@@ -178,6 +225,17 @@ DG_HD double max_speed(int d, const double *u, const Prim &P, double g) {
 }
 
 // ---------------------------------------------------------------- recovery
+// 1/x for a Newton step, where full accuracy is not needed: the hardware
+// reciprocal refined by one Newton-Raphson step on the device.
+DG_HD double step_rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rcp(x);
+  return r * (2.0 - x * r);
+#else
+  return 1.0 / x;
+#endif
+}
+
 struct C2PResult {
   Prim P;
   int iters;
@@ -270,21 +328,31 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
   R.P.p = hi;
   if (!(D > 0.0) || !(hi > 0.0) || !(E > 0.0)) return R;
   if (SYS == kSR && !(E * E - S2 > D * D)) return R;  // f(0) <= 0: no physical state
+  const double Sabs = sqrt(S2);
   double p = (p0 > lo && p0 < hi) ? p0 : hi;
   double em_prev = -1.0, e_prev = 0.0;
   double z = 0.0, em = 0.0, W = 1.0;
   double prev_step = 1e300;
+  bool last_small = false;
   int conv = 0;
 #pragma unroll 1
   for (int it = 1; it <= maxit; ++it) {
     R.iters = it;
     int valid = 1;
     double v2, e = 0.0;
-    double iz = 0.0;
+    double iz = 0.0, t = 0.0, uu = 0.0, sqw = 0.0;
     if (SYS == kSR) {
+      // q = z^2 - S^2 = z^2 / W^2 without the cancellation of 1 - v^2; one
+      // division t = 1/(z sqrt(q)) gives 1/z, W and sqrt(1 - v^2)
       z = tau + D + p;
-      iz = 1.0 / z;
+      const double q = (z - Sabs) * (z + Sabs);
+      const double sqq = sqrt(q);
+      t = 1.0 / (z * sqq);
+      iz = sqq * t;
       v2 = S2 * iz * iz;
+      uu = q * iz * iz;
+      sqw = q * t;
+      W = z * z * t;
     } else {
       e = E + p + 0.5 * BB;
       const double x0 = (em_prev > 0.0) ? fmax(em_prev + (e - e_prev), 2.0 * e / 3.0 + 1e-3 * e) : e;
@@ -302,9 +370,11 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
       p = pn;
       continue;
     }
-    const double uu = 1.0 - v2;  // 1/W^2
-    const double sqw = sqrt(uu);
-    W = 1.0 / sqw;
+    if (SYS == kMHD) {
+      uu = 1.0 - v2;  // 1/W^2
+      sqw = sqrt(uu);
+      W = 1.0 / sqw;
+    }
     const double rho_eps = z * uu - D * sqw - p;
     const double f = gm1 * rho_eps - p;
     if (tol > 0.0 && fabs(f) * W * W <= tol * gm1 * E) {
@@ -314,7 +384,7 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     if (f > 0.0) lo = p; else hi = p;
     double df;
     if (SYS == kSR) {
-      df = gm1 * v2 * (1.0 - D * W * iz) - 1.0;
+      df = gm1 * v2 * (1.0 - D * z * t) - 1.0;  // W / z = z t
     } else {
       const double dem = em / (3.0 * em - 2.0 * e);  // d eps_m / dp
       const double iz = 1.0 / z, iem = 1.0 / em;
@@ -327,21 +397,36 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
       conv = 1;
       break;
     }
-    double pn = p - f / df;
-    if (!(pn > lo && pn < hi)) pn = 0.5 * (lo + hi);
-    const double step = fabs(pn - p);
-    p = pn;
-    // Polishing: Newton converges quadratically, so after a step below
-    // 1e-11 p the new iterate is accurate to rounding; a step that no longer
-    // halves (once below 1e-9 p) marks the rounding floor of f.
-    if (tol <= 0.0 && (step <= 1e-11 * p || hi - lo <= 1e-14 * p || (step <= 1e-9 * p && step >= 0.5 * prev_step))) {
+    double pn = p - f * step_rcp(df);
+    // closed bracket: at the root f is rounding noise and the proposal can
+    // land on the end point just set to p
+    const bool newton = (pn >= lo && pn <= hi);
+    // Right after a Newton step below 1e-9 p the iterate sits at the rounding
+    // floor of f; a proposal outside the bracket is then noise.
+    if (tol <= 0.0 && !newton && last_small) {
       conv = 1;
       break;
     }
-    prev_step = step;
+    if (!newton) pn = 0.5 * (lo + hi);
+    const double step = fabs(pn - p);
+    p = pn;
+    // Polishing.  A bracket below 1e-14 p pins the root.  Otherwise only a
+    // genuine Newton step may end the iteration: Newton converges
+    // quadratically, so after a step below 1e-11 p the new iterate is
+    // accurate to rounding, and a Newton step that no longer halves (once
+    // below 1e-9 p) marks the rounding floor of f.  (A bisection step can be
+    // small without the iterate being close.)
+    if (tol <= 0.0 && (hi - lo <= 1e-14 * p ||
+                       (newton && (step <= 1e-11 * p || (step <= 1e-9 * p && step >= 0.5 * prev_step))))) {
+      conv = 1;
+      break;
+    }
+    prev_step = newton ? step : 1e300;
+    last_small = newton && step <= 1e-9 * p;
   }
   // primitives at the final pressure
   double v2;
+  double rho_w = 0.0;  // sqrt(1 - v^2)
   if (SYS == kSR) {
     z = tau + D + p;
     const double iz = 1.0 / z;
@@ -349,6 +434,7 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     R.P.v[1] = S1 * iz;
     R.P.v[2] = S2c * iz;
     v2 = S2 * iz * iz;
+    rho_w = sqrt((z - Sabs) * (z + Sabs)) * iz;
   } else {
     const double e = E + p + 0.5 * BB;
     const double x0 = (em_prev > 0.0) ? fmax(em_prev + (e - e_prev), 2.0 * e / 3.0 + 1e-3 * e) : e;
@@ -362,7 +448,8 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     conv = conv && (em > 0.0) && (z > 0.0);
   }
   R.P.p = p;
-  R.P.rho = D * sqrt(1.0 - v2);
+  if (SYS == kMHD) rho_w = sqrt(1.0 - v2);
+  R.P.rho = D * rho_w;
   R.ok = conv && (v2 < 1.0) && (p > 0.0) && (R.P.rho > 0.0);
   return R;
 }

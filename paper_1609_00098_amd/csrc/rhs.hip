@@ -22,6 +22,13 @@
 
 namespace dgmi {
 
+// Pick among three values by a run-time direction without indexing an
+// array (indexed private arrays are placed in scratch memory).
+__device__ __forceinline__ double sel3(int d, double a, double b, double c) {
+  return d == 0 ? a : (d == 1 ? b : c);
+}
+__device__ __forceinline__ int sel3i(int d, int a, int b, int c) { return d == 0 ? a : (d == 1 ? b : c); }
+
 template <int SYS, int N>
 struct RhsCfg {
   static constexpr int NP = N + 1;
@@ -84,14 +91,15 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
   for (int d = 0; d < 3; ++d) {
     if (active) {
       double F[NV];
-      flux_dir<SYS>(d, u, P, F);
+      flux_normal<SYS>(d, u, P, F);
 #pragma unroll
       for (int v = 0; v < NV; ++v) mybuf[v * NPE + a] = F[v];
     }
     __syncthreads();
     if (active) {
-      const int idx = (d == 0) ? ci : (d == 1) ? cj : ck;
-      const int stride = (d == 0) ? 1 : (d == 1) ? NP : NF;
+      const int idx = sel3i(d, ci, cj, ck);
+      const int stride = sel3i(d, 1, NP, NF);
+      const double scale = sel3(d, A.scale[0], A.scale[1], A.scale[2]);
       const int base = a - idx * stride;
       double Drow[NP];
 #pragma unroll
@@ -101,7 +109,7 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
         double s = 0.0;
 #pragma unroll
         for (int l = 0; l < NP; ++l) s += Drow[l] * mybuf[v * NPE + base + l * stride];
-        acc[v] -= A.scale[d] * s;
+        acc[v] -= scale * s;
       }
     }
     __syncthreads();
@@ -132,8 +140,8 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
     Pi.p = A.P[4 * nn + qi];
     Pe.rho = A.P[qe]; Pe.v[0] = A.P[nn + qe]; Pe.v[1] = A.P[2 * nn + qe]; Pe.v[2] = A.P[3 * nn + qe];
     Pe.p = A.P[4 * nn + qe];
-    flux_dir<SYS>(d, ui, Pi, Fi);
-    flux_dir<SYS>(d, ue, Pe, Fe);
+    flux_normal<SYS>(d, ui, Pi, Fi);
+    flux_normal<SYS>(d, ue, Pe, Fe);
     const double alpha = fmax(max_speed<SYS>(d, ui, Pi, A.gamma), max_speed<SYS>(d, ue, Pe, A.gamma));
     const double hs = side ? 0.5 : -0.5;
     double *fb = sbuf + (fle * NV) * (6 * NF) + f * NF + fn;
@@ -148,16 +156,16 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
 
   if (!active) return;
   const double *myface = sbuf + (le * NV) * (6 * NF);
-  const int cc[3] = {ci, cj, ck};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int idx = cc[d];
-    if (idx != 0 && idx != N) continue;
-    const int f = 2 * d + (idx == N ? 1 : 0);
-    const int fn = (d == 0) ? (cj + NP * ck) : (d == 1) ? (ci + NP * ck) : (ci + NP * cj);
-    const double sc = A.scale[d] * A.inv_wend;
+    const int idx = sel3i(d, ci, cj, ck);
+    if (idx == 0 || idx == N) {
+      const int f = 2 * d + (idx == N ? 1 : 0);
+      const int fn = sel3i(d, cj + NP * ck, ci + NP * ck, ci + NP * cj);
+      const double sc = sel3(d, A.scale[0], A.scale[1], A.scale[2]) * A.inv_wend;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] -= sc * myface[v * 6 * NF + f * NF + fn];
+      for (int v = 0; v < NV; ++v) acc[v] -= sc * myface[v * 6 * NF + f * NF + fn];
+    }
   }
 
   if (STAGE == 0) {

@@ -154,8 +154,9 @@ def test_dg_step_parity(ora, dg, system, N):
     m, G = _pair(ora, dg, system, (3, 2, 2), N, flags=2)
     U, prim = _state(ora, system, m, seed=20 + N, wmax=3.0 if system else None)
     Lo, _, _ = ora.rhs(m, U)
-    # a step that moves U by ~1e-3 of its range (the random state is rough)
-    dt = 1e-3 * np.abs(U).max() / np.abs(Lo).max()
+    # every node's D and tau (positive) change by at most ~0.1 % in a stage;
+    # the random state spans four decades of pressure
+    dt = 1e-3 / max(np.abs(Lo[0] / U[0]).max(), np.abs(Lo[4] / U[4]).max())
     Uo, nf = ora.step(m, U, dt)
     assert nf == 0
     Ud = to_dev(U)
@@ -165,7 +166,7 @@ def test_dg_step_parity(ora, dg, system, N):
     tol = _step_tolerance(Lo, U, dt)
     assert np.all(diff <= tol), (diff, tol)
     # the step did move the state by far more than the tolerance
-    assert np.all(np.abs(Uo - U).max(axis=1)[:5] > 1e3 * tol[:5])
+    assert np.all(np.abs(Uo - U).max(axis=1)[:5] > 1e2 * tol[:5])
     assert dg.dgmi_failures(G) == 0
     # primitives written back are those of the new state
     Po, _, _ = ora.cons2prim(system, m.gamma, Uo)
