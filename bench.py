@@ -49,7 +49,89 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the SRMHD blast-wave RK3 steps and the learned-vs-plain recovery comparison")
+    ap.add_argument("--c2p-points", type=int, default=100_000_000)
+    ap.add_argument("--train-samples", type=int, default=10_000_000)
     return ap.parse_args()
+
+
+def srmhd_blast_steps(dg, synth, torch, steps=10, warmup=2):
+    """SRMHD, Gamma 4/3, kappa 0.5, periodic [-0.5, 0.5]^3, 64^3 elements of
+    degree 3 (16,777,216 nodes); blast data: rho 1, p 100 inside r < 0.05,
+    ln p falling linearly to p = 0.01 at r = 0.15 (a sharp jump at r = 0.1
+    drives the unlimited scheme to unphysical states within one step), v 0,
+    B = (sqrt 10, 0, 0) (magnetisation 10), Phi 0; SSP-RK3 steps of dt 4e-4
+    with the primitives recovered at every node of every stage."""
+    G = dg.Mesh(dg.SR_MHD, (64, 64, 64), 3, GAMMA, lo=(-0.5, -0.5, -0.5), hi=(0.5, 0.5, 0.5), kappa=0.5)
+    xyz = G.node_coords()
+    prim, mag = synth.blast_wave(xyz, shell=(0.05, 0.15))
+    del xyz
+    prim = prim.contiguous()
+    U = dg.dgmi_prim2cons(dg.SR_MHD, GAMMA, prim, mag.contiguous())
+    del mag
+    dt = 4e-4
+    ms = time_loop(torch, lambda i: dg.dg_step(G, U, prim, dt), steps, warmup)
+    nfail = dg.dgmi_failures(G)
+    finite = bool(torch.isfinite(U).all().item())
+    nn = G.nnodes
+    out = {"workload": "SRMHD blast wave (log-linear shell 0.05 < r < 0.15), 64^3 elements, degree 3, "
+                       "RK3 steps with recovery at every node",
+           "nodes": nn, "ms_per_step": ms, "dof_updates_per_s": nn * 9 / (ms * 1e-3),
+           "steps_timed": steps, "failed_recoveries": nfail, "state_finite": finite}
+    del G, U, prim
+    torch.cuda.empty_cache()
+    return out
+
+
+def learned_vs_plain(dg, synth, torch, npts, ntrain):
+    """Recovery throughput on npts SRMHD states drawn like the training set
+    (rho log-uniform [1e-3, 1e2], p/rho log-uniform [1e-4, 1e2], W up to 20,
+    magnetisation up to 10), at backward residual 1e-10, seeded three ways:
+    the bracket's upper end (plain), the trained network (learned), and the
+    true pressure times 1.01 (warm reference).  The network is trained
+    in-library on ntrain samples of a different seed."""
+    res = {"workload": f"SRMHD con2prim, {npts:.0e} points, tol 1e-10; MLP 5-64-64-1 SiLU trained on {ntrain:.0e}"}
+    # training
+    prim, mag = synth.srmhd_samples(ntrain, seed=1, xp="torch", device="cuda")
+    Ut = dg.dgmi_prim2cons(dg.SR_MHD, GAMMA, prim.contiguous(), mag.contiguous())
+    x, t = dg.mlp_features(dg.SR_MHD, GAMMA, Ut, prim=prim.contiguous())
+    del prim, mag, Ut
+    net = dg.Mlp(seed=7)
+    dg.mlp_fit_normalization(net, x, t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = dg.mlp_train(net, x, t, batch=8192, epochs=4, lr0=3e-3, lr1=1e-5)
+    torch.cuda.synchronize()
+    res["train_seconds"] = time.perf_counter() - t0
+    res["train_steps"] = int(hist.numel())
+    res["train_loss_first_last"] = [float(hist[:50].mean()), float(hist[-50:].mean())]
+    del x, t, hist
+    # queries
+    prim, mag = synth.srmhd_samples(npts, seed=2, xp="torch", device="cuda")
+    U = dg.dgmi_prim2cons(dg.SR_MHD, GAMMA, prim.contiguous(), mag.contiguous())
+    del mag
+    ptrue = prim[4].clone()
+    del prim
+    P = torch.empty((5, npts), dtype=torch.float64, device="cuda")
+    iters = torch.empty(npts, dtype=torch.uint8, device="cuda")
+    nfail = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for name, guess in (("plain", dg.GUESS_PLAIN), ("learned", dg.GUESS_LEARNED), ("warm_1pct", dg.GUESS_INPUT)):
+        def run(i):
+            if guess == dg.GUESS_INPUT:
+                P[4].copy_(ptrue).mul_(1.01)
+            dg.con2prim(dg.SR_MHD, GAMMA, U, P, guess=guess, mlp=net if guess == dg.GUESS_LEARNED else None,
+                        tol=1e-10, iters_out=iters, n_failed=nfail)
+        nfail.zero_()
+        ms = time_loop(torch, run, 3, 1)
+        it = iters.float()
+        res[name] = {"pts_per_s": npts / (ms * 1e-3), "ms": ms, "mean_iters": float(it.mean()),
+                     "max_iters": int(iters.max()), "failed": int(nfail.item()) // 4}
+    if "warm_1pct" in res:
+        res["warm_1pct"]["note"] = "includes a copy of the seed pressures each call"
+    del U, P, iters, ptrue, net
+    torch.cuda.empty_cache()
+    return res
 
 
 def make_inputs(dg, synth, torch):
@@ -173,6 +255,11 @@ def main():
                    "nodes": nn, "dof": nn * NV, "failed_recoveries": nfail},
         "roofline": roof,
     }
+    if not args.no_extras:
+        del Ua, Ub, P, dUa, dUb, G
+        torch.cuda.empty_cache()
+        out["srmhd_blast_dg_step"] = srmhd_blast_steps(dg, synth, torch)
+        out["con2prim_learned_vs_plain"] = learned_vs_plain(dg, synth, torch, args.c2p_points, args.train_samples)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

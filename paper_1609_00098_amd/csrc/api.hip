@@ -287,6 +287,9 @@ static dgmi::RhsArgs rhs_args(dgmi_ctx *c) {
   a.kappa = c->kappa;
   for (int d = 0; d < 3; ++d) a.scale[d] = 2.0 / c->dx[d];
   a.inv_wend = 1.0 / c->wend[c->degree];
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nz = c->nz;
   return a;
 }
 

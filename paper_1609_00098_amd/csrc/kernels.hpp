@@ -20,7 +20,8 @@ struct RhsArgs {
   double scale[3];     // 2/dx_d
   double inv_wend;     // 1/w_0 = N(N+1)/2
   double a, b, dt;     // Shu-Osher stage: out = a Un + b (U + dt L(U))
-  int nblocks;         // logical blocks (elements / elements-per-block)
+  int nx, ny, nz;      // elements per direction
+  int nblocks;         // logical blocks (set at launch)
 };
 
 // Launch dg RHS (stage == 0) or RK stage (stage == 1).

@@ -1,14 +1,17 @@
 // Uniform-degree DG right-hand side (eq. 411) and fused SSP-RK3 stage.
 //
 // One workgroup owns EPB whole elements, one thread per volume node.
-//   1. Each thread loads its node's U and primitives and forms the flux
-//      along one direction at a time; the direction's nodal fluxes go through
-//      one LDS buffer (EPB x nv x (N+1)^3 doubles) and every thread contracts
-//      its pencil with the row of D (eq. for D^{1bar}) scaled by 2/dx_d.
-//   2. The 6 (N+1)^2 face nodes of each element are handed out densely to
-//      the workgroup's threads: each computes the LLF flux difference
-//      F*.n - F.n (eq. LLF) against the coincident node of the periodic
-//      neighbour (read from global memory/L2) and parks it in LDS.
+//   1. Each thread loads its node's U and primitives (coalesced), keeps U in
+//      LDS for the face phase, and forms the flux along one direction at a
+//      time; the direction's nodal fluxes go through an LDS buffer and every
+//      thread contracts its pencil with its row of D (eq. for D^{1bar}),
+//      scaled by 2/dx_d.  A node on a face of that direction also parks its
+//      normal flux and its largest wave speed in the face slot: the interior
+//      half of the numerical flux is done by the node that owns it.
+//   2. The EPB*6*(N+1)^2 face nodes are handed out densely: each task reads
+//      the exterior state (the coincident node of the periodic neighbour,
+//      from global memory), forms its flux and speed, and turns the slot into
+//      the LLF difference F*.n - F.n (eq. LLF).
 //   3. Each volume thread adds -(2/dx_d)(1/w_end)(F*.n - F.n) for every face
 //      it lies on (edge and corner nodes receive two or three terms).
 //   4. RHS mode writes dU/dt; stage mode forms the Shu-Osher combination
@@ -35,18 +38,37 @@ struct RhsCfg {
   static constexpr int NPE = NP * NP * NP;
   static constexpr int NF = NP * NP;
   static constexpr int NV = SysTraits<SYS>::nv;
-  static constexpr int EPB = (N == 1) ? 8 : (N == 2) ? 9 : (N == 3) ? 4 : (N == 4) ? 2 : 1;
+  static constexpr int EPB = (N == 1) ? 8 : (N == 2) ? 9 : (N == 3) ? (SYS == kMHD ? 2 : 4) : (N == 4) ? 2 : 1;
   static constexpr int THREADS = ((EPB * NPE + 63) / 64) * 64;
   static constexpr int FACE_TASKS = EPB * 6 * NF;
-  static constexpr int SLOT = (NPE > 6 * NF) ? NPE : 6 * NF;  // doubles per variable per element
-  static constexpr int LDS_DOUBLES = EPB * NV * SLOT;
+  // LDS (doubles): volume flux [EPB][NV][NPE], own state [EPB][NV][NPE],
+  // face slots [EPB][NV][6][NF], interior wave speeds [EPB][6][NF]
+  static constexpr int VOL = EPB * NV * NPE;
+  static constexpr int OWN = EPB * NV * NPE;
+  static constexpr int SLOT = EPB * NV * 6 * NF;
+  static constexpr int SPD = EPB * 6 * NF;
 };
+
+template <int SYS>
+__device__ __forceinline__ void load_node(const double *U, const double *Pr, int64_t nn, int64_t q, double *u,
+                                          Prim &P) {
+#pragma unroll
+  for (int v = 0; v < SysTraits<SYS>::nv; ++v) u[v] = U[v * nn + q];
+  P.rho = Pr[q];
+  P.v[0] = Pr[nn + q];
+  P.v[1] = Pr[2 * nn + q];
+  P.v[2] = Pr[3 * nn + q];
+  P.p = Pr[4 * nn + q];
+}
 
 template <int SYS, int N, int STAGE>
 __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const RhsArgs A) {
   using C = RhsCfg<SYS, N>;
   constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
-  __shared__ double sbuf[C::LDS_DOUBLES];
+  __shared__ double svol[C::VOL];
+  __shared__ double sown[C::OWN];
+  __shared__ double sslot[C::SLOT];
+  __shared__ double sspd[C::SPD];
   __shared__ double sD[NP * NP];
 
   // XCD-major block order: hardware block b runs on XCD b % 8.
@@ -71,20 +93,18 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   if (active) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = A.U[v * nn + q];
-    P.rho = A.P[q];
-    P.v[0] = A.P[nn + q];
-    P.v[1] = A.P[2 * nn + q];
-    P.v[2] = A.P[3 * nn + q];
-    P.p = A.P[4 * nn + q];
+    load_node<SYS>(A.U, A.P, nn, q, u, P);
     if (SYS == kMHD) acc[8] = -A.kappa * u[8];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sown[(le * NV + v) * NPE + a] = u[v];
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = 0.0;
     P.rho = 1.0; P.v[0] = P.v[1] = P.v[2] = 0.0; P.p = 1.0;
   }
-  double *mybuf = sbuf + le * NV * NPE;  // [v][node] for this element
+  double *mybuf = svol + le * NV * NPE;  // [v][node] for this element
+  double *myslot = sslot + le * NV * 6 * NF;
+  double *myspd = sspd + le * 6 * NF;
 
   // ---- volume term, one direction at a time
 #pragma unroll
@@ -94,13 +114,22 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
       flux_normal<SYS>(d, u, P, F);
 #pragma unroll
       for (int v = 0; v < NV; ++v) mybuf[v * NPE + a] = F[v];
+      // a face node of this direction parks its half of the face flux
+      const int idx = sel3i(d, ci, cj, ck);
+      if (idx == 0 || idx == N) {
+        const int f = 2 * d + (idx == N ? 1 : 0);
+        const int fn = sel3i(d, cj + NP * ck, ci + NP * ck, ci + NP * cj);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) myslot[(v * 6 + f) * NF + fn] = F[v];
+        myspd[f * NF + fn] = max_speed<SYS>(d, u, P, A.gamma);
+      }
     }
     __syncthreads();
     if (active) {
       const int idx = sel3i(d, ci, cj, ck);
       const int stride = sel3i(d, 1, NP, NF);
-      const double scale = sel3(d, A.scale[0], A.scale[1], A.scale[2]);
       const int base = a - idx * stride;
+      const double scale = sel3(d, A.scale[0], A.scale[1], A.scale[2]);
       double Drow[NP];
 #pragma unroll
       for (int l = 0; l < NP; ++l) Drow[l] = sD[idx * NP + l];
@@ -130,32 +159,26 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
     else if (d == 1) { c0 = ta; c1 = side ? N : 0; c2 = tb; n0 = ta; n1 = side ? 0 : N; n2 = tb; }
     else { c0 = ta; c1 = tb; c2 = side ? N : 0; n0 = ta; n1 = tb; n2 = side ? 0 : N; }
     const int64_t en = A.nbr[fe * 6 + f];
-    const int64_t qi = fe * NPE + c0 + NP * (c1 + NP * c2);
-    const int64_t qe = en * NPE + n0 + NP * (n1 + NP * n2);
-    double ui[NV], ue[NV], Fi[NV], Fe[NV];
-    Prim Pi, Pe;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) { ui[v] = A.U[v * nn + qi]; ue[v] = A.U[v * nn + qe]; }
-    Pi.rho = A.P[qi]; Pi.v[0] = A.P[nn + qi]; Pi.v[1] = A.P[2 * nn + qi]; Pi.v[2] = A.P[3 * nn + qi];
-    Pi.p = A.P[4 * nn + qi];
-    Pe.rho = A.P[qe]; Pe.v[0] = A.P[nn + qe]; Pe.v[1] = A.P[2 * nn + qe]; Pe.v[2] = A.P[3 * nn + qe];
-    Pe.p = A.P[4 * nn + qe];
-    flux_normal<SYS>(d, ui, Pi, Fi);
+    const int ai = c0 + NP * (c1 + NP * c2);
+    double ue[NV], Fe[NV];
+    Prim Pe;
+    load_node<SYS>(A.U, A.P, nn, en * NPE + n0 + NP * (n1 + NP * n2), ue, Pe);
     flux_normal<SYS>(d, ue, Pe, Fe);
-    const double alpha = fmax(max_speed<SYS>(d, ui, Pi, A.gamma), max_speed<SYS>(d, ue, Pe, A.gamma));
+    const double *own = sown + fle * NV * NPE + ai;
+    double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
+    const double alpha = fmax(sspd[(fle * 6 + f) * NF + fn], max_speed<SYS>(d, ue, Pe, A.gamma));
     const double hs = side ? 0.5 : -0.5;
-    double *fb = sbuf + (fle * NV) * (6 * NF) + f * NF + fn;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double al = alpha;
       if (SYS == kMHD && (v == 8 || v == 5 + d)) al = 1.0;
-      fb[v * 6 * NF] = hs * (Fe[v] - Fi[v]) - 0.5 * al * (ue[v] - ui[v]);
+      const double Fi = slot[v * 6 * NF];
+      slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * al * (ue[v] - own[v * NPE]);
     }
   }
   __syncthreads();
 
   if (!active) return;
-  const double *myface = sbuf + (le * NV) * (6 * NF);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int idx = sel3i(d, ci, cj, ck);
@@ -164,7 +187,7 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
       const int fn = sel3i(d, cj + NP * ck, ci + NP * ck, ci + NP * cj);
       const double sc = sel3(d, A.scale[0], A.scale[1], A.scale[2]) * A.inv_wend;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] -= sc * myface[v * 6 * NF + f * NF + fn];
+      for (int v = 0; v < NV; ++v) acc[v] -= sc * myslot[(v * 6 + f) * NF + fn];
     }
   }
 
@@ -174,28 +197,28 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
     return;
   }
   // ---- Shu-Osher combination and tail recovery
-  double un[NV];
+  double us[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const double base = A.Un[v * nn + q];
-    un[v] = A.a * base + A.b * (u[v] + A.dt * acc[v]);
-    A.out[v * nn + q] = un[v];
+    us[v] = A.a * A.Un[v * nn + q] + A.b * (u[v] + A.dt * acc[v]);
+    A.out[v * nn + q] = us[v];
   }
-  const C2PResult R = recover<SYS>(un, A.gamma, P.p, 0.0, 100);
+  const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100);
   A.Pout[q] = R.P.rho;
   A.Pout[nn + q] = R.P.v[0];
   A.Pout[2 * nn + q] = R.P.v[1];
   A.Pout[3 * nn + q] = R.P.v[2];
   A.Pout[4 * nn + q] = R.P.p;
-  const unsigned long long bad = __ballot(!R.ok);
-  if (bad && (threadIdx.x & 63) == (__ffsll((long long)bad) - 1)) atomicAdd(A.nfail, (unsigned long long)__popcll(bad));
+  if (!R.ok) atomicAdd(A.nfail, 1ull);
 }
 
 template <int SYS, int N>
 static hipError_t launch_one(int stage, const RhsArgs &a, hipStream_t s) {
   using C = RhsCfg<SYS, N>;
   RhsArgs b = a;
-  b.nblocks = (int)((a.nelem + C::EPB - 1) / C::EPB);
+  const int64_t nblocks = (a.nelem + C::EPB - 1) / C::EPB;
+  if (nblocks > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+  b.nblocks = (int)nblocks;
   const int grid = ((b.nblocks + 7) / 8) * 8;
   if (stage == 0)
     hipLaunchKernelGGL((rhs_kernel<SYS, N, 0>), dim3(grid), dim3(C::THREADS), 0, s, b);

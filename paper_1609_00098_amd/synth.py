@@ -119,16 +119,24 @@ def fourier_random_prims(xyz, seed=1609, modes=8, rho_range=(0.1, 10.0), p_range
     return m.stack([rho, u[0] / w, u[1] / w, u[2] / w, p])
 
 
-def blast_wave(xyz, centre=(0.0, 0.0, 0.0), radius=0.1, rho=1.0, p_in=100.0, p_out=0.01, bfield=(10.0 ** 0.5, 0, 0)):
+def blast_wave(xyz, centre=(0.0, 0.0, 0.0), radius=0.1, rho=1.0, p_in=100.0, p_out=0.01, bfield=(10.0 ** 0.5, 0, 0),
+               shell=None):
     """Spherical magnetised blast: uniform rho, v = 0, p = p_in inside r <
-    radius and p_out outside (sharp nodal jump), uniform B, Phi = 0.
-    Returns (prim[5][n], mag[4][n])."""
+    radius and p_out outside, uniform B, Phi = 0.  shell=None gives a sharp
+    nodal jump; shell=(r0, r1) makes ln p fall linearly from ln p_in at r0
+    to ln p_out at r1 instead.  Returns (prim[5][n], mag[4][n])."""
     xp = np if isinstance(xyz, np.ndarray) else _torch()
     r2 = (xyz[0] - centre[0]) ** 2 + (xyz[1] - centre[1]) ** 2 + (xyz[2] - centre[2]) ** 2
-    inside = r2 < radius * radius
     ones = xp.ones_like(xyz[0])
     zeros = xp.zeros_like(xyz[0])
-    p = xp.where(inside, p_in * ones, p_out * ones)
+    if shell is None:
+        inside = r2 < radius * radius
+        p = xp.where(inside, p_in * ones, p_out * ones)
+    else:
+        r0, r1 = shell
+        s = (xp.sqrt(r2) - r0) / (r1 - r0)
+        s = xp.clip(s, 0.0, 1.0) if xp is np else s.clamp(0.0, 1.0)
+        p = xp.exp(math.log(p_in) + (math.log(p_out) - math.log(p_in)) * s)
     prim = xp.stack([rho * ones, zeros, zeros, zeros, p])
     mag = xp.stack([bfield[0] * ones, bfield[1] * ones, bfield[2] * ones, zeros])
     return prim, mag
