@@ -98,6 +98,11 @@ def _load():
         "ora_evolve": (I64, [MP, D, ctypes.c_double, I64]),
         "ora_l1_error": (ctypes.c_double, [MP, ctypes.c_int, D, D]),
         "ora_integrate": (ctypes.c_int, [MP, ctypes.c_int, D, D]),
+        "ora_mixed_num_nodes": (I64, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
+        "ora_mixed_node_coords": (ctypes.c_int, [MP, ctypes.POINTER(ctypes.c_int32), D]),
+        "ora_rhs_mixed": (I64, [MP, ctypes.POINTER(ctypes.c_int32), D, D, D]),
+        "ora_mixed_integrate": (ctypes.c_int, [MP, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, D, D]),
+        "ora_step_mixed": (I64, [MP, ctypes.POINTER(ctypes.c_int32), D, ctypes.c_double]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -296,3 +301,50 @@ def integrate(m, q):
     out = np.zeros(q.shape[0])
     _load().ora_integrate(ctypes.byref(m), q.shape[0], _p(q), _p(out))
     return out
+
+
+# ------------------------------------------------------- mixed degrees
+def _deg(deg):
+    d = np.ascontiguousarray(deg, dtype=np.int32)
+    return d, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def mixed_num_nodes(deg):
+    d, dp = _deg(deg)
+    return int(_load().ora_mixed_num_nodes(len(d), dp))
+
+
+def mixed_node_coords(m, deg):
+    d, dp = _deg(deg)
+    n = mixed_num_nodes(d)
+    xyz = np.zeros((3, n))
+    if _load().ora_mixed_node_coords(ctypes.byref(m), dp, _p(xyz)) != 0:
+        raise ValueError("bad degrees")
+    return xyz
+
+
+def rhs_mixed(m, deg, U):
+    """Mixed-degree operator (mortar of the max degree on unequal faces)."""
+    d, dp = _deg(deg)
+    U = _c(U)
+    prim = np.zeros((5, U.shape[1]))
+    dU = np.zeros_like(U)
+    nf = _load().ora_rhs_mixed(ctypes.byref(m), dp, _p(U), _p(prim), _p(dU))
+    if nf < 0:
+        raise ValueError("bad degrees")
+    return dU, prim, int(nf)
+
+
+def mixed_integrate(m, deg, q):
+    d, dp = _deg(deg)
+    q = _c(q)
+    out = np.zeros(q.shape[0])
+    _load().ora_mixed_integrate(ctypes.byref(m), dp, q.shape[0], _p(q), _p(out))
+    return out
+
+
+def step_mixed(m, deg, U, dt):
+    d, dp = _deg(deg)
+    U = _c(U).copy()
+    nf = _load().ora_step_mixed(ctypes.byref(m), dp, _p(U), dt)
+    return U, int(nf)

@@ -878,3 +878,294 @@ int ora_integrate(const ora_mesh *m, int ncomp, const double *q, double *out) {
   }
   return ORA_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Mixed polynomial degrees (the paper leaves coupling of unequal degrees to */
+/* future work).  Reading used here: on a face between degrees Na and Nb the */
+/* mortar has degree Nm = max(Na, Nb) with the GLL nodes of that degree.     */
+/*  - The lower-degree side interpolates its face primitives (rho, W v, p,  */
+/*    and B, Phi for MHD) to the mortar nodes with the tensor Lagrange matrix */
+/*    I(m,i) = l_i^(Nlo)(x_m^(Nm)) and maps them to conserved variables;     */
+/*    the higher-degree side's face nodes are the mortar nodes.              */
+/*  - One LLF flux F*.n per mortar node from the two mortar states.          */
+/*  - The higher-degree side lifts as in the uniform operator; the lower side */
+/*    uses P (F*.n - I F_h.n) with I the interpolation of its own nodal      */
+/*    fluxes to the mortar and P(i,m) = w_m^(Nm) l_i^(Nlo)(x_m) / w_i^(Nlo)  */
+/*    (tensorised): the face integral of the flux difference against its own */
+/*    basis, with the mortar's GLL rule, over its lumped face mass.          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  double x[9], w[9], D[81];
+} tab_t;
+
+static void make_tab(int N, tab_t *T) {
+  ora_gll(N, T->x, T->w);
+  ora_diff_matrix(N, T->x, T->D);
+}
+
+/* Interpolation state at one node, a flat array of 9:
+ * (rho, u^x, u^y, u^z, p, B^x, B^y, B^z, Phi), where u^i = W v^i is the
+ * spatial four-velocity for the relativistic systems (any value is a
+ * subluminal velocity, so interpolation cannot overshoot the light speed)
+ * and u^i = v^i for the Newtonian system.                                   */
+static void node_state9(int sys, int64_t n, const double *U, const double *prim, int64_t q, double *s9) {
+  for (int c = 0; c < 5; ++c) s9[c] = prim[(int64_t)c * n + q];
+  if (sys != 0) {
+    double v2 = s9[1] * s9[1] + s9[2] * s9[2] + s9[3] * s9[3];
+    double W = 1.0 / sqrt(1.0 - v2);
+    for (int c = 1; c < 4; ++c) s9[c] *= W;
+  }
+  for (int c = 0; c < 4; ++c) s9[5 + c] = (sys == 2) ? U[(int64_t)(5 + c) * n + q] : 0.0;
+}
+
+static void state9_to_cp(int sys, double g, const double *s9, cons_t *C, prim_t *P) {
+  double iW = 1.0;
+  if (sys != 0) iW = 1.0 / sqrt(1.0 + s9[1] * s9[1] + s9[2] * s9[2] + s9[3] * s9[3]);
+  P->rho = s9[0]; P->v[0] = s9[1] * iW; P->v[1] = s9[2] * iW; P->v[2] = s9[3] * iW; P->p = s9[4];
+  if (sys == 0) ne_p2c(g, P, C);
+  else if (sys == 1) sr_p2c(g, P, C);
+  else mhd_p2c(g, P, &s9[5], s9[8], C);
+}
+
+int64_t ora_mixed_num_nodes(int nelem, const int32_t *deg) {
+  int64_t n = 0;
+  for (int e = 0; e < nelem; ++e) n += (int64_t)(deg[e] + 1) * (deg[e] + 1) * (deg[e] + 1);
+  return n;
+}
+
+/* Node coordinates of a mixed-degree mesh (nodes of element e are
+ * contiguous, elements in lexicographic order). */
+int ora_mixed_node_coords(const ora_mesh *m, const int32_t *deg, double *xyz) {
+  int64_t ne = (int64_t)m->nx * m->ny * m->nz;
+  int64_t n = ora_mixed_num_nodes((int)ne, deg);
+  double dx[3] = {(m->hi[0] - m->lo[0]) / m->nx, (m->hi[1] - m->lo[1]) / m->ny, (m->hi[2] - m->lo[2]) / m->nz};
+  int64_t off = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    tab_t T;
+    int N = deg[e], np = N + 1;
+    if (N < 1 || N > 8) return ORA_EINVAL;
+    make_tab(N, &T);
+    int64_t c[3] = {e % m->nx, (e / m->nx) % m->ny, e / ((int64_t)m->nx * m->ny)};
+    for (int k = 0; k < np; ++k)
+      for (int j = 0; j < np; ++j)
+        for (int i = 0; i < np; ++i) {
+          int ijk[3] = {i, j, k};
+          int64_t q = off + i + np * (j + np * k);
+          for (int d = 0; d < 3; ++d) xyz[d * n + q] = m->lo[d] + c[d] * dx[d] + 0.5 * (1.0 + T.x[ijk[d]]) * dx[d];
+        }
+    off += (int64_t)np * np * np;
+  }
+  return ORA_OK;
+}
+
+/* Face node (a, b) of face (d, side) of an element of degree N -> local node. */
+static int face_node(int N, int d, int side, int a, int b) {
+  int np = N + 1, c[3];
+  int nrm = side ? N : 0;
+  if (d == 0) { c[0] = nrm; c[1] = a; c[2] = b; }
+  else if (d == 1) { c[0] = a; c[1] = nrm; c[2] = b; }
+  else { c[0] = a; c[1] = b; c[2] = nrm; }
+  return c[0] + np * (c[1] + np * c[2]);
+}
+
+/* Mixed-degree strong-form operator.  The mesh's deg[] field is ignored;
+ * deg[e] gives each element's degree.  Returns failed recoveries or <0. */
+int64_t ora_rhs_mixed(const ora_mesh *m, const int32_t *deg, const double *U, double *prim_out, double *dUdt) {
+  int sys = m->sys, nv = nvars_of(sys);
+  double g = m->gamma;
+  int64_t ne = (int64_t)m->nx * m->ny * m->nz;
+  int64_t n = ora_mixed_num_nodes((int)ne, deg);
+  int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (ne + 1));
+  off[0] = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    if (deg[e] < 1 || deg[e] > 8) { free(off); return ORA_EINVAL; }
+    off[e + 1] = off[e] + (int64_t)(deg[e] + 1) * (deg[e] + 1) * (deg[e] + 1);
+  }
+  tab_t tabs[9];
+  for (int N = 1; N <= 8; ++N) make_tab(N, &tabs[N]);
+  double *prim = prim_out ? prim_out : (double *)malloc(sizeof(double) * 5 * n);
+  int64_t nf = ora_cons2prim(sys, g, n, U, prim, NULL);
+  double dx[3] = {(m->hi[0] - m->lo[0]) / m->nx, (m->hi[1] - m->lo[1]) / m->ny, (m->hi[2] - m->lo[2]) / m->nz};
+#pragma omp parallel for schedule(dynamic, 1) if (n > 4096)
+  for (int64_t e = 0; e < ne; ++e) {
+    int N = deg[e], np = N + 1, npe = np * np * np;
+    const tab_t *T = &tabs[N];
+    double *F = (double *)malloc(sizeof(double) * 3 * nv * npe);
+    double *L = (double *)calloc((size_t)nv * npe, sizeof(double));
+    for (int a = 0; a < npe; ++a) {
+      cons_t C; prim_t P; double f[9];
+      load_cons(nv, n, U, off[e] + a, &C);
+      load_prim(n, prim, off[e] + a, &P);
+      for (int d = 0; d < 3; ++d) {
+        flux(sys, g, d, &C, &P, f);
+        for (int v = 0; v < nv; ++v) F[(d * nv + v) * npe + a] = f[v];
+      }
+      if (sys == 2) L[8 * npe + a] = -m->kappa * C.u[8];
+    }
+    /* volume term */
+    for (int k = 0; k < np; ++k)
+      for (int j = 0; j < np; ++j)
+        for (int i = 0; i < np; ++i) {
+          int ijk[3] = {i, j, k};
+          int a = i + np * (j + np * k);
+          for (int d = 0; d < 3; ++d)
+            for (int v = 0; v < nv; ++v) {
+              double acc = 0.0;
+              for (int l = 0; l < np; ++l) {
+                int c[3] = {i, j, k};
+                c[d] = l;
+                acc += T->D[ijk[d] * np + l] * F[(d * nv + v) * npe + c[0] + np * (c[1] + np * c[2])];
+              }
+              L[v * npe + a] -= (2.0 / dx[d]) * acc;
+            }
+        }
+    /* faces through mortars */
+    for (int d = 0; d < 3; ++d)
+      for (int side = 0; side < 2; ++side) {
+        int64_t en = neighbour(m, e, d, side);
+        int Nn = deg[en], Nm = N > Nn ? N : Nn, nm = Nm + 1;
+        const tab_t *Tm = &tabs[Nm];
+        double sgn = side ? 1.0 : -1.0;
+        /* mortar states of both sides: a conforming side (degree Nm) uses its
+         * stored conserved state and primitives; a lower-degree side
+         * interpolates its face primitives and maps them to conserved.       */
+        cons_t *Cm = (cons_t *)malloc(sizeof(cons_t) * 2 * nm * nm);
+        prim_t *Pq = (prim_t *)malloc(sizeof(prim_t) * 2 * nm * nm);
+        double *fs = (double *)malloc(sizeof(double) * nv * nm * nm);
+        for (int side2 = 0; side2 < 2; ++side2) {
+          /* side2 = 0: this element's face; 1: the neighbour's facing face */
+          int Ns = side2 ? Nn : N;
+          int sd = side2 ? !side : side;
+          int64_t es = side2 ? en : e;
+          const tab_t *Ts = &tabs[Ns];
+          int ns = Ns + 1;
+          double Iab[81];
+          ora_lagrange_matrix(ns, Ts->x, nm, Tm->x, Iab); /* Iab[mm*ns + ii] = l_ii(x_mm) */
+          for (int mb = 0; mb < nm; ++mb)
+            for (int ma = 0; ma < nm; ++ma) {
+              int slot = side2 * nm * nm + ma + nm * mb;
+              if (Ns == Nm) {
+                int64_t q = off[es] + face_node(Ns, d, sd, ma, mb);
+                load_cons(nv, n, U, q, &Cm[slot]);
+                load_prim(n, prim, q, &Pq[slot]);
+              } else {
+                double s9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                for (int ib = 0; ib < ns; ++ib)
+                  for (int ia = 0; ia < ns; ++ia) {
+                    double t9[9];
+                    double wgt = Iab[ma * ns + ia] * Iab[mb * ns + ib];
+                    node_state9(sys, n, U, prim, off[es] + face_node(Ns, d, sd, ia, ib), t9);
+                    for (int c = 0; c < 9; ++c) s9[c] += wgt * t9[c];
+                  }
+                state9_to_cp(sys, g, s9, &Cm[slot], &Pq[slot]);
+              }
+            }
+        }
+        for (int mm = 0; mm < nm * nm; ++mm) {
+          double Fs[9], Fi[9];
+          llf(sys, g, d, sgn, &Cm[mm], &Pq[mm], &Cm[nm * nm + mm], &Pq[nm * nm + mm], Fs, Fi);
+          for (int v = 0; v < nv; ++v) fs[v * nm * nm + mm] = Fs[v];
+        }
+        /* Lift onto this element's face nodes.  Conforming side: F* - F.n at
+         * its own face nodes.  Lower-degree side: the surface integral of
+         * (F* - F_h.n) against its own face basis, taken with the mortar's
+         * GLL rule and divided by its own (diagonal) face mass, where F_h is
+         * the interpolant of its nodal fluxes: P (F* - I F_h.n).            */
+        double *fo = (double *)malloc(sizeof(double) * nv * np * np);
+        for (int b = 0; b < np; ++b)
+          for (int a = 0; a < np; ++a) {
+            cons_t Co; prim_t Po; double f9[9];
+            int64_t q = off[e] + face_node(N, d, side, a, b);
+            load_cons(nv, n, U, q, &Co);
+            load_prim(n, prim, q, &Po);
+            flux(sys, g, d, &Co, &Po, f9);
+            for (int v = 0; v < nv; ++v) fo[v * np * np + a + np * b] = sgn * f9[v];
+          }
+        double *dF = (double *)malloc(sizeof(double) * nv * np * np);
+        if (N == Nm) {
+          for (int v = 0; v < nv; ++v)
+            for (int ab = 0; ab < np * np; ++ab) dF[v * np * np + ab] = fs[v * nm * nm + ab] - fo[v * np * np + ab];
+        } else {
+          double Il[81], Pm[81];
+          ora_lagrange_matrix(np, T->x, nm, Tm->x, Il); /* Il[mm*np + i] = l_i(x_m) */
+          for (int i = 0; i < np; ++i)
+            for (int mm = 0; mm < nm; ++mm) Pm[i * nm + mm] = Tm->w[mm] * Il[mm * np + i] / T->w[i];
+          double *jm = (double *)malloc(sizeof(double) * nv * nm * nm);
+          for (int v = 0; v < nv; ++v)
+            for (int mb = 0; mb < nm; ++mb)
+              for (int ma = 0; ma < nm; ++ma) {
+                double fh = 0.0;
+                for (int ib = 0; ib < np; ++ib)
+                  for (int ia = 0; ia < np; ++ia) fh += Il[ma * np + ia] * Il[mb * np + ib] * fo[v * np * np + ia + np * ib];
+                jm[v * nm * nm + ma + nm * mb] = fs[v * nm * nm + ma + nm * mb] - fh;
+              }
+          for (int v = 0; v < nv; ++v)
+            for (int b = 0; b < np; ++b)
+              for (int a = 0; a < np; ++a) {
+                double acc = 0.0;
+                for (int mb = 0; mb < nm; ++mb)
+                  for (int ma = 0; ma < nm; ++ma) acc += Pm[a * nm + ma] * Pm[b * nm + mb] * jm[v * nm * nm + ma + nm * mb];
+                dF[v * np * np + a + np * b] = acc;
+              }
+          free(jm);
+        }
+        for (int b = 0; b < np; ++b)
+          for (int a = 0; a < np; ++a) {
+            int loc = face_node(N, d, side, a, b);
+            for (int v = 0; v < nv; ++v)
+              L[v * npe + loc] -= (2.0 / dx[d]) * (1.0 / T->w[side ? N : 0]) * dF[v * np * np + a + np * b];
+          }
+        free(fo); free(dF);
+        free(Cm); free(Pq); free(fs);
+      }
+    for (int v = 0; v < nv; ++v)
+      for (int a = 0; a < npe; ++a) dUdt[(int64_t)v * n + off[e] + a] = L[v * npe + a];
+    free(F); free(L);
+  }
+  if (!prim_out) free(prim);
+  free(off);
+  return nf;
+}
+
+/* Discrete integral with each element's own GLL rule (mixed degrees). */
+int ora_mixed_integrate(const ora_mesh *m, const int32_t *deg, int ncomp, const double *q, double *out) {
+  int64_t ne = (int64_t)m->nx * m->ny * m->nz;
+  int64_t n = ora_mixed_num_nodes((int)ne, deg);
+  double vol = ((m->hi[0] - m->lo[0]) / m->nx / 2.0) * ((m->hi[1] - m->lo[1]) / m->ny / 2.0) *
+               ((m->hi[2] - m->lo[2]) / m->nz / 2.0);
+  for (int c = 0; c < ncomp; ++c) out[c] = 0.0;
+  int64_t off = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    tab_t T;
+    int N = deg[e], np = N + 1;
+    make_tab(N, &T);
+    for (int k = 0; k < np; ++k)
+      for (int j = 0; j < np; ++j)
+        for (int i = 0; i < np; ++i) {
+          double w = T.w[i] * T.w[j] * T.w[k] * vol;
+          for (int c = 0; c < ncomp; ++c) out[c] += w * q[(int64_t)c * n + off + i + np * (j + np * k)];
+        }
+    off += (int64_t)np * np * np;
+  }
+  return ORA_OK;
+}
+
+/* SSP-RK3 step on a mixed-degree mesh. */
+int64_t ora_step_mixed(const ora_mesh *m, const int32_t *deg, double *U, double dt) {
+  int64_t ne = (int64_t)m->nx * m->ny * m->nz;
+  int nv = nvars_of(m->sys);
+  int64_t n = (int64_t)nv * ora_mixed_num_nodes((int)ne, deg);
+  double *L = (double *)malloc(sizeof(double) * n);
+  double *U1 = (double *)malloc(sizeof(double) * n);
+  double *U2 = (double *)malloc(sizeof(double) * n);
+  int64_t nf = 0;
+  nf += ora_rhs_mixed(m, deg, U, NULL, L);
+  ora_rk3_combine(1, dt, n, U, U, L, U1);
+  nf += ora_rhs_mixed(m, deg, U1, NULL, L);
+  ora_rk3_combine(2, dt, n, U, U1, L, U2);
+  nf += ora_rhs_mixed(m, deg, U2, NULL, L);
+  ora_rk3_combine(3, dt, n, U, U2, L, U);
+  free(L); free(U1); free(U2);
+  return nf;
+}
