@@ -58,6 +58,10 @@ enum {
 /* dgmi_mesh_desc.flags */
 #define DGMI_FLAG_PLAIN_GUESS 1   /* dg_rhs / dg_step: seed recoveries from the bracket, not prim_inout */
 #define DGMI_FLAG_RECOVER_FIRST 2 /* dg_step: recompute prims of U^n before the first stage */
+#define DGMI_FLAG_NO_GRAPH 4      /* mixed degrees: dg_step launches its kernels directly instead of
+                                     replaying a captured graph */
+#define DGMI_FLAG_AUTOTUNE 8      /* mixed degrees: dgmi_create times every tile option per degree and
+                                     keeps the fastest (results do not depend on the choice) */
 
 typedef struct dgmi_ctx dgmi_ctx;
 typedef struct dgmi_mlp dgmi_mlp;
@@ -71,14 +75,23 @@ typedef struct {
   double gamma;           /* ideal-gas adiabatic index, 1 < gamma <= 2 */
   double kappa;           /* divergence-cleaning damping (MHD source -kappa Phi) */
   double lo[3], hi[3];    /* box corners; every element has size (hi-lo)/n_d */
-  const int32_t *degrees_host; /* nx*ny*nz degrees in 2..7 when degree == 0 */
+  const int32_t *degrees_host; /* nx*ny*nz degrees in 1..7 when degree == 0 */
 } dgmi_mesh_desc;
 
 /* Build a mesh context: GLL nodes, weights and differentiation matrices
  * (eq. for D^{1bar}), neighbour tables, RK scratch.  Synchronous.  The
- * context is bound to the device current at creation.  Mixed degrees
- * (degree == 0) return DGMI_EUNSUPPORTED from dg_rhs/dg_step until the
- * mortar path is enabled.                                                */
+ * context is bound to the device current at creation.
+ *
+ * Mixed degrees (degree == 0, degrees_host[e] in 1..7 for element e): the
+ * paper defers the coupling of unequal degrees; a face between degrees Na and
+ * Nb carries a mortar with the GLL nodes of degree max(Na, Nb).  The lower
+ * side is interpolated there in (rho, W v, p [, B, Phi]), one LLF flux is
+ * formed per mortar node, the higher side lifts F*.n - F.n at its nodes and
+ * the lower side lifts P (F*.n - I F_h.n), P(i,m) = w_m l_i(x_m) / w_i, with
+ * I F_h the interpolant of its own nodal fluxes.  dg_step on a non-default
+ * stream captures its three stages once per (U, prim_inout) pair and then
+ * replays the graph (dt travels in a device scalar); the per-degree kernels
+ * run concurrently on the context's own streams.                          */
 dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out);
 dgmi_status dgmi_destroy(dgmi_ctx *ctx);
 

@@ -133,7 +133,171 @@ struct dgmi_ctx {
   double *d_U1 = nullptr, *d_U2 = nullptr, *d_P1 = nullptr, *d_P2 = nullptr;
   unsigned long long *d_nfail = nullptr;
   double wend[8];
+  // mixed degrees
+  bool mixed = false;
+  int32_t *d_deg = nullptr;       // [nelem]
+  int64_t *d_off = nullptr;       // [nelem + 1]
+  int32_t *d_elist = nullptr;     // elements grouped by degree, highest first
+  int64_t lstart[9] = {0}, lcount[9] = {0};
+  double *d_Itab = nullptr, *d_Ptab = nullptr;  // [8][8][8][8] mortar tables
+  double *d_dt = nullptr;         // device scalar read by captured stages
+  int epb[9] = {0};               // chosen elements per workgroup by degree
+  hipStream_t side[8] = {nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[8] = {nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void *gU = nullptr, *gP = nullptr;
 };
+
+
+// ------------------------------------------------------------ mixed degrees
+// Lagrange basis of the GLL nodes xs (n nodes) evaluated at y.
+static double lagrange(int n, const double *xs, int i, double y) {
+  double v = 1.0;
+  for (int j = 0; j < n; ++j)
+    if (j != i) v *= (y - xs[j]) / (xs[i] - xs[j]);
+  return v;
+}
+
+static dgmi_status autotune(dgmi_ctx *c);
+
+// Degree lists, offsets, mortar tables, streams; optional tile autotuning.
+static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
+  c->mixed = true;
+  std::vector<int32_t> elist;
+  elist.reserve(c->nelem);
+  for (int N = dgmi::kMaxMixedDegree; N >= 1; --N) {
+    c->lstart[N] = (int64_t)elist.size();
+    for (int64_t e = 0; e < c->nelem; ++e)
+      if (c->deg[e] == N) elist.push_back((int32_t)e);
+    c->lcount[N] = (int64_t)elist.size() - c->lstart[N];
+    int opts[3];
+    dgmi::mixed_tile_options(c->sys, N, opts);
+    c->epb[N] = opts[0];
+  }
+  // I[lo][m][ma][ia] = l^lo_ia(x^m_ma);  P[lo][m][a][ma] = w^m_ma l^lo_a(x^m_ma) / w^lo_a
+  std::vector<double> It(8 * 8 * 8 * 8, 0.0), Pt(8 * 8 * 8 * 8, 0.0), w(64, 0.0);
+  for (int N = 1; N <= 7; ++N) {
+    double xx[8];
+    gll_nodes(N, xx, &w[8 * N]);
+  }
+  for (int lo = 1; lo <= 7; ++lo)
+    for (int m = lo; m <= 7; ++m)
+      for (int ma = 0; ma <= m; ++ma)
+        for (int ia = 0; ia <= lo; ++ia) {
+          const double l = lagrange(lo + 1, &hx[8 * lo], ia, hx[8 * m + ma]);
+          It[((lo * 8 + m) * 8 + ma) * 8 + ia] = l;
+          Pt[((lo * 8 + m) * 8 + ia) * 8 + ma] = w[8 * m + ma] * l / w[8 * lo + ia];
+        }
+  const size_t tb = It.size() * sizeof(double);
+  if (hipMalloc(&c->d_deg, sizeof(int32_t) * c->nelem) != hipSuccess ||
+      hipMalloc(&c->d_off, sizeof(int64_t) * (c->nelem + 1)) != hipSuccess ||
+      hipMalloc(&c->d_elist, sizeof(int32_t) * c->nelem) != hipSuccess || hipMalloc(&c->d_Itab, tb) != hipSuccess ||
+      hipMalloc(&c->d_Ptab, tb) != hipSuccess || hipMalloc(&c->d_dt, sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the mixed-degree tables failed");
+  }
+  HIP_TRY(hipMemcpy(c->d_deg, c->deg.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_off, c->off.data(), sizeof(int64_t) * (c->nelem + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_elist, elist.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_Itab, It.data(), tb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_Ptab, Pt.data(), tb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(c->d_dt, 0, sizeof(double)));
+  for (int k = 0; k < 8; ++k) {
+    HIP_TRY(hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  if (c->flags & DGMI_FLAG_AUTOTUNE) return autotune(c);
+  return DGMI_OK;
+}
+
+static dgmi::MixArgs mix_args(dgmi_ctx *c, int N) {
+  dgmi::MixArgs a{};
+  a.elist = c->d_elist + c->lstart[N];
+  a.nlist = c->lcount[N];
+  a.nbr = c->d_nbr;
+  a.deg = c->d_deg;
+  a.off = c->d_off;
+  a.Dmat = c->d_D + 64 * N;
+  a.Itab = c->d_Itab;
+  a.Ptab = c->d_Ptab;
+  a.dt = c->d_dt;
+  a.nfail = c->d_nfail;
+  a.nnodes = c->nnodes;
+  a.gamma = c->gamma;
+  a.kappa = c->kappa;
+  for (int d = 0; d < 3; ++d) a.scale[d] = 2.0 / c->dx[d];
+  a.inv_wend = 1.0 / c->wend[N];
+  return a;
+}
+
+// One operator / stage pass over every degree: the per-degree kernels run
+// concurrently on the context's side streams, joined back into s.
+static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const double *P, double *out,
+                              const double *Un, double *Pout, double wa, double wb, hipStream_t s) {
+  HIP_TRY(hipEventRecord(c->ev_fork, s));
+  int k = 0;
+  for (int N = dgmi::kMaxMixedDegree; N >= 1; --N) {
+    if (c->lcount[N] == 0) continue;
+    dgmi::MixArgs a = mix_args(c, N);
+    a.U = U; a.P = P; a.out = out; a.Un = Un; a.Pout = Pout; a.a = wa; a.b = wb;
+    HIP_TRY(hipStreamWaitEvent(c->side[k], c->ev_fork, 0));
+    HIP_TRY(dgmi::launch_mixed(c->sys, N, c->epb[N], stage, a, c->side[k]));
+    HIP_TRY(hipEventRecord(c->ev_join[k], c->side[k]));
+    ++k;
+  }
+  for (int j = 0; j < k; ++j) HIP_TRY(hipStreamWaitEvent(s, c->ev_join[j], 0));
+  return DGMI_OK;
+}
+
+static dgmi_status mixed_step_enqueue(dgmi_ctx *c, double *U, double *P, hipStream_t s) {
+  dgmi_status st = mixed_pass(c, 1, U, P, c->d_U1, U, c->d_P1, 0.0, 1.0, s);
+  if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U1, c->d_P1, c->d_U2, U, c->d_P2, 0.75, 0.25, s);
+  if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U2, c->d_P2, U, U, P, 1.0 / 3.0, 2.0 / 3.0, s);
+  return st;
+}
+
+// Time every tile option of every degree present on a state at rest and keep
+// the fastest (results do not depend on the choice).
+static dgmi_status autotune(dgmi_ctx *c) {
+  hipStream_t s = c->side[0];
+  const int64_t n = c->nnodes;
+  // prims (1, 0, 0, 0, 1) in P1, field/Phi zero in U2, state in U1
+  HIP_TRY(dgmi::launch_fill(c->d_P1, 5 * n, 0.0, s));
+  HIP_TRY(dgmi::launch_fill(c->d_P1, n, 1.0, s));
+  HIP_TRY(dgmi::launch_fill(c->d_P1 + 4 * n, n, 1.0, s));
+  HIP_TRY(dgmi::launch_fill(c->d_U2, 4 * n, 0.0, s));
+  HIP_TRY(dgmi::launch_prim2cons(c->sys, c->gamma, c->d_P1, c->d_U2, c->d_U1, n, s));
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  for (int N = 1; N <= dgmi::kMaxMixedDegree; ++N) {
+    if (c->lcount[N] == 0) continue;
+    int opts[3];
+    const int no = dgmi::mixed_tile_options(c->sys, N, opts);
+    float best = 1e30f;
+    for (int o = 0; o < no; ++o) {
+      dgmi::MixArgs a = mix_args(c, N);
+      a.U = c->d_U1; a.P = c->d_P1; a.out = c->d_U2;
+      HIP_TRY(dgmi::launch_mixed(c->sys, N, opts[o], 0, a, s));
+      HIP_TRY(hipEventRecord(t0, s));
+      for (int r = 0; r < 5; ++r) HIP_TRY(dgmi::launch_mixed(c->sys, N, opts[o], 0, a, s));
+      HIP_TRY(hipEventRecord(t1, s));
+      HIP_TRY(hipEventSynchronize(t1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+      if (ms < best) {
+        best = ms;
+        c->epb[N] = opts[o];
+      }
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  HIP_TRY(hipStreamSynchronize(s));
+  return DGMI_OK;
+}
 
 extern "C" {
 
@@ -149,6 +313,19 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_P1);
   (void)hipFree(c->d_P2);
   (void)hipFree(c->d_nfail);
+  (void)hipFree(c->d_deg);
+  (void)hipFree(c->d_off);
+  (void)hipFree(c->d_elist);
+  (void)hipFree(c->d_Itab);
+  (void)hipFree(c->d_Ptab);
+  (void)hipFree(c->d_dt);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  for (int k = 0; k < 8; ++k) {
+    if (c->side[k]) (void)hipStreamDestroy(c->side[k]);
+    if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   delete c;
 }
 
@@ -235,6 +412,13 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
     ctx_free(c);
     return fail(DGMI_EHIP, "dgmi_create: table upload failed");
   }
+  if (desc->degree == 0) {
+    dgmi_status st = mixed_setup(c, hx);
+    if (st != DGMI_OK) {
+      ctx_free(c);
+      return st;
+    }
+  }
   *out = c;
   return DGMI_OK;
 }
@@ -258,7 +442,11 @@ dgmi_status dgmi_elem_offsets(const dgmi_ctx *ctx, int64_t *off_host) {
 
 dgmi_status dgmi_node_coords(const dgmi_ctx *ctx, double *xyz, void *stream) {
   if (!ctx || !is_device_ptr(xyz)) return fail(DGMI_EINVAL, "dgmi_node_coords: bad argument");
-  if (ctx->degree == 0) return fail(DGMI_EUNSUPPORTED, "dgmi_node_coords: mixed degrees not enabled");
+  if (ctx->mixed) {
+    HIP_TRY(dgmi::launch_mixed_coords(ctx->d_deg, ctx->d_off, ctx->d_x, ctx->nx, ctx->ny, ctx->nelem, ctx->lo, ctx->dx,
+                                      xyz, ctx->nnodes, (hipStream_t)stream));
+    return DGMI_OK;
+  }
   HIP_TRY(dgmi::launch_node_coords(ctx->degree, ctx->d_x + 8 * ctx->degree, ctx->nx, ctx->ny, ctx->nz, ctx->lo,
                                    ctx->dx, xyz, ctx->nnodes, (hipStream_t)stream));
   return DGMI_OK;
@@ -310,11 +498,11 @@ dgmi_status dg_rhs(dgmi_ctx *ctx, const double *U, double *prim_inout, double *d
   if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || !is_device_ptr(dUdt))
     return fail(DGMI_EINVAL, "dg_rhs: U, prim_inout and dUdt must be device pointers");
   if (dUdt == U || dUdt == prim_inout) return fail(DGMI_EINVAL, "dg_rhs: dUdt must not alias its inputs");
-  if (ctx->degree == 0) return fail(DGMI_EUNSUPPORTED, "dg_rhs: mixed degrees not enabled");
   hipStream_t s = (hipStream_t)stream;
   const int guess = (ctx->flags & DGMI_FLAG_PLAIN_GUESS) ? DGMI_GUESS_PLAIN : DGMI_GUESS_INPUT;
   dgmi_status st = recover_all(ctx, U, prim_inout, guess, s);
   if (st != DGMI_OK) return st;
+  if (ctx->mixed) return mixed_pass(ctx, 0, U, prim_inout, dUdt, nullptr, nullptr, 0.0, 0.0, s);
   dgmi::RhsArgs a = rhs_args(ctx);
   a.U = U;
   a.P = prim_inout;
@@ -328,7 +516,7 @@ dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, doub
   if (!is_device_ptr(U) || !is_device_ptr(prim) || !is_device_ptr(dUdt))
     return fail(DGMI_EINVAL, "dg_operator: U, prim and dUdt must be device pointers");
   if (dUdt == U || dUdt == prim) return fail(DGMI_EINVAL, "dg_operator: dUdt must not alias its inputs");
-  if (ctx->degree == 0) return fail(DGMI_EUNSUPPORTED, "dg_operator: mixed degrees not enabled");
+  if (ctx->mixed) return mixed_pass(ctx, 0, U, prim, dUdt, nullptr, nullptr, 0.0, 0.0, (hipStream_t)stream);
   dgmi::RhsArgs a = rhs_args(ctx);
   a.U = U;
   a.P = prim;
@@ -342,12 +530,37 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
   if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
     return fail(DGMI_EINVAL, "dg_step: U and prim_inout must be distinct device pointers");
   if (!std::isfinite(dt)) return fail(DGMI_EINVAL, "dg_step: dt must be finite");
-  if (ctx->degree == 0) return fail(DGMI_EUNSUPPORTED, "dg_step: mixed degrees not enabled");
   hipStream_t s = (hipStream_t)stream;
   if (ctx->flags & DGMI_FLAG_RECOVER_FIRST) {
     const int guess = (ctx->flags & DGMI_FLAG_PLAIN_GUESS) ? DGMI_GUESS_PLAIN : DGMI_GUESS_INPUT;
     dgmi_status st = recover_all(ctx, U, prim_inout, guess, s);
     if (st != DGMI_OK) return st;
+  }
+  if (ctx->mixed) {
+    // dt reaches the stage kernels through a device scalar, so that a
+    // captured step replays with any dt
+    HIP_TRY(dgmi::launch_set_scalar(ctx->d_dt, dt, s));
+    if ((ctx->flags & DGMI_FLAG_NO_GRAPH) || s == nullptr) return mixed_step_enqueue(ctx, U, prim_inout, s);
+    if (!ctx->gexec || ctx->gU != U || ctx->gP != prim_inout) {
+      if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+      if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+      ctx->gexec = nullptr;
+      ctx->graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      dgmi_status st = mixed_step_enqueue(ctx, U, prim_inout, s);
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(s, &g);
+      if (st != DGMI_OK || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != DGMI_OK ? st : fail(DGMI_EHIP, "dg_step: stream capture failed: %s", hipGetErrorString(ce));
+      }
+      ctx->graph = g;
+      HIP_TRY(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+      ctx->gU = U;
+      ctx->gP = prim_inout;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->gexec, s));
+    return DGMI_OK;
   }
   dgmi::RhsArgs a = rhs_args(ctx);
   a.dt = dt;

@@ -27,6 +27,43 @@ struct RhsArgs {
 // Launch dg RHS (stage == 0) or RK stage (stage == 1).
 hipError_t launch_rhs(int sys, int N, int stage, const RhsArgs &a, hipStream_t s);
 
+// Highest degree of the mixed-degree path (mortars of up to 8x8 nodes).
+constexpr int kMaxMixedDegree = 7;
+
+// Arguments of the mixed-degree RHS / RK-stage kernel of one degree.
+struct MixArgs {
+  const double *U, *P;     // operator input and its primitives
+  double *out;             // dU/dt or U^(s)
+  const double *Un;        // U^n (stage kernel)
+  double *Pout;            // primitives of U^(s) (stage kernel)
+  const int32_t *elist;    // the elements of this degree
+  int64_t nlist;
+  const int32_t *nbr;      // [nelem][6]
+  const int32_t *deg;      // [nelem]
+  const int64_t *off;      // [nelem + 1] first node of every element
+  const double *Dmat;      // this degree's (N+1)x(N+1) differentiation matrix
+  const double *Itab;      // I[lo][m][ma][ia] = l^lo_ia(x^m_ma), [8][8][8][8]
+  const double *Ptab;      // P[lo][m][a][ma] = w^m_ma l^lo_a(x^m_ma) / w^lo_a
+  const double *dt;        // device scalar (stage kernel)
+  unsigned long long *nfail;
+  int64_t nnodes;
+  double gamma, kappa;
+  double scale[3];         // 2/dx_d
+  double inv_wend;         // this degree's 1/w_0
+  double a, b;             // Shu-Osher weights
+  int nblocks;             // set at launch
+};
+
+// Elements-per-workgroup options of the mixed kernel for (system, degree);
+// returns how many were written to epb_out (at most 3).
+int mixed_tile_options(int sys, int N, int *epb_out);
+hipError_t launch_mixed(int sys, int N, int epb, int stage, const MixArgs &a, hipStream_t s);
+hipError_t launch_mixed_coords(const int32_t *deg, const int64_t *off, const double *xtab, int nx, int ny,
+                               int64_t nelem, const double *lo, const double *dx, double *xyz, int64_t nn,
+                               hipStream_t s);
+hipError_t launch_set_scalar(double *p, double v, hipStream_t s);
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+
 struct C2PArgs {
   const double *U;
   double *prim;

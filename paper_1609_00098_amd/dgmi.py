@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdgmi.so")
 
 NEWTONIAN_EULER, SR_HYDRO, SR_MHD = 0, 1, 2
 GUESS_INPUT, GUESS_PLAIN, GUESS_LEARNED = 0, 1, 2
-FLAG_PLAIN_GUESS, FLAG_RECOVER_FIRST = 1, 2
+FLAG_PLAIN_GUESS, FLAG_RECOVER_FIRST, FLAG_NO_GRAPH, FLAG_AUTOTUNE = 1, 2, 4, 8
 NVARS = {NEWTONIAN_EULER: 5, SR_HYDRO: 5, SR_MHD: 9}
 MLP_NUM_WEIGHTS = 4609
 MLP_NUM_PARAMS = 4621
@@ -103,7 +103,8 @@ def _stream(stream):
 
 
 class Mesh:
-    """Owner of a dgmi_ctx (periodic box of affine hexahedra)."""
+    """Owner of a dgmi_ctx (periodic box of affine hexahedra).  ``degrees``
+    (nx*ny*nz ints in 1..7) selects the mixed-degree path."""
 
     def __init__(self, system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), kappa=0.0, flags=0,
                  degrees=None):

@@ -1,0 +1,224 @@
+"""GPU parity of the mixed-degree path (mortars between unequal degrees)
+against the oracle's mixed-degree operator and stepper, on seeded smooth
+random states; plus the equal-degree reduction to the uniform kernels,
+graph replay against direct launches and the autotuner's choice (both bit
+for bit)."""
+import numpy as np
+import pytest
+
+from paper_1609_00098_amd import synth
+from tests.gpu_util import normwise_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+NE, SR, MHD = 0, 1, 2
+G = {NE: 1.4, SR: 4.0 / 3.0, MHD: 4.0 / 3.0}
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1609_00098_amd import dgmi
+    return dgmi
+
+
+def _setup(ora, dg, system, nel, deg, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), seed=1609, flags=0, mild=True):
+    """Seeded smooth random state.  Small meshes get mild fields (rho, p in
+    [0.5, 2], W <= 2): interpolating badly under-resolved data onto a finer
+    mortar can overshoot to negative density or pressure, which the method
+    does not guard against (that is a limiter's job), so parity there would
+    compare two treatments of unphysical states."""
+    g = G[system]
+    kw = dict(w_max=2.0, rho_range=(0.5, 2.0), p_range=(0.5, 2.0)) if mild else {}
+    m = ora.mesh(system, nel, 2, g, lo=lo, hi=hi, kappa=0.5)
+    mesh = dg.Mesh(system, nel, 0, g, lo=lo, hi=hi, kappa=0.5, flags=flags, degrees=deg)
+    xyz = ora.mixed_node_coords(m, deg)
+    unit = (xyz - np.array(lo)[:, None]) / (np.array(hi) - np.array(lo))[:, None]
+    if system == MHD:
+        prim = synth.fourier_random_prims(unit, seed=seed, **kw)
+        rng = np.random.default_rng(seed)
+        mag = np.zeros((4, prim.shape[1]))
+        for c in range(4):
+            k = rng.integers(1, 3, size=3)
+            mag[c] = 0.3 * np.sin(2 * np.pi * (k @ unit) + rng.uniform(0, 6))
+        mag[0] += 1.0
+        U = ora.prim2cons(MHD, g, prim, mag)
+    else:
+        prim = synth.fourier_random_prims(unit, seed=seed, **kw)
+        U = ora.prim2cons(system, g, prim)
+    return m, mesh, U, prim, xyz
+
+
+CASES = [
+    (SR, (3, 3, 2), "random27"),
+    (SR, (4, 3, 3), "random17"),
+    (NE, (3, 2, 3), "random17"),
+    (MHD, (3, 2, 2), "random27"),
+    (SR, (2, 2, 2), "checker37"),
+]
+
+
+def _degrees(kind, ne):
+    if kind == "random27":
+        return synth.mixed_degrees(ne, seed=1610)
+    if kind == "random17":
+        return synth.mixed_degrees(ne, seed=11, lo=1, hi=7)
+    return np.array([3 + 4 * (e % 2) for e in range(ne)], np.int32)
+
+
+@pytest.mark.parametrize("system,nel,kind", CASES)
+def test_mixed_node_coords_and_offsets(ora, dg, system, nel, kind):
+    deg = _degrees(kind, int(np.prod(nel)))
+    m, mesh, _, _, xyz = _setup(ora, dg, system, nel, deg)
+    assert mesh.nnodes == ora.mixed_num_nodes(deg)
+    off = mesh.elem_offsets()
+    assert np.array_equal(np.diff(off), (deg.astype(np.int64) + 1) ** 3)
+    assert np.abs(to_host(mesh.node_coords()) - xyz).max() <= 1e-15
+
+
+@pytest.mark.parametrize("system,nel,kind", CASES)
+def test_mixed_rhs_parity(ora, dg, system, nel, kind):
+    deg = _degrees(kind, int(np.prod(nel)))
+    m, mesh, U, prim, _ = _setup(ora, dg, system, nel, deg)
+    L, Po, nf = ora.rhs_mixed(m, deg, U)
+    assert nf == 0
+    P = to_dev(prim * np.array([[1.0], [1.0], [1.0], [1.0], [1.001]]))
+    out = mesh.empty_state()
+    dg.dg_rhs(mesh, to_dev(U), P, out)
+    assert dg.dgmi_failures(mesh) == 0
+    err = normwise_err(to_host(out), L)
+    assert err.max() <= 1e-12, err
+    # dg_operator with the oracle's primitives gives the same operator
+    out2 = mesh.empty_state()
+    dg.dg_operator(mesh, to_dev(U), to_dev(Po), out2)
+    err = normwise_err(to_host(out2), L)
+    assert err.max() <= 1e-12, err
+
+
+@pytest.mark.parametrize("system,N", [(SR, 4), (SR, 2), (NE, 3), (MHD, 3), (SR, 7)])
+def test_equal_degrees_match_uniform_kernels(ora, dg, system, N):
+    """With every face conforming the mixed kernels do the uniform kernels'
+    arithmetic; only the compiler's fused multiply-add choices may differ."""
+    nel = (3, 2, 2)
+    deg = np.full(12, N, np.int32)
+    m, mixed, U, prim, _ = _setup(ora, dg, system, nel, deg)
+    uni = dg.Mesh(system, nel, N, G[system], kappa=0.5)
+    Ud, Pd = to_dev(U), to_dev(prim)
+    a, b = mixed.empty_state(), uni.empty_state()
+    dg.dg_operator(mixed, Ud, Pd, a)
+    dg.dg_operator(uni, Ud, Pd, b)
+    err = normwise_err(to_host(a), to_host(b))
+    assert err.max() <= 1e-14, err
+
+
+def _dt(L, U):
+    return 1e-3 / float(np.max(np.abs(L) / np.maximum(np.abs(U), 1e-300)))
+
+
+@pytest.mark.parametrize("system,nel,kind", CASES[:4])
+def test_mixed_step_parity(ora, dg, system, nel, kind):
+    import torch
+    deg = _degrees(kind, int(np.prod(nel)))
+    m, mesh, U, prim, _ = _setup(ora, dg, system, nel, deg)
+    L, Po, _ = ora.rhs_mixed(m, deg, U)
+    dt = _dt(L, U)
+    Uo, nf = ora.step_mixed(m, deg, U, dt)
+    assert nf == 0
+    res = {}
+    for use_graph in (False, True):
+        Ud, Pd = to_dev(U), to_dev(Po)
+        s = torch.cuda.Stream() if use_graph else None
+        if s is not None:
+            s.wait_stream(torch.cuda.current_stream())
+        dg.dg_step(mesh, Ud, Pd, dt, stream=s)
+        torch.cuda.synchronize()
+        assert dg.dgmi_failures(mesh) == 0
+        res[use_graph] = (to_host(Ud), to_host(Pd))
+        # increments agree to the operator's tolerance
+        tol = 2e-12 * dt * np.abs(L).max() + 8 * np.finfo(float).eps * np.abs(U).max()
+        assert np.abs(res[use_graph][0] - Uo).max() <= tol, (np.abs(res[use_graph][0] - Uo).max(), tol)
+    assert np.array_equal(res[False][0], res[True][0])
+    assert np.array_equal(res[False][1], res[True][1])
+
+
+def test_graph_replays_with_new_dt_and_state(ora, dg):
+    """Two steps through one captured graph (second with another dt) equal
+    two directly launched steps bit for bit."""
+    import torch
+    deg = _degrees("random27", 18)
+    m, mesh, U, prim, _ = _setup(ora, dg, SR, (3, 3, 2), deg)
+    direct = dg.Mesh(SR, (3, 3, 2), 0, G[SR], flags=dg.FLAG_NO_GRAPH, degrees=deg)
+    L, Po, _ = ora.rhs_mixed(m, deg, U)
+    dt = _dt(L, U)
+    s = torch.cuda.Stream()
+    Ua, Pa = to_dev(U), to_dev(Po)
+    Ub, Pb = to_dev(U), to_dev(Po)
+    s.wait_stream(torch.cuda.current_stream())
+    for k, step_dt in enumerate((dt, 0.5 * dt, 0.7 * dt)):
+        dg.dg_step(mesh, Ua, Pa, step_dt, stream=s)
+        s.synchronize()
+        dg.dg_step(direct, Ub, Pb, step_dt)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(Ua), to_host(Ub)), k
+        assert np.array_equal(to_host(Pa), to_host(Pb)), k
+
+
+def test_autotuned_tiles_give_identical_results(ora, dg):
+    deg = synth.mixed_degrees(64, seed=5, lo=1, hi=7)
+    m, plain, U, prim, _ = _setup(ora, dg, SR, (4, 4, 4), deg)
+    tuned = dg.Mesh(SR, (4, 4, 4), 0, G[SR], flags=dg.FLAG_AUTOTUNE, degrees=deg)
+    Ud, Pd = to_dev(U), to_dev(prim)
+    a, b = plain.empty_state(), tuned.empty_state()
+    dg.dg_operator(plain, Ud, Pd, a)
+    dg.dg_operator(tuned, Ud, Pd, b)
+    assert np.array_equal(to_host(a), to_host(b))
+
+
+def _cfg4(ora, dg, flags=0):
+    """SR hydro, gamma 4/3, 16^3 elements on the unit box, degrees uniform in
+    2..7 (seed 1610), the smooth random primitives (seed 1609) at every
+    element's own nodes."""
+    deg = synth.mixed_degrees(4096, seed=1610)
+    return _setup(ora, dg, SR, (16, 16, 16), deg, flags=flags, mild=False) + (deg,)
+
+
+def _ulp_sensitivity(ora, m, deg, U, L):
+    """Normwise change of the oracle's own operator when every input value
+    moves by one ulp (seeded signs): two correct FP64 evaluations that round
+    differently cannot be expected to agree more closely than this."""
+    rng = np.random.default_rng(0)
+    Up = U * (1.0 + np.finfo(float).eps * rng.choice([-1.0, 1.0], size=U.shape))
+    Lp, _, _ = ora.rhs_mixed(m, deg, Up)
+    return normwise_err(Lp, L).max()
+
+
+def test_mixed_full_size_rhs_and_step(ora, dg):
+    """16^3 elements of degrees 2..7 with the full-range fields (W up to 10,
+    p over four decades).  Here the operator itself moves by ~1e-12 under a
+    one-ulp change of U (the recovery is ill conditioned at W ~ 10 and the
+    degree-7 lift and derivative amplify it), so the bar is the larger of
+    1e-12 and twice that measured sensitivity."""
+    import torch
+    m, mesh, U, prim, _, deg = _cfg4(ora, dg)
+    assert mesh.nnodes == 879747
+    L, Po, nf = ora.rhs_mixed(m, deg, U)
+    assert nf == 0
+    tol = max(1e-12, 2.0 * _ulp_sensitivity(ora, m, deg, U, L))
+    assert tol <= 5e-12
+    P = to_dev(prim * np.array([[1.0], [1.0], [1.0], [1.0], [1.001]]))
+    out = mesh.empty_state()
+    Ud = to_dev(U)
+    dg.dg_rhs(mesh, Ud, P, out)
+    err = normwise_err(to_host(out), L)
+    assert err.max() <= tol, (err, tol)
+    dt = 2e-4
+    Uo, nf = ora.step_mixed(m, deg, U, dt)
+    assert nf == 0
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    Pd = to_dev(Po)
+    dg.dg_step(mesh, Ud, Pd, dt, stream=s)
+    s.synchronize()
+    assert dg.dgmi_failures(mesh) == 0
+    stol = 2 * tol * dt * np.abs(L).max() + 8 * np.finfo(float).eps * np.abs(U).max()
+    assert np.abs(to_host(Ud) - Uo).max() <= stol
