@@ -101,7 +101,9 @@ struct MixCfg {
   static constexpr int NF = NP * NP;
   static constexpr int NV = SysTraits<SYS>::nv;
   static constexpr int NS = Interp<SYS>::ns;
-  static constexpr int THREADS = ((EPB * NPE + 63) / 64) * 64;
+  // at least 256 threads: the mortar phase has up to 6 x 64 tasks per
+  // element, far more than a low-degree element has nodes
+  static constexpr int THREADS = ((EPB * NPE + 63) / 64) * 64 > 256 ? ((EPB * NPE + 63) / 64) * 64 : 256;
   static constexpr int NFACE = EPB * 6;
   static constexpr int MAXM = 64;  // mortar nodes of a degree-7 face
   static constexpr bool LOWER = N < kMaxMixedDegree;  // can have higher-degree neighbours
