@@ -160,7 +160,9 @@ dgmi_status con2prim(int32_t system, double gamma, const double *U, double *prim
  * SiLU activations in FP32 that proposes the recovery's initial pressure
  * (p0 = D exp(y), y the predicted ln(p/D)).  The FP64 bracketed Newton
  * iteration still decides every result.  Inputs are the raw features
- *   x = [ln D, ln(tau/D), ln(1 + |S|/D), ln(1 + B^2/D), S.B/(|S||B| + tiny)]
+ *   x = [ln(tau/D), ln(1 + |S|/D), ln(1 + B^2/D), S.B/(|S||B| + tiny), ln(f(0)/D)]
+ * with f the recovery's pressure function (f(0) = (gamma-1) rho eps at zero
+ * pressure, the thermal energy left after the kinetic and magnetic parts),
  * in x[5][batch] (float32, device), normalised inside the library with the
  * stored feature means/deviations; targets t[batch] are raw ln(p/D).
  * Parameter vector: 4609 weights W1[64][5] b1[64] W2[64][64] b2[64] W3[64] b3
