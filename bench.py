@@ -34,9 +34,9 @@ NEL = (32, 32, 32)
 DEG = 4
 NV = 5
 # algorithmic bytes per node of each kernel (FP64): the operator reads U and
-# the primitives and writes dU/dt; the recovery reads U and the pressure seed
-# and writes the primitives.
-OP_BYTES_PER_NODE = 8 * (NV + 5 + NV)
+# the pressure (the other primitives follow from them) and writes dU/dt; the
+# recovery reads U and the pressure seed and writes the five primitives.
+OP_BYTES_PER_NODE = 8 * (NV + 1 + NV)
 C2P_BYTES_PER_NODE = 8 * (NV + 1 + 5)
 
 

@@ -573,6 +573,7 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
   HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, a, s));
   // stage 3: U <- 1/3 U + 2/3 (U2 + dt L(U2))  (each thread reads U^n at its own node before writing it)
   a.U = ctx->d_U2; a.P = ctx->d_P2; a.out = U; a.Pout = prim_inout; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
+  a.full_prims = 1;
   HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, a, s));
   return DGMI_OK;
 }

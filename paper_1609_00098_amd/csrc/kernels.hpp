@@ -21,6 +21,7 @@ struct RhsArgs {
   double inv_wend;     // 1/w_0 = N(N+1)/2
   double a, b, dt;     // Shu-Osher stage: out = a Un + b (U + dt L(U))
   int nx, ny, nz;      // elements per direction
+  int full_prims;      // stage kernel: write all five primitive rows (else NE/SR write only p)
   int nblocks;         // logical blocks (set at launch)
 };
 

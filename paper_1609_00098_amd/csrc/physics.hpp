@@ -236,6 +236,37 @@ DG_HD double step_rcp(double x) {
 #endif
 }
 
+// Primitives of a conserved state whose pressure is known.  NE: from U alone
+// (p is recomputed, the argument ignored).  SR: closed form with
+// z = tau + D + p: v = S / z, rho = D sqrt(1 - v^2), sqrt(1 - v^2) formed as
+// sqrt((z - |S|)(z + |S|)) / z.  (MHD needs the root of its cubic and is not
+// handled here.)  The recovery returns exactly these values for its final
+// pressure, so a kernel that stores only p can rebuild the rest.
+template <int SYS>
+DG_HD Prim prims_at_pressure(const double *u, double g, double p) {
+  Prim P;
+  if (SYS == kNE) {
+    const double irho = 1.0 / u[0];
+    P.rho = u[0];
+    P.v[0] = u[1] * irho;
+    P.v[1] = u[2] * irho;
+    P.v[2] = u[3] * irho;
+    const double m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    P.p = (g - 1.0) * (u[4] - 0.5 * m2 * irho);
+    return P;
+  }
+  const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+  const double Sabs = sqrt(S2);
+  const double z = u[4] + u[0] + p;
+  const double iz = 1.0 / z;
+  P.v[0] = u[1] * iz;
+  P.v[1] = u[2] * iz;
+  P.v[2] = u[3] * iz;
+  P.rho = u[0] * (sqrt((z - Sabs) * (z + Sabs)) * iz);
+  P.p = p;
+  return P;
+}
+
 struct C2PResult {
   Prim P;
   int iters;
@@ -300,13 +331,7 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
   const double D = u[0];
   const double tau = u[4];
   if (SYS == kNE) {
-    const double irho = 1.0 / D;
-    R.P.rho = D;
-    R.P.v[0] = u[1] * irho;
-    R.P.v[1] = u[2] * irho;
-    R.P.v[2] = u[3] * irho;
-    const double m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
-    R.P.p = (g - 1.0) * (tau - 0.5 * m2 * irho);
+    R.P = prims_at_pressure<kNE>(u, g, 0.0);
     R.ok = (D > 0.0) && (R.P.p > 0.0);
     return R;
   }
@@ -425,17 +450,16 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     last_small = newton && step <= 1e-9 * p;
   }
   // primitives at the final pressure
+  if (SYS == kSR) {
+    R.P = prims_at_pressure<kSR>(u, g, p);
+    const double iz = 1.0 / (tau + D + p);
+    const double v2 = S2 * iz * iz;
+    R.ok = conv && (v2 < 1.0) && (p > 0.0) && (R.P.rho > 0.0);
+    return R;
+  }
   double v2;
   double rho_w = 0.0;  // sqrt(1 - v^2)
-  if (SYS == kSR) {
-    z = tau + D + p;
-    const double iz = 1.0 / z;
-    R.P.v[0] = S0 * iz;
-    R.P.v[1] = S1 * iz;
-    R.P.v[2] = S2c * iz;
-    v2 = S2 * iz * iz;
-    rho_w = sqrt((z - Sabs) * (z + Sabs)) * iz;
-  } else {
+  {
     const double e = E + p + 0.5 * BB;
     const double x0 = (em_prev > 0.0) ? fmax(em_prev + (e - e_prev), 2.0 * e / 3.0 + 1e-3 * e) : e;
     em = cubic_top_root(e, dcub, fmin(x0, e));

@@ -49,16 +49,23 @@ struct RhsCfg {
   static constexpr int SPD = EPB * 6 * NF;
 };
 
+// A node's conserved state and primitives.  SRMHD reads all five primitive
+// rows; SR reads only the pressure and NE no primitive at all: the rest
+// follows from U (and p) in closed form, exactly as the recovery returned it.
 template <int SYS>
-__device__ __forceinline__ void load_node(const double *U, const double *Pr, int64_t nn, int64_t q, double *u,
-                                          Prim &P) {
+__device__ __forceinline__ void load_node(const double *U, const double *Pr, int64_t nn, int64_t q, double g,
+                                          double *u, Prim &P) {
 #pragma unroll
   for (int v = 0; v < SysTraits<SYS>::nv; ++v) u[v] = U[v * nn + q];
-  P.rho = Pr[q];
-  P.v[0] = Pr[nn + q];
-  P.v[1] = Pr[2 * nn + q];
-  P.v[2] = Pr[3 * nn + q];
-  P.p = Pr[4 * nn + q];
+  if (SYS == kMHD) {
+    P.rho = Pr[q];
+    P.v[0] = Pr[nn + q];
+    P.v[1] = Pr[2 * nn + q];
+    P.v[2] = Pr[3 * nn + q];
+    P.p = Pr[4 * nn + q];
+  } else {
+    P = prims_at_pressure<SYS>(u, g, SYS == kSR ? Pr[4 * nn + q] : 0.0);
+  }
 }
 
 template <int SYS, int N, int STAGE>
@@ -93,7 +100,7 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   if (active) {
-    load_node<SYS>(A.U, A.P, nn, q, u, P);
+    load_node<SYS>(A.U, A.P, nn, q, A.gamma, u, P);
     if (SYS == kMHD) acc[8] = -A.kappa * u[8];
 #pragma unroll
     for (int v = 0; v < NV; ++v) sown[(le * NV + v) * NPE + a] = u[v];
@@ -162,7 +169,7 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
     const int ai = c0 + NP * (c1 + NP * c2);
     double ue[NV], Fe[NV];
     Prim Pe;
-    load_node<SYS>(A.U, A.P, nn, en * NPE + n0 + NP * (n1 + NP * n2), ue, Pe);
+    load_node<SYS>(A.U, A.P, nn, en * NPE + n0 + NP * (n1 + NP * n2), A.gamma, ue, Pe);
     flux_normal<SYS>(d, ue, Pe, Fe);
     const double *own = sown + fle * NV * NPE + ai;
     double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
@@ -204,10 +211,14 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
     A.out[v * nn + q] = us[v];
   }
   const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100);
-  A.Pout[q] = R.P.rho;
-  A.Pout[nn + q] = R.P.v[0];
-  A.Pout[2 * nn + q] = R.P.v[1];
-  A.Pout[3 * nn + q] = R.P.v[2];
+  // intermediate stages of NE / SR keep only the pressure (the next stage
+  // rebuilds the rest); SRMHD and the caller's buffers get all five rows
+  if (SYS == kMHD || A.full_prims) {
+    A.Pout[q] = R.P.rho;
+    A.Pout[nn + q] = R.P.v[0];
+    A.Pout[2 * nn + q] = R.P.v[1];
+    A.Pout[3 * nn + q] = R.P.v[2];
+  }
   A.Pout[4 * nn + q] = R.P.p;
   if (!R.ok) atomicAdd(A.nfail, 1ull);
 }
