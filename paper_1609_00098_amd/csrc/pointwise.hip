@@ -12,20 +12,35 @@ __global__ void __launch_bounds__(256) con2prim_kernel(const C2PArgs A) {
   const int64_t n = A.n;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   unsigned long long nbad = 0;
-  MlpSmem *sm = nullptr;
+  MlpSeedShared *sm = nullptr;
+  MlpSeedWave *ws = nullptr;
   if (GUESS == 2) {
-    __shared__ MlpSmem smem;
+    __shared__ MlpSeedShared smem;
+    __shared__ MlpSeedWave wsm[4];
     sm = &smem;
-    mlp_load_smem(A.mlp, sm);
+    ws = &wsm[threadIdx.x >> 6];
+    mlp_seed_load_shared(A.mlp, sm);
     __syncthreads();
   }
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+  // wave-uniform trip count (the learned seed runs all 64 lanes together)
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  for (int64_t base = start; base < n; base += stride) {
+    const int64_t q = base + (threadIdx.x & 63);
+    const bool valid = q < n;
     double u[NV];
+    if (valid) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = A.U[v * n + q];
+      for (int v = 0; v < NV; ++v) u[v] = A.U[v * n + q];
+    } else {  // a state at rest keeps idle lanes of the seed network finite
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = 0.0;
+      u[0] = 1.0;
+      u[4] = 1.0;
+    }
     double p0 = -1.0;
-    if (GUESS == 0) p0 = A.prim[4 * n + q];
-    if (GUESS == 2) p0 = mlp_guess<SYS>(sm, u, A.gamma);
+    if (GUESS == 0 && valid) p0 = A.prim[4 * n + q];
+    if (GUESS == 2) p0 = mlp_seed_wave<SYS>(sm, ws, u, A.gamma);
+    if (!valid) continue;
     const C2PResult R = recover<SYS>(u, A.gamma, p0, A.tol, 100);
     A.prim[q] = R.P.rho;
     A.prim[n + q] = R.P.v[0];

@@ -140,3 +140,30 @@ def test_trained_guess_cuts_iterations_at_equal_residual(ora, dg):
         assert r.max() <= 1e-10
         res[guess] = to_host(it).astype(np.float64).mean()
     assert res[dg.GUESS_LEARNED] < 0.8 * res[dg.GUESS_PLAIN], res
+
+
+def test_recovery_seed_matches_network(ora, dg):
+    """The recovery's learned seed (layer 2 on fp16 matrix cores, FP32
+    accumulation) against the FP64 network: with an unreachable tolerance the
+    recovery stops at its first evaluation and returns the seed itself
+    whenever the seed lies inside the bracket."""
+    import torch
+    U, prim = _samples(ora, 20000, 47)
+    x = M.features(MHD, G43, U)
+    t = np.log(prim[4] / U[0])
+    p = _params(9)
+    p[M.O_MU:M.O_MU + 5] = x.mean(1)
+    p[M.O_SD:M.O_SD + 5] = x.std(1)
+    p[M.O_YMU], p[M.O_YSD] = t.mean(), t.std()
+    net = dg.Mlp(seed=0)
+    dg.mlp_set(net, to_dev(p.astype(np.float32)))
+    P = torch.zeros((5, U.shape[1]), dtype=torch.float64, device="cuda")
+    dg.con2prim(MHD, G43, to_dev(U), P, guess=dg.GUESS_LEARNED, mlp=net, tol=1e300)
+    got = np.log(to_host(P)[4] / U[0])
+    want = M.predict(p.astype(np.float32).astype(np.float64), x)
+    BB = (U[5:8] ** 2).sum(0)
+    p_hi = (G43 - 1.0) * (U[4] - 0.5 * BB)
+    inside = np.exp(want) * U[0] < 0.9 * p_hi
+    assert inside.sum() > 1000
+    d = np.abs(got - want)[inside]
+    assert d.max() <= 0.05 and d.mean() <= 0.01, (d.max(), d.mean())
