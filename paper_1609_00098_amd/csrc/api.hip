@@ -140,6 +140,10 @@ struct dgmi_ctx {
   int32_t *d_elist = nullptr;     // elements grouped by degree, highest first
   int64_t lstart[9] = {0}, lcount[9] = {0};
   double *d_Itab = nullptr, *d_Ptab = nullptr;  // [8][8][8][8] mortar tables
+  int64_t *d_foff = nullptr;      // [nelem][6] lift-term offsets of non-conforming faces (-1: conforming)
+  int32_t *d_faces = nullptr;     // [nfaces][2] non-conforming faces, each once
+  int64_t nfaces = 0;
+  double *d_facebuf = nullptr;    // lift terms written by the mortar kernel
   double *d_dt = nullptr;         // device scalar read by captured stages
   int epb[9] = {0};               // chosen elements per workgroup by degree
   hipStream_t side[8] = {nullptr};
@@ -160,6 +164,15 @@ static double lagrange(int n, const double *xs, int i, double y) {
 }
 
 static dgmi_status autotune(dgmi_ctx *c);
+
+// Periodic neighbour of element e across face f (-x, +x, -y, +y, -z, +z).
+static int64_t nbr_of(const dgmi_ctx *c, int64_t e, int f) {
+  const int64_t ne[3] = {c->nx, c->ny, c->nz};
+  int64_t k[3] = {e % c->nx, (e / c->nx) % c->ny, e / ((int64_t)c->nx * c->ny)};
+  const int d = f >> 1;
+  k[d] = (k[d] + ((f & 1) ? 1 : ne[d] - 1)) % ne[d];
+  return k[0] + ne[0] * (k[1] + ne[1] * k[2]);
+}
 
 // Degree lists, offsets, mortar tables, streams; optional tile autotuning.
 static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
@@ -202,6 +215,31 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
   HIP_TRY(hipMemcpy(c->d_elist, elist.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_Itab, It.data(), tb, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_Ptab, Pt.data(), tb, hipMemcpyHostToDevice));
+  // faces between unequal degrees: each listed once (from the element whose
+  // upper face it is); both sides get a block of lift terms in the face buffer
+  std::vector<int64_t> foff(c->nelem * 6, -1);
+  std::vector<int32_t> faces;
+  int64_t cursor = 0;
+  for (int64_t e = 0; e < c->nelem; ++e)
+    for (int f = 0; f < 6; ++f) {
+      const int64_t en = nbr_of(c, e, f);
+      if (c->deg[en] == c->deg[e]) continue;
+      foff[e * 6 + f] = cursor;
+      cursor += (int64_t)c->nv * (c->deg[e] + 1) * (c->deg[e] + 1);
+      if (f & 1) {
+        faces.push_back((int32_t)e);
+        faces.push_back(f);
+      }
+    }
+  c->nfaces = (int64_t)faces.size() / 2;
+  if (hipMalloc(&c->d_foff, sizeof(int64_t) * foff.size()) != hipSuccess ||
+      hipMalloc(&c->d_faces, sizeof(int32_t) * (faces.size() + 2)) != hipSuccess ||
+      hipMalloc(&c->d_facebuf, sizeof(double) * (cursor + 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the mortar buffers failed");
+  }
+  HIP_TRY(hipMemcpy(c->d_foff, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice));
+  if (!faces.empty()) HIP_TRY(hipMemcpy(c->d_faces, faces.data(), sizeof(int32_t) * faces.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(c->d_dt, 0, sizeof(double)));
   for (int k = 0; k < 8; ++k) {
     HIP_TRY(hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));
@@ -212,38 +250,61 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
   return DGMI_OK;
 }
 
-static dgmi::MixArgs mix_args(dgmi_ctx *c, int N) {
-  dgmi::MixArgs a{};
+static dgmi::RhsArgs mix_args(dgmi_ctx *c, int N) {
+  dgmi::RhsArgs a{};
   a.elist = c->d_elist + c->lstart[N];
   a.nlist = c->lcount[N];
-  a.nbr = c->d_nbr;
-  a.deg = c->d_deg;
   a.off = c->d_off;
+  a.foff = c->d_foff;
+  a.facebuf = c->d_facebuf;
+  a.nbr = c->d_nbr;
   a.Dmat = c->d_D + 64 * N;
-  a.Itab = c->d_Itab;
-  a.Ptab = c->d_Ptab;
-  a.dt = c->d_dt;
+  a.dtp = c->d_dt;
   a.nfail = c->d_nfail;
+  a.nelem = c->nelem;
   a.nnodes = c->nnodes;
   a.gamma = c->gamma;
   a.kappa = c->kappa;
   for (int d = 0; d < 3; ++d) a.scale[d] = 2.0 / c->dx[d];
   a.inv_wend = 1.0 / c->wend[N];
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nz = c->nz;
   return a;
 }
 
-// One operator / stage pass over every degree: the per-degree kernels run
-// concurrently on the context's side streams, joined back into s.
+static dgmi::MortarArgs mortar_args(dgmi_ctx *c, const double *U, const double *P) {
+  dgmi::MortarArgs m{};
+  m.U = U;
+  m.P = P;
+  m.faces = c->d_faces;
+  m.nfaces = c->nfaces;
+  m.nbr = c->d_nbr;
+  m.deg = c->d_deg;
+  m.off = c->d_off;
+  m.foff = c->d_foff;
+  m.facebuf = c->d_facebuf;
+  m.Itab = c->d_Itab;
+  m.Ptab = c->d_Ptab;
+  m.nnodes = c->nnodes;
+  m.gamma = c->gamma;
+  return m;
+}
+
+// One operator / stage pass over every degree: the mortar kernel writes the
+// lift terms of the non-conforming faces, then the per-degree element kernels
+// run concurrently on the context's side streams, joined back into s.
 static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const double *P, double *out,
-                              const double *Un, double *Pout, double wa, double wb, hipStream_t s) {
+                              const double *Un, double *Pout, double wa, double wb, int full_prims, hipStream_t s) {
+  HIP_TRY(dgmi::launch_mortar(c->sys, mortar_args(c, U, P), s));
   HIP_TRY(hipEventRecord(c->ev_fork, s));
   int k = 0;
   for (int N = dgmi::kMaxMixedDegree; N >= 1; --N) {
     if (c->lcount[N] == 0) continue;
-    dgmi::MixArgs a = mix_args(c, N);
-    a.U = U; a.P = P; a.out = out; a.Un = Un; a.Pout = Pout; a.a = wa; a.b = wb;
+    dgmi::RhsArgs a = mix_args(c, N);
+    a.U = U; a.P = P; a.out = out; a.Un = Un; a.Pout = Pout; a.a = wa; a.b = wb; a.full_prims = full_prims;
     HIP_TRY(hipStreamWaitEvent(c->side[k], c->ev_fork, 0));
-    HIP_TRY(dgmi::launch_mixed(c->sys, N, c->epb[N], stage, a, c->side[k]));
+    HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, c->epb[N], stage, a, c->side[k]));
     HIP_TRY(hipEventRecord(c->ev_join[k], c->side[k]));
     ++k;
   }
@@ -252,9 +313,9 @@ static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const dou
 }
 
 static dgmi_status mixed_step_enqueue(dgmi_ctx *c, double *U, double *P, hipStream_t s) {
-  dgmi_status st = mixed_pass(c, 1, U, P, c->d_U1, U, c->d_P1, 0.0, 1.0, s);
-  if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U1, c->d_P1, c->d_U2, U, c->d_P2, 0.75, 0.25, s);
-  if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U2, c->d_P2, U, U, P, 1.0 / 3.0, 2.0 / 3.0, s);
+  dgmi_status st = mixed_pass(c, 1, U, P, c->d_U1, U, c->d_P1, 0.0, 1.0, 0, s);
+  if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U1, c->d_P1, c->d_U2, U, c->d_P2, 0.75, 0.25, 0, s);
+  if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U2, c->d_P2, U, U, P, 1.0 / 3.0, 2.0 / 3.0, 1, s);
   return st;
 }
 
@@ -269,6 +330,7 @@ static dgmi_status autotune(dgmi_ctx *c) {
   HIP_TRY(dgmi::launch_fill(c->d_P1 + 4 * n, n, 1.0, s));
   HIP_TRY(dgmi::launch_fill(c->d_U2, 4 * n, 0.0, s));
   HIP_TRY(dgmi::launch_prim2cons(c->sys, c->gamma, c->d_P1, c->d_U2, c->d_U1, n, s));
+  HIP_TRY(dgmi::launch_mortar(c->sys, mortar_args(c, c->d_U1, c->d_P1), s));
   hipEvent_t t0, t1;
   HIP_TRY(hipEventCreate(&t0));
   HIP_TRY(hipEventCreate(&t1));
@@ -278,11 +340,11 @@ static dgmi_status autotune(dgmi_ctx *c) {
     const int no = dgmi::mixed_tile_options(c->sys, N, opts);
     float best = 1e30f;
     for (int o = 0; o < no; ++o) {
-      dgmi::MixArgs a = mix_args(c, N);
+      dgmi::RhsArgs a = mix_args(c, N);
       a.U = c->d_U1; a.P = c->d_P1; a.out = c->d_U2;
-      HIP_TRY(dgmi::launch_mixed(c->sys, N, opts[o], 0, a, s));
+      HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, opts[o], 0, a, s));
       HIP_TRY(hipEventRecord(t0, s));
-      for (int r = 0; r < 5; ++r) HIP_TRY(dgmi::launch_mixed(c->sys, N, opts[o], 0, a, s));
+      for (int r = 0; r < 5; ++r) HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, opts[o], 0, a, s));
       HIP_TRY(hipEventRecord(t1, s));
       HIP_TRY(hipEventSynchronize(t1));
       float ms = 0.f;
@@ -318,6 +380,9 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_elist);
   (void)hipFree(c->d_Itab);
   (void)hipFree(c->d_Ptab);
+  (void)hipFree(c->d_foff);
+  (void)hipFree(c->d_faces);
+  (void)hipFree(c->d_facebuf);
   (void)hipFree(c->d_dt);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -502,7 +567,7 @@ dgmi_status dg_rhs(dgmi_ctx *ctx, const double *U, double *prim_inout, double *d
   const int guess = (ctx->flags & DGMI_FLAG_PLAIN_GUESS) ? DGMI_GUESS_PLAIN : DGMI_GUESS_INPUT;
   dgmi_status st = recover_all(ctx, U, prim_inout, guess, s);
   if (st != DGMI_OK) return st;
-  if (ctx->mixed) return mixed_pass(ctx, 0, U, prim_inout, dUdt, nullptr, nullptr, 0.0, 0.0, s);
+  if (ctx->mixed) return mixed_pass(ctx, 0, U, prim_inout, dUdt, nullptr, nullptr, 0.0, 0.0, 0, s);
   dgmi::RhsArgs a = rhs_args(ctx);
   a.U = U;
   a.P = prim_inout;
@@ -516,7 +581,7 @@ dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, doub
   if (!is_device_ptr(U) || !is_device_ptr(prim) || !is_device_ptr(dUdt))
     return fail(DGMI_EINVAL, "dg_operator: U, prim and dUdt must be device pointers");
   if (dUdt == U || dUdt == prim) return fail(DGMI_EINVAL, "dg_operator: dUdt must not alias its inputs");
-  if (ctx->mixed) return mixed_pass(ctx, 0, U, prim, dUdt, nullptr, nullptr, 0.0, 0.0, (hipStream_t)stream);
+  if (ctx->mixed) return mixed_pass(ctx, 0, U, prim, dUdt, nullptr, nullptr, 0.0, 0.0, 0, (hipStream_t)stream);
   dgmi::RhsArgs a = rhs_args(ctx);
   a.U = U;
   a.P = prim;

@@ -22,43 +22,48 @@ struct RhsArgs {
   double a, b, dt;     // Shu-Osher stage: out = a Un + b (U + dt L(U))
   int nx, ny, nz;      // elements per direction
   int full_prims;      // stage kernel: write all five primitive rows (else NE/SR write only p)
+  const double *dtp;   // stage kernel: if set, dt is read from this device scalar
+  // mixed degrees: the launch of degree N processes the nlist elements in
+  // elist; node blocks start at off[e]; a face with foff[e*6+f] >= 0 takes its
+  // lift terms facebuf[foff + v*(N+1)^2 + node] from the mortar kernel
+  const int32_t *elist;
+  int64_t nlist;
+  const int64_t *off;
+  const int64_t *foff;
+  const double *facebuf;
   int nblocks;         // logical blocks (set at launch)
 };
 
 // Launch dg RHS (stage == 0) or RK stage (stage == 1).
 hipError_t launch_rhs(int sys, int N, int stage, const RhsArgs &a, hipStream_t s);
+// The same kernels over one degree's elements of a mixed-degree mesh, epb
+// elements per workgroup (one of mixed_tile_options).
+hipError_t launch_rhs_mixed(int sys, int N, int epb, int stage, const RhsArgs &a, hipStream_t s);
 
 // Highest degree of the mixed-degree path (mortars of up to 8x8 nodes).
 constexpr int kMaxMixedDegree = 7;
 
-// Arguments of the mixed-degree RHS / RK-stage kernel of one degree.
-struct MixArgs {
-  const double *U, *P;     // operator input and its primitives
-  double *out;             // dU/dt or U^(s)
-  const double *Un;        // U^n (stage kernel)
-  double *Pout;            // primitives of U^(s) (stage kernel)
-  const int32_t *elist;    // the elements of this degree
-  int64_t nlist;
+// Arguments of the mortar kernel: one wave per face between elements of
+// unequal degree (each such face listed once, from its lower-x/y/z element).
+struct MortarArgs {
+  const double *U, *P;     // state and primitives (NE/SR: only p is read)
+  const int32_t *faces;    // [nfaces][2]: element e and its upper face f (1, 3 or 5)
+  int64_t nfaces;
   const int32_t *nbr;      // [nelem][6]
   const int32_t *deg;      // [nelem]
-  const int64_t *off;      // [nelem + 1] first node of every element
-  const double *Dmat;      // this degree's (N+1)x(N+1) differentiation matrix
+  const int64_t *off;      // [nelem + 1]
+  const int64_t *foff;     // [nelem][6] start of each face's lift terms in facebuf
+  double *facebuf;         // lift terms [v][(N_e+1)^2] per non-conforming face side
   const double *Itab;      // I[lo][m][ma][ia] = l^lo_ia(x^m_ma), [8][8][8][8]
   const double *Ptab;      // P[lo][m][a][ma] = w^m_ma l^lo_a(x^m_ma) / w^lo_a
-  const double *dt;        // device scalar (stage kernel)
-  unsigned long long *nfail;
   int64_t nnodes;
-  double gamma, kappa;
-  double scale[3];         // 2/dx_d
-  double inv_wend;         // this degree's 1/w_0
-  double a, b;             // Shu-Osher weights
-  int nblocks;             // set at launch
+  double gamma;
 };
 
-// Elements-per-workgroup options of the mixed kernel for (system, degree);
-// returns how many were written to epb_out (at most 3).
+// Elements-per-workgroup options of the mixed-degree element kernel for
+// (system, degree); returns how many were written to epb_out (at most 2).
 int mixed_tile_options(int sys, int N, int *epb_out);
-hipError_t launch_mixed(int sys, int N, int epb, int stage, const MixArgs &a, hipStream_t s);
+hipError_t launch_mortar(int sys, const MortarArgs &a, hipStream_t s);
 hipError_t launch_mixed_coords(const int32_t *deg, const int64_t *off, const double *xtab, int nx, int ny,
                                int64_t nelem, const double *lo, const double *dx, double *xyz, int64_t nn,
                                hipStream_t s);

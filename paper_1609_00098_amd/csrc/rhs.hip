@@ -20,6 +20,12 @@
 //      the next stage finds neighbour primitives ready.
 // Workgroups are mapped XCD-major: consecutive element groups land on the
 // same XCD (and L2), so face neighbours along x and y are usually L2 hits.
+//
+// Mixed degrees (MIXED = true): one launch per degree N takes its elements
+// from a degree-sorted list, finds node blocks through per-element offsets,
+// and on faces whose neighbour has another degree loads the lift terms
+// F*.n - F.n (or their projection) that the mortar kernel wrote; conforming
+// faces are handled exactly as above.
 #include "kernels.hpp"
 #include "physics.hpp"
 
@@ -33,12 +39,17 @@ __device__ __forceinline__ double sel3(int d, double a, double b, double c) {
 __device__ __forceinline__ int sel3i(int d, int a, int b, int c) { return d == 0 ? a : (d == 1 ? b : c); }
 
 template <int SYS, int N>
+constexpr int default_epb() {
+  return (N == 1) ? 8 : (N == 2) ? 9 : (N == 3) ? (SYS == kMHD ? 2 : 4) : (N == 4) ? 2 : 1;
+}
+
+template <int SYS, int N, int EPB_ = default_epb<SYS, N>()>
 struct RhsCfg {
   static constexpr int NP = N + 1;
   static constexpr int NPE = NP * NP * NP;
   static constexpr int NF = NP * NP;
   static constexpr int NV = SysTraits<SYS>::nv;
-  static constexpr int EPB = (N == 1) ? 8 : (N == 2) ? 9 : (N == 3) ? (SYS == kMHD ? 2 : 4) : (N == 4) ? 2 : 1;
+  static constexpr int EPB = EPB_;
   static constexpr int THREADS = ((EPB * NPE + 63) / 64) * 64;
   static constexpr int FACE_TASKS = EPB * 6 * NF;
   // LDS (doubles): volume flux [EPB][NV][NPE], own state [EPB][NV][NPE],
@@ -68,9 +79,9 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
   }
 }
 
-template <int SYS, int N, int STAGE>
-__global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const RhsArgs A) {
-  using C = RhsCfg<SYS, N>;
+template <int SYS, int N, int STAGE, int EPB_ = default_epb<SYS, N>(), bool MIXED = false>
+__global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(const RhsArgs A) {
+  using C = RhsCfg<SYS, N, EPB_>;
   constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
   __shared__ double svol[C::VOL];
   __shared__ double sown[C::OWN];
@@ -88,10 +99,17 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
 
   const int le = tid / NPE;
   const int a = tid - le * NPE;
-  const int64_t e = (int64_t)grp * EPB + le;
-  const bool active = (le < EPB) && (e < A.nelem);
+  const int64_t sl = (int64_t)grp * EPB + le;
+  bool active;
+  int64_t q;
+  if constexpr (MIXED) {
+    active = (le < EPB) && (sl < A.nlist);
+    q = active ? A.off[A.elist[sl]] + a : 0;
+  } else {
+    active = (le < EPB) && (sl < A.nelem);
+    q = sl * NPE + a;
+  }
   const int ci = a % NP, cj = (a / NP) % NP, ck = a / NF;
-  const int64_t q = e * NPE + a;
   const int64_t nn = A.nnodes;
 
   double u[NV];
@@ -157,8 +175,18 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
     const int r = t - fle * 6 * NF;
     const int f = r / NF;
     const int fn = r - f * NF;
-    const int64_t fe = (int64_t)grp * EPB + fle;
-    if (fe >= A.nelem) continue;
+    const int64_t fsl = (int64_t)grp * EPB + fle;
+    if (fsl >= (MIXED ? A.nlist : A.nelem)) continue;
+    const int64_t fe = MIXED ? (int64_t)A.elist[fsl] : fsl;
+    if constexpr (MIXED) {
+      const int64_t fo = A.foff[fe * 6 + f];
+      if (fo >= 0) {  // neighbour of another degree: the mortar kernel's lift terms
+        double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) slot[v * 6 * NF] = A.facebuf[fo + v * NF + fn];
+        continue;
+      }
+    }
     const int d = f >> 1, side = f & 1;
     const int ta = fn % NP, tb = fn / NP;
     int c0, c1, c2, n0, n1, n2;
@@ -169,7 +197,8 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
     const int ai = c0 + NP * (c1 + NP * c2);
     double ue[NV], Fe[NV];
     Prim Pe;
-    load_node<SYS>(A.U, A.P, nn, en * NPE + n0 + NP * (n1 + NP * n2), A.gamma, ue, Pe);
+    const int64_t ebase = MIXED ? A.off[en] : en * NPE;
+    load_node<SYS>(A.U, A.P, nn, ebase + n0 + NP * (n1 + NP * n2), A.gamma, ue, Pe);
     flux_normal<SYS>(d, ue, Pe, Fe);
     const double *own = sown + fle * NV * NPE + ai;
     double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
@@ -205,9 +234,10 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N>::THREADS)) rhs_kernel(const Rh
   }
   // ---- Shu-Osher combination and tail recovery
   double us[NV];
+  const double dt = A.dtp ? *A.dtp : A.dt;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    us[v] = A.a * A.Un[v * nn + q] + A.b * (u[v] + A.dt * acc[v]);
+    us[v] = A.a * A.Un[v * nn + q] + A.b * (u[v] + dt * acc[v]);
     A.out[v * nn + q] = us[v];
   }
   const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100);
@@ -236,6 +266,69 @@ static hipError_t launch_one(int stage, const RhsArgs &a, hipStream_t s) {
   else
     hipLaunchKernelGGL((rhs_kernel<SYS, N, 1>), dim3(grid), dim3(C::THREADS), 0, s, b);
   return hipGetLastError();
+}
+
+template <int SYS, int N, int EPB>
+static hipError_t launch_mixed_one(int stage, const RhsArgs &a, hipStream_t s) {
+  using C = RhsCfg<SYS, N, EPB>;
+  RhsArgs b = a;
+  const int64_t nblocks = (a.nlist + EPB - 1) / EPB;
+  if (nblocks > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+  if (nblocks == 0) return hipSuccess;
+  b.nblocks = (int)nblocks;
+  const int grid = ((b.nblocks + 7) / 8) * 8;
+  if (stage == 0)
+    hipLaunchKernelGGL((rhs_kernel<SYS, N, 0, EPB, true>), dim3(grid), dim3(C::THREADS), 0, s, b);
+  else
+    hipLaunchKernelGGL((rhs_kernel<SYS, N, 1, EPB, true>), dim3(grid), dim3(C::THREADS), 0, s, b);
+  return hipGetLastError();
+}
+
+// Tile options (elements per workgroup) of the mixed-degree element kernel.
+int mixed_tile_options(int sys, int N, int *epb_out) {
+  if (N < 1 || N > kMaxMixedDegree) return 0;
+  static const int sr[8][2] = {{0, 0}, {8, 4}, {9, 4}, {4, 2}, {2, 1}, {1, 0}, {1, 0}, {1, 0}};
+  if (sys == kSR) {
+    int n = 0;
+    for (int k = 0; k < 2 && sr[N][k]; ++k) epb_out[n++] = sr[N][k];
+    return n;
+  }
+  static const int dflt[3][8] = {{0, 8, 9, 4, 2, 1, 1, 1}, {0}, {0, 8, 9, 2, 2, 1, 1, 1}};
+  epb_out[0] = dflt[sys][N];
+  return 1;
+}
+
+template <int SYS, int N>
+static hipError_t launch_mixed_deg(int epb, int stage, const RhsArgs &a, hipStream_t s) {
+  constexpr int E0 = default_epb<SYS, N>();
+  if constexpr (SYS == kSR) {
+    constexpr int E1 = (N == 1) ? 4 : (N == 2) ? 4 : (N == 3) ? 2 : (N == 4) ? 1 : E0;
+    if (epb == E1 && E1 != E0) return launch_mixed_one<SYS, N, E1>(stage, a, s);
+  }
+  return launch_mixed_one<SYS, N, E0>(stage, a, s);
+}
+
+template <int SYS>
+static hipError_t launch_mixed_sys(int N, int epb, int stage, const RhsArgs &a, hipStream_t s) {
+  switch (N) {
+    case 1: return launch_mixed_deg<SYS, 1>(epb, stage, a, s);
+    case 2: return launch_mixed_deg<SYS, 2>(epb, stage, a, s);
+    case 3: return launch_mixed_deg<SYS, 3>(epb, stage, a, s);
+    case 4: return launch_mixed_deg<SYS, 4>(epb, stage, a, s);
+    case 5: return launch_mixed_deg<SYS, 5>(epb, stage, a, s);
+    case 6: return launch_mixed_deg<SYS, 6>(epb, stage, a, s);
+    case 7: return launch_mixed_deg<SYS, 7>(epb, stage, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rhs_mixed(int sys, int N, int epb, int stage, const RhsArgs &a, hipStream_t s) {
+  switch (sys) {
+    case kNE: return launch_mixed_sys<kNE>(N, epb, stage, a, s);
+    case kSR: return launch_mixed_sys<kSR>(N, epb, stage, a, s);
+    case kMHD: return launch_mixed_sys<kMHD>(N, epb, stage, a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int SYS>
