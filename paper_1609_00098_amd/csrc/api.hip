@@ -139,7 +139,7 @@ struct dgmi_ctx {
   int64_t *d_off = nullptr;       // [nelem + 1]
   int32_t *d_elist = nullptr;     // elements grouped by degree, highest first
   int64_t lstart[9] = {0}, lcount[9] = {0};
-  double *d_Itab = nullptr, *d_Ptab = nullptr;  // [8][8][8][8] mortar tables
+  double *d_Itab = nullptr, *d_Ptab = nullptr, *d_Qtab = nullptr;  // [8][8][8][8] mortar tables
   int64_t *d_foff = nullptr;      // [nelem][6] lift-term offsets of non-conforming faces (-1: conforming)
   int32_t *d_faces = nullptr;     // [nfaces][2] non-conforming faces, each once
   int64_t nfaces = 0;
@@ -202,11 +202,23 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
           It[((lo * 8 + m) * 8 + ma) * 8 + ia] = l;
           Pt[((lo * 8 + m) * 8 + ia) * 8 + ma] = w[8 * m + ma] * l / w[8 * lo + ia];
         }
+  // Q = P I: the projection of the interpolant of the lower side's own fluxes
+  std::vector<double> Qt(8 * 8 * 8 * 8, 0.0);
+  for (int lo = 1; lo <= 7; ++lo)
+    for (int m = lo; m <= 7; ++m)
+      for (int a = 0; a <= lo; ++a)
+        for (int ia = 0; ia <= lo; ++ia) {
+          double q = 0.0;
+          for (int ma = 0; ma <= m; ++ma)
+            q += Pt[((lo * 8 + m) * 8 + a) * 8 + ma] * It[((lo * 8 + m) * 8 + ma) * 8 + ia];
+          Qt[((lo * 8 + m) * 8 + a) * 8 + ia] = q;
+        }
   const size_t tb = It.size() * sizeof(double);
   if (hipMalloc(&c->d_deg, sizeof(int32_t) * c->nelem) != hipSuccess ||
       hipMalloc(&c->d_off, sizeof(int64_t) * (c->nelem + 1)) != hipSuccess ||
       hipMalloc(&c->d_elist, sizeof(int32_t) * c->nelem) != hipSuccess || hipMalloc(&c->d_Itab, tb) != hipSuccess ||
-      hipMalloc(&c->d_Ptab, tb) != hipSuccess || hipMalloc(&c->d_dt, sizeof(double)) != hipSuccess) {
+      hipMalloc(&c->d_Ptab, tb) != hipSuccess || hipMalloc(&c->d_Qtab, tb) != hipSuccess ||
+      hipMalloc(&c->d_dt, sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the mixed-degree tables failed");
   }
@@ -215,6 +227,7 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
   HIP_TRY(hipMemcpy(c->d_elist, elist.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_Itab, It.data(), tb, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_Ptab, Pt.data(), tb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_Qtab, Qt.data(), tb, hipMemcpyHostToDevice));
   // faces between unequal degrees: each listed once (from the element whose
   // upper face it is); both sides get a block of lift terms in the face buffer
   std::vector<int64_t> foff(c->nelem * 6, -1);
@@ -286,6 +299,7 @@ static dgmi::MortarArgs mortar_args(dgmi_ctx *c, const double *U, const double *
   m.facebuf = c->d_facebuf;
   m.Itab = c->d_Itab;
   m.Ptab = c->d_Ptab;
+  m.Qtab = c->d_Qtab;
   m.nnodes = c->nnodes;
   m.gamma = c->gamma;
   return m;
@@ -380,6 +394,7 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_elist);
   (void)hipFree(c->d_Itab);
   (void)hipFree(c->d_Ptab);
+  (void)hipFree(c->d_Qtab);
   (void)hipFree(c->d_foff);
   (void)hipFree(c->d_faces);
   (void)hipFree(c->d_facebuf);

@@ -56,6 +56,7 @@ struct MortarArgs {
   double *facebuf;         // lift terms [v][(N_e+1)^2] per non-conforming face side
   const double *Itab;      // I[lo][m][ma][ia] = l^lo_ia(x^m_ma), [8][8][8][8]
   const double *Ptab;      // P[lo][m][a][ma] = w^m_ma l^lo_a(x^m_ma) / w^lo_a
+  const double *Qtab;      // Q[lo][m][a][ia] = sum_ma P[a][ma] I[ma][ia]
   int64_t nnodes;
   double gamma;
 };

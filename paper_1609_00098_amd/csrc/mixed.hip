@@ -76,15 +76,26 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
 }  // namespace
 
 
-// One wave per non-conforming face.  Lanes: staging of the lower side's
-// (Nlo+1)^2 face nodes, then one mortar node each, then one lower-side face
-// node each for the projection.
+// One wave per non-conforming face, in separable passes (tensor-product
+// interpolation and projection one direction at a time):
+//   L  lanes k < (Nlo+1)^2 load the lower side's face nodes: interpolation
+//      state and normal fluxes F_h;
+//   I1 interpolate the state along the first tangential direction;
+//   I2 finish the interpolation at the mortar nodes; each mortar lane (which
+//      loaded its higher-side node at the start) forms F*.n and writes the
+//      higher side's lift term F*.n - F.n;
+//   P1, P2 project F*.n_lo onto the lower side's nodes along each direction
+//      and subtract Q F_h, Q = P I (the projection of the interpolant of its
+//      own fluxes, a fixed (Nlo+1)^2 operator).
 template <int SYS>
 __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   constexpr int NV = SysTraits<SYS>::nv, NS = Interp<SYS>::ns;
-  __shared__ double st[64 * NS];  // lower side's interpolation state, [node][c]
+  __shared__ double st[NS * 64];  // lower side's interpolation state, [c][node]
   __shared__ double fl[NV * 64];  // lower side's nodal normal fluxes, [v][node]
-  __shared__ double jm[NV * 64];  // mortar differences for the lower side, [v][m]
+  __shared__ double t1[NS * 64];  // state interpolated along a, [c][ma + nm ib]
+  __shared__ double jm[NV * 64];  // F*.n_lo at the mortar nodes, [v][m]
+  __shared__ double g1[NV * 64];  // projection along a, [v][a + nl mb]
+  __shared__ double sI[64], sP[64], sQ[64];
   const int64_t t = blockIdx.x;
   if (t >= A.nfaces) return;
   const int l = threadIdx.x;
@@ -93,7 +104,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   const int d = f >> 1;
   const int64_t en = A.nbr[e * 6 + f];
   const int Ne = A.deg[e], Nn = A.deg[en];
-  // hi / lo sides; e sees the face as its upper (side 1) face, en as its lower
+  // e sees the face as its upper (side 1) face, en as its lower
   const bool e_hi = Ne > Nn;
   const int64_t ehi = e_hi ? e : en, elo = e_hi ? en : e;
   const int Nm = e_hi ? Ne : Nn, Nlo = e_hi ? Nn : Ne;
@@ -101,8 +112,27 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   const int nm = Nm + 1, nl = Nlo + 1;
   const double sgn_hi = side_hi ? 1.0 : -1.0, sgn_lo = -sgn_hi;
   const int64_t nn = A.nnodes;
+  const int tab = (Nlo * 8 + Nm) * 64;
+  sI[l] = A.Itab[tab + l];  // I[ma][ia] (row stride 8)
+  sP[l] = A.Ptab[tab + l];  // P[a][ma]
+  sQ[l] = A.Qtab[tab + l];  // Q[a][ia]
 
-  // lower side: interpolation state and normal fluxes at its face nodes
+  // the higher side's node of this lane's mortar position, loaded up front so
+  // that its latency overlaps the lower side's loads
+  double uh[NV], Fh[NV], ah = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    uh[v] = 0.0;
+    Fh[v] = 0.0;
+  }
+  if (l < nm * nm) {
+    Prim Ph;
+    load_node<SYS>(A.U, A.P, nn, A.off[ehi] + face_idx(nm, d, side_hi ? Nm : 0, l % nm, l / nm), A.gamma, uh, Ph);
+    flux_normal<SYS>(d, uh, Ph, Fh);
+    ah = max_speed<SYS>(d, uh, Ph, A.gamma);
+  }
+
+  // L: lower side's face nodes
   if (l < nl * nl) {
     const int ka = l % nl, kb = l / nl;
     const int64_t q = A.off[elo] + face_idx(nl, d, side_lo ? Nlo : 0, ka, kb);
@@ -111,15 +141,14 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     load_node<SYS>(A.U, A.P, nn, q, A.gamma, u, P);
     double W = 1.0;
     if (SYS != kNE) W = 1.0 / sqrt(1.0 - (P.v[0] * P.v[0] + P.v[1] * P.v[1] + P.v[2] * P.v[2]));
-    double *sp = st + l * NS;
-    sp[0] = P.rho;
-    sp[1] = P.v[0] * W;
-    sp[2] = P.v[1] * W;
-    sp[3] = P.v[2] * W;
-    sp[4] = P.p;
+    st[l] = P.rho;
+    st[64 + l] = P.v[0] * W;
+    st[128 + l] = P.v[1] * W;
+    st[192 + l] = P.v[2] * W;
+    st[256 + l] = P.p;
     if (SYS == kMHD) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) sp[5 + c] = u[5 + c];
+      for (int c = 0; c < 4; ++c) st[(5 + c) * 64 + l] = u[5 + c];
     }
     double F[NV];
     flux_normal<SYS>(d, u, P, F);
@@ -128,32 +157,32 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   }
   __syncthreads();
 
+  // I1: t1[c][ma + nm ib] = sum_ia I[ma][ia] st[c][ia + nl ib]
+  if (l < nm * nl) {
+    const int ma = l % nm, ib = l / nm;
+    double acc[NS];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) acc[c] = 0.0;
+    for (int ia = 0; ia < nl; ++ia) {
+      const double w = sI[ma * 8 + ia];
+#pragma unroll
+      for (int c = 0; c < NS; ++c) acc[c] += w * st[c * 64 + ia + nl * ib];
+    }
+#pragma unroll
+    for (int c = 0; c < NS; ++c) t1[c * 64 + l] = acc[c];
+  }
+  __syncthreads();
+
+  // I2 + flux at the mortar node
   if (l < nm * nm) {
     const int ma = l % nm, mb = l / nm;
-    // higher side: its own face node
-    double uh[NV], Fh[NV];
-    Prim Ph;
-    load_node<SYS>(A.U, A.P, nn, A.off[ehi] + face_idx(nm, d, side_hi ? Nm : 0, ma, mb), A.gamma, uh, Ph);
-    flux_normal<SYS>(d, uh, Ph, Fh);
-    const double ah = max_speed<SYS>(d, uh, Ph, A.gamma);
-    // lower side interpolated to this mortar node, and its interpolated fluxes
-    const double *Ia = A.Itab + ((Nlo * 8 + Nm) * 8 + ma) * 8;
-    const double *Ib = A.Itab + ((Nlo * 8 + Nm) * 8 + mb) * 8;
-    double s[NS], IF[NV];
+    double s[NS];
 #pragma unroll
     for (int c = 0; c < NS; ++c) s[c] = 0.0;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) IF[v] = 0.0;
     for (int ib = 0; ib < nl; ++ib) {
-      const double wb = Ib[ib];
-      for (int ia = 0; ia < nl; ++ia) {
-        const double w = Ia[ia] * wb;
-        const int k = ia + nl * ib;
+      const double w = sI[mb * 8 + ib];
 #pragma unroll
-        for (int c = 0; c < NS; ++c) s[c] += w * st[k * NS + c];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) IF[v] += w * fl[v * 64 + k];
-      }
+      for (int c = 0; c < NS; ++c) s[c] += w * t1[c * 64 + ma + nm * ib];
     }
     double ul[NV], Fl[NV];
     Prim Pl;
@@ -166,33 +195,55 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     for (int v = 0; v < NV; ++v) {
       double al = alpha;
       if (SYS == kMHD && (v == 8 || v == 5 + d)) al = 1.0;
-      // F*.n_hi with the higher side interior: (F_h + F_l).n_hi / 2 - al (u_l - u_h) / 2
-      const double fstar = hs * (Fh[v] + Fl[v]) - 0.5 * al * (ul[v] - uh[v]);
-      out_hi[v * nm * nm] = hs * (Fl[v] - Fh[v]) - 0.5 * al * (ul[v] - uh[v]);
-      jm[v * 64 + l] = -fstar - sgn_lo * IF[v];
+      // F*.n_hi with the higher side interior
+      const double diss = 0.5 * al * (ul[v] - uh[v]);
+      out_hi[v * nm * nm] = hs * (Fl[v] - Fh[v]) - diss;
+      jm[v * 64 + l] = diss - hs * (Fh[v] + Fl[v]);  // F*.n_lo = -F*.n_hi
     }
   }
   __syncthreads();
 
-  // lower side: project onto its face nodes
+  // P1: g1[v][a + nl mb] = sum_ma P[a][ma] jm[v][ma + nm mb]
+  if (l < nl * nm) {
+    const int a = l % nl, mb = l / nl;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int ma = 0; ma < nm; ++ma) {
+      const double w = sP[a * 8 + ma];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += w * jm[v * 64 + ma + nm * mb];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) g1[v * 64 + l] = acc[v];
+  }
+  __syncthreads();
+
+  // P2: lower side's lift term P F*.n_lo - sgn_lo (Q x Q) F_h at node (a, b)
   if (l < nl * nl) {
-    const int ta = l % nl, tb = l / nl;
-    const double *Pa = A.Ptab + ((Nlo * 8 + Nm) * 8 + ta) * 8;
-    const double *Pb = A.Ptab + ((Nlo * 8 + Nm) * 8 + tb) * 8;
-    double g[NV];
+    const int a = l % nl, b = l / nl;
+    double g[NV], h[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) g[v] = 0.0;
+    for (int v = 0; v < NV; ++v) {
+      g[v] = 0.0;
+      h[v] = 0.0;
+    }
     for (int mb = 0; mb < nm; ++mb) {
-      const double wb = Pb[mb];
-      for (int ma = 0; ma < nm; ++ma) {
-        const double w = Pa[ma] * wb;
+      const double w = sP[b * 8 + mb];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) g[v] += w * jm[v * 64 + ma + nm * mb];
+      for (int v = 0; v < NV; ++v) g[v] += w * g1[v * 64 + a + nl * mb];
+    }
+    for (int ib = 0; ib < nl; ++ib) {
+      const double wb = sQ[b * 8 + ib];
+      for (int ia = 0; ia < nl; ++ia) {
+        const double w = sQ[a * 8 + ia] * wb;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) h[v] += w * fl[v * 64 + ia + nl * ib];
       }
     }
     double *out_lo = A.facebuf + A.foff[elo * 6 + 2 * d + side_lo] + l;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out_lo[v * nl * nl] = g[v];
+    for (int v = 0; v < NV; ++v) out_lo[v * nl * nl] = g[v] - sgn_lo * h[v];
   }
 }
 
