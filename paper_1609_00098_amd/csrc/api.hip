@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/dgmi.h"
@@ -146,6 +147,10 @@ struct dgmi_ctx {
   double *d_facebuf = nullptr;    // lift terms written by the mortar kernel
   double *d_dt = nullptr;         // device scalar read by captured stages
   int epb[9] = {0};               // chosen elements per workgroup by degree
+  int lane_of[9] = {0};           // side stream of each degree's element kernel
+  int lane_order[9] = {0};        // degrees in launch order (largest work first)
+  int ndeg = 0;
+  double last_dt = NAN;           // dt held by d_dt
   hipStream_t side[8] = {nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[8] = {nullptr};
   hipGraph_t graph = nullptr;
@@ -164,6 +169,7 @@ static double lagrange(int n, const double *xs, int i, double y) {
 }
 
 static dgmi_status autotune(dgmi_ctx *c);
+constexpr int kMixedLanes = 4;
 
 // Periodic neighbour of element e across face f (-x, +x, -y, +y, -z, +z).
 static int64_t nbr_of(const dgmi_ctx *c, int64_t e, int f) {
@@ -259,6 +265,28 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
     HIP_TRY(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
   }
   HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  // the per-degree element kernels share kMixedLanes streams (the hardware
+  // runs a few queues at once); degrees go, largest node count first, to the
+  // least loaded stream
+  {
+    int64_t load[kMixedLanes] = {0};
+    int order[8], nd = 0;
+    for (int N = 1; N <= dgmi::kMaxMixedDegree; ++N)
+      if (c->lcount[N] > 0) order[nd++] = N;
+    auto work = [c](int N) { return c->lcount[N] * (int64_t)(N + 1) * (N + 1) * (N + 1); };
+    for (int i = 0; i < nd; ++i)
+      for (int j = i + 1; j < nd; ++j)
+        if (work(order[j]) > work(order[i])) std::swap(order[i], order[j]);
+    for (int i = 0; i < nd; ++i) {
+      int best = 0;
+      for (int k = 1; k < kMixedLanes; ++k)
+        if (load[k] < load[best]) best = k;
+      c->lane_of[order[i]] = best;
+      load[best] += work(order[i]);
+      c->lane_order[i] = order[i];
+    }
+    c->ndeg = nd;
+  }
   if (c->flags & DGMI_FLAG_AUTOTUNE) return autotune(c);
   return DGMI_OK;
 }
@@ -312,17 +340,20 @@ static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const dou
                               const double *Un, double *Pout, double wa, double wb, int full_prims, hipStream_t s) {
   HIP_TRY(dgmi::launch_mortar(c->sys, mortar_args(c, U, P), s));
   HIP_TRY(hipEventRecord(c->ev_fork, s));
-  int k = 0;
-  for (int N = dgmi::kMaxMixedDegree; N >= 1; --N) {
-    if (c->lcount[N] == 0) continue;
+  bool used[kMixedLanes] = {false};
+  for (int i = 0; i < c->ndeg; ++i) {
+    const int N = c->lane_order[i], k = c->lane_of[N];
     dgmi::RhsArgs a = mix_args(c, N);
     a.U = U; a.P = P; a.out = out; a.Un = Un; a.Pout = Pout; a.a = wa; a.b = wb; a.full_prims = full_prims;
-    HIP_TRY(hipStreamWaitEvent(c->side[k], c->ev_fork, 0));
+    if (!used[k]) HIP_TRY(hipStreamWaitEvent(c->side[k], c->ev_fork, 0));
+    used[k] = true;
     HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, c->epb[N], stage, a, c->side[k]));
-    HIP_TRY(hipEventRecord(c->ev_join[k], c->side[k]));
-    ++k;
   }
-  for (int j = 0; j < k; ++j) HIP_TRY(hipStreamWaitEvent(s, c->ev_join[j], 0));
+  for (int k = 0; k < kMixedLanes; ++k) {
+    if (!used[k]) continue;
+    HIP_TRY(hipEventRecord(c->ev_join[k], c->side[k]));
+    HIP_TRY(hipStreamWaitEvent(s, c->ev_join[k], 0));
+  }
   return DGMI_OK;
 }
 
@@ -618,8 +649,11 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
   }
   if (ctx->mixed) {
     // dt reaches the stage kernels through a device scalar, so that a
-    // captured step replays with any dt
-    HIP_TRY(dgmi::launch_set_scalar(ctx->d_dt, dt, s));
+    // captured step replays with any dt (rewritten only when it changes)
+    if (!(dt == ctx->last_dt)) {
+      HIP_TRY(dgmi::launch_set_scalar(ctx->d_dt, dt, s));
+      ctx->last_dt = dt;
+    }
     if ((ctx->flags & DGMI_FLAG_NO_GRAPH) || s == nullptr) return mixed_step_enqueue(ctx, U, prim_inout, s);
     if (!ctx->gexec || ctx->gU != U || ctx->gP != prim_inout) {
       if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
