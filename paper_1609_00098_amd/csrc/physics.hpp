@@ -194,6 +194,41 @@ DG_HD void flux_all(const double *u, const Prim &P, double (*F)[SysTraits<SYS>::
   }
 }
 
+// ---------------------------------------------------------------- fast FP64
+// Reciprocal and square root for quantities that feed the wave speeds and
+// the primitives rebuilt from (U, p): the hardware estimate refined by
+// Newton-Raphson steps on the device (within about an ulp; the IEEE-rounded
+// expansions cost two to three times the instructions), exact on the host.
+DG_HD double fast_rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
+// sqrt(x) for x >= 0 (0 for x <= 0).
+DG_HD double fast_sqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // Goldschmidt iteration from the hardware 1/sqrt estimate: g -> sqrt(x),
+  // h -> 1/(2 sqrt(x)), then one Newton correction of g with the residual
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r, h = 0.5 * r;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  const double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
+#else
+  return x > 0.0 ? sqrt(x) : 0.0;
+#endif
+}
+
 // ---------------------------------------------------------------- speeds
 // Largest |lambda| along +-e_d for the fluid sub-system.
 // NE: |v_n| + c_s.  SR / MHD: the acoustic (fast) pair
@@ -205,23 +240,22 @@ template <int SYS>
 DG_HD double max_speed(int d, const double *u, const Prim P, double g) {
   const double v0 = P.v[0], v1 = P.v[1], v2s = P.v[2];
   const double vn = (d == 0) ? v0 : ((d == 1) ? v1 : v2s);
-  if (SYS == kNE) return fabs(vn) + sqrt(g * P.p / P.rho);
+  if (SYS == kNE) return fabs(vn) + fast_sqrt(g * P.p * fast_rcp(P.rho));
   const double v2 = v0 * v0 + v1 * v1 + v2s * v2s;
   const double rhoh = P.rho + g / (g - 1.0) * P.p;
   double c2;
   if (SYS == kSR) {
-    c2 = g * P.p / rhoh;
+    c2 = g * P.p * fast_rcp(rhoh);
   } else {
     const double BB = sq(u[5]) + sq(u[6]) + sq(u[7]);
     const double Bv = u[5] * v0 + u[6] * v1 + u[7] * v2s;
     const double b2 = BB * (1.0 - v2) + Bv * Bv;
-    const double cs2 = g * P.p / rhoh;
-    const double vA2 = b2 / (rhoh + b2);
+    const double cs2 = g * P.p * fast_rcp(rhoh);
+    const double vA2 = b2 * fast_rcp(rhoh + b2);
     c2 = vA2 + cs2 * (1.0 - vA2);
   }
-  double disc = (1.0 - v2) * (1.0 - v2 * c2 - vn * vn * (1.0 - c2));
-  disc = disc > 0.0 ? disc : 0.0;
-  return (fabs(vn) * (1.0 - c2) + sqrt(c2 * disc)) / (1.0 - v2 * c2);
+  const double disc = (1.0 - v2) * (1.0 - v2 * c2 - vn * vn * (1.0 - c2));
+  return (fabs(vn) * (1.0 - c2) + fast_sqrt(c2 * disc)) * fast_rcp(1.0 - v2 * c2);
 }
 
 // ---------------------------------------------------------------- recovery
@@ -246,7 +280,7 @@ template <int SYS>
 DG_HD Prim prims_at_pressure(const double *u, double g, double p) {
   Prim P;
   if (SYS == kNE) {
-    const double irho = 1.0 / u[0];
+    const double irho = fast_rcp(u[0]);
     P.rho = u[0];
     P.v[0] = u[1] * irho;
     P.v[1] = u[2] * irho;
@@ -256,13 +290,13 @@ DG_HD Prim prims_at_pressure(const double *u, double g, double p) {
     return P;
   }
   const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
-  const double Sabs = sqrt(S2);
+  const double Sabs = fast_sqrt(S2);
   const double z = u[4] + u[0] + p;
-  const double iz = 1.0 / z;
+  const double iz = fast_rcp(z);
   P.v[0] = u[1] * iz;
   P.v[1] = u[2] * iz;
   P.v[2] = u[3] * iz;
-  P.rho = u[0] * (sqrt((z - Sabs) * (z + Sabs)) * iz);
+  P.rho = u[0] * (fast_sqrt((z - Sabs) * (z + Sabs)) * iz);
   P.p = p;
   return P;
 }

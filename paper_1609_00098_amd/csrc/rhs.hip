@@ -38,6 +38,27 @@ __device__ __forceinline__ double sel3(int d, double a, double b, double c) {
 }
 __device__ __forceinline__ int sel3i(int d, int a, int b, int c) { return d == 0 ? a : (d == 1 ? b : c); }
 
+// Processing order of element groups (EPB consecutive elements along x):
+// bricks of 8 x 8 x 8 elements one after another, lexicographic inside a
+// brick, so that the neighbours a group reads across its faces were loaded
+// shortly before by the same XCD and are still in its L2 (in plain
+// lexicographic order the z neighbour of an element is a whole plane of
+// elements away).  Used when the group grid tiles into bricks exactly;
+// otherwise the order stays lexicographic.
+template <int EPB>
+__device__ __forceinline__ int brick_order(int seq, int nx, int ny, int nz) {
+  constexpr int BX = EPB >= 8 ? 1 : 8 / EPB, BY = 8, BZ = 8;
+  if (nx % EPB != 0) return seq;
+  const int ngx = nx / EPB;
+  if (ngx % BX != 0 || ny % BY != 0 || nz % BZ != 0 || 8 % EPB != 0) return seq;
+  constexpr int V = BX * BY * BZ;
+  const int b = seq / V, r = seq - b * V;
+  const int nbx = ngx / BX, nby = ny / BY;
+  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+  const int gx = bx * BX + r % BX, gy = by * BY + (r / BX) % BY, gz = bz * BZ + r / (BX * BY);
+  return gx + ngx * (gy + ny * gz);
+}
+
 template <int SYS, int N>
 constexpr int default_epb() {
   return (N == 1) ? 8 : (N == 2) ? 9 : (N == 3) ? (SYS == kMHD ? 2 : 4) : (N == 4) ? 2 : 1;
@@ -89,10 +110,13 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(co
   __shared__ double sspd[C::SPD];
   __shared__ double sD[NP * NP];
 
-  // XCD-major block order: hardware block b runs on XCD b % 8.
+  // XCD-major block order: hardware block b runs on XCD b % 8, which walks
+  // its own contiguous range of the processing order.
   const int per = (A.nblocks + 7) >> 3;
-  const int grp = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (grp >= A.nblocks) return;
+  const int seq = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (seq >= A.nblocks) return;
+  int grp = seq;
+  if constexpr (!MIXED) grp = brick_order<EPB>(seq, A.nx, A.ny, A.nz);
 
   const int tid = threadIdx.x;
   for (int t = tid; t < NP * NP; t += C::THREADS) sD[t] = A.Dmat[t];
