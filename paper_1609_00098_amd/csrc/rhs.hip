@@ -26,6 +26,8 @@
 // and on faces whose neighbour has another degree loads the lift terms
 // F*.n - F.n (or their projection) that the mortar kernel wrote; conforming
 // faces are handled exactly as above.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "physics.hpp"
 
@@ -193,14 +195,19 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(co
     __syncthreads();
   }
 
-  // ---- face terms: dense assignment of the EPB*6*(N+1)^2 face nodes
-  for (int t = tid; t < C::FACE_TASKS; t += C::THREADS) {
-    const int fle = t / (6 * NF);
-    const int r = t - fle * 6 * NF;
-    const int f = r / NF;
-    const int fn = r - f * NF;
+  // ---- face terms: dense assignment of the EPB*6*(N+1)^2 face nodes,
+  // ordered by direction so that each branch is compiled for a fixed d (no
+  // run-time selects in the fluxes and speeds); a wave spans at most two
+  // directions
+  auto face_task = [&](auto dc, int r) {
+    constexpr int d = decltype(dc)::value;
+    const int fle = r / (2 * NF);
+    const int r2 = r - fle * 2 * NF;
+    const int side = r2 / NF;
+    const int fn = r2 - side * NF;
+    const int f = 2 * d + side;
     const int64_t fsl = (int64_t)grp * EPB + fle;
-    if (fsl >= (MIXED ? A.nlist : A.nelem)) continue;
+    if (fsl >= (MIXED ? A.nlist : A.nelem)) return;
     const int64_t fe = MIXED ? (int64_t)A.elist[fsl] : fsl;
     if constexpr (MIXED) {
       const int64_t fo = A.foff[fe * 6 + f];
@@ -208,14 +215,13 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(co
         double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
 #pragma unroll
         for (int v = 0; v < NV; ++v) slot[v * 6 * NF] = A.facebuf[fo + v * NF + fn];
-        continue;
+        return;
       }
     }
-    const int d = f >> 1, side = f & 1;
     const int ta = fn % NP, tb = fn / NP;
     int c0, c1, c2, n0, n1, n2;
-    if (d == 0) { c0 = side ? N : 0; c1 = ta; c2 = tb; n0 = side ? 0 : N; n1 = ta; n2 = tb; }
-    else if (d == 1) { c0 = ta; c1 = side ? N : 0; c2 = tb; n0 = ta; n1 = side ? 0 : N; n2 = tb; }
+    if constexpr (d == 0) { c0 = side ? N : 0; c1 = ta; c2 = tb; n0 = side ? 0 : N; n1 = ta; n2 = tb; }
+    else if constexpr (d == 1) { c0 = ta; c1 = side ? N : 0; c2 = tb; n0 = ta; n1 = side ? 0 : N; n2 = tb; }
     else { c0 = ta; c1 = tb; c2 = side ? N : 0; n0 = ta; n1 = tb; n2 = side ? 0 : N; }
     const int64_t en = A.nbr[fe * 6 + f];
     const int ai = c0 + NP * (c1 + NP * c2);
@@ -235,6 +241,12 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(co
       const double Fi = slot[v * 6 * NF];
       slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * al * (ue[v] - own[v * NPE]);
     }
+  };
+  constexpr int TPD = EPB * 2 * NF;  // tasks per direction
+  for (int t = tid; t < C::FACE_TASKS; t += C::THREADS) {
+    if (t < TPD) face_task(std::integral_constant<int, 0>{}, t);
+    else if (t < 2 * TPD) face_task(std::integral_constant<int, 1>{}, t - TPD);
+    else face_task(std::integral_constant<int, 2>{}, t - 2 * TPD);
   }
   __syncthreads();
 
