@@ -73,8 +73,12 @@ struct RhsCfg {
   static constexpr int NF = NP * NP;
   static constexpr int NV = SysTraits<SYS>::nv;
   static constexpr int EPB = EPB_;
-  static constexpr int THREADS = ((EPB * NPE + 63) / 64) * 64;
   static constexpr int FACE_TASKS = EPB * 6 * NF;
+  // one thread per volume node; SRMHD gets one per face task when there are
+  // more of those (its face tasks are long, a second round of them costs
+  // more than the idle threads of the volume phase: measured 5% at degree 3)
+  static constexpr int WORK = (SYS == kMHD && FACE_TASKS > EPB * NPE) ? FACE_TASKS : EPB * NPE;
+  static constexpr int THREADS = ((WORK + 63) / 64) * 64;
   // LDS (doubles): volume flux [EPB][NV][NPE], own state [EPB][NV][NPE],
   // face slots [EPB][NV][6][NF], interior wave speeds [EPB][6][NF]
   static constexpr int VOL = EPB * NV * NPE;
