@@ -151,6 +151,9 @@ struct dgmi_ctx {
   int lane_order[9] = {0};        // degrees in launch order (largest work first)
   int ndeg = 0;
   double last_dt = NAN;           // dt held by d_dt
+  bool single_launch = true;      // all degrees' element kernels in one launch
+  int32_t *d_blk = nullptr;       // [2][nblk] workgroup table of the single launch
+  int nblk = 0;
   hipStream_t side[8] = {nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[8] = {nullptr};
   hipGraph_t graph = nullptr;
@@ -287,6 +290,28 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
     }
     c->ndeg = nd;
   }
+  // workgroup table of the single-launch element kernel: degrees highest
+  // first, each degree's element list cut into groups of mixed_all_epb
+  {
+    std::vector<int32_t> bdeg, bgrp;
+    for (int N = dgmi::kMaxMixedDegree; N >= 1; --N) {
+      const int e = dgmi::mixed_all_epb(c->sys, N);
+      const int64_t nb = (c->lcount[N] + e - 1) / e;
+      for (int64_t g = 0; g < nb; ++g) {
+        bdeg.push_back(N);
+        bgrp.push_back((int32_t)g);
+      }
+    }
+    c->nblk = (int)bdeg.size();
+    if (hipMalloc(&c->d_blk, sizeof(int32_t) * 2 * (bdeg.size() + 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the workgroup table failed");
+    }
+    if (c->nblk > 0) {
+      HIP_TRY(hipMemcpy(c->d_blk, bdeg.data(), sizeof(int32_t) * bdeg.size(), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(c->d_blk + c->nblk, bgrp.data(), sizeof(int32_t) * bgrp.size(), hipMemcpyHostToDevice));
+    }
+  }
   if (c->flags & DGMI_FLAG_AUTOTUNE) return autotune(c);
   return DGMI_OK;
 }
@@ -314,6 +339,48 @@ static dgmi::RhsArgs mix_args(dgmi_ctx *c, int N) {
   return a;
 }
 
+static dgmi::MixedAllArgs all_args(dgmi_ctx *c) {
+  dgmi::MixedAllArgs m{};
+  m.blk_deg = c->d_blk;
+  m.blk_grp = c->d_blk + c->nblk;
+  m.nblocks = c->nblk;
+  for (int N = 0; N < 8; ++N) {
+    m.lstart[N] = c->lstart[N];
+    m.lcount[N] = c->lcount[N];
+    m.inv_wend[N] = N >= 1 ? 1.0 / c->wend[N] : 0.0;
+  }
+  m.D = c->d_D;
+  return m;
+}
+
+// The element kernels of one pass: all degrees in one launch on s, or the
+// per-degree kernels spread over the context's streams.
+static dgmi_status element_pass(dgmi_ctx *c, int stage, const dgmi::RhsArgs &base, bool single, hipStream_t s) {
+  if (single) {
+    dgmi::RhsArgs a = base;
+    a.elist = c->d_elist;
+    HIP_TRY(dgmi::launch_rhs_mixed_all(c->sys, stage, a, all_args(c), s));
+    return DGMI_OK;
+  }
+  HIP_TRY(hipEventRecord(c->ev_fork, s));
+  bool used[kMixedLanes] = {false};
+  for (int i = 0; i < c->ndeg; ++i) {
+    const int N = c->lane_order[i], k = c->lane_of[N];
+    dgmi::RhsArgs a = mix_args(c, N);
+    a.U = base.U; a.P = base.P; a.out = base.out; a.Un = base.Un; a.Pout = base.Pout;
+    a.a = base.a; a.b = base.b; a.full_prims = base.full_prims;
+    if (!used[k]) HIP_TRY(hipStreamWaitEvent(c->side[k], c->ev_fork, 0));
+    used[k] = true;
+    HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, c->epb[N], stage, a, c->side[k]));
+  }
+  for (int k = 0; k < kMixedLanes; ++k) {
+    if (!used[k]) continue;
+    HIP_TRY(hipEventRecord(c->ev_join[k], c->side[k]));
+    HIP_TRY(hipStreamWaitEvent(s, c->ev_join[k], 0));
+  }
+  return DGMI_OK;
+}
+
 static dgmi::MortarArgs mortar_args(dgmi_ctx *c, const double *U, const double *P) {
   dgmi::MortarArgs m{};
   m.U = U;
@@ -334,27 +401,13 @@ static dgmi::MortarArgs mortar_args(dgmi_ctx *c, const double *U, const double *
 }
 
 // One operator / stage pass over every degree: the mortar kernel writes the
-// lift terms of the non-conforming faces, then the per-degree element kernels
-// run concurrently on the context's side streams, joined back into s.
+// lift terms of the non-conforming faces, then the element kernels run.
 static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const double *P, double *out,
                               const double *Un, double *Pout, double wa, double wb, int full_prims, hipStream_t s) {
   HIP_TRY(dgmi::launch_mortar(c->sys, mortar_args(c, U, P), s));
-  HIP_TRY(hipEventRecord(c->ev_fork, s));
-  bool used[kMixedLanes] = {false};
-  for (int i = 0; i < c->ndeg; ++i) {
-    const int N = c->lane_order[i], k = c->lane_of[N];
-    dgmi::RhsArgs a = mix_args(c, N);
-    a.U = U; a.P = P; a.out = out; a.Un = Un; a.Pout = Pout; a.a = wa; a.b = wb; a.full_prims = full_prims;
-    if (!used[k]) HIP_TRY(hipStreamWaitEvent(c->side[k], c->ev_fork, 0));
-    used[k] = true;
-    HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, c->epb[N], stage, a, c->side[k]));
-  }
-  for (int k = 0; k < kMixedLanes; ++k) {
-    if (!used[k]) continue;
-    HIP_TRY(hipEventRecord(c->ev_join[k], c->side[k]));
-    HIP_TRY(hipStreamWaitEvent(s, c->ev_join[k], 0));
-  }
-  return DGMI_OK;
+  dgmi::RhsArgs a = mix_args(c, dgmi::kMaxMixedDegree);
+  a.U = U; a.P = P; a.out = out; a.Un = Un; a.Pout = Pout; a.a = wa; a.b = wb; a.full_prims = full_prims;
+  return element_pass(c, stage, a, c->single_launch, s);
 }
 
 static dgmi_status mixed_step_enqueue(dgmi_ctx *c, double *U, double *P, hipStream_t s) {
@@ -400,6 +453,21 @@ static dgmi_status autotune(dgmi_ctx *c) {
       }
     }
   }
+  // single launch against the per-degree kernels on their streams
+  float tmode[2] = {0.f, 0.f};
+  for (int mode = 0; mode < 2; ++mode) {
+    dgmi::RhsArgs a = mix_args(c, dgmi::kMaxMixedDegree);
+    a.U = c->d_U1; a.P = c->d_P1; a.out = c->d_U2;
+    dgmi_status st = element_pass(c, 0, a, mode == 0, s);
+    if (st != DGMI_OK) return st;
+    HIP_TRY(hipEventRecord(t0, s));
+    for (int r = 0; r < 5 && st == DGMI_OK; ++r) st = element_pass(c, 0, a, mode == 0, s);
+    if (st != DGMI_OK) return st;
+    HIP_TRY(hipEventRecord(t1, s));
+    HIP_TRY(hipEventSynchronize(t1));
+    HIP_TRY(hipEventElapsedTime(&tmode[mode], t0, t1));
+  }
+  c->single_launch = tmode[0] <= tmode[1];
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   HIP_TRY(hipStreamSynchronize(s));
@@ -427,6 +495,7 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_Ptab);
   (void)hipFree(c->d_Qtab);
   (void)hipFree(c->d_foff);
+  (void)hipFree(c->d_blk);
   (void)hipFree(c->d_faces);
   (void)hipFree(c->d_facebuf);
   (void)hipFree(c->d_dt);

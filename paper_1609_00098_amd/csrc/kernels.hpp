@@ -61,6 +61,19 @@ struct MortarArgs {
   double gamma;
 };
 
+// All degrees of a mixed mesh in one launch: a table of workgroups (degree,
+// element group within that degree's list), highest degree first.
+struct MixedAllArgs {
+  const int32_t *blk_deg, *blk_grp;
+  int nblocks;
+  int64_t lstart[8], lcount[8];  // per degree: start and length in the element list
+  const double *D;               // [8][64] differentiation matrices
+  double inv_wend[8];
+};
+// Elements per workgroup of degree N in the single-launch kernel.
+int mixed_all_epb(int sys, int N);
+hipError_t launch_rhs_mixed_all(int sys, int stage, const RhsArgs &a, const MixedAllArgs &m, hipStream_t s);
+
 // Elements-per-workgroup options of the mixed-degree element kernel for
 // (system, degree); returns how many were written to epb_out (at most 2).
 int mixed_tile_options(int sys, int N, int *epb_out);

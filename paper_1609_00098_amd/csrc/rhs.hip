@@ -85,6 +85,7 @@ struct RhsCfg {
   static constexpr int OWN = EPB * NV * NPE;
   static constexpr int SLOT = EPB * NV * 6 * NF;
   static constexpr int SPD = EPB * 6 * NF;
+  static constexpr int LDS = VOL + OWN + SLOT + SPD + NP * NP;  // doubles
 };
 
 // A node's conserved state and primitives.  SRMHD reads all five primitive
@@ -106,26 +107,20 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
   }
 }
 
-template <int SYS, int N, int STAGE, int EPB_ = default_epb<SYS, N>(), bool MIXED = false>
-__global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(const RhsArgs A) {
+// The work of one workgroup on element group grp, with BT threads and the
+// LDS block smem (the kernels below choose grp and provide both).
+template <int SYS, int N, int STAGE, int EPB_, bool MIXED, int BT>
+__device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem) {
   using C = RhsCfg<SYS, N, EPB_>;
   constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
-  __shared__ double svol[C::VOL];
-  __shared__ double sown[C::OWN];
-  __shared__ double sslot[C::SLOT];
-  __shared__ double sspd[C::SPD];
-  __shared__ double sD[NP * NP];
-
-  // XCD-major block order: hardware block b runs on XCD b % 8, which walks
-  // its own contiguous range of the processing order.
-  const int per = (A.nblocks + 7) >> 3;
-  const int seq = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (seq >= A.nblocks) return;
-  int grp = seq;
-  if constexpr (!MIXED) grp = brick_order<EPB>(seq, A.nx, A.ny, A.nz);
+  double *svol = smem;
+  double *sown = svol + C::VOL;
+  double *sslot = sown + C::OWN;
+  double *sspd = sslot + C::SLOT;
+  double *sD = sspd + C::SPD;
 
   const int tid = threadIdx.x;
-  for (int t = tid; t < NP * NP; t += C::THREADS) sD[t] = A.Dmat[t];
+  for (int t = tid; t < NP * NP; t += BT) sD[t] = A.Dmat[t];
 
   const int le = tid / NPE;
   const int a = tid - le * NPE;
@@ -247,7 +242,7 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(co
     }
   };
   constexpr int TPD = EPB * 2 * NF;  // tasks per direction
-  for (int t = tid; t < C::FACE_TASKS; t += C::THREADS) {
+  for (int t = tid; t < C::FACE_TASKS; t += BT) {
     if (t < TPD) face_task(std::integral_constant<int, 0>{}, t);
     else if (t < 2 * TPD) face_task(std::integral_constant<int, 1>{}, t - TPD);
     else face_task(std::integral_constant<int, 2>{}, t - 2 * TPD);
@@ -291,6 +286,89 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(co
   }
   A.Pout[4 * nn + q] = R.P.p;
   if (!R.ok) atomicAdd(A.nfail, 1ull);
+}
+
+// Uniform mesh (or one degree of a mixed mesh): one launch, EPB elements
+// per workgroup, one thread per volume node.
+template <int SYS, int N, int STAGE, int EPB_ = default_epb<SYS, N>(), bool MIXED = false>
+__global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(const RhsArgs A) {
+  using C = RhsCfg<SYS, N, EPB_>;
+  __shared__ double smem[C::LDS];
+  // XCD-major block order: hardware block b runs on XCD b % 8, which walks
+  // its own contiguous range of the processing order.
+  const int per = (A.nblocks + 7) >> 3;
+  const int seq = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (seq >= A.nblocks) return;
+  int grp = seq;
+  if constexpr (!MIXED) grp = brick_order<C::EPB>(seq, A.nx, A.ny, A.nz);
+  rhs_body<SYS, N, STAGE, EPB_, MIXED, C::THREADS>(A, grp, smem);
+}
+
+// Every degree of a mixed mesh in one launch: 512-thread workgroups, each
+// taking one group of elements of one degree from a block table ordered by
+// degree (highest first); per degree as many elements per workgroup as fit
+// 512 threads and the LDS budget of the largest degree.
+constexpr int kAllThreads = 512;
+template <int SYS>
+constexpr int all_budget() {  // doubles of LDS: 64 KB, or degree 7 alone if larger
+  return RhsCfg<SYS, 7, 1>::LDS > 8192 ? RhsCfg<SYS, 7, 1>::LDS : 8192;
+}
+template <int SYS, int N>
+constexpr int all_epb() {
+  int e = kAllThreads / ((N + 1) * (N + 1) * (N + 1));
+  if (e < 1) e = 1;
+  while (e > 1 && (e * (RhsCfg<SYS, N, 1>::LDS - (N + 1) * (N + 1)) + (N + 1) * (N + 1)) > all_budget<SYS>()) --e;
+  return e;
+}
+
+template <int SYS, int STAGE>
+__global__ void __launch_bounds__(kAllThreads) rhs_mixed_all_kernel(const RhsArgs A, const MixedAllArgs M) {
+  __shared__ double smem[all_budget<SYS>()];
+  const int b = blockIdx.x;
+  if (b >= M.nblocks) return;
+  const int N = M.blk_deg[b];
+  const int grp = M.blk_grp[b];
+  RhsArgs a = A;
+  a.elist = A.elist + M.lstart[N];
+  a.nlist = M.lcount[N];
+  a.Dmat = M.D + 64 * N;
+  a.inv_wend = M.inv_wend[N];
+  switch (N) {
+    case 1: rhs_body<SYS, 1, STAGE, all_epb<SYS, 1>(), true, kAllThreads>(a, grp, smem); break;
+    case 2: rhs_body<SYS, 2, STAGE, all_epb<SYS, 2>(), true, kAllThreads>(a, grp, smem); break;
+    case 3: rhs_body<SYS, 3, STAGE, all_epb<SYS, 3>(), true, kAllThreads>(a, grp, smem); break;
+    case 4: rhs_body<SYS, 4, STAGE, all_epb<SYS, 4>(), true, kAllThreads>(a, grp, smem); break;
+    case 5: rhs_body<SYS, 5, STAGE, all_epb<SYS, 5>(), true, kAllThreads>(a, grp, smem); break;
+    case 6: rhs_body<SYS, 6, STAGE, all_epb<SYS, 6>(), true, kAllThreads>(a, grp, smem); break;
+    case 7: rhs_body<SYS, 7, STAGE, all_epb<SYS, 7>(), true, kAllThreads>(a, grp, smem); break;
+  }
+}
+
+int mixed_all_epb(int sys, int N) {
+  static const int t[3][8] = {
+      {0, all_epb<kNE, 1>(), all_epb<kNE, 2>(), all_epb<kNE, 3>(), all_epb<kNE, 4>(), all_epb<kNE, 5>(),
+       all_epb<kNE, 6>(), all_epb<kNE, 7>()},
+      {0, all_epb<kSR, 1>(), all_epb<kSR, 2>(), all_epb<kSR, 3>(), all_epb<kSR, 4>(), all_epb<kSR, 5>(),
+       all_epb<kSR, 6>(), all_epb<kSR, 7>()},
+      {0, all_epb<kMHD, 1>(), all_epb<kMHD, 2>(), all_epb<kMHD, 3>(), all_epb<kMHD, 4>(), all_epb<kMHD, 5>(),
+       all_epb<kMHD, 6>(), all_epb<kMHD, 7>()}};
+  if (sys < 0 || sys > 2 || N < 1 || N > 7) return 0;
+  return t[sys][N];
+}
+
+hipError_t launch_rhs_mixed_all(int sys, int stage, const RhsArgs &a, const MixedAllArgs &m, hipStream_t s) {
+  if (m.nblocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)m.nblocks), block(kAllThreads);
+  switch (sys * 2 + (stage ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((rhs_mixed_all_kernel<kNE, 0>), grid, block, 0, s, a, m); break;
+    case 1: hipLaunchKernelGGL((rhs_mixed_all_kernel<kNE, 1>), grid, block, 0, s, a, m); break;
+    case 2: hipLaunchKernelGGL((rhs_mixed_all_kernel<kSR, 0>), grid, block, 0, s, a, m); break;
+    case 3: hipLaunchKernelGGL((rhs_mixed_all_kernel<kSR, 1>), grid, block, 0, s, a, m); break;
+    case 4: hipLaunchKernelGGL((rhs_mixed_all_kernel<kMHD, 0>), grid, block, 0, s, a, m); break;
+    case 5: hipLaunchKernelGGL((rhs_mixed_all_kernel<kMHD, 1>), grid, block, 0, s, a, m); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int SYS, int N>
