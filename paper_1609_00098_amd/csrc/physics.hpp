@@ -29,6 +29,41 @@ struct Prim {
 
 DG_HD double sq(double x) { return x * x; }
 
+// ---------------------------------------------------------------- fast FP64
+// Reciprocal and square root for quantities that feed the wave speeds and
+// the primitives rebuilt from (U, p): the hardware estimate refined by
+// Newton-Raphson steps on the device (within about an ulp; the IEEE-rounded
+// expansions cost two to three times the instructions), exact on the host.
+DG_HD double fast_rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
+// sqrt(x) for x >= 0 (0 for x <= 0).
+DG_HD double fast_sqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // Goldschmidt iteration from the hardware 1/sqrt estimate: g -> sqrt(x),
+  // h -> 1/(2 sqrt(x)), then one Newton correction of g with the residual
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r, h = 0.5 * r;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  const double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
+#else
+  return x > 0.0 ? sqrt(x) : 0.0;
+#endif
+}
+
 // ---------------------------------------------------------------- p -> U
 // NE: (rho, rho v, p/(g-1) + rho v^2/2).
 // SR: D = rho W, S = rho h W^2 v, tau = rho h W^2 - p - D, rho h = rho + g p/(g-1).
@@ -194,41 +229,6 @@ DG_HD void flux_all(const double *u, const Prim &P, double (*F)[SysTraits<SYS>::
   }
 }
 
-// ---------------------------------------------------------------- fast FP64
-// Reciprocal and square root for quantities that feed the wave speeds and
-// the primitives rebuilt from (U, p): the hardware estimate refined by
-// Newton-Raphson steps on the device (within about an ulp; the IEEE-rounded
-// expansions cost two to three times the instructions), exact on the host.
-DG_HD double fast_rcp(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-#else
-  return 1.0 / x;
-#endif
-}
-
-// sqrt(x) for x >= 0 (0 for x <= 0).
-DG_HD double fast_sqrt(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  // Goldschmidt iteration from the hardware 1/sqrt estimate: g -> sqrt(x),
-  // h -> 1/(2 sqrt(x)), then one Newton correction of g with the residual
-  const double r = __builtin_amdgcn_rsq(x);
-  double g = x * r, h = 0.5 * r;
-  const double e = fma(-h, g, 0.5);
-  g = fma(g, e, g);
-  h = fma(h, e, h);
-  const double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  return x > 0.0 ? g : 0.0;
-#else
-  return x > 0.0 ? sqrt(x) : 0.0;
-#endif
-}
-
 // ---------------------------------------------------------------- speeds
 // Largest |lambda| along +-e_d for the fluid sub-system.
 // NE: |v_n| + c_s.  SR / MHD: the acoustic (fast) pair
@@ -316,7 +316,7 @@ DG_HD double cubic_top_root(double e, double d, double x0) {
     const double q = x * x * (x - e) + d;
     const double dq = x * (3.0 * x - 2.0 * e);
     if (!(dq > 0.0)) return -1.0;
-    const double dx = q / dq;
+    const double dx = q * fast_rcp(dq);
     x -= dx;
     if (fabs(dx) <= 4.0e-16 * x) break;
   }
@@ -405,8 +405,8 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
       // division t = 1/(z sqrt(q)) gives 1/z, W and sqrt(1 - v^2)
       z = tau + D + p;
       const double q = (z - Sabs) * (z + Sabs);
-      const double sqq = sqrt(q);
-      t = 1.0 / (z * sqq);
+      const double sqq = fast_sqrt(q);
+      t = fast_rcp(z * sqq);
       iz = sqq * t;
       v2 = S2 * iz * iz;
       uu = q * iz * iz;
@@ -418,7 +418,7 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
       em = cubic_top_root(e, dcub, fmin(x0, e));
       z = em - BB;
       valid = (em > 0.0) && (z > 0.0);
-      v2 = valid ? (S2 * z * z + T * T * (z + em)) / (z * z * em * em) : 1.0;
+      v2 = valid ? (S2 * z * z + T * T * (z + em)) * fast_rcp(z * z * em * em) : 1.0;
       if (valid) { em_prev = em; e_prev = e; }
     }
     valid = valid && (v2 < 1.0);
@@ -431,8 +431,8 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     }
     if (SYS == kMHD) {
       uu = 1.0 - v2;  // 1/W^2
-      sqw = sqrt(uu);
-      W = 1.0 / sqw;
+      sqw = fast_sqrt(uu);
+      W = fast_rcp(sqw);
     }
     const double rho_eps = z * uu - D * sqw - p;
     const double f = gm1 * rho_eps - p;
@@ -445,8 +445,8 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     if (SYS == kSR) {
       df = gm1 * v2 * (1.0 - D * z * t) - 1.0;  // W / z = z t
     } else {
-      const double dem = em / (3.0 * em - 2.0 * e);  // d eps_m / dp
-      const double iz = 1.0 / z, iem = 1.0 / em;
+      const double dem = em * fast_rcp(3.0 * em - 2.0 * e);  // d eps_m / dp
+      const double iz = fast_rcp(z), iem = fast_rcp(em);
       const double dv2 = -2.0 * dem * (S2 * iem * iem * iem +
                                        T * T * (iz * iz * iem * iem + iz * iem * iem * iem + iz * iz * iz * iem));
       const double drho_eps = dem * uu - dv2 * (z - 0.5 * D * W) - 1.0;
@@ -498,7 +498,7 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     const double x0 = (em_prev > 0.0) ? fmax(em_prev + (e - e_prev), 2.0 * e / 3.0 + 1e-3 * e) : e;
     em = cubic_top_root(e, dcub, fmin(x0, e));
     z = em - BB;
-    const double Tz = T / z, iem = 1.0 / em;
+    const double Tz = T * fast_rcp(z), iem = fast_rcp(em);
     R.P.v[0] = (S0 + Tz * u[5]) * iem;
     R.P.v[1] = (S1 + Tz * u[6]) * iem;
     R.P.v[2] = (S2c + Tz * u[7]) * iem;
@@ -506,7 +506,7 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     conv = conv && (em > 0.0) && (z > 0.0);
   }
   R.P.p = p;
-  if (SYS == kMHD) rho_w = sqrt(1.0 - v2);
+  if (SYS == kMHD) rho_w = fast_sqrt(1.0 - v2);
   R.P.rho = D * rho_w;
   R.ok = conv && (v2 < 1.0) && (p > 0.0) && (R.P.rho > 0.0);
   return R;
