@@ -41,7 +41,7 @@ struct Interp {
 template <int SYS>
 __device__ __forceinline__ void interp_to_state(const double *s, double g, double *u, Prim &P) {
   double iW = 1.0;
-  if (SYS != kNE) iW = 1.0 / sqrt(1.0 + s[1] * s[1] + s[2] * s[2] + s[3] * s[3]);
+  if (SYS != kNE) iW = fast_rcp(fast_sqrt(1.0 + s[1] * s[1] + s[2] * s[2] + s[3] * s[3]));
   P.rho = s[0];
   P.v[0] = s[1] * iW;
   P.v[1] = s[2] * iW;
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     Prim P;
     load_node<SYS>(A.U, A.P, nn, q, A.gamma, u, P);
     double W = 1.0;
-    if (SYS != kNE) W = 1.0 / sqrt(1.0 - (P.v[0] * P.v[0] + P.v[1] * P.v[1] + P.v[2] * P.v[2]));
+    if (SYS != kNE) W = fast_rcp(fast_sqrt(1.0 - (P.v[0] * P.v[0] + P.v[1] * P.v[1] + P.v[2] * P.v[2])));
     st[l] = P.rho;
     st[64 + l] = P.v[0] * W;
     st[128 + l] = P.v[1] * W;

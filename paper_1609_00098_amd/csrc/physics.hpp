@@ -80,8 +80,8 @@ DG_HD void prim_to_cons(const Prim &P, const double *mag, double g, double *u) {
     u[4] = P.p / (g - 1.0) + 0.5 * P.rho * v2;
     return;
   }
-  const double W2 = 1.0 / (1.0 - v2);
-  const double W = sqrt(W2);
+  const double W2 = fast_rcp(1.0 - v2);
+  const double W = fast_sqrt(W2);
   const double rhoh = P.rho + g / (g - 1.0) * P.p;
   const double z = rhoh * W2;
   const double D = P.rho * W;
