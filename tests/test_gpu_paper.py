@@ -1,6 +1,12 @@
-"""The HIP path reproduces the paper's convergence table for the 3D
-relativistic smooth flow (tab:RE3D_convergence) at mesh sizes the CPU oracle
-cannot reach in seconds: density wave rho = 1 + 0.2 sin(2 pi (x + y + z - 0.6 t)),
+"""The HIP path reproduces the paper's convergence tables.
+
+tab:Bugner_comparison (Appendix B): the 1D relativistic smooth flow, run here
+as a 3D mesh of n_x x 1 x 1 elements (the state is constant along y and z,
+so those directions contribute only rounding), dt = 1e-4 to T = 2, all 24
+printed entries to their three digits (down to the rounding floor).
+
+tab:RE3D_convergence, including mesh sizes the CPU oracle cannot reach in
+seconds: density wave rho = 1 + 0.2 sin(2 pi (x + y + z - 0.6 t)),
 v = (0.2, 0.2, 0.2), p = 1, gamma 5/3, periodic unit cube of K^3 elements
 with N_C GLL points per direction, LLF flux, SSP-RK3 with dt = 1.7e-4 (one
 final partial step to reach T = 2), L1 error of the conserved variables at
@@ -59,7 +65,13 @@ def _re3d_gpu(ora, dg, NC, K):
     assert abs(err - expected) <= 0.5e-1 * expected * 1.0001, (err, expected)
 
 
-@pytest.mark.parametrize("NC,K", [(2, 4), (3, 4), (4, 4), (5, 4), (2, 8), (3, 8), (4, 8), (5, 8), (6, 4), (2, 16)])
+# K = 1 only for N_C = 2, 3: the table's caption has K running from 2, and for
+# N_C >= 4 its K = 1 entries (0.30, 0.18, 0.11) are reproduced by neither
+# implementation (oracle and GPU agree on 0.159, recovery failures, 0.0251):
+# a single element cannot resolve the wave and those entries follow a setup
+# the paper does not describe.
+@pytest.mark.parametrize("NC,K", [(2, 1), (3, 1)] + [(nc, 2) for nc in (2, 3, 4, 5, 6)] +
+                         [(2, 4), (3, 4), (4, 4), (5, 4), (2, 8), (3, 8), (4, 8), (5, 8), (6, 4), (2, 16)])
 def test_re3d_table_on_gpu(ora, dg, NC, K):
     _re3d_gpu(ora, dg, NC, K)
 
@@ -69,3 +81,38 @@ def test_re3d_table_on_gpu(ora, dg, NC, K):
                                   (2, 64), (3, 64), (4, 64), (5, 64)])
 def test_re3d_table_on_gpu_large(ora, dg, NC, K):
     _re3d_gpu(ora, dg, NC, K)
+
+
+def _bugner_gpu(ora, dg, NC, nx):
+    import torch
+    tab = json.load(open(os.path.join(GOLD, "bugner_table.json")))
+    expected = tab["rows_NC"][str(NC)][tab["columns_nx"].index(nx)]
+    g, T, dt, v = 5.0 / 3.0, 2.0, 1e-4, (0.2, 0.0, 0.0)
+    m = ora.mesh(SR, (nx, 1, 1), NC - 1, g)
+    G = dg.Mesh(SR, (nx, 1, 1), NC - 1, g)
+    xyz = ora.node_coords(m)
+    act = (True, False, False)
+    prim0 = synth.smooth_flow(xyz, 0.0, 0.2, 2 * math.pi, v, active=act)
+    U = to_dev(ora.prim2cons(SR, g, prim0))
+    P = to_dev(prim0)
+    nfull = int(math.floor(T / dt + 1e-9))
+    for _ in range(nfull):
+        dg.dg_step(G, U, P, dt)
+    rem = T - nfull * dt
+    if rem > 1e-12:
+        dg.dg_step(G, U, P, rem)
+    torch.cuda.synchronize()
+    assert dg.dgmi_failures(G) == 0
+    Ue = ora.prim2cons(SR, g, synth.smooth_flow(xyz, T, 0.2, 2 * math.pi, v, active=act))
+    err = ora.l1_error(m, Ue, to_host(U))
+    print(f"Bugner N_C={NC} n_x={nx}: L1 {err:.4e}, printed {expected:.2e}", flush=True)
+    # three significant digits printed, or 2e-12 absolute for the finest
+    # meshes of N_C = 4, 5, where the error reaches the level of FP64
+    # rounding accumulated over 20,000 steps (the paper's own comparison with
+    # the reference code agrees to a few 1e-12 there)
+    assert abs(err - expected) <= max(0.5e-2 * expected * 1.0001, 2e-12), (err, expected)
+
+
+@pytest.mark.parametrize("NC,nx", [(nc, n) for nc in (2, 3, 4, 5) for n in (10, 20, 40, 80, 160, 320)])
+def test_bugner_table_on_gpu(ora, dg, NC, nx):
+    _bugner_gpu(ora, dg, NC, nx)
