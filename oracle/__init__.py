@@ -42,20 +42,22 @@ _lib = None
 
 class Mesh(ctypes.Structure):
     _fields_ = [("sys", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("nz", ctypes.c_int32), ("deg", ctypes.c_int32 * 3), ("pad", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("deg", ctypes.c_int32 * 3), ("flux", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
 
 
-def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), kappa=0.0):
+def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), kappa=0.0, flux="llf"):
     """Periodic box of nelem=(nx,ny,nz) affine elements.  degree is an int or a
-    per-direction triple; a 0 entry collapses that direction."""
+    per-direction triple; a 0 entry collapses that direction.  flux: "llf"
+    (eq. LLF) or "hll" (eq. HLL)."""
     if isinstance(degree, int):
         degree = (degree, degree, degree)
     m = Mesh()
     m.sys = system
     m.nx, m.ny, m.nz = nelem
     m.deg[:] = list(degree)
+    m.flux = {"llf": 0, "hll": 1}[flux]
     m.gamma = gamma
     m.kappa = kappa
     m.lo[:] = list(lo)
@@ -98,6 +100,7 @@ def _load():
         "ora_evolve": (I64, [MP, D, ctypes.c_double, I64]),
         "ora_l1_error": (ctypes.c_double, [MP, ctypes.c_int, D, D]),
         "ora_integrate": (ctypes.c_int, [MP, ctypes.c_int, D, D]),
+        "ora_hll": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, D, D, D, D, D]),
         "ora_mixed_num_nodes": (I64, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
         "ora_mixed_node_coords": (ctypes.c_int, [MP, ctypes.POINTER(ctypes.c_int32), D]),
         "ora_rhs_mixed": (I64, [MP, ctypes.POINTER(ctypes.c_int32), D, D, D]),
@@ -224,6 +227,12 @@ def max_speed(system, gamma, d, U, prim):
 def llf(system, gamma, d, sgn, ui, pi, ue, pe):
     out = np.zeros(NVARS[system])
     _load().ora_llf(system, gamma, d, sgn, _p(_c(ui)), _p(_c(pi)), _p(_c(ue)), _p(_c(pe)), _p(out))
+    return out
+
+
+def hll(system, gamma, d, sgn, ui, pi, ue, pe):
+    out = np.zeros(NVARS[system])
+    _load().ora_hll(system, gamma, d, sgn, _p(_c(ui)), _p(_c(pi)), _p(_c(ue)), _p(_c(pe)), _p(out))
     return out
 
 

@@ -506,6 +506,88 @@ static void llf(int sys, double g, int d, double sgn, const cons_t *Ci, const pr
   }
 }
 
+/* Signed characteristic speed bounds along +e_d, per component: lm[c] <= lp[c].
+ * NE: v_d -+ c_s.  SR, and the fluid part of MHD with the fast-speed bound:
+ * the acoustic pair of the SR wave-speed formula.  MHD (B_d, Phi): -+1.     */
+static void wave_speeds(int sys, double g, int d, const cons_t *C, const prim_t *P, double *lm, double *lp) {
+  const double *v = P->v;
+  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  int nv = nvars_of(sys);
+  double m, q;
+  if (sys == 0) {
+    double cs = sqrt(g * P->p / P->rho);
+    m = v[d] - cs;
+    q = v[d] + cs;
+  } else {
+    double h = 1.0 + P->p / ((g - 1.0) * P->rho) + P->p / P->rho;
+    double c2 = g * P->p / (P->rho * h);
+    if (sys == 2) {
+      double W = 1.0 / sqrt(1.0 - v2);
+      double b0, b[3], b2;
+      mhd_b(P, &C->u[5], W, &b0, b, &b2);
+      double vA2 = b2 / (P->rho * h + b2);
+      c2 = vA2 + c2 * (1.0 - vA2);
+    }
+    double vn = v[d];
+    double disc = (1.0 - v2) * (1.0 - v2 * c2 - vn * vn * (1.0 - c2));
+    if (disc < 0.0) disc = 0.0;
+    double c = sqrt(c2);
+    q = (vn * (1.0 - c2) + c * sqrt(disc)) / (1.0 - v2 * c2);
+    m = (vn * (1.0 - c2) - c * sqrt(disc)) / (1.0 - v2 * c2);
+  }
+  for (int c_ = 0; c_ < nv; ++c_) {
+    lm[c_] = m;
+    lp[c_] = q;
+  }
+  if (sys == 2) {
+    lm[5 + d] = -1.0; lp[5 + d] = 1.0;
+    lm[8] = -1.0; lp[8] = 1.0;
+  }
+}
+
+/* HLL numerical flux (eq. HLL) for one face point with the element's
+ * outward unit normal n = sgn e_d: with the speeds along n and
+ *   s+ = max(0, lambda+_int, lambda+_ext),  s- = min(0, lambda-_int, lambda-_ext),
+ *   F*.n = (s+ F(U_int).n - s- F(U_ext).n + s+ s- (U_ext - U_int)) / (s+ - s-).  */
+static void hll(int sys, double g, int d, double sgn, const cons_t *Ci, const prim_t *Pi, const cons_t *Ce,
+                const prim_t *Pe, double *Fstar_n, double *Fint_n) {
+  int nv = nvars_of(sys);
+  double fi[9], fe[9], lmi[9], lpi[9], lme[9], lpe[9];
+  flux(sys, g, d, Ci, Pi, fi);
+  flux(sys, g, d, Ce, Pe, fe);
+  wave_speeds(sys, g, d, Ci, Pi, lmi, lpi);
+  wave_speeds(sys, g, d, Ce, Pe, lme, lpe);
+  for (int c = 0; c < nv; ++c) {
+    /* speeds along n: for n = -e_d the bounds swap and change sign */
+    double pi_ = sgn > 0 ? lpi[c] : -lmi[c], mi_ = sgn > 0 ? lmi[c] : -lpi[c];
+    double pe_ = sgn > 0 ? lpe[c] : -lme[c], me_ = sgn > 0 ? lme[c] : -lpe[c];
+    double sp = fmax(0.0, fmax(pi_, pe_)), sm = fmin(0.0, fmin(mi_, me_));
+    double fin = sgn * fi[c], fen = sgn * fe[c];
+    Fint_n[c] = fin;
+    Fstar_n[c] = (sp * fin - sm * fen + sp * sm * (Ce->u[c] - Ci->u[c])) / (sp - sm);
+  }
+}
+
+/* The numerical flux selected by the mesh. */
+static void numflux(int kind, int sys, double g, int d, double sgn, const cons_t *Ci, const prim_t *Pi,
+                    const cons_t *Ce, const prim_t *Pe, double *Fstar_n, double *Fint_n) {
+  if (kind == 1)
+    hll(sys, g, d, sgn, Ci, Pi, Ce, Pe, Fstar_n, Fint_n);
+  else
+    llf(sys, g, d, sgn, Ci, Pi, Ce, Pe, Fstar_n, Fint_n);
+}
+
+int ora_hll(int sys, double g, int d, double sgn, const double *ui, const double *pi_, const double *ue,
+            const double *pe, double *fstar_n) {
+  cons_t Ci, Ce; prim_t Pi, Pe; double fin[9];
+  int nv = nvars_of(sys);
+  for (int v = 0; v < nv; ++v) { Ci.u[v] = ui[v]; Ce.u[v] = ue[v]; }
+  Pi.rho = pi_[0]; Pi.v[0] = pi_[1]; Pi.v[1] = pi_[2]; Pi.v[2] = pi_[3]; Pi.p = pi_[4];
+  Pe.rho = pe[0]; Pe.v[0] = pe[1]; Pe.v[1] = pe[2]; Pe.v[2] = pe[3]; Pe.p = pe[4];
+  hll(sys, g, d, sgn, &Ci, &Pi, &Ce, &Pe, fstar_n, fin);
+  return ORA_OK;
+}
+
 int ora_llf(int sys, double g, int d, double sgn, const double *ui, const double *pi_, const double *ue,
             const double *pe, double *fstar_n) {
   cons_t Ci, Ce; prim_t Pi, Pe; double fin[9];
@@ -525,7 +607,7 @@ typedef struct {
   int32_t sys;
   int32_t nx, ny, nz;
   int32_t deg[3];
-  int32_t pad;
+  int32_t flux; /* numerical flux: 0 local Lax-Friedrichs (eq. LLF), 1 HLL (eq. HLL) */
   double gamma, kappa;
   double lo[3], hi[3];
 } ora_mesh;
@@ -667,7 +749,7 @@ static int rhs_strong(const ora_mesh *m, const geom_t *G, const double *U, const
               load_cons(nv, N, U, en * npe + b, &Ce);
               load_prim(N, prim, en * npe + b, &Pe);
               double Fs[9], Fi[9];
-              llf(sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
+              numflux(m->flux, sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
               double wend = G->w[d][side ? Nd : 0];
               double sc = 2.0 / G->dx[d];
               for (int v = 0; v < nv; ++v) L[v] -= sc * (1.0 / wend) * (Fs[v] - Fi[v]);
@@ -740,7 +822,7 @@ static int rhs_weak(const ora_mesh *m, const geom_t *G, const double *U, const d
               load_cons(nv, N, U, en * npe + b, &Ce);
               load_prim(N, prim, en * npe + b, &Pe);
               double Fs[9], Fi[9];
-              llf(sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
+              numflux(m->flux, sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
               double sc = 2.0 / G->dx[d];
               for (int v = 0; v < nv; ++v) L[v] -= sc * Fs[v] / G->w[d][side ? Nd : 0];
             }
@@ -1064,7 +1146,7 @@ int64_t ora_rhs_mixed(const ora_mesh *m, const int32_t *deg, const double *U, do
         }
         for (int mm = 0; mm < nm * nm; ++mm) {
           double Fs[9], Fi[9];
-          llf(sys, g, d, sgn, &Cm[mm], &Pq[mm], &Cm[nm * nm + mm], &Pq[nm * nm + mm], Fs, Fi);
+          numflux(m->flux, sys, g, d, sgn, &Cm[mm], &Pq[mm], &Cm[nm * nm + mm], &Pq[nm * nm + mm], Fs, Fi);
           for (int v = 0; v < nv; ++v) fs[v * nm * nm + mm] = Fs[v];
         }
         /* Lift onto this element's face nodes.  Conforming side: F* - F.n at
