@@ -62,6 +62,9 @@ enum {
                                      replaying a captured graph */
 #define DGMI_FLAG_AUTOTUNE 8      /* mixed degrees: dgmi_create times every tile option per degree and
                                      keeps the fastest (results do not depend on the choice) */
+#define DGMI_FLAG_HLL 16          /* numerical flux HLL (eq. HLL) instead of local Lax-Friedrichs
+                                     (eq. LLF); uniform degrees only, a mixed-degree mesh with it
+                                     returns DGMI_EUNSUPPORTED */
 
 typedef struct dgmi_ctx dgmi_ctx;
 typedef struct dgmi_mlp dgmi_mlp;

@@ -175,6 +175,8 @@ static dgmi_status autotune(dgmi_ctx *c);
 constexpr int kMixedLanes = 4;
 
 // Periodic neighbour of element e across face f (-x, +x, -y, +y, -z, +z).
+static int flux_of(const dgmi_ctx *c) { return (c->flags & DGMI_FLAG_HLL) ? dgmi::kHLL : dgmi::kLLF; }
+
 static int64_t nbr_of(const dgmi_ctx *c, int64_t e, int f) {
   const int64_t ne[3] = {c->nx, c->ny, c->nz};
   int64_t k[3] = {e % c->nx, (e / c->nx) % c->ny, e / ((int64_t)c->nx * c->ny)};
@@ -523,6 +525,8 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
   if (desc->degree < 0 || desc->degree > 7) return fail(DGMI_EINVAL, "dgmi_create: degree must be 1..7 or 0");
   if (desc->degree == 0 && !desc->degrees_host)
     return fail(DGMI_EINVAL, "dgmi_create: degree 0 needs degrees_host");
+  if (desc->degree == 0 && (desc->flags & DGMI_FLAG_HLL))
+    return fail(DGMI_EUNSUPPORTED, "dgmi_create: the HLL flux is implemented for uniform degrees only");
   dgmi_ctx *c = new (std::nothrow) dgmi_ctx();
   if (!c) return fail(DGMI_ENOMEM, "dgmi_create: out of host memory");
   (void)hipGetDevice(&c->device);
@@ -687,7 +691,7 @@ dgmi_status dg_rhs(dgmi_ctx *ctx, const double *U, double *prim_inout, double *d
   a.U = U;
   a.P = prim_inout;
   a.out = dUdt;
-  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 0, a, s));
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 0, flux_of(ctx), a, s));
   return DGMI_OK;
 }
 
@@ -701,7 +705,7 @@ dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, doub
   a.U = U;
   a.P = prim;
   a.out = dUdt;
-  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 0, a, (hipStream_t)stream));
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 0, flux_of(ctx), a, (hipStream_t)stream));
   return DGMI_OK;
 }
 
@@ -750,14 +754,14 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
   a.Un = U;
   // stage 1: U1 = U + dt L(U)
   a.U = U; a.P = prim_inout; a.out = ctx->d_U1; a.Pout = ctx->d_P1; a.a = 0.0; a.b = 1.0;
-  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, a, s));
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
   // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
   a.U = ctx->d_U1; a.P = ctx->d_P1; a.out = ctx->d_U2; a.Pout = ctx->d_P2; a.a = 0.75; a.b = 0.25;
-  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, a, s));
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
   // stage 3: U <- 1/3 U + 2/3 (U2 + dt L(U2))  (each thread reads U^n at its own node before writing it)
   a.U = ctx->d_U2; a.P = ctx->d_P2; a.out = U; a.Pout = prim_inout; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
   a.full_prims = 1;
-  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, a, s));
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
   return DGMI_OK;
 }
 

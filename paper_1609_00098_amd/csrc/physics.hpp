@@ -258,6 +258,37 @@ DG_HD double max_speed(int d, const double *u, const Prim P, double g) {
   return (fabs(vn) * (1.0 - c2) + fast_sqrt(c2 * disc)) * fast_rcp(1.0 - v2 * c2);
 }
 
+// Both fluid speed bounds along +e_d, lm <= lp (the pair above; NE: v_n -+ c_s).
+template <int SYS>
+DG_HD void wave_bounds(int d, const double *u, const Prim P, double g, double &lm, double &lp) {
+  const double v0 = P.v[0], v1 = P.v[1], v2s = P.v[2];
+  const double vn = (d == 0) ? v0 : ((d == 1) ? v1 : v2s);
+  if (SYS == kNE) {
+    const double cs = fast_sqrt(g * P.p * fast_rcp(P.rho));
+    lm = vn - cs;
+    lp = vn + cs;
+    return;
+  }
+  const double v2 = v0 * v0 + v1 * v1 + v2s * v2s;
+  const double rhoh = P.rho + g / (g - 1.0) * P.p;
+  double c2;
+  if (SYS == kSR) {
+    c2 = g * P.p * fast_rcp(rhoh);
+  } else {
+    const double BB = sq(u[5]) + sq(u[6]) + sq(u[7]);
+    const double Bv = u[5] * v0 + u[6] * v1 + u[7] * v2s;
+    const double b2 = BB * (1.0 - v2) + Bv * Bv;
+    const double cs2 = g * P.p * fast_rcp(rhoh);
+    const double vA2 = b2 * fast_rcp(rhoh + b2);
+    c2 = vA2 + cs2 * (1.0 - vA2);
+  }
+  const double disc = (1.0 - v2) * (1.0 - v2 * c2 - vn * vn * (1.0 - c2));
+  const double r = fast_rcp(1.0 - v2 * c2);
+  const double a = vn * (1.0 - c2), b = fast_sqrt(c2 * disc);
+  lm = (a - b) * r;
+  lp = (a + b) * r;
+}
+
 // ---------------------------------------------------------------- recovery
 // 1/x for a Newton step, where full accuracy is not needed: the hardware
 // reciprocal refined by one Newton-Raphson step on the device.

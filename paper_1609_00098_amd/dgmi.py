@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdgmi.so")
 
 NEWTONIAN_EULER, SR_HYDRO, SR_MHD = 0, 1, 2
 GUESS_INPUT, GUESS_PLAIN, GUESS_LEARNED = 0, 1, 2
-FLAG_PLAIN_GUESS, FLAG_RECOVER_FIRST, FLAG_NO_GRAPH, FLAG_AUTOTUNE = 1, 2, 4, 8
+FLAG_PLAIN_GUESS, FLAG_RECOVER_FIRST, FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_HLL = 1, 2, 4, 8, 16
 NVARS = {NEWTONIAN_EULER: 5, SR_HYDRO: 5, SR_MHD: 9}
 MLP_NUM_WEIGHTS = 4609
 MLP_NUM_PARAMS = 4621

@@ -1,0 +1,168 @@
+"""GPU parity of the HLL flux (eq. HLL) path against the oracle.
+
+Same bars as the local Lax-Friedrichs path: relative 1e-12 norm-wise per
+variable for dg_rhs, the three-stage error budget for dg_step.  States carry
+a 2% per-node perturbation so that the two sides of every face differ (for
+continuous face data every consistent flux reduces to F(U).n and the test
+would not see the flux).
+"""
+import numpy as np
+import pytest
+
+from paper_1609_00098_amd import synth
+from tests.gpu_util import normwise_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+NE, SR, MHD = 0, 1, 2
+RHS_TOL = 1e-12
+LO, HI = (-0.3, 0.1, 0.0), (0.7, 1.6, 2.0)
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1609_00098_amd import dgmi
+    return dgmi
+
+
+def _gamma(system):
+    return 4.0 / 3.0 if system else 1.4
+
+
+def _state(ora, system, m, seed):
+    xyz = ora.node_coords(m)
+    unit = (xyz - np.array(LO)[:, None]) / (np.array(HI) - np.array(LO))[:, None]
+    z = 0.02 * np.random.default_rng(seed + 100).standard_normal((5, xyz.shape[1]))
+    noise = 1.0 + z
+    noise[1:4] = 1.0 - np.abs(z[1:4])  # only slow the flow down: |v| stays below 1
+    if system == MHD:
+        prim = synth.fourier_random_prims(unit, seed=seed, w_max=3.0, rho_range=(0.5, 2.0),
+                                          p_range=(0.1, 10.0)) * noise
+        rng = np.random.default_rng(seed)
+        mag = np.zeros((4, prim.shape[1]))
+        for c in range(4):
+            k = rng.integers(1, 3, size=3)
+            mag[c] = 0.3 * np.sin(2 * np.pi * (k @ unit) + rng.uniform(0, 6))
+        mag[0] += 1.0
+        return ora.prim2cons(MHD, m.gamma, prim, mag), prim
+    prim = synth.fourier_random_prims(unit, seed=seed, w_max=5.0 if system == SR else 1.5) * noise
+    return ora.prim2cons(system, m.gamma, prim), prim
+
+
+def _pair(ora, dg, system, nel, N, flags=0):
+    g = _gamma(system)
+    m = ora.mesh(system, nel, N, g, lo=LO, hi=HI, kappa=0.5, flux="hll")
+    G = dg.Mesh(system, nel, N, g, lo=LO, hi=HI, kappa=0.5, flags=flags | dg.FLAG_HLL)
+    return m, G
+
+
+@pytest.mark.parametrize("system,N", [(s, N) for s in (NE, SR, MHD) for N in range(1, 8)])
+def test_hll_rhs_parity(ora, dg, system, N):
+    nel = (3, 2, 2) if N <= 4 else (2, 2, 1)
+    m, G = _pair(ora, dg, system, nel, N)
+    U, prim = _state(ora, system, m, seed=40 + N)
+    dUo, Po, nf = ora.rhs(m, U)
+    assert nf == 0
+    Pd = to_dev(prim * (1 + 1e-3))
+    dUd = G.empty_state()
+    dg.dg_rhs(G, to_dev(U), Pd, dUd)
+    err = normwise_err(to_host(dUd), dUo)
+    assert np.all(err <= RHS_TOL), err
+    assert dg.dgmi_failures(G) == 0
+
+
+@pytest.mark.parametrize("system", [NE, SR, MHD])
+def test_hll_is_not_llf_on_gpu(ora, dg, system):
+    """The flag switches the flux: the LLF mesh reproduces the oracle's LLF
+    operator and differs from the HLL one far beyond the parity bar."""
+    m, G = _pair(ora, dg, system, (3, 2, 2), 3)
+    g = _gamma(system)
+    m_llf = ora.mesh(system, (3, 2, 2), 3, g, lo=LO, hi=HI, kappa=0.5)
+    G_llf = dg.Mesh(system, (3, 2, 2), 3, g, lo=LO, hi=HI, kappa=0.5)
+    U, prim = _state(ora, system, m, seed=7)
+    h = G.empty_state()
+    l = G_llf.empty_state()
+    dg.dg_rhs(G, to_dev(U), to_dev(prim), h)
+    dg.dg_rhs(G_llf, to_dev(U), to_dev(prim), l)
+    lo_, _, _ = ora.rhs(m_llf, U)
+    assert np.all(normwise_err(to_host(l), lo_) <= RHS_TOL)
+    assert np.all(normwise_err(to_host(h), lo_)[:5] > 1e-6)
+
+
+@pytest.mark.parametrize("system,N", [(NE, 3), (SR, 4), (MHD, 3), (SR, 6)])
+def test_hll_step_parity(ora, dg, system, N):
+    m, G = _pair(ora, dg, system, (3, 2, 2), N, flags=dg.FLAG_RECOVER_FIRST)
+    U, prim = _state(ora, system, m, seed=50 + N)
+    Lo, _, _ = ora.rhs(m, U)
+    dt = 1e-3 / max(np.abs(Lo[0] / U[0]).max(), np.abs(Lo[4] / U[4]).max())
+    Uo, nf = ora.step(m, U, dt)
+    assert nf == 0
+    Ud = to_dev(U)
+    Pd = to_dev(prim)
+    dg.dg_step(G, Ud, Pd, dt)
+    eps = np.finfo(np.float64).eps
+    tol = 2e-12 * dt * np.abs(Lo).max(axis=1) + 8 * eps * np.abs(U).max(axis=1)
+    diff = np.abs(to_host(Ud) - Uo).max(axis=1)
+    assert np.all(diff <= tol), (diff, tol)
+    assert np.all(np.abs(Uo - U).max(axis=1)[:5] > 1e2 * tol[:5])
+    assert dg.dgmi_failures(G) == 0
+
+
+@pytest.mark.parametrize("system", [NE, SR, MHD])
+def test_hll_free_stream_and_conservation_on_gpu(ora, dg, system):
+    m, G = _pair(ora, dg, system, (3, 3, 2), 4)
+    n = G.nnodes
+    prim = np.tile(np.array([[1.3], [0.3], [-0.2], [0.25], [0.7]]), (1, n))
+    mag = np.tile(np.array([[0.4], [-0.3], [0.2], [0.0]]), (1, n))
+    Uc = ora.prim2cons(system, m.gamma, prim, mag if system == MHD else None)
+    dUd = G.empty_state()
+    dg.dg_rhs(G, to_dev(Uc), to_dev(prim), dUd)
+    assert np.abs(to_host(dUd)).max() < 1e-12
+    U, p = _state(ora, system, m, seed=9)
+    dg.dg_rhs(G, to_dev(U), to_dev(p), dUd)
+    dU = to_host(dUd)
+    tot = ora.integrate(m, dU)
+    absint = ora.integrate(m, np.abs(dU))
+    if system == MHD:
+        tot[8] -= ora.integrate(m, -m.kappa * U[8:9])[0]
+    assert np.all(np.abs(tot) <= 1e-13 * absint.max())
+
+
+def test_hll_rejected_on_mixed_degrees(dg):
+    deg = np.array([2, 3] * 4, dtype=np.int32)
+    with pytest.raises(dg.DgmiError):
+        dg.Mesh(SR, (2, 2, 2), 0, 4.0 / 3.0, flags=dg.FLAG_HLL, degrees=deg)
+
+
+def test_hll_full_size_sampled(ora, dg):
+    """3D SR hydro at the benchmark size (32^3 elements of degree 4) with the
+    HLL flux, in the benchmark's launch configuration, on the perturbed
+    state: dU/dt on 64 sampled elements recomputed by the oracle."""
+    import torch
+    g = 4.0 / 3.0
+    m = ora.mesh(SR, (32, 32, 32), 4, g, flux="hll")
+    G = dg.Mesh(SR, (32, 32, 32), 4, g, flags=dg.FLAG_HLL)
+    xyz = ora.node_coords(m)
+    z = 0.02 * np.random.default_rng(1709).standard_normal((5, xyz.shape[1]))
+    noise = 1.0 + z
+    noise[1:4] = 1.0 - np.abs(z[1:4])
+    prim = synth.fourier_random_prims(xyz, seed=1609) * noise
+    U = ora.prim2cons(SR, g, prim)
+    Ud = to_dev(U)
+    Pd = to_dev(prim * (1 + 1e-3))
+    dUd = G.empty_state()
+    dg.dg_rhs(G, Ud, Pd, dUd)
+    assert dg.dgmi_failures(G) == 0
+    Po, _, nf = ora.cons2prim(SR, g, U)
+    assert nf == 0
+    rng = np.random.default_rng(77)
+    elems = np.concatenate([[0, 31, 32 * 32 - 1, 32 ** 3 - 1], rng.choice(32 ** 3, 60, replace=False)])
+    ref = ora.rhs_elements(m, U, Po, elems)
+    idx = (elems[:, None] * 125 + np.arange(125)[None, :]).ravel()
+    got = to_host(dUd)[:, idx]
+    err = np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)
+    assert np.all(err <= RHS_TOL), err
+    del Ud, Pd, dUd
+    torch.cuda.empty_cache()
