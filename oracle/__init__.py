@@ -44,13 +44,24 @@ class Mesh(ctypes.Structure):
     _fields_ = [("sys", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("deg", ctypes.c_int32 * 3), ("flux", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("bc", ctypes.c_int32 * 3), ("limiter", ctypes.c_int32), ("lim_M", ctypes.c_double),
+                ("bc_u", (ctypes.c_double * 9) * 6), ("bc_p", (ctypes.c_double * 5) * 6)]
 
 
-def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), kappa=0.0, flux="llf"):
-    """Periodic box of nelem=(nx,ny,nz) affine elements.  degree is an int or a
-    per-direction triple; a 0 entry collapses that direction.  flux: "llf"
-    (eq. LLF) or "hll" (eq. HLL)."""
+LIMITERS = {"none": 0, "minmod": 1, "muscl": 2}
+
+
+def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), kappa=0.0, flux="llf",
+         bc=None, limiter="none", M=0.0):
+    """Box of nelem=(nx,ny,nz) affine elements, periodic unless ``bc`` says
+    otherwise.  degree is an int or a per-direction triple; a 0 entry
+    collapses that direction.  flux: "llf" (eq. LLF) or "hll" (eq. HLL).
+    bc: {d: (state_lo, state_hi)} gives direction d fixed exterior states on
+    its two box faces, each state a primitive 5-vector (rho, v, p), or for
+    SRMHD a 9-vector (rho, v, p, B, Phi).  limiter: "none", "minmod" (beta 2)
+    or "muscl" (beta 1), with the minmodB constant M, applied after every
+    RK stage."""
     if isinstance(degree, int):
         degree = (degree, degree, degree)
     m = Mesh()
@@ -58,6 +69,17 @@ def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), k
     m.nx, m.ny, m.nz = nelem
     m.deg[:] = list(degree)
     m.flux = {"llf": 0, "hll": 1}[flux]
+    m.limiter = LIMITERS[limiter]
+    m.lim_M = M
+    for d, states in (bc or {}).items():
+        m.bc[d] = 1
+        for side, st in enumerate(states):
+            st = np.asarray(st, dtype=np.float64)
+            prim = st[:5].reshape(5, 1)
+            mag = st[5:9].reshape(4, 1) if system == MHD else None
+            u = prim2cons(system, gamma, prim, mag)[:, 0]
+            m.bc_u[2 * d + side][:len(u)] = list(u)
+            m.bc_p[2 * d + side][:] = list(prim[:, 0])
     m.gamma = gamma
     m.kappa = kappa
     m.lo[:] = list(lo)
@@ -106,6 +128,9 @@ def _load():
         "ora_rhs_mixed": (I64, [MP, ctypes.POINTER(ctypes.c_int32), D, D, D]),
         "ora_mixed_integrate": (ctypes.c_int, [MP, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, D, D]),
         "ora_step_mixed": (I64, [MP, ctypes.POINTER(ctypes.c_int32), D, ctypes.c_double]),
+        "ora_minmodB": (ctypes.c_double, [ctypes.c_double] * 5),
+        "ora_limit": (I64, [MP, D]),
+        "ora_limiter_moments": (ctypes.c_int, [MP, D, D, U8]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -278,6 +303,32 @@ def rhs_weak(m, U):
     dU = np.zeros_like(U)
     _load().ora_rhs_weak(ctypes.byref(m), _p(U), _p(dU))
     return dU
+
+
+def minmodB(a1, a2, a3, M=0.0, dx=1.0):
+    return float(_load().ora_minmodB(a1, a2, a3, M, dx))
+
+
+def limit(m, U):
+    """Returns (limited copy of U, number of limited element components)."""
+    U = _c(U).copy()
+    n = _load().ora_limit(ctypes.byref(m), _p(U))
+    if n < 0:
+        raise ValueError("bad mesh")
+    return U, int(n)
+
+
+def limiter_moments(m, U):
+    """Per element [10][nv]: mean, Legendre slope coefficients c_x, c_y, c_z,
+    face means -x, +x, -y, +y, -z, +z; and the unphysical-node flag."""
+    U = _c(U)
+    ne = m.nx * m.ny * m.nz
+    out = np.zeros((ne, 10, U.shape[0]))
+    bad = np.zeros(ne, dtype=np.uint8)
+    if _load().ora_limiter_moments(ctypes.byref(m), _p(U), _p(out),
+                                   bad.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))) != 0:
+        raise ValueError("bad mesh")
+    return out, bad
 
 
 def rk3_combine(stage, dt, Un, Uprev, L):

@@ -610,6 +610,14 @@ typedef struct {
   int32_t flux; /* numerical flux: 0 local Lax-Friedrichs (eq. LLF), 1 HLL (eq. HLL) */
   double gamma, kappa;
   double lo[3], hi[3];
+  /* per direction: 0 periodic; 1 both box faces take a fixed exterior state
+   * (the analytic boundary condition for a solution that is constant
+   * outside the box), supplied below */
+  int32_t bc[3];
+  int32_t limiter; /* 0 none; 1 minmod (beta = 2); 2 MUSCL (beta = 1); applied after every RK stage */
+  double lim_M;    /* constant M of the minmodB function (eq. MinModB) */
+  double bc_u[6][9]; /* exterior conserved state of box face 2d + side */
+  double bc_p[6][5]; /* its primitives (rho, v, p) */
 } ora_mesh;
 
 typedef struct {
@@ -621,6 +629,9 @@ typedef struct {
 
 static int make_geom(const ora_mesh *m, geom_t *G) {
   if (m->nx < 1 || m->ny < 1 || m->nz < 1) return ORA_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (m->bc[d] != 0 && m->bc[d] != 1) return ORA_EINVAL;
+  if (m->limiter < 0 || m->limiter > 2 || !(m->lim_M >= 0.0)) return ORA_EINVAL;
   int ne[3] = {m->nx, m->ny, m->nz};
   for (int d = 0; d < 3; ++d) {
     if (m->deg[d] < 0 || m->deg[d] > 32) return ORA_EINVAL;
@@ -668,12 +679,28 @@ int ora_node_coords(const ora_mesh *m, double *xyz) {
   return ORA_OK;
 }
 
-/* Neighbouring element across face (d, side) with periodic wrap. */
+/* Neighbouring element across face (d, side): periodic wrap, or -1 on a box
+ * face of a direction with a fixed exterior state.                         */
 static int64_t neighbour(const ora_mesh *m, int64_t e, int d, int side) {
   int64_t c[3] = {e % m->nx, (e / m->nx) % m->ny, e / ((int64_t)m->nx * m->ny)};
   int64_t ne[3] = {m->nx, m->ny, m->nz};
+  if (m->bc[d] && (side ? c[d] == ne[d] - 1 : c[d] == 0)) return -1;
   c[d] = (c[d] + (side ? 1 : ne[d] - 1)) % ne[d];
   return c[0] + ne[0] * (c[1] + ne[1] * c[2]);
+}
+
+/* Exterior state of face (d, side) of element e at the neighbour's node b:
+ * the neighbour's node, or the box face's fixed state.                     */
+static void exterior(const ora_mesh *m, int nv, int64_t N, int64_t npe, const double *U, const double *prim,
+                     int64_t en, int64_t b, int d, int side, cons_t *Ce, prim_t *Pe) {
+  if (en >= 0) {
+    load_cons(nv, N, U, en * npe + b, Ce);
+    load_prim(N, prim, en * npe + b, Pe);
+    return;
+  }
+  const double *u = m->bc_u[2 * d + side], *p = m->bc_p[2 * d + side];
+  for (int v = 0; v < nv; ++v) Ce->u[v] = u[v];
+  Pe->rho = p[0]; Pe->v[0] = p[1]; Pe->v[1] = p[2]; Pe->v[2] = p[3]; Pe->p = p[4];
 }
 
 /* Strong-form semi-discrete operator (eq. 411) for the elements listed in
@@ -746,8 +773,7 @@ static int rhs_strong(const ora_mesh *m, const geom_t *G, const double *U, const
               cons_t Ci, Ce; prim_t Pi, Pe;
               load_cons(nv, N, U, e * npe + a, &Ci);
               load_prim(N, prim, e * npe + a, &Pi);
-              load_cons(nv, N, U, en * npe + b, &Ce);
-              load_prim(N, prim, en * npe + b, &Pe);
+              exterior(m, nv, N, npe, U, prim, en, b, d, side, &Ce, &Pe);
               double Fs[9], Fi[9];
               numflux(m->flux, sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
               double wend = G->w[d][side ? Nd : 0];
@@ -819,8 +845,7 @@ static int rhs_weak(const ora_mesh *m, const geom_t *G, const double *U, const d
               cons_t Ci, Ce; prim_t Pi, Pe;
               load_cons(nv, N, U, e * npe + a, &Ci);
               load_prim(N, prim, e * npe + a, &Pi);
-              load_cons(nv, N, U, en * npe + b, &Ce);
-              load_prim(N, prim, en * npe + b, &Pe);
+              exterior(m, nv, N, npe, U, prim, en, b, d, side, &Ce, &Pe);
               double Fs[9], Fi[9];
               numflux(m->flux, sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
               double sc = 2.0 / G->dx[d];
@@ -869,6 +894,183 @@ int64_t ora_rhs_weak(const ora_mesh *m, const double *U, double *dUdt) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Minmod-family slope limiter (high-resolution shock-capturing section).   */
+/*                                                                          */
+/* Applied component by component to the conserved variables.  Per element */
+/* k and active direction d (degree >= 1 along d):                          */
+/*  - U0: the element mean; U_x: the slope of its linear part, where the    */
+/*    linear part keeps the Legendre modes 1, xi, eta, zeta of the nodal    */
+/*    polynomial (all higher modes dropped), so U_x = (2/dx) c_d with       */
+/*    c_d = (3/2) * int(U xi_d) / int(1) over the other directions;         */
+/*  - the slope estimates a1 = U_x, a2 = (U0(k+1) - U0(k)) beta/dx,         */
+/*    a3 = (U0(k) - U0(k-1)) beta/dx, and a_d = minmodB(a1, a2, a3; M)      */
+/*    (eqs. MinModB and MinMod), beta = 2 minmod, 1 MUSCL.                  */
+/* Degree 1 in every active direction: the element is limited when some     */
+/* a_d differs from its a1.  Higher degree: the troubled-cell test of the   */
+/* generalized minmodB limiter on the two face means per direction          */
+/*   v_l = U0 - m(U0 - Uface_l, U0 - U0(k-1), U0(k+1) - U0),                */
+/*   v_r = U0 + m(Uface_r - U0, U0 - U0(k-1), U0(k+1) - U0),                */
+/* limiting when |v_l - Uface_l| or |v_r - Uface_r| exceeds 1e-8 for any d. */
+/* A limited component becomes U0 + sum_d a_d (x_d - x_d0) (eq. MinModSol). */
+/* An element with a node whose primitives cannot be recovered is limited   */
+/* in every component.  Across a box face with a fixed exterior state the   */
+/* neighbour mean is that state.  All means are taken before any element is */
+/* changed.                                                                 */
+/* ------------------------------------------------------------------------ */
+static double sgn_of(double a) { return a > 0.0 ? 1.0 : (a < 0.0 ? -1.0 : 0.0); }
+
+static double minmod3(double a1, double a2, double a3) {
+  double s = sgn_of(a1);
+  if (s == 0.0 || sgn_of(a2) != s || sgn_of(a3) != s) return 0.0;
+  return s * fmin(fabs(a1), fmin(fabs(a2), fabs(a3)));
+}
+
+static double minmodB(double a1, double a2, double a3, double M, double dx) {
+  if (fabs(a1) <= M * dx * dx) return a1;
+  return minmod3(a1, a2, a3);
+}
+
+double ora_minmodB(double a1, double a2, double a3, double M, double dx) { return minmodB(a1, a2, a3, M, dx); }
+
+/* mu[i] = int_{-1}^{1} ell_i(xi) xi dxi for the GLL nodes of degree N, by the
+ * GLL rule of degree N + 1 (exact: the integrand has degree N + 1).         */
+static void first_moments(int N, const double *x, double *mu) {
+  double X[34], W[34], I[34 * 33];
+  ora_gll(N + 1, X, W);
+  ora_lagrange_matrix(N + 1, x, N + 2, X, I);
+  for (int i = 0; i <= N; ++i) {
+    double s = 0.0;
+    for (int q = 0; q < N + 2; ++q) s += W[q] * X[q] * I[q * (N + 1) + i];
+    mu[i] = s;
+  }
+}
+
+typedef struct {
+  double mean[9], c[3][9], face[6][9];
+  int bad;
+} moments_t;
+
+static void element_moments(const ora_mesh *m, const geom_t *G, const double *U, int64_t e, const double mu[3][33],
+                            moments_t *M) {
+  int nv = nvars_of(m->sys);
+  int64_t N = G->nnodes, npe = G->npe;
+  int n0 = G->n[0], n1 = G->n[1], n2 = G->n[2];
+  memset(M, 0, sizeof(*M));
+  for (int k = 0; k < n2; ++k)
+    for (int j = 0; j < n1; ++j)
+      for (int i = 0; i < n0; ++i) {
+        int ijk[3] = {i, j, k};
+        int64_t q = e * npe + i + n0 * (j + n1 * k);
+        double h[3] = {G->w[0][i] / 2.0, G->w[1][j] / 2.0, G->w[2][k] / 2.0};
+        cons_t C; prim_t P;
+        load_cons(nv, N, U, q, &C);
+        if (!c2p_point(m->sys, m->gamma, &C, &P)) M->bad = 1;
+        for (int v = 0; v < nv; ++v) {
+          double u = U[(int64_t)v * N + q];
+          M->mean[v] += h[0] * h[1] * h[2] * u;
+          for (int d = 0; d < 3; ++d) {
+            if (G->n[d] < 2) continue;
+            double o = 1.0;
+            for (int dd = 0; dd < 3; ++dd) o *= dd == d ? 1.5 * mu[d][ijk[d]] : h[dd];
+            M->c[d][v] += o * u;
+            int Nd = G->n[d] - 1;
+            if (ijk[d] == 0 || ijk[d] == Nd) {
+              double fw = 1.0;
+              for (int dd = 0; dd < 3; ++dd)
+                if (dd != d) fw *= h[dd];
+              M->face[2 * d + (ijk[d] == Nd)][v] += fw * u;
+            }
+          }
+        }
+      }
+}
+
+/* Limit U in place; returns the number of limited element components, or <0
+ * on bad input.                                                            */
+int64_t ora_limit(const ora_mesh *m, double *U) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
+  if (m->limiter == 0) return 0;
+  int nv = nvars_of(m->sys);
+  double beta = m->limiter == 1 ? 2.0 : 1.0;
+  double mu[3][33];
+  int high = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (G.n[d] >= 2) first_moments(G.n[d] - 1, G.x[d], mu[d]);
+    if (G.n[d] >= 3) high = 1;
+  }
+  moments_t *Mo = (moments_t *)malloc(sizeof(moments_t) * G.nelem);
+  if (!Mo) return ORA_EINVAL;
+#pragma omp parallel for schedule(static) if (G.nnodes > 4096)
+  for (int64_t e = 0; e < G.nelem; ++e) element_moments(m, &G, U, e, mu, &Mo[e]);
+  int64_t nlim = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nlim) if (G.nnodes > 4096)
+  for (int64_t e = 0; e < G.nelem; ++e) {
+    const moments_t *Me = &Mo[e];
+    for (int v = 0; v < nv; ++v) {
+      double a[3] = {0.0, 0.0, 0.0};
+      int troubled = Me->bad;
+      for (int d = 0; d < 3; ++d) {
+        if (G.n[d] < 2) continue;
+        double nb[2];
+        for (int side = 0; side < 2; ++side) {
+          int64_t en = neighbour(m, e, d, side);
+          nb[side] = en >= 0 ? Mo[en].mean[v] : m->bc_u[2 * d + side][v];
+        }
+        double u0 = Me->mean[v], dx = G.dx[d];
+        double a1 = Me->c[d][v] * 2.0 / dx;
+        a[d] = minmodB(a1, (nb[1] - u0) * beta / dx, (u0 - nb[0]) * beta / dx, m->lim_M, dx);
+        if (high) {
+          double fl = Me->face[2 * d][v], fr = Me->face[2 * d + 1][v];
+          double vl = u0 - minmod3(u0 - fl, u0 - nb[0], nb[1] - u0);
+          double vr = u0 + minmod3(fr - u0, u0 - nb[0], nb[1] - u0);
+          if (fabs(vl - fl) > 1e-8 || fabs(vr - fr) > 1e-8) troubled = 1;
+        } else if (a[d] != a1) {
+          troubled = 1;
+        }
+      }
+      if (!troubled) continue;
+      ++nlim;
+      for (int k = 0; k < G.n[2]; ++k)
+        for (int j = 0; j < G.n[1]; ++j)
+          for (int i = 0; i < G.n[0]; ++i) {
+            double xi[3] = {G.x[0][i], G.x[1][j], G.x[2][k]};
+            double u = Me->mean[v];
+            for (int d = 0; d < 3; ++d)
+              if (G.n[d] >= 2) u += a[d] * 0.5 * G.dx[d] * xi[d];
+            U[(int64_t)v * G.nnodes + e * G.npe + i + G.n[0] * (j + G.n[1] * k)] = u;
+          }
+    }
+  }
+  free(Mo);
+  return nlim;
+}
+
+/* Element means, Legendre slope coefficients c_d and face means of every
+ * element: out[e][10][nv] = mean, c_x, c_y, c_z, face -x, +x, -y, +y, -z, +z;
+ * bad[e] = 1 when some node of e has no physical primitives.               */
+int ora_limiter_moments(const ora_mesh *m, const double *U, double *out, uint8_t *bad) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
+  int nv = nvars_of(m->sys);
+  double mu[3][33];
+  for (int d = 0; d < 3; ++d)
+    if (G.n[d] >= 2) first_moments(G.n[d] - 1, G.x[d], mu[d]);
+  for (int64_t e = 0; e < G.nelem; ++e) {
+    moments_t M;
+    element_moments(m, &G, U, e, mu, &M);
+    double *o = out + e * 10 * nv;
+    for (int v = 0; v < nv; ++v) {
+      o[v] = M.mean[v];
+      for (int d = 0; d < 3; ++d) o[(1 + d) * nv + v] = M.c[d][v];
+      for (int f = 0; f < 6; ++f) o[(4 + f) * nv + v] = M.face[f][v];
+    }
+    if (bad) bad[e] = (uint8_t)M.bad;
+  }
+  return ORA_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Third-order strong-stability-preserving Runge-Kutta (Shu-Osher form):     */
 /*   U1 = Un + dt L(Un)                                                      */
 /*   U2 = 3/4 Un + 1/4 (U1 + dt L(U1))                                       */
@@ -897,12 +1099,17 @@ int64_t ora_step(const ora_mesh *m, double *U, double dt) {
   double *U1 = (double *)malloc(sizeof(double) * n);
   double *U2 = (double *)malloc(sizeof(double) * n);
   int64_t nf = 0;
+  /* with a limiter, every stage result is limited before its primitives
+   * are recovered for the next stage */
   nf += ora_rhs(m, U, NULL, L);
   ora_rk3_combine(1, dt, n, U, U, L, U1);
+  ora_limit(m, U1);
   nf += ora_rhs(m, U1, NULL, L);
   ora_rk3_combine(2, dt, n, U, U1, L, U2);
+  ora_limit(m, U2);
   nf += ora_rhs(m, U2, NULL, L);
   ora_rk3_combine(3, dt, n, U, U2, L, U);
+  ora_limit(m, U);
   free(L); free(U1); free(U2);
   return nf;
 }
@@ -1054,6 +1261,7 @@ static int face_node(int N, int d, int side, int a, int b) {
 /* Mixed-degree strong-form operator.  The mesh's deg[] field is ignored;
  * deg[e] gives each element's degree.  Returns failed recoveries or <0. */
 int64_t ora_rhs_mixed(const ora_mesh *m, const int32_t *deg, const double *U, double *prim_out, double *dUdt) {
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter) return ORA_EINVAL; /* periodic, unlimited only */
   int sys = m->sys, nv = nvars_of(sys);
   double g = m->gamma;
   int64_t ne = (int64_t)m->nx * m->ny * m->nz;
@@ -1235,6 +1443,7 @@ int ora_mixed_integrate(const ora_mesh *m, const int32_t *deg, int ncomp, const 
 
 /* SSP-RK3 step on a mixed-degree mesh. */
 int64_t ora_step_mixed(const ora_mesh *m, const int32_t *deg, double *U, double dt) {
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter) return ORA_EINVAL;
   int64_t ne = (int64_t)m->nx * m->ny * m->nz;
   int nv = nvars_of(m->sys);
   int64_t n = (int64_t)nv * ora_mixed_num_nodes((int)ne, deg);

@@ -1,0 +1,259 @@
+"""Pins of the oracle's minmod-family slope limiter (eqs. MinModSol, MinModB,
+MinMod and the generalized troubled-cell test), its fixed-state box
+boundaries, and the exact Riemann solution used as reference:
+
+* minmodB on hand cases (eqs. MinModB, MinMod);
+* the Legendre slope coefficient and face means on polynomials with closed
+  forms (xi^3 = 2/5 P3 + 3/5 P1);
+* fields the limiter must leave alone (constants, linear ramps continued by
+  the boundary states) and fields it must change (a local extremum, a jump,
+  an unphysical node); element means are never changed;
+* the exact Riemann solution obeys the Rankine-Hugoniot conditions across
+  its shock, keeps the Riemann invariant and the entropy through its fan
+  and is continuous in u and p across its contact;
+* the scheme (LLF or HLL flux + limiter + RK3) reproduces the printed rows of
+  tab:NE_sod.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import riemann
+
+NE, SR, MHD = 0, 1, 2
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+SLOW = os.environ.get("DGMI_SLOW") == "1"
+
+
+def test_minmodB_cases(ora):
+    assert ora.minmodB(1.0, 2.0, 3.0) == 1.0
+    assert ora.minmodB(-3.0, -2.0, -0.5) == -0.5
+    assert ora.minmodB(1.0, -2.0, 3.0) == 0.0
+    assert ora.minmodB(0.0, 1.0, 1.0) == 0.0
+    assert ora.minmodB(2.0, 1.0, 0.0) == 0.0
+    # |a1| <= M dx^2 keeps a1 whatever the neighbours say
+    assert ora.minmodB(0.5, -1.0, 1.0, M=60.0, dx=0.1) == 0.5
+    assert ora.minmodB(0.7, -1.0, 1.0, M=60.0, dx=0.1) == 0.0
+
+
+@pytest.mark.parametrize("N", [1, 3, 4])
+def test_moments_closed_forms(ora, N):
+    """One element on [-1,1]^3 (dx = 2, so 2/dx = 1):
+    U = xi^3 + eta^2 + 2 zeta: mean 1/3, c_x = 3/5 (for N >= 3), c_y = 0,
+    c_z = 2; face means: -x: -1 + 1/3, +x: 1 + 1/3, -z: 1/3 - 2."""
+    m = ora.mesh(NE, (1, 1, 1), N, 1.4, lo=(-1, -1, -1), hi=(1, 1, 1))
+    x = ora.node_coords(m)
+    U = np.tile(x[0] ** 3 + x[1] ** 2 + 2 * x[2], (5, 1))
+    mo, bad = ora.limiter_moments(m, U)
+    mom = mo[0, :, 0]
+    # the nodal polynomial of degree N interpolates the field; below degree 3
+    # it is not xi^3 itself, so only the exactly represented parts are fixed
+    if N >= 3:
+        assert abs(mom[1] - 0.6) < 1e-14
+        assert abs(mom[4] - (-1 + 1 / 3)) < 1e-14 and abs(mom[5] - (1 + 1 / 3)) < 1e-14
+    if N >= 2:
+        assert abs(mom[0] - 1 / 3) < 1e-14
+    assert abs(mom[2]) < 1e-14
+    assert abs(mom[3] - 2.0) < 1e-14
+    assert abs(mom[8] - ((1 / 3 if N >= 2 else 1.0) - 2)) < 1e-13
+
+
+def _ne_state(ora, m, rho):
+    n = rho.size
+    prim = np.zeros((5, n))
+    prim[0] = rho
+    prim[1] = 0.1
+    prim[4] = 1.0
+    return ora.prim2cons(NE, m.gamma, prim)
+
+
+@pytest.mark.parametrize("N", [1, 3])
+@pytest.mark.parametrize("lim", ["minmod", "muscl"])
+def test_constant_and_continued_ramp_untouched(ora, N, lim):
+    nx = 6
+    g = 1.4
+    # density ramp rho = 1 + 0.5 x on [0, 1]; the exterior states are the ramp's
+    # means one element beyond each end, so every slope estimate agrees
+    dx = 1.0 / nx
+    st_lo = (1 + 0.5 * (-dx / 2), 0.1, 0, 0, 1.0)
+    st_hi = (1 + 0.5 * (1 + dx / 2), 0.1, 0, 0, 1.0)
+    m = ora.mesh(NE, (nx, 1, 1), (N, 0, 0), g, bc={0: (st_lo, st_hi)}, limiter=lim)
+    x = ora.node_coords(m)
+    U = _ne_state(ora, m, 1 + 0.5 * x[0])
+    # momentum and energy are not linear in x here; check density only
+    U1, _ = ora.limit(m, U)
+    assert np.abs(U1[0] - U[0]).max() < 1e-14
+    Uc = _ne_state(ora, m, np.full(x.shape[1], 1.3))
+    mc = ora.mesh(NE, (nx, 2, 1), (N, N, 0), g, limiter=lim)
+    Uc = _ne_state(ora, mc, np.full(ora.num_nodes(mc), 1.3))
+    Uc1, nlim = ora.limit(mc, Uc)
+    assert nlim == 0 and np.array_equal(Uc1, Uc)
+
+
+def test_local_extremum_is_flattened_and_means_kept(ora):
+    """N = 1, M = 0: an element whose mean exceeds both neighbours' loses its
+    slope; every element keeps its mean."""
+    g = 1.4
+    m = ora.mesh(NE, (5, 1, 1), (1, 0, 0), g, limiter="minmod")
+    rho = np.array([1.0, 1.0, 1.2, 1.4, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0])  # element 1: slope up, mean 1.3 > both
+    rho = np.array([1.0, 1.0, 1.5, 2.5, 1.2, 1.2, 1.0, 1.0, 1.0, 1.0])
+    U = _ne_state(ora, m, rho)
+    U1, nlim = ora.limit(m, U)
+    assert nlim > 0
+    assert np.allclose(U1[0, 2:4], [2.0, 2.0], rtol=0, atol=1e-15)
+    before, _ = ora.limiter_moments(m, U)
+    after, _ = ora.limiter_moments(m, U1)
+    assert np.allclose(after[:, 0, :], before[:, 0, :], rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_jump_is_detected_and_smooth_elements_kept(ora, N):
+    """Generalized troubled-cell test: a density jump near the right end of element 3 of 8
+    trips it (and its oscillation-free neighbours stay), after which the
+    element is linear with the limited slope; a smooth monotone density is
+    left alone."""
+    g = 1.4
+    m = ora.mesh(NE, (8, 1, 1), (N, 0, 0), g, limiter="minmod")
+    x = ora.node_coords(m)[0]
+    rho = np.where(x < 0.49, 1.0, 0.5)  # between the last two nodes of element 3
+    U = _ne_state(ora, m, rho)
+    U1, nlim = ora.limit(m, U)
+    npe = N + 1
+    changed = [e for e in range(8) if np.abs(U1[:, e * npe:(e + 1) * npe] - U[:, e * npe:(e + 1) * npe]).max() > 0]
+    assert 3 in changed
+    for e in (0, 1, 5, 6):
+        assert e not in changed
+    xe = x[3 * npe:4 * npe]
+    r = U1[0, 3 * npe:4 * npe]
+    slope = np.polyfit(xe, r, 1)[0]
+    assert np.abs(r - np.polyval(np.polyfit(xe, r, 1), xe)).max() < 1e-14
+    assert slope <= 0.0
+    # smooth and monotone: rho = 1 + 0.05 sin(x) on [0, 1] with the exterior
+    # states taken from the same function one element beyond each end
+    nx = 16
+    dx = 1.0 / nx
+    ms = ora.mesh(NE, (nx, 1, 1), (N, 0, 0), g, limiter="minmod",
+                  bc={0: ((1 + 0.05 * math.sin(-dx / 2), 0.1, 0, 0, 1.0),
+                          (1 + 0.05 * math.sin(1 + dx / 2), 0.1, 0, 0, 1.0))})
+    xs = ora.node_coords(ms)[0]
+    Us = _ne_state(ora, ms, 1 + 0.05 * np.sin(xs))
+    Us1, _ = ora.limit(ms, Us)
+    assert np.array_equal(Us1[0], Us[0])
+
+
+def test_unphysical_node_limits_every_component(ora):
+    g = 4.0 / 3.0
+    m = ora.mesh(SR, (4, 1, 1), (1, 0, 0), g, limiter="minmod", M=1e6)
+    x = ora.node_coords(m)[0]
+    prim = np.zeros((5, x.size))
+    prim[0] = 1 + 0.1 * np.sin(2 * np.pi * x)
+    prim[1] = 0.2
+    prim[4] = 1.0
+    U = ora.prim2cons(SR, g, prim)
+    _, nlim = ora.limit(m, U)
+    assert nlim == 0  # M = 1e6: nothing smooth is limited
+    U[4, 4] = -1.0  # tau < 0 at the first node of element 2
+    U1, nlim = ora.limit(m, U)
+    assert nlim == 5
+    assert np.abs(U1[:, :4] - U[:, :4]).max() == 0 and np.abs(U1[:, 6:] - U[:, 6:]).max() == 0
+    assert np.abs(U1[:, 4:6] - U[:, 4:6]).max() > 0
+
+
+SOD_L, SOD_R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+
+
+def test_exact_riemann_solution_is_a_weak_solution():
+    g = 1.4
+    ps, us = riemann.star_state(SOD_L, SOD_R, g)
+    t = 0.25
+    x = np.linspace(-0.5, 0.5, 20001)
+    w = riemann.sample(SOD_L, SOD_R, g, x, t)
+    rho, u, p = w
+    # right shock: find it, and check the three jump conditions in its frame
+    jump = np.argmax(np.abs(np.diff(rho)) * (x[:-1] > us * t + 0.01))
+    s = (x[jump] + x[jump + 1]) / (2 * t)
+    a, b = jump - 3, jump + 4  # star side, pre-shock side
+    for (ra, ua, pa), (rb, ub, pb) in [((rho[a], u[a], p[a]), (rho[b], u[b], p[b]))]:
+        m1, m2 = ra * (ua - s), rb * (ub - s)
+        assert abs(m1 - m2) < 2e-3 * abs(m2)
+        assert abs((m1 * (ua - s) + pa) - (m2 * (ub - s) + pb)) < 2e-3 * pb * 10
+        ea = pa / (g - 1) / ra + 0.5 * (ua - s) ** 2 + pa / ra
+        eb = pb / (g - 1) / rb + 0.5 * (ub - s) ** 2 + pb / rb
+        assert abs(ea - eb) < 2e-3 * eb
+    # exact shock speed from the star state: mass conservation across it
+    rs = rho[a]
+    s_exact = (rs * us - SOD_R[0] * SOD_R[1]) / (rs - SOD_R[0])
+    assert abs(s - s_exact) < 1e-3
+    # the fan: u + 2c/(g-1) and p / rho^g are constant
+    c = np.sqrt(g * p / rho)
+    fan = (x / t > -math.sqrt(g) + 1e-3) & (x / t < us - np.sqrt(g * ps / rho) - 1e-3) & (x < 0)
+    assert fan.sum() > 100
+    inv = u[fan] + 2 * c[fan] / (g - 1)
+    assert np.abs(inv - 2 * math.sqrt(g) / (g - 1)).max() < 1e-12
+    assert np.abs(p[fan] / rho[fan] ** g - 1.0).max() < 1e-12
+    # contact: u and p continuous, rho jumps
+    left_c = (x / t < us) & (x / t > us - 0.05)
+    right_c = (x / t > us) & (x / t < us + 0.05)
+    assert np.allclose(u[left_c], us) and np.allclose(u[right_c], us)
+    assert np.allclose(p[left_c], ps) and np.allclose(p[right_c], ps)
+    assert rho[left_c].min() > rho[right_c].max() + 0.1
+    # mirror symmetry: the reflected problem gives the reflected solution
+    wm = riemann.sample((SOD_R[0], -SOD_R[1], SOD_R[2]), (SOD_L[0], -SOD_L[1], SOD_L[2]), g, -x, t)
+    assert np.allclose(wm[0], rho) and np.allclose(-wm[1], u) and np.allclose(wm[2], p)
+
+
+def sod_error(ora, nx, flux, limiter="muscl", dt_factor=0.15):
+    """Sod tube on (nx, 1, 1) elements of degree (1, 0, 0) with fixed
+    exterior states; initial data interpolated pointwise (left state for
+    x <= 0, eq. RP); dt = dt_factor * dx; L1 error (eq. L1) of the conserved
+    variables against the exact solution at T = 0.25."""
+    g = 1.4
+    m = ora.mesh(NE, (nx, 1, 1), (1, 0, 0), g, lo=(-0.5, 0, 0), hi=(0.5, 1, 1), flux=flux,
+                 bc={0: ((1.0, 0, 0, 0, 1.0), (0.125, 0, 0, 0, 0.1))}, limiter=limiter)
+    x = ora.node_coords(m)[0]
+
+    def cons(w):
+        prim = np.zeros((5, x.size))
+        prim[0], prim[1], prim[4] = w
+        return ora.prim2cons(NE, g, prim)
+
+    left = x <= 0.0
+    U0 = cons((np.where(left, 1.0, 0.125), 0.0 * x, np.where(left, 1.0, 0.1)))
+    T = 0.25
+    nst = int(math.ceil(T / (dt_factor / nx)))
+    U1, nf = ora.evolve(m, U0, T / nst, nst)
+    assert nf == 0
+    return ora.l1_error(m, cons(riemann.sample(SOD_L, SOD_R, g, x, T)), U1), m, U0, T / nst
+
+
+@pytest.mark.parametrize("flux", ["hll", "llf"])
+def test_ne_sod_table(ora, flux):
+    """tab:NE_sod, rows HLL-MinMod-2 and LLF-MinMod-2: each error within 5% of
+    the printed two-digit value (n_x = 20, 40, 80; up to 640 with
+    DGMI_SLOW=1).  The rows are reproduced with beta = 1 in the slope
+    estimates (with beta = 2 the errors come out 15-25% below the printed
+    ones); the time step, not given, changes them by under 2% between
+    dt = 0.05 dx and 0.3 dx."""
+    gold = json.load(open(os.path.join(GOLD, "ne_sod_table.json")))
+    cols = gold["columns_nx"] if SLOW else gold["columns_nx"][:3]
+    for nx, ref in zip(cols, gold["rows"][flux]):
+        err = sod_error(ora, nx, flux)[0]
+        assert abs(err - ref) <= 0.05 * ref, (nx, err, ref)
+
+
+def test_fixed_state_boundary_free_stream(ora):
+    """Exterior states equal to a constant interior flow: no change at the
+    boundaries (or anywhere)."""
+    for system in (NE, SR, MHD):
+        g = 4.0 / 3.0 if system else 1.4
+        st = (1.3, 0.3, -0.2, 0.25, 0.7, 0.4, -0.3, 0.2, 0.0)
+        m = ora.mesh(system, (3, 2, 2), 3, g, bc={0: (st, st), 2: (st, st)}, kappa=0.5)
+        n = ora.num_nodes(m)
+        prim = np.tile(np.array(st[:5])[:, None], (1, n))
+        mag = np.tile(np.array(st[5:])[:, None], (1, n))
+        U = ora.prim2cons(system, g, prim, mag if system == MHD else None)
+        dU, _, _ = ora.rhs(m, U)
+        assert np.abs(dU).max() < 1e-12
