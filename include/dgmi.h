@@ -116,7 +116,9 @@ dgmi_status dgmi_prim2cons(int32_t system, double gamma, const double *prim, con
 
 /* Semi-discrete operator dUdt = L(U) of eq. 411:
  *   L = S - sum_d (2/dx_d) D^(d) F^d - sum_faces (2/dx_d)(1/w_end)(F*.n - F.n),
- * F*.n the LLF flux with the unit outward normal.  First recovers the
+ * F*.n the LLF flux (HLL with DGMI_FLAG_HLL) with the unit outward normal;
+ * across a box face with a fixed exterior state (dgmi_set_boundary) the
+ * exterior is that state.  First recovers the
  * primitives of every node (Newton polished to rounding level, seeded from
  * prim_inout's pressure unless DGMI_FLAG_PLAIN_GUESS), which are written
  * back to prim_inout.  Failed recoveries are counted (dgmi_failures).
@@ -134,8 +136,53 @@ dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, doub
  *   U <- 1/3 U + 2/3 (U2 + dt L(U2)).
  * prim_inout must hold the primitives of U on entry (or set
  * DGMI_FLAG_RECOVER_FIRST); on exit it holds those of the new U.  Each stage
- * is one kernel that also recovers the primitives of its output. */
+ * is one kernel that also recovers the primitives of its output.  With a
+ * slope limiter set (dgmi_set_limiter), every stage result is limited
+ * (as dg_limit does) before its primitives are final. */
 dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream);
+
+/* Box faces with a fixed exterior state (the analytic boundary condition of
+ * the section on initial data, boundary conditions and time steppers, for a
+ * solution that is constant outside the box; uniform meshes only, mixed
+ * degrees return DGMI_EUNSUPPORTED).  direction 0..2 (x, y, z);
+ * state_lo_host / state_hi_host (host memory, copied) are the exterior
+ * primitives (rho, v_x, v_y, v_z, p) beyond the lower / upper box face, for
+ * SRMHD followed by (B_x, B_y, B_z, Phi); both NULL restores periodicity.
+ * States must be physical (rho, p > 0; |v| < 1 for the relativistic
+ * systems), else DGMI_EINVAL.  Synchronous; affects later dg_rhs, dg_operator,
+ * dg_step and dg_limit calls. */
+dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *state_lo_host,
+                              const double *state_hi_host);
+
+/* Minmod-family slope limiter (high-resolution shock-capturing section,
+ * eqs. MinModSol, MinModB and MinMod), uniform meshes only. */
+enum {
+  DGMI_LIMITER_NONE = 0,
+  DGMI_LIMITER_MINMOD = 1, /* neighbour slope estimates with beta = 2 */
+  DGMI_LIMITER_MUSCL = 2   /* beta = 1 */
+};
+
+/* Select the limiter used by dg_step (after every stage) and dg_limit; M is
+ * the minmodB constant (>= 0; 0 gives plain minmod).  Per conserved component
+ * of each element: degree 1 limits when a neighbour estimate changes the
+ * slope; degree >= 2 limits when the face means fail the generalized
+ * troubled-cell test; a limited component becomes mean + limited slopes
+ * (the linear part keeps the Legendre modes 1, x, y, z).  Elements holding a
+ * node whose primitives cannot be recovered are limited in every
+ * component.  Allocates 80 nv bytes per element of device scratch on first
+ * use; DGMI_EUNSUPPORTED on mixed-degree meshes. */
+dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M);
+
+/* Limit U in place with the selected limiter (DGMI_EINVAL if none).
+ * prim_inout: on entry its pressure seeds the recovery of every node; on exit
+ * it holds the primitives of the limited U.  Limited element components are
+ * counted (dgmi_limited); failed recoveries after limiting are counted
+ * (dgmi_failures). */
+dgmi_status dg_limit(dgmi_ctx *ctx, double *U, double *prim_inout, void *stream);
+
+/* Number of limited element components since the last call (synchronises
+ * `stream`, then resets the counter). */
+dgmi_status dgmi_limited(dgmi_ctx *ctx, int64_t *n_limited_host, void *stream);
 
 /* Number of failed recoveries since the last call (synchronises `stream`,
  * then resets the counter). */

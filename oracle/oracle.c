@@ -969,20 +969,40 @@ static void element_moments(const ora_mesh *m, const geom_t *G, const double *U,
           double u = U[(int64_t)v * N + q];
           M->mean[v] += h[0] * h[1] * h[2] * u;
           for (int d = 0; d < 3; ++d) {
-            if (G->n[d] < 2) continue;
-            double o = 1.0;
-            for (int dd = 0; dd < 3; ++dd) o *= dd == d ? 1.5 * mu[d][ijk[d]] : h[dd];
-            M->c[d][v] += o * u;
             int Nd = G->n[d] - 1;
-            if (ijk[d] == 0 || ijk[d] == Nd) {
-              double fw = 1.0;
-              for (int dd = 0; dd < 3; ++dd)
-                if (dd != d) fw *= h[dd];
-              M->face[2 * d + (ijk[d] == Nd)][v] += fw * u;
-            }
+            if (Nd < 1 || (ijk[d] != 0 && ijk[d] != Nd)) continue;
+            double fw = 1.0;
+            for (int dd = 0; dd < 3; ++dd)
+              if (dd != d) fw *= h[dd];
+            M->face[2 * d + (ijk[d] == Nd)][v] += fw * u;
           }
         }
       }
+  /* slope coefficients line by line along d: with the GLL nodes symmetric,
+   * mu[N - i] = -mu[i], so int(U xi) = sum_{i < N - i} mu[N - i] (u[N - i] - u[i]),
+   * which is exactly zero on a line where U is constant */
+  for (int d = 0; d < 3; ++d) {
+    int Nd = G->n[d] - 1;
+    if (Nd < 1) continue;
+    int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+    for (int b = 0; b < G->n[db]; ++b)
+      for (int a = 0; a < G->n[da]; ++a) {
+        double hab = G->w[da][a] / 2.0 * G->w[db][b] / 2.0;
+        for (int v = 0; v < nv; ++v) {
+          double ls = 0.0;
+          for (int i = 0; i < Nd - i; ++i) {
+            int c_hi[3], c_lo[3];
+            c_hi[d] = Nd - i; c_lo[d] = i;
+            c_hi[da] = c_lo[da] = a;
+            c_hi[db] = c_lo[db] = b;
+            int64_t qh = e * npe + c_hi[0] + n0 * (c_hi[1] + n1 * c_hi[2]);
+            int64_t ql = e * npe + c_lo[0] + n0 * (c_lo[1] + n1 * c_lo[2]);
+            ls += mu[d][Nd - i] * (U[(int64_t)v * N + qh] - U[(int64_t)v * N + ql]);
+          }
+          M->c[d][v] += 1.5 * hab * ls;
+        }
+      }
+  }
 }
 
 /* Limit U in place; returns the number of limited element components, or <0

@@ -14,6 +14,7 @@
 
 #include "../../include/dgmi.h"
 #include "kernels.hpp"
+#include "physics.hpp"
 
 namespace {
 
@@ -159,7 +160,39 @@ struct dgmi_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   const void *gU = nullptr, *gP = nullptr;
+  // box faces with fixed exterior states (uniform meshes)
+  int bc[3] = {0, 0, 0};          // per direction: 0 periodic, 1 fixed states
+  double hbc[6 * 16] = {0};       // per box face: conserved [0, nv), primitives [9, 14)
+  double *d_bc = nullptr;         // device copy
+  // slope limiter (uniform meshes)
+  int lim_kind = 0;               // DGMI_LIMITER_*
+  double lim_M = 0.0;
+  double *d_limtab = nullptr;     // [3][8]: w/2, 3/2 int(ell xi), GLL node of the mesh degree
+  double *d_mom = nullptr;        // [nelem][10][nv]
+  int32_t *d_bad = nullptr;       // [nelem]
+  unsigned long long *d_nlim = nullptr;
 };
+
+// Neighbour table [nelem][6] (-x,+x,-y,+y,-z,+z): periodic wrap, or -1 on the
+// box faces of a direction with fixed exterior states.
+static std::vector<int32_t> neighbour_table(const dgmi_ctx *c) {
+  const int64_t ne[3] = {c->nx, c->ny, c->nz};
+  std::vector<int32_t> nbr(c->nelem * 6);
+  for (int64_t e = 0; e < c->nelem; ++e) {
+    const int64_t cc[3] = {e % c->nx, (e / c->nx) % c->ny, e / ((int64_t)c->nx * c->ny)};
+    for (int f = 0; f < 6; ++f) {
+      int64_t k[3] = {cc[0], cc[1], cc[2]};
+      const int d = f >> 1;
+      if (c->bc[d] && ((f & 1) ? k[d] == ne[d] - 1 : k[d] == 0)) {
+        nbr[e * 6 + f] = -1;
+        continue;
+      }
+      k[d] = (k[d] + ((f & 1) ? 1 : ne[d] - 1)) % ne[d];
+      nbr[e * 6 + f] = (int32_t)(k[0] + ne[0] * (k[1] + ne[1] * k[2]));
+    }
+  }
+  return nbr;
+}
 
 
 // ------------------------------------------------------------ mixed degrees
@@ -501,6 +534,11 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_faces);
   (void)hipFree(c->d_facebuf);
   (void)hipFree(c->d_dt);
+  (void)hipFree(c->d_bc);
+  (void)hipFree(c->d_limtab);
+  (void)hipFree(c->d_mom);
+  (void)hipFree(c->d_bad);
+  (void)hipFree(c->d_nlim);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   for (int k = 0; k < 8; ++k) {
@@ -566,17 +604,7 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
     diff_matrix(N, &hx[N * 8], &hD[N * 64]);
     c->wend[N] = w[0];
   }
-  std::vector<int32_t> nbr(c->nelem * 6);
-  for (int64_t e = 0; e < c->nelem; ++e) {
-    const int64_t ex = e % c->nx, ey = (e / c->nx) % c->ny, ez = e / ((int64_t)c->nx * c->ny);
-    const int64_t cc[3] = {ex, ey, ez};
-    for (int f = 0; f < 6; ++f) {
-      int64_t k[3] = {cc[0], cc[1], cc[2]};
-      const int d = f >> 1;
-      k[d] = (k[d] + ((f & 1) ? 1 : ne[d] - 1)) % ne[d];
-      nbr[e * 6 + f] = (int32_t)(k[0] + ne[0] * (k[1] + ne[1] * k[2]));
-    }
-  }
+  const std::vector<int32_t> nbr = neighbour_table(c);
   const size_t ubytes = sizeof(double) * (size_t)c->nv * c->nnodes;
   const size_t pbytes = sizeof(double) * 5 * (size_t)c->nnodes;
   if (hipMalloc(&c->d_D, hD.size() * sizeof(double)) != hipSuccess ||
@@ -584,7 +612,9 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
       hipMalloc(&c->d_nbr, nbr.size() * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&c->d_nfail, sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->d_U1, ubytes) != hipSuccess || hipMalloc(&c->d_U2, ubytes) != hipSuccess ||
-      hipMalloc(&c->d_P1, pbytes) != hipSuccess || hipMalloc(&c->d_P2, pbytes) != hipSuccess) {
+      hipMalloc(&c->d_P1, pbytes) != hipSuccess || hipMalloc(&c->d_P2, pbytes) != hipSuccess ||
+      hipMalloc(&c->d_bc, sizeof(c->hbc)) != hipSuccess || hipMalloc(&c->d_limtab, 24 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_nlim, sizeof(unsigned long long)) != hipSuccess) {
     (void)hipGetLastError();
     ctx_free(c);
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation failed (%lld nodes)", (long long)c->nnodes);
@@ -592,7 +622,9 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
   if (hipMemcpy(c->d_D, hD.data(), hD.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_x, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(c->d_nfail, 0, sizeof(unsigned long long)) != hipSuccess) {
+      hipMemset(c->d_nfail, 0, sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_nlim, 0, sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_bc, 0, sizeof(c->hbc)) != hipSuccess) {
     ctx_free(c);
     return fail(DGMI_EHIP, "dgmi_create: table upload failed");
   }
@@ -651,6 +683,7 @@ dgmi_status dgmi_prim2cons(int32_t system, double gamma, const double *prim, con
 static dgmi::RhsArgs rhs_args(dgmi_ctx *c) {
   dgmi::RhsArgs a{};
   a.nbr = c->d_nbr;
+  a.bcs = c->d_bc;
   a.Dmat = c->d_D + 64 * c->degree;
   a.nfail = c->d_nfail;
   a.nelem = c->nelem;
@@ -662,6 +695,29 @@ static dgmi::RhsArgs rhs_args(dgmi_ctx *c) {
   a.nx = c->nx;
   a.ny = c->ny;
   a.nz = c->nz;
+  return a;
+}
+
+static dgmi::LimArgs lim_args(dgmi_ctx *c, double *U, const double *Pseed, double *Pout) {
+  dgmi::LimArgs a{};
+  a.U = U;
+  a.Pseed = Pseed;
+  a.Pout = Pout;
+  a.mom = c->d_mom;
+  a.bad = c->d_bad;
+  a.nbr = c->d_nbr;
+  a.bcs = c->d_bc;
+  a.h = c->d_limtab;
+  a.mu = c->d_limtab + 8;
+  a.xi = c->d_limtab + 16;
+  a.nelem = c->nelem;
+  a.nnodes = c->nnodes;
+  a.gamma = c->gamma;
+  a.beta = c->lim_kind == DGMI_LIMITER_MINMOD ? 2.0 : 1.0;
+  a.M = c->lim_M;
+  for (int d = 0; d < 3; ++d) a.dx[d] = c->dx[d];
+  a.nlim = c->d_nlim;
+  a.nfail = c->d_nfail;
   return a;
 }
 
@@ -752,16 +808,121 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
   dgmi::RhsArgs a = rhs_args(ctx);
   a.dt = dt;
   a.Un = U;
+  // with a limiter, a stage kernel writes U^(s) only; the limiter then
+  // recovers every node, limits, and recovers the nodes it changed
+  const bool limit = ctx->lim_kind != DGMI_LIMITER_NONE;
+  a.no_recover = limit ? 1 : 0;
   // stage 1: U1 = U + dt L(U)
   a.U = U; a.P = prim_inout; a.out = ctx->d_U1; a.Pout = ctx->d_P1; a.a = 0.0; a.b = 1.0;
   HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
+  if (limit) HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, lim_args(ctx, ctx->d_U1, prim_inout, ctx->d_P1), s));
   // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
   a.U = ctx->d_U1; a.P = ctx->d_P1; a.out = ctx->d_U2; a.Pout = ctx->d_P2; a.a = 0.75; a.b = 0.25;
   HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
+  if (limit) HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, lim_args(ctx, ctx->d_U2, ctx->d_P1, ctx->d_P2), s));
   // stage 3: U <- 1/3 U + 2/3 (U2 + dt L(U2))  (each thread reads U^n at its own node before writing it)
   a.U = ctx->d_U2; a.P = ctx->d_P2; a.out = U; a.Pout = prim_inout; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
   a.full_prims = 1;
   HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
+  if (limit) HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, lim_args(ctx, U, ctx->d_P2, prim_inout), s));
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *state_lo_host,
+                              const double *state_hi_host) {
+  if (!ctx) return fail(DGMI_EINVAL, "dgmi_set_boundary: null context");
+  if (ctx->mixed) return fail(DGMI_EUNSUPPORTED, "dgmi_set_boundary: mixed-degree meshes are periodic only");
+  if (direction < 0 || direction > 2) return fail(DGMI_EINVAL, "dgmi_set_boundary: direction must be 0, 1 or 2");
+  if ((state_lo_host == nullptr) != (state_hi_host == nullptr))
+    return fail(DGMI_EINVAL, "dgmi_set_boundary: give both states or neither");
+  double hbc[6 * 16];
+  std::memcpy(hbc, ctx->hbc, sizeof(hbc));
+  int bc = 0;
+  if (state_lo_host) {
+    const int nin = ctx->sys == 2 ? 9 : 5;
+    for (int side = 0; side < 2; ++side) {
+      const double *st = side ? state_hi_host : state_lo_host;
+      for (int k = 0; k < nin; ++k)
+        if (!std::isfinite(st[k])) return fail(DGMI_EINVAL, "dgmi_set_boundary: non-finite state");
+      const double v2 = st[1] * st[1] + st[2] * st[2] + st[3] * st[3];
+      if (!(st[0] > 0.0) || !(st[4] > 0.0) || (ctx->sys != 0 && !(v2 < 1.0)))
+        return fail(DGMI_EINVAL, "dgmi_set_boundary: state is not physical (rho, p > 0, |v| < 1)");
+      dgmi::Prim P;
+      P.rho = st[0]; P.v[0] = st[1]; P.v[1] = st[2]; P.v[2] = st[3]; P.p = st[4];
+      double *row = hbc + (2 * direction + side) * 16;
+      for (int k = 0; k < 16; ++k) row[k] = 0.0;
+      switch (ctx->sys) {
+        case 0: dgmi::prim_to_cons<dgmi::kNE>(P, nullptr, ctx->gamma, row); break;
+        case 1: dgmi::prim_to_cons<dgmi::kSR>(P, nullptr, ctx->gamma, row); break;
+        default: dgmi::prim_to_cons<dgmi::kMHD>(P, st + 5, ctx->gamma, row); break;
+      }
+      for (int k = 0; k < 5; ++k) row[9 + k] = st[k];
+    }
+    bc = 1;
+  }
+  const int old = ctx->bc[direction];
+  ctx->bc[direction] = bc;
+  const std::vector<int32_t> nbr = neighbour_table(ctx);
+  if (hipMemcpy(ctx->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ctx->d_bc, hbc, sizeof(hbc), hipMemcpyHostToDevice) != hipSuccess) {
+    ctx->bc[direction] = old;
+    return fail(DGMI_EHIP, "dgmi_set_boundary: table upload failed");
+  }
+  std::memcpy(ctx->hbc, hbc, sizeof(hbc));
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M) {
+  if (!ctx) return fail(DGMI_EINVAL, "dgmi_set_limiter: null context");
+  if (kind < DGMI_LIMITER_NONE || kind > DGMI_LIMITER_MUSCL) return fail(DGMI_EINVAL, "dgmi_set_limiter: unknown kind");
+  if (!(M >= 0.0) || !std::isfinite(M)) return fail(DGMI_EINVAL, "dgmi_set_limiter: M must be finite and >= 0");
+  if (ctx->mixed && kind != DGMI_LIMITER_NONE)
+    return fail(DGMI_EUNSUPPORTED, "dgmi_set_limiter: the limiter is implemented for uniform degrees only");
+  if (kind != DGMI_LIMITER_NONE && !ctx->d_mom) {
+    if (hipMalloc(&ctx->d_mom, sizeof(double) * 10 * ctx->nv * ctx->nelem) != hipSuccess ||
+        hipMalloc(&ctx->d_bad, sizeof(int32_t) * ctx->nelem) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(ctx->d_mom);
+      ctx->d_mom = nullptr;
+      return fail(DGMI_ENOMEM, "dgmi_set_limiter: device allocation failed");
+    }
+    // per node index of the mesh degree: w/2, 3/2 int(ell_i xi), x_i; the
+    // first moment int(ell_i xi) is w_i x_i (GLL quadrature is exact for the
+    // degree N+1 integrand when N >= 2) and -+1/3 at degree 1
+    const int N = ctx->degree;
+    double x[8], w[8], tab[24] = {0};
+    gll_nodes(N, x, w);
+    for (int i = 0; i <= N; ++i) {
+      tab[i] = 0.5 * w[i];
+      tab[8 + i] = 1.5 * (N == 1 ? (i ? 1.0 / 3.0 : -1.0 / 3.0) : w[i] * x[i]);
+      tab[16 + i] = x[i];
+    }
+    if (hipMemcpy(ctx->d_limtab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(DGMI_EHIP, "dgmi_set_limiter: table upload failed");
+  }
+  ctx->lim_kind = kind;
+  ctx->lim_M = M;
+  return DGMI_OK;
+}
+
+dgmi_status dg_limit(dgmi_ctx *ctx, double *U, double *prim_inout, void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dg_limit: null context");
+  if (ctx->lim_kind == DGMI_LIMITER_NONE) return fail(DGMI_EINVAL, "dg_limit: no limiter set (dgmi_set_limiter)");
+  if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
+    return fail(DGMI_EINVAL, "dg_limit: U and prim_inout must be distinct device pointers");
+  HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, lim_args(ctx, U, prim_inout, prim_inout), (hipStream_t)stream));
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_limited(dgmi_ctx *ctx, int64_t *n_limited_host, void *stream) {
+  if (!ctx || !n_limited_host) return fail(DGMI_EINVAL, "dgmi_limited: null argument");
+  unsigned long long v = 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(&v, ctx->d_nlim, sizeof(v), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemsetAsync(ctx->d_nlim, 0, sizeof(v), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *n_limited_host = (int64_t)v;
   return DGMI_OK;
 }
 

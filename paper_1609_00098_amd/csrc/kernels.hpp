@@ -32,6 +32,11 @@ struct RhsArgs {
   const int64_t *foff;
   const double *facebuf;
   int nblocks;         // logical blocks (set at launch)
+  // uniform meshes: a face whose neighbour index is negative lies on a box
+  // face with a fixed exterior state, bcs[f][0..nv) conserved and
+  // bcs[f][9..14) primitives (16 doubles per box face f)
+  const double *bcs;
+  int no_recover;      // stage kernel: write U^(s) only (the limiter recovers afterwards)
 };
 
 // Numerical fluxes of the uniform-mesh element kernels.
@@ -44,6 +49,26 @@ hipError_t launch_rhs_hll(int sys, int N, int stage, const RhsArgs &a, hipStream
 // The same kernels over one degree's elements of a mixed-degree mesh, epb
 // elements per workgroup (one of mixed_tile_options).
 hipError_t launch_rhs_mixed(int sys, int N, int epb, int stage, const RhsArgs &a, hipStream_t s);
+
+// Minmod-family slope limiter on a uniform mesh of degree N: moments and
+// primitives of U (prims seeded from Pseed's pressure, written to Pout,
+// which may be Pseed), then the limited U in place with the primitives of
+// the changed nodes.  mom: [nelem][10][nv] scratch, bad: [nelem].
+struct LimArgs {
+  double *U;
+  const double *Pseed;
+  double *Pout;
+  double *mom;
+  int32_t *bad;
+  const int32_t *nbr;
+  const double *bcs;
+  const double *h, *mu, *xi;  // per node index: w/2, 3/2 int(ell xi), GLL node
+  int64_t nelem, nnodes;
+  double gamma, beta, M;
+  double dx[3];
+  unsigned long long *nlim, *nfail;
+};
+hipError_t launch_limiter(int sys, int N, const LimArgs &a, hipStream_t s);
 
 // Highest degree of the mixed-degree path (mortars of up to 8x8 nodes).
 constexpr int kMaxMixedDegree = 7;

@@ -21,6 +21,8 @@
 //      a U^n + b (U + dt L) and recovers the primitives of the result with
 //      the previous stage's pressure as the Newton seed (tail recovery), so
 //      the next stage finds neighbour primitives ready.
+// A face on a box face with a fixed exterior state (negative neighbour
+// index, uniform meshes) takes that state as its exterior.
 // Workgroups are mapped XCD-major: consecutive element groups land on the
 // same XCD (and L2), so face neighbours along x and y are usually L2 hits.
 //
@@ -239,8 +241,15 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     const int ai = c0 + NP * (c1 + NP * c2);
     double ue[NV], Fe[NV];
     Prim Pe;
-    const int64_t ebase = MIXED ? A.off[en] : en * NPE;
-    load_node<SYS>(A.U, A.P, nn, ebase + n0 + NP * (n1 + NP * n2), A.gamma, ue, Pe);
+    if (!MIXED && en < 0) {  // box face with a fixed exterior state
+      const double *bs = A.bcs + f * 16;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ue[v] = bs[v];
+      Pe.rho = bs[9]; Pe.v[0] = bs[10]; Pe.v[1] = bs[11]; Pe.v[2] = bs[12]; Pe.p = bs[13];
+    } else {
+      const int64_t ebase = MIXED ? A.off[en] : en * NPE;
+      load_node<SYS>(A.U, A.P, nn, ebase + n0 + NP * (n1 + NP * n2), A.gamma, ue, Pe);
+    }
     flux_normal<SYS>(d, ue, Pe, Fe);
     const double *own = sown + fle * NV * NPE + ai;
     double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
@@ -308,6 +317,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     us[v] = A.a * A.Un[v * nn + q] + A.b * (u[v] + dt * acc[v]);
     A.out[v * nn + q] = us[v];
   }
+  if (A.no_recover) return;
   const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100);
   // intermediate stages of NE / SR keep only the pressure (the next stage
   // rebuilds the rest); SRMHD and the caller's buffers get all five rows

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libdgmi.so")
 NEWTONIAN_EULER, SR_HYDRO, SR_MHD = 0, 1, 2
 GUESS_INPUT, GUESS_PLAIN, GUESS_LEARNED = 0, 1, 2
 FLAG_PLAIN_GUESS, FLAG_RECOVER_FIRST, FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_HLL = 1, 2, 4, 8, 16
+LIMITER_NONE, LIMITER_MINMOD, LIMITER_MUSCL = 0, 1, 2
 NVARS = {NEWTONIAN_EULER: 5, SR_HYDRO: 5, SR_MHD: 9}
 MLP_NUM_WEIGHTS = 4609
 MLP_NUM_PARAMS = 4621
@@ -56,6 +57,10 @@ _SIGS = {
     "dg_step": (_I32, [_P, _P, _P, _D, _P]),
     "dg_operator": (_I32, [_P, _P, _P, _P, _P]),
     "dgmi_failures": (_I32, [_P, ctypes.POINTER(_I64), _P]),
+    "dgmi_set_boundary": (_I32, [_P, _I32, _P, _P]),
+    "dgmi_set_limiter": (_I32, [_P, _I32, _D]),
+    "dg_limit": (_I32, [_P, _P, _P, _P]),
+    "dgmi_limited": (_I32, [_P, ctypes.POINTER(_I64), _P]),
     "con2prim": (_I32, [_I32, _D, _P, _P, _I64, _I32, _P, _D, _P, _P, _P, _P]),
     "dgmi_last_error": (ctypes.c_char_p, []),
     "mlp_create": (_I32, [ctypes.POINTER(_P), ctypes.c_uint64]),
@@ -189,6 +194,39 @@ def dg_operator(mesh, U, prim, dUdt, stream=None):
     _check(_lib.dg_operator(mesh.handle, _ptr(U, numel=mesh.nv * n, name="U"), _ptr(prim, numel=5 * n, name="prim"),
                             _ptr(dUdt, numel=mesh.nv * n, name="dUdt"), _stream(stream)), "dg_operator")
     return dUdt
+
+
+def dgmi_set_boundary(mesh, direction, state_lo=None, state_hi=None):
+    """Fixed exterior states (primitives, + B and Phi for SRMHD) on the two box
+    faces of ``direction``; both None restores periodicity."""
+    import numpy as np
+    if state_lo is None and state_hi is None:
+        _check(_lib.dgmi_set_boundary(mesh.handle, direction, None, None), "dgmi_set_boundary")
+        return
+    lo = np.ascontiguousarray(state_lo, dtype=np.float64)
+    hi = np.ascontiguousarray(state_hi, dtype=np.float64)
+    need = 9 if mesh.system == SR_MHD else 5
+    if lo.size != need or hi.size != need:
+        raise ValueError(f"states must have {need} entries")
+    _check(_lib.dgmi_set_boundary(mesh.handle, direction, lo.ctypes.data_as(ctypes.c_void_p),
+                                  hi.ctypes.data_as(ctypes.c_void_p)), "dgmi_set_boundary")
+
+
+def dgmi_set_limiter(mesh, kind, M=0.0):
+    _check(_lib.dgmi_set_limiter(mesh.handle, kind, float(M)), "dgmi_set_limiter")
+
+
+def dg_limit(mesh, U, prim_inout, stream=None):
+    n = mesh.nnodes
+    _check(_lib.dg_limit(mesh.handle, _ptr(U, numel=mesh.nv * n, name="U"),
+                         _ptr(prim_inout, numel=5 * n, name="prim_inout"), _stream(stream)), "dg_limit")
+    return U
+
+
+def dgmi_limited(mesh, stream=None):
+    v = _I64(0)
+    _check(_lib.dgmi_limited(mesh.handle, ctypes.byref(v), _stream(stream)), "dgmi_limited")
+    return int(v.value)
 
 
 def dg_step(mesh, U, prim_inout, dt, stream=None):
