@@ -51,7 +51,7 @@ def parse():
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the SRMHD blast-wave RK3 steps and the learned-vs-plain recovery comparison")
-    ap.add_argument("--only", choices=["blast", "mixed", "c2p"], default=None,
+    ap.add_argument("--only", choices=["blast", "mixed", "c2p", "limiter"], default=None,
                     help="run one extra section alone and print its JSON (for profiling its kernels)")
     ap.add_argument("--c2p-points", type=int, default=100_000_000)
     ap.add_argument("--train-samples", type=int, default=10_000_000)
@@ -62,8 +62,8 @@ def parse():
 # (FETCH_SIZE, WRITE_SIZE) summarised in profiles/; it is reported only while
 # the kernel's sources are the ones those counters were taken on.
 PROFILE = os.path.join(ROOT, "profiles", "dg_rhs_sr_hydro_32x32x32_deg4.md")
-KERNEL_SOURCES = ["paper_1609_00098_amd/csrc/rhs.hip", "paper_1609_00098_amd/csrc/physics.hpp",
-                  "paper_1609_00098_amd/csrc/kernels.hpp"]
+KERNEL_SOURCES = ["paper_1609_00098_amd/csrc/rhs_body.hpp", "paper_1609_00098_amd/csrc/rhs.hip",
+                  "paper_1609_00098_amd/csrc/physics.hpp", "paper_1609_00098_amd/csrc/kernels.hpp"]
 
 
 def kernel_source_hash():
@@ -199,6 +199,78 @@ def learned_vs_plain(dg, synth, torch, npts, ntrain):
     return res
 
 
+def hll_flux(dg, torch, Ua, Ub, P, dUa, dUb, steps, ms_llf, ms_op_llf):
+    """The headline workload with the HLL flux (eq. HLL) instead of LLF:
+    dg_rhs and the operator alone, same inputs and alternation."""
+    H = dg.Mesh(SR, NEL, DEG, GAMMA, flags=dg.FLAG_HLL)
+
+    def rhs(i):
+        dg.dg_rhs(H, Ua if i % 2 == 0 else Ub, P, dUa if i % 2 == 0 else dUb)
+
+    def op(i):
+        dg.dg_operator(H, Ua if i % 2 == 0 else Ub, P, dUa if i % 2 == 0 else dUb)
+
+    ms = time_loop(torch, rhs, steps, 4)
+    ms_op = time_loop(torch, op, max(steps // 2, 10), 4)
+    nn = H.nnodes
+    out = {"workload": "the dg_rhs workload above with the HLL flux", "ms_per_step": ms,
+           "dof_updates_per_s": nn * NV / (ms * 1e-3), "operator_ms": ms_op,
+           "operator_ms_llf": ms_op_llf, "ms_per_step_llf": ms_llf, "failed_recoveries": dg.dgmi_failures(H)}
+    del H
+    return out
+
+
+def limiter_steps(dg, synth, torch, steps=20, warmup=3):
+    """SR hydro, Gamma 4/3, periodic 32^3 elements of degree 4, smooth random
+    primitives (rho, p in [0.5, 2], W <= 1.5) with density and pressure
+    dropping by 0.3 and 0.2 across x = 0.37; MUSCL slope limiter.  Times
+    dg_limit alone (moments + apply kernels) and RK3 steps of dt 1e-4 with
+    and without limiting every stage."""
+    G = dg.Mesh(SR, NEL, DEG, GAMMA)
+    xyz = G.node_coords()
+    prim = synth.fourier_random_prims(xyz, seed=1609, w_max=1.5, rho_range=(0.5, 2.0), p_range=(0.5, 2.0),
+                                      xp="torch", device="cuda")
+    step = xyz[0] > 0.37
+    prim[0] = torch.where(step, 0.3 * prim[0], prim[0])
+    prim[4] = torch.where(step, 0.2 * prim[4], prim[4])
+    del xyz, step
+    prim = prim.contiguous()
+    U0 = dg.dgmi_prim2cons(SR, GAMMA, prim)
+    U = U0.clone()
+    P = prim.clone()
+    nn = G.nnodes
+    dg.dgmi_set_limiter(G, dg.LIMITER_MUSCL, 0.0)
+    dg.dgmi_limited(G)
+    dg.dg_limit(G, U, P)
+    limited = dg.dgmi_limited(G)
+    fails_limit = dg.dgmi_failures(G)
+
+    def lim(i):
+        U.copy_(U0)
+        dg.dg_limit(G, U, P)
+
+    def copy_only(i):
+        U.copy_(U0)
+
+    ms_lim = time_loop(torch, lim, steps, warmup) - time_loop(torch, copy_only, steps, warmup)
+    U.copy_(U0)
+    P.copy_(prim)
+    dg.dg_limit(G, U, P)
+    dt = 1e-4
+    ms_step_lim = time_loop(torch, lambda i: dg.dg_step(G, U, P, dt), steps, warmup)
+    fails_lim = dg.dgmi_failures(G)
+    dg.dgmi_set_limiter(G, dg.LIMITER_NONE, 0.0)
+    ms_step = time_loop(torch, lambda i: dg.dg_step(G, U, P, dt), steps, warmup)
+    out = {"workload": "SR hydro, 32^3 elements, degree 4, smooth random primitives with a jump, MUSCL limiter",
+           "nodes": nn, "limited_components_fraction": limited / (G.nelem[0] * G.nelem[1] * G.nelem[2] * NV),
+           "dg_limit_ms": ms_lim, "dg_limit_nodes_per_s": nn / (ms_lim * 1e-3),
+           "dg_step_ms_limited": ms_step_lim, "dg_step_ms_unlimited": ms_step,
+           "failed_recoveries": fails_limit + fails_lim + dg.dgmi_failures(G)}
+    del G, U, U0, P, prim
+    torch.cuda.empty_cache()
+    return out
+
+
 def make_inputs(dg, synth, torch):
     G = dg.Mesh(SR, NEL, DEG, GAMMA)
     xyz = G.node_coords()
@@ -269,7 +341,8 @@ def main():
     if args.only:
         fn = {"blast": lambda: srmhd_blast_steps(dg, synth, torch),
               "mixed": lambda: mixed_degree_steps(dg, synth, torch),
-              "c2p": lambda: learned_vs_plain(dg, synth, torch, args.c2p_points, args.train_samples)}[args.only]
+              "c2p": lambda: learned_vs_plain(dg, synth, torch, args.c2p_points, args.train_samples),
+              "limiter": lambda: limiter_steps(dg, synth, torch)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     G, Ua, Ub, P, dUa, dUb = make_inputs(dg, synth, torch)
@@ -330,10 +403,12 @@ def main():
         "roofline": roof,
     }
     if not args.no_extras:
+        out["hll_flux_dg_rhs"] = hll_flux(dg, torch, Ua, Ub, P, dUa, dUb, args.steps, ms, ms_op)
         del Ua, Ub, P, dUa, dUb, G
         torch.cuda.empty_cache()
         out["srmhd_blast_dg_step"] = srmhd_blast_steps(dg, synth, torch)
         out["mixed_degree_dg_step"] = mixed_degree_steps(dg, synth, torch)
+        out["limiter"] = limiter_steps(dg, synth, torch)
         out["con2prim_learned_vs_plain"] = learned_vs_plain(dg, synth, torch, args.c2p_points, args.train_samples)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
