@@ -808,24 +808,36 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
   dgmi::RhsArgs a = rhs_args(ctx);
   a.dt = dt;
   a.Un = U;
-  // with a limiter, a stage kernel writes U^(s) only; the limiter then
-  // recovers every node, limits, and recovers the nodes it changed
+  // with a limiter, each stage kernel also recovers every node of its result
+  // and writes the element moments; the limiter's decide and apply kernels
+  // follow (the apply kernel re-recovers the nodes it changes)
   const bool limit = ctx->lim_kind != DGMI_LIMITER_NONE;
-  a.no_recover = limit ? 1 : 0;
+  auto stage = [&](double *out, double *Pout) -> dgmi_status {
+    a.out = out;
+    a.Pout = Pout;
+    if (!limit) {
+      HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
+      return DGMI_OK;
+    }
+    a.mom = ctx->d_mom;
+    a.bad = ctx->d_bad;
+    a.lim_h = ctx->d_limtab;
+    a.lim_mu = ctx->d_limtab + 8;
+    HIP_TRY(dgmi::launch_rhs_stage_moments(ctx->sys, ctx->degree, flux_of(ctx), a, s));
+    HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, false, lim_args(ctx, out, Pout, Pout), s));
+    return DGMI_OK;
+  };
+  dgmi_status st;
   // stage 1: U1 = U + dt L(U)
-  a.U = U; a.P = prim_inout; a.out = ctx->d_U1; a.Pout = ctx->d_P1; a.a = 0.0; a.b = 1.0;
-  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
-  if (limit) HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, lim_args(ctx, ctx->d_U1, prim_inout, ctx->d_P1), s));
+  a.U = U; a.P = prim_inout; a.a = 0.0; a.b = 1.0;
+  if ((st = stage(ctx->d_U1, ctx->d_P1)) != DGMI_OK) return st;
   // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
-  a.U = ctx->d_U1; a.P = ctx->d_P1; a.out = ctx->d_U2; a.Pout = ctx->d_P2; a.a = 0.75; a.b = 0.25;
-  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
-  if (limit) HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, lim_args(ctx, ctx->d_U2, ctx->d_P1, ctx->d_P2), s));
+  a.U = ctx->d_U1; a.P = ctx->d_P1; a.a = 0.75; a.b = 0.25;
+  if ((st = stage(ctx->d_U2, ctx->d_P2)) != DGMI_OK) return st;
   // stage 3: U <- 1/3 U + 2/3 (U2 + dt L(U2))  (each thread reads U^n at its own node before writing it)
-  a.U = ctx->d_U2; a.P = ctx->d_P2; a.out = U; a.Pout = prim_inout; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
+  a.U = ctx->d_U2; a.P = ctx->d_P2; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
   a.full_prims = 1;
-  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
-  if (limit) HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, lim_args(ctx, U, ctx->d_P2, prim_inout), s));
-  return DGMI_OK;
+  return stage(U, prim_inout);
 }
 
 dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *state_lo_host,
@@ -910,7 +922,8 @@ dgmi_status dg_limit(dgmi_ctx *ctx, double *U, double *prim_inout, void *stream)
   if (ctx->lim_kind == DGMI_LIMITER_NONE) return fail(DGMI_EINVAL, "dg_limit: no limiter set (dgmi_set_limiter)");
   if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
     return fail(DGMI_EINVAL, "dg_limit: U and prim_inout must be distinct device pointers");
-  HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, lim_args(ctx, U, prim_inout, prim_inout), (hipStream_t)stream));
+  HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, true, lim_args(ctx, U, prim_inout, prim_inout),
+                               (hipStream_t)stream));
   return DGMI_OK;
 }
 

@@ -36,7 +36,11 @@ struct RhsArgs {
   // face with a fixed exterior state, bcs[f][0..nv) conserved and
   // bcs[f][9..14) primitives (16 doubles per box face f)
   const double *bcs;
-  int no_recover;      // stage kernel: write U^(s) only (the limiter recovers afterwards)
+  // limited stage kernel: element moments [nelem][10][nv] and unphysical flags
+  // of U^(s) for the slope limiter; lim_h, lim_mu: w/2 and 3/2 int(ell xi)
+  double *mom;
+  int32_t *bad;
+  const double *lim_h, *lim_mu;
 };
 
 // Numerical fluxes of the uniform-mesh element kernels.
@@ -68,7 +72,12 @@ struct LimArgs {
   double dx[3];
   unsigned long long *nlim, *nfail;
 };
-hipError_t launch_limiter(int sys, int N, const LimArgs &a, hipStream_t s);
+// moments = false: the moments (and the primitives of every node) are
+// already in place, written by the limited RK stage kernel.
+hipError_t launch_limiter(int sys, int N, bool moments, const LimArgs &a, hipStream_t s);
+// RK stage (uniform mesh) that also writes the limiter's element moments and
+// unphysical-node flags of its result (RhsArgs::mom, bad, lim_h, lim_mu).
+hipError_t launch_rhs_stage_moments(int sys, int N, int flux, const RhsArgs &a, hipStream_t s);
 
 // Highest degree of the mixed-degree path (mortars of up to 8x8 nodes).
 constexpr int kMaxMixedDegree = 7;

@@ -1,21 +1,24 @@
 // Minmod-family slope limiter (high-resolution shock-capturing section:
 // eqs. MinModSol, MinModB, MinMod and the generalized troubled-cell test),
-// on uniform meshes, in two launches with a grid-wide dependency between
+// on uniform meshes, in three steps with grid-wide dependencies between
 // them (a limited element needs its neighbours' means):
 //
-//   limiter_moments_kernel  one thread per node: recovers the node's
-//       primitives (seeded with the pressure of the state the stage started
-//       from), flags the element when a recovery fails, and reduces the
-//       element's nodes in LDS to ten numbers per conserved component: the
-//       mean, the Legendre slope coefficients c_x, c_y, c_z of its linear
-//       part, and the six face means.  U is read once; prims are written.
-//   limiter_apply_kernel    one thread per (element, component) decides
-//       from the moments of the element and its six neighbours (or a box
-//       face's fixed exterior state) whether the component is troubled and
-//       what its limited slopes are; then one thread per node rewrites the
-//       troubled components as U0 + sum_d a_d (x_d - x_d0) and recovers the
-//       primitives of the rewritten nodes.  Elements with nothing troubled
-//       touch no node data at all.
+//   moments   one thread per node: recover the node's primitives (seeded
+//       with the pressure of the state the stage started from), flag the
+//       element when a recovery fails, and reduce the element's nodes in
+//       LDS to ten numbers per conserved component: the mean, the Legendre
+//       slope coefficients c_x, c_y, c_z of its linear part, and the six
+//       face means.  Inside dg_step the RK stage kernel does this itself on
+//       the state it has just formed (limiter_moments_kernel serves
+//       dg_limit).
+//   decide    one thread per (element, component): from the moments of the
+//       element and its six neighbours (or a box face's fixed exterior
+//       state), whether the component is troubled and its limited slopes,
+//       written over the element's moments.
+//   apply     one thread per node of an element with a troubled component:
+//       rewrite the troubled components as U0 + sum_d a_d (x_d - x_d0) and
+//       recover the node's primitives.  Other elements read one flag per
+//       component and touch no node data.
 //
 // Per component k of element e and direction d (every direction has degree
 // N >= 1 on a uniform mesh):
@@ -28,21 +31,10 @@
 // F_lo, F_hi the face means.  An element with an unrecoverable node is
 // troubled in every component.
 #include "kernels.hpp"
+#include "limiter.hpp"
 #include "physics.hpp"
 
 namespace dgmi {
-
-__device__ __forceinline__ double mm_sign(double a) { return a > 0.0 ? 1.0 : (a < 0.0 ? -1.0 : 0.0); }
-
-__device__ __forceinline__ double minmod3(double a1, double a2, double a3) {
-  const double s = mm_sign(a1);
-  if (s == 0.0 || mm_sign(a2) != s || mm_sign(a3) != s) return 0.0;
-  return s * fmin(fabs(a1), fmin(fabs(a2), fabs(a3)));
-}
-
-__device__ __forceinline__ double minmodB(double a1, double a2, double a3, double M, double dx) {
-  return fabs(a1) <= M * dx * dx ? a1 : minmod3(a1, a2, a3);
-}
 
 template <int N>
 constexpr int lim_epb() {
@@ -57,7 +49,6 @@ struct LimCfg {
   static constexpr int THREADS = ((EPB * NPE + 63) / 64) * 64;
 };
 
-template <int SYS>
 __device__ __forceinline__ void store_prims(double *Pout, int64_t nn, int64_t q, const Prim &P) {
   Pout[q] = P.rho;
   Pout[nn + q] = P.v[0];
@@ -69,8 +60,9 @@ __device__ __forceinline__ void store_prims(double *Pout, int64_t nn, int64_t q,
 template <int SYS, int N>
 __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_moments_kernel(const LimArgs A) {
   using C = LimCfg<SYS, N>;
-  constexpr int NP = C::NP, NPE = C::NPE, NV = C::NV, EPB = C::EPB;
+  constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
   __shared__ double su[EPB * NV * NPE];
+  __shared__ double lines[4 * EPB * NV * NF];
   __shared__ double sh[NP], smu[NP];
   __shared__ int sbad[EPB];
   const int tid = threadIdx.x;
@@ -81,7 +73,7 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_moments_ker
   if (tid < EPB) sbad[tid] = 0;
   __syncthreads();
   const int le = tid / NPE, a = tid - le * NPE;
-  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  const int64_t e0 = (int64_t)blockIdx.x * EPB, e = e0 + le;
   const int64_t nn = A.nnodes;
   if (le < EPB && e < A.nelem) {
     const int64_t q = e * NPE + a;
@@ -92,72 +84,29 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_moments_ker
       su[(le * NV + v) * NPE + a] = u[v];
     }
     const C2PResult R = recover<SYS>(u, A.gamma, A.Pseed[4 * nn + q], 0.0, 100);
-    store_prims<SYS>(A.Pout, nn, q, R.P);
+    store_prims(A.Pout, nn, q, R.P);
     if (!R.ok) sbad[le] = 1;
   }
   __syncthreads();
-  // ten reductions per component: mean, c_x, c_y, c_z, faces -x +x -y +y -z +z
-  for (int t = tid; t < EPB * NV * 10; t += C::THREADS) {
-    const int le2 = t / (NV * 10), r = t - le2 * NV * 10;
-    const int kind = r / NV, v = r - kind * NV;
-    const int64_t e2 = (int64_t)blockIdx.x * EPB + le2;
-    if (e2 >= A.nelem) continue;
-    const double *uu = su + (le2 * NV + v) * NPE;
-    double s = 0.0;
-    if (kind == 0) {
-      for (int k = 0; k < NP; ++k)
-        for (int j = 0; j < NP; ++j)
-          for (int i = 0; i < NP; ++i) s += sh[i] * sh[j] * sh[k] * uu[i + NP * (j + NP * k)];
-    } else if (kind < 4) {
-      // line by line along d, pairing mirror nodes (mu is odd about the
-      // element centre): a line on which U is constant adds exactly zero
-      const int d = kind - 1;
-      const int sd = d == 0 ? 1 : (d == 1 ? NP : NP * NP);
-      const int sa = d == 0 ? NP : 1, sb = d == 2 ? NP : NP * NP;
-      for (int b = 0; b < NP; ++b)
-        for (int c = 0; c < NP; ++c) {
-          const double *line = uu + c * sa + b * sb;
-          double ls = 0.0;
-          for (int i = 0; i < N - i; ++i) ls += smu[N - i] * (line[(N - i) * sd] - line[i * sd]);
-          s += sh[c] * sh[b] * ls;
-        }
-    } else {
-      const int f = kind - 4, d = f >> 1, idx = (f & 1) ? N : 0;
-      for (int b = 0; b < NP; ++b)
-        for (int c = 0; c < NP; ++c) {
-          const int i = d == 0 ? idx : c, j = d == 1 ? idx : (d == 0 ? c : b), k = d == 2 ? idx : b;
-          const double w = (d == 0 ? 1.0 : sh[i]) * (d == 1 ? 1.0 : sh[j]) * (d == 2 ? 1.0 : sh[k]);
-          s += w * uu[i + NP * (j + NP * k)];
-        }
-    }
-    A.mom[(e2 * 10 + kind) * NV + v] = s;
-  }
-  if (tid < EPB) {
-    const int64_t e2 = (int64_t)blockIdx.x * EPB + tid;
-    if (e2 < A.nelem) A.bad[e2] = sbad[tid];
-  }
+  element_moments<N, NV, EPB, C::THREADS>(su, lines, sh, smu, A.mom, e0, A.nelem);
+  if (tid < EPB && e0 + tid < A.nelem) A.bad[e0 + tid] = sbad[tid];
 }
 
-template <int SYS, int N>
-__global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_apply_kernel(const LimArgs A) {
-  using C = LimCfg<SYS, N>;
-  constexpr int NP = C::NP, NPE = C::NPE, NV = C::NV, EPB = C::EPB;
-  __shared__ double sa[EPB * NV * 3], smean[EPB * NV];
-  __shared__ int strb[EPB * NV], sany[EPB];
-  const int tid = threadIdx.x;
-  if (tid < EPB) sany[tid] = 0;
-  __syncthreads();
-  int lim_here = 0;
-  for (int t = tid; t < EPB * NV; t += C::THREADS) {
-    const int le = t / NV, v = t - le * NV;
-    const int64_t e = (int64_t)blockIdx.x * EPB + le;
-    if (e >= A.nelem) {
-      strb[t] = 0;
-      continue;
-    }
-    const double *me = A.mom + e * 10 * NV;
+// One thread per (element, component): troubled or not, and the limited
+// slopes, written over the element's moments (slots 1..3: a_x, a_y, a_z;
+// slot 4: 1 when troubled).  Reads only the element's own slots and the
+// neighbours' means (slot 0), which nothing here overwrites.
+template <int N, int NV>
+__global__ void __launch_bounds__(256) limiter_decide_kernel(const LimArgs A) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int troubled = 0;
+  if (t < A.nelem * NV) {
+    const int64_t e = t / NV;
+    const int v = (int)(t - e * NV);
+    double *me = A.mom + e * 10 * NV;
     const double u0 = me[v];
-    int troubled = A.bad[e] != 0;
+    troubled = A.bad[e] != 0;
+    double ad[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int32_t elo = A.nbr[e * 6 + 2 * d], ehi = A.nbr[e * 6 + 2 * d + 1];
@@ -165,28 +114,53 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_apply_kerne
       const double nhi = ehi >= 0 ? A.mom[(int64_t)ehi * 10 * NV + v] : A.bcs[(2 * d + 1) * 16 + v];
       const double dx = A.dx[d];
       const double a1 = me[(1 + d) * NV + v] * (2.0 / dx);
-      const double ad = minmodB(a1, (nhi - u0) * A.beta / dx, (u0 - nlo) * A.beta / dx, A.M, dx);
-      sa[t * 3 + d] = ad;
+      ad[d] = minmodB(a1, (nhi - u0) * A.beta / dx, (u0 - nlo) * A.beta / dx, A.M, dx);
       if (N >= 2) {
         const double fl = me[(4 + 2 * d) * NV + v], fr = me[(5 + 2 * d) * NV + v];
         const double vl = u0 - minmod3(u0 - fl, u0 - nlo, nhi - u0);
         const double vr = u0 + minmod3(fr - u0, u0 - nlo, nhi - u0);
         if (fabs(vl - fl) > 1e-8 || fabs(vr - fr) > 1e-8) troubled = 1;
-      } else if (ad != a1) {
+      } else if (ad[d] != a1) {
         troubled = 1;
       }
     }
-    smean[t] = u0;
-    strb[t] = troubled;
-    if (troubled) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) me[(1 + d) * NV + v] = ad[d];
+    me[4 * NV + v] = troubled ? 1.0 : 0.0;
+  }
+  // one counter update per wave
+  const unsigned long long bal = __ballot(troubled);
+  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(A.nlim, (unsigned long long)__popcll(bal));
+}
+
+template <int SYS, int N>
+__global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_apply_kernel(const LimArgs A) {
+  using C = LimCfg<SYS, N>;
+  constexpr int NP = C::NP, NPE = C::NPE, NV = C::NV, EPB = C::EPB;
+  __shared__ double sa[EPB * NV * 4];
+  __shared__ int strb[EPB * NV], sany[EPB];
+  const int tid = threadIdx.x;
+  if (tid < EPB) sany[tid] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * EPB;
+  for (int t = tid; t < EPB * NV; t += C::THREADS) {
+    const int le = t / NV, v = t - le * NV;
+    const int64_t e = e0 + le;
+    if (e >= A.nelem) continue;
+    const double *me = A.mom + e * 10 * NV;
+    const bool tr = me[4 * NV + v] != 0.0;
+    strb[t] = tr;
+    if (tr) {
+      sa[t * 4] = me[v];
+      sa[t * 4 + 1] = me[NV + v];
+      sa[t * 4 + 2] = me[2 * NV + v];
+      sa[t * 4 + 3] = me[3 * NV + v];
       sany[le] = 1;
-      ++lim_here;
     }
   }
-  if (lim_here) atomicAdd(A.nlim, (unsigned long long)lim_here);
   __syncthreads();
   const int le = tid / NPE, a = tid - le * NPE;
-  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  const int64_t e = e0 + le;
   if (le >= EPB || e >= A.nelem || !sany[le]) return;
   const int64_t nn = A.nnodes, q = e * NPE + a;
   const int i = a % NP, j = (a / NP) % NP, k = a / (NP * NP);
@@ -194,58 +168,59 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_apply_kerne
   double u[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const int t = le * NV + v;
-    if (strb[t]) {
-      u[v] = smean[t] + sa[t * 3] * xo + sa[t * 3 + 1] * yo + sa[t * 3 + 2] * zo;
+    const double *r = sa + (le * NV + v) * 4;
+    if (strb[le * NV + v]) {
+      u[v] = r[0] + r[1] * xo + r[2] * yo + r[3] * zo;
       A.U[v * nn + q] = u[v];
     } else {
       u[v] = A.U[v * nn + q];
     }
   }
   const C2PResult R = recover<SYS>(u, A.gamma, A.Pout[4 * nn + q], 0.0, 100);
-  store_prims<SYS>(A.Pout, nn, q, R.P);
+  store_prims(A.Pout, nn, q, R.P);
   if (!R.ok) atomicAdd(A.nfail, 1ull);
 }
 
 template <int SYS, int N>
-static hipError_t launch_lim_n(int phase, const LimArgs &a, hipStream_t s) {
+static hipError_t launch_lim_n(bool moments, const LimArgs &a, hipStream_t s) {
   using C = LimCfg<SYS, N>;
   const int64_t nb = (a.nelem + C::EPB - 1) / C::EPB;
-  if (nb > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+  const int64_t nd = (a.nelem * C::NV + 255) / 256;
+  if (nb > ((int64_t)1 << 30) || nd > ((int64_t)1 << 30)) return hipErrorInvalidValue;
   if (nb == 0) return hipSuccess;
-  if (phase == 0)
+  if (moments) {
     hipLaunchKernelGGL((limiter_moments_kernel<SYS, N>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, a);
-  else
-    hipLaunchKernelGGL((limiter_apply_kernel<SYS, N>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, a);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL((limiter_decide_kernel<(N >= 2 ? 2 : 1), C::NV>), dim3((unsigned)nd), dim3(256), 0, s, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((limiter_apply_kernel<SYS, N>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
 template <int SYS>
-static hipError_t launch_lim_sys(int N, int phase, const LimArgs &a, hipStream_t s) {
+static hipError_t launch_lim_sys(int N, bool moments, const LimArgs &a, hipStream_t s) {
   switch (N) {
-    case 1: return launch_lim_n<SYS, 1>(phase, a, s);
-    case 2: return launch_lim_n<SYS, 2>(phase, a, s);
-    case 3: return launch_lim_n<SYS, 3>(phase, a, s);
-    case 4: return launch_lim_n<SYS, 4>(phase, a, s);
-    case 5: return launch_lim_n<SYS, 5>(phase, a, s);
-    case 6: return launch_lim_n<SYS, 6>(phase, a, s);
-    case 7: return launch_lim_n<SYS, 7>(phase, a, s);
+    case 1: return launch_lim_n<SYS, 1>(moments, a, s);
+    case 2: return launch_lim_n<SYS, 2>(moments, a, s);
+    case 3: return launch_lim_n<SYS, 3>(moments, a, s);
+    case 4: return launch_lim_n<SYS, 4>(moments, a, s);
+    case 5: return launch_lim_n<SYS, 5>(moments, a, s);
+    case 6: return launch_lim_n<SYS, 6>(moments, a, s);
+    case 7: return launch_lim_n<SYS, 7>(moments, a, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_limiter(int sys, int N, const LimArgs &a, hipStream_t s) {
-  hipError_t err = hipErrorInvalidValue;
-  for (int phase = 0; phase < 2; ++phase) {
-    switch (sys) {
-      case kNE: err = launch_lim_sys<kNE>(N, phase, a, s); break;
-      case kSR: err = launch_lim_sys<kSR>(N, phase, a, s); break;
-      case kMHD: err = launch_lim_sys<kMHD>(N, phase, a, s); break;
-      default: return hipErrorInvalidValue;
-    }
-    if (err != hipSuccess) return err;
+hipError_t launch_limiter(int sys, int N, bool moments, const LimArgs &a, hipStream_t s) {
+  switch (sys) {
+    case kNE: return launch_lim_sys<kNE>(N, moments, a, s);
+    case kSR: return launch_lim_sys<kSR>(N, moments, a, s);
+    case kMHD: return launch_lim_sys<kMHD>(N, moments, a, s);
   }
-  return err;
+  return hipErrorInvalidValue;
 }
 
 }  // namespace dgmi

@@ -35,6 +35,7 @@
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "limiter.hpp"
 #include "physics.hpp"
 
 namespace dgmi {
@@ -117,7 +118,7 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
 
 // The work of one workgroup on element group grp, with BT threads and the
 // LDS block smem (the kernels below choose grp and provide both).
-template <int SYS, int N, int STAGE, int EPB_, bool MIXED, int BT, int FLUX = kLLF>
+template <int SYS, int N, int STAGE, int EPB_, bool MIXED, int BT, int FLUX = kLLF, bool MOM = false>
 __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem) {
   using C = RhsCfg<SYS, N, EPB_, FLUX>;
   constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
@@ -291,11 +292,12 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   }
   __syncthreads();
 
-  if (!active) return;
+  // (the limited stage, MOM, keeps every thread for the moment reduction)
+  if (!MOM && !active) return;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int idx = sel3i(d, ci, cj, ck);
-    if (idx == 0 || idx == N) {
+    if (active && (idx == 0 || idx == N)) {
       const int f = 2 * d + (idx == N ? 1 : 0);
       const int fn = sel3i(d, cj + NP * ck, ci + NP * ck, ci + NP * cj);
       const double sc = sel3(d, A.scale[0], A.scale[1], A.scale[2]) * A.inv_wend;
@@ -312,12 +314,44 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   // ---- Shu-Osher combination and tail recovery
   double us[NV];
   const double dt = A.dtp ? *A.dtp : A.dt;
+  if constexpr (MOM) {
+    // limited stage: recover every node of U^(s), then reduce each element to
+    // the limiter's moments (the slope limiter runs next, over the grid)
+    double *su = svol, *okf = sown, *tabs = sD;
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        us[v] = A.a * A.Un[v * nn + q] + A.b * (u[v] + dt * acc[v]);
+        A.out[v * nn + q] = us[v];
+        su[(le * NV + v) * NPE + a] = us[v];
+      }
+      const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100);
+      A.Pout[q] = R.P.rho;
+      A.Pout[nn + q] = R.P.v[0];
+      A.Pout[2 * nn + q] = R.P.v[1];
+      A.Pout[3 * nn + q] = R.P.v[2];
+      A.Pout[4 * nn + q] = R.P.p;
+      okf[le * NPE + a] = R.ok ? 1.0 : 0.0;
+    }
+    if (tid < NP) {
+      tabs[tid] = A.lim_h[tid];
+      tabs[NP + tid] = A.lim_mu[tid];
+    }
+    __syncthreads();
+    const int64_t e0 = (int64_t)grp * EPB;
+    if (tid < EPB && e0 + tid < A.nelem) {
+      int bad = 0;
+      for (int b = 0; b < NPE; ++b) bad |= okf[tid * NPE + b] == 0.0;
+      A.bad[e0 + tid] = bad;
+    }
+    element_moments<N, NV, EPB, BT>(su, sslot, tabs, tabs + NP, A.mom, e0, A.nelem);
+    return;
+  }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     us[v] = A.a * A.Un[v * nn + q] + A.b * (u[v] + dt * acc[v]);
     A.out[v * nn + q] = us[v];
   }
-  if (A.no_recover) return;
   const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100);
   // intermediate stages of NE / SR keep only the pressure (the next stage
   // rebuilds the rest); SRMHD and the caller's buffers get all five rows
@@ -333,7 +367,8 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
 
 // Uniform mesh (or one degree of a mixed mesh): one launch, EPB elements
 // per workgroup, one thread per volume node.
-template <int SYS, int N, int STAGE, int EPB_ = default_epb<SYS, N>(), bool MIXED = false, int FLUX = kLLF>
+template <int SYS, int N, int STAGE, int EPB_ = default_epb<SYS, N>(), bool MIXED = false, int FLUX = kLLF,
+          bool MOM = false>
 __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(const RhsArgs A) {
   using C = RhsCfg<SYS, N, EPB_, FLUX>;
   __shared__ double smem[C::LDS];
@@ -344,7 +379,20 @@ __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(co
   if (seq >= A.nblocks) return;
   int grp = seq;
   if constexpr (!MIXED) grp = brick_order<C::EPB>(seq, A.nx, A.ny, A.nz);
-  rhs_body<SYS, N, STAGE, EPB_, MIXED, C::THREADS, FLUX>(A, grp, smem);
+  rhs_body<SYS, N, STAGE, EPB_, MIXED, C::THREADS, FLUX, MOM>(A, grp, smem);
+}
+
+// The RK stage that also writes the limiter's moments.
+template <int SYS, int N, int FLUX>
+hipError_t launch_one_moments(const RhsArgs &a, hipStream_t s) {
+  using C = RhsCfg<SYS, N, default_epb<SYS, N>(), FLUX>;
+  RhsArgs b = a;
+  const int64_t nblocks = (a.nelem + C::EPB - 1) / C::EPB;
+  if (nblocks > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+  b.nblocks = (int)nblocks;
+  const int grid = ((b.nblocks + 7) / 8) * 8;
+  hipLaunchKernelGGL((rhs_kernel<SYS, N, 1, C::EPB, false, FLUX, true>), dim3(grid), dim3(C::THREADS), 0, s, b);
+  return hipGetLastError();
 }
 
 // One uniform-mesh launch of degree N with the given numerical flux.
