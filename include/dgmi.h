@@ -62,6 +62,11 @@ enum {
                                      replaying a captured graph */
 #define DGMI_FLAG_AUTOTUNE 8      /* mixed degrees: dgmi_create times every tile option per degree and
                                      keeps the fastest (results do not depend on the choice) */
+#define DGMI_FLAG_POLYTROPIC 32   /* Newtonian Euler with the polytropic equation of state p = rho^gamma
+                                     (K = 1; the adiabatic one of the isentropic vortex test) instead of
+                                     the ideal gas; uniform degrees only.  The energy is still evolved;
+                                     the standalone con2prim call stays ideal-gas.  Fixed boundary states
+                                     take p = rho^gamma. */
 #define DGMI_FLAG_HLL 16          /* numerical flux HLL (eq. HLL) instead of local Lax-Friedrichs
                                      (eq. LLF); uniform degrees only, a mixed-degree mesh with it
                                      returns DGMI_EUNSUPPORTED */
@@ -117,8 +122,8 @@ dgmi_status dgmi_prim2cons(int32_t system, double gamma, const double *prim, con
 /* Semi-discrete operator dUdt = L(U) of eq. 411:
  *   L = S - sum_d (2/dx_d) D^(d) F^d - sum_faces (2/dx_d)(1/w_end)(F*.n - F.n),
  * F*.n the LLF flux (HLL with DGMI_FLAG_HLL) with the unit outward normal;
- * across a box face with a fixed exterior state (dgmi_set_boundary) the
- * exterior is that state.  First recovers the
+ * across a box face with a fixed exterior state (dgmi_set_boundary) or an
+ * analytic one (dgmi_set_analytic_boundary) the exterior is that state.  First recovers the
  * primitives of every node (Newton polished to rounding level, seeded from
  * prim_inout's pressure unless DGMI_FLAG_PLAIN_GUESS), which are written
  * back to prim_inout.  Failed recoveries are counted (dgmi_failures).
@@ -138,7 +143,8 @@ dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, doub
  * DGMI_FLAG_RECOVER_FIRST); on exit it holds those of the new U.  Each stage
  * is one kernel that also recovers the primitives of its output.  With a
  * slope limiter set (dgmi_set_limiter), every stage result is limited
- * (as dg_limit does) before its primitives are final. */
+ * (as dg_limit does) before its primitives are final.  Advances the
+ * context's time by dt. */
 dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream);
 
 /* Box faces with a fixed exterior state (the analytic boundary condition of
@@ -153,6 +159,28 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
  * dg_step and dg_limit calls. */
 dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *state_lo_host,
                               const double *state_hi_host);
+
+/* Analytic solutions available as exterior states (uniform meshes). */
+enum {
+  DGMI_SOLUTION_ISENTROPIC_VORTEX = 1 /* eq. isen_vortex, Newtonian Euler; params: beta, X0, Y0, U, V, W
+                                         (gamma from the mesh, p = rho^gamma) */
+};
+
+/* Box faces of `direction` (0..2) take the analytic solution as their
+ * exterior state (the analytic boundary condition of the section on initial
+ * data, boundary conditions and time steppers): before every operator
+ * evaluation the solution is evaluated at each boundary face node at the
+ * operator's time (the context's time for dg_rhs / dg_operator; t, t + dt,
+ * t + dt/2 for the three stages of dg_step).  params_host: nparams (6)
+ * doubles, copied.  Newtonian Euler on uniform meshes only, and not with the
+ * slope limiter (DGMI_EUNSUPPORTED); synchronous. */
+dgmi_status dgmi_set_analytic_boundary(dgmi_ctx *ctx, int32_t direction, int32_t solution, const double *params_host,
+                                       int32_t nparams);
+
+/* Time of the state held by the caller (0 at creation; dg_step advances it
+ * by dt).  Only analytic boundary states depend on it. */
+dgmi_status dgmi_set_time(dgmi_ctx *ctx, double t);
+dgmi_status dgmi_get_time(const dgmi_ctx *ctx, double *t_host);
 
 /* Minmod-family slope limiter (high-resolution shock-capturing section,
  * eqs. MinModSol, MinModB and MinMod), uniform meshes only. */
@@ -170,7 +198,8 @@ enum {
  * (the linear part keeps the Legendre modes 1, x, y, z).  Elements holding a
  * node whose primitives cannot be recovered are limited in every
  * component.  Allocates 80 nv bytes per element of device scratch on first
- * use; DGMI_EUNSUPPORTED on mixed-degree meshes. */
+ * use; DGMI_EUNSUPPORTED on mixed-degree meshes and with analytic
+ * boundaries (the limiter's exterior means need fixed states). */
 dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M);
 
 /* Limit U in place with the selected limiter (DGMI_EINVAL if none).

@@ -46,22 +46,28 @@ class Mesh(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("bc", ctypes.c_int32 * 3), ("limiter", ctypes.c_int32), ("lim_M", ctypes.c_double),
-                ("bc_u", (ctypes.c_double * 9) * 6), ("bc_p", (ctypes.c_double * 5) * 6)]
+                ("bc_u", (ctypes.c_double * 9) * 6), ("bc_p", (ctypes.c_double * 5) * 6),
+                ("time", ctypes.c_double), ("vortex", ctypes.c_double * 6), ("eos", ctypes.c_int32)]
 
 
 LIMITERS = {"none": 0, "minmod": 1, "muscl": 2}
 
 
 def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), kappa=0.0, flux="llf",
-         bc=None, limiter="none", M=0.0):
+         bc=None, limiter="none", M=0.0, vortex=None, time=0.0, eos="ideal"):
     """Box of nelem=(nx,ny,nz) affine elements, periodic unless ``bc`` says
     otherwise.  degree is an int or a per-direction triple; a 0 entry
     collapses that direction.  flux: "llf" (eq. LLF) or "hll" (eq. HLL).
     bc: {d: (state_lo, state_hi)} gives direction d fixed exterior states on
     its two box faces, each state a primitive 5-vector (rho, v, p), or for
-    SRMHD a 9-vector (rho, v, p, B, Phi).  limiter: "none", "minmod" (beta 2)
-    or "muscl" (beta 1), with the minmodB constant M, applied after every
-    RK stage."""
+    SRMHD a 9-vector (rho, v, p, B, Phi); {d: "vortex"} makes the exterior
+    state the isentropic vortex (eq. isen_vortex, NE) with
+    vortex = (beta, X0, Y0, U, V, W) at the face node and the mesh time.
+    limiter: "none", "minmod" (beta 2) or "muscl" (beta 1), with the minmodB
+    constant M, applied after every RK stage.  time: the time of the state
+    rhs() is applied to, and of the first step of step() / evolve().
+    eos: "ideal" (p = (gamma-1) rho eps) or, for NE, "polytropic"
+    (p = rho^gamma)."""
     if isinstance(degree, int):
         degree = (degree, degree, degree)
     m = Mesh()
@@ -71,7 +77,15 @@ def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), k
     m.flux = {"llf": 0, "hll": 1}[flux]
     m.limiter = LIMITERS[limiter]
     m.lim_M = M
+    m.time = time
+    m.eos = {"ideal": 0, "polytropic": 1}[eos]
+    if vortex is not None:
+        m.vortex[:] = list(vortex)
     for d, states in (bc or {}).items():
+        if isinstance(states, str):
+            assert states == "vortex"
+            m.bc[d] = 2
+            continue
         m.bc[d] = 1
         for side, st in enumerate(states):
             st = np.asarray(st, dtype=np.float64)
@@ -131,6 +145,7 @@ def _load():
         "ora_minmodB": (ctypes.c_double, [ctypes.c_double] * 5),
         "ora_limit": (I64, [MP, D]),
         "ora_limiter_moments": (ctypes.c_int, [MP, D, D, U8]),
+        "ora_isentropic_vortex": (ctypes.c_int, [ctypes.c_double, D, I64, D, ctypes.c_double, D]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -303,6 +318,17 @@ def rhs_weak(m, U):
     dU = np.zeros_like(U)
     _load().ora_rhs_weak(ctypes.byref(m), _p(U), _p(dU))
     return dU
+
+
+def isentropic_vortex(gamma, params, xyz, t):
+    """Primitives of eq. isen_vortex (params = beta, X0, Y0, U, V, W) at the
+    points xyz[3][n] and time t."""
+    xyz = _c(xyz)
+    n = xyz.shape[1]
+    par = _c(params)
+    out = np.zeros((5, n))
+    _load().ora_isentropic_vortex(gamma, _p(par), n, _p(xyz), t, _p(out))
+    return out
 
 
 def minmodB(a1, a2, a3, M=0.0, dx=1.0):

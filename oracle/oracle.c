@@ -250,14 +250,16 @@ static int c2p_eval(int sys, double g, const cons_t *C, double p, double *f, pri
  * plain bisection until the bracket cannot shrink.  f is defined and
  * positive at p = 0 and non-positive at p_hi for every physical state;
  * anything else is reported as a failure (return 0).                       */
-static int c2p_point(int sys, double g, const cons_t *C, prim_t *P) {
+static int c2p_point(int sys, int eos, double g, const cons_t *C, prim_t *P) {
   if (sys == 0) {
     double rho = C->u[0];
     if (!(rho > 0.0)) return 0;
     double m2 = 0.0;
     for (int i = 0; i < 3; ++i) { P->v[i] = C->u[1 + i] / rho; m2 += C->u[1 + i] * C->u[1 + i]; }
     P->rho = rho;
-    P->p = (g - 1.0) * (C->u[4] - 0.5 * m2 / rho);
+    /* ideal gas p = (gamma-1) rho eps; polytropic p = rho^gamma (K = 1), the
+     * adiabatic equation of state of the isentropic vortex test */
+    P->p = eos == 1 ? pow(rho, g) : (g - 1.0) * (C->u[4] - 0.5 * m2 / rho);
     return P->p > 0.0;
   }
   double D = C->u[0], tau = C->u[4];
@@ -395,14 +397,20 @@ int ora_prim2cons(int sys, double g, int64_t n, const double *prim, const double
 
 /* fail[n] (nullable): 1 where no physical primitive state exists.  Returns
  * the number of failed points.                                             */
+static int64_t cons2prim_eos(int sys, int eos, double g, int64_t n, const double *U, double *prim, uint8_t *fail);
+
 int64_t ora_cons2prim(int sys, double g, int64_t n, const double *U, double *prim, uint8_t *fail) {
+  return cons2prim_eos(sys, 0, g, n, U, prim, fail);
+}
+
+static int64_t cons2prim_eos(int sys, int eos, double g, int64_t n, const double *U, double *prim, uint8_t *fail) {
   int nv = nvars_of(sys);
   int64_t nfail = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : nfail) if (n > 4096)
   for (int64_t q = 0; q < n; ++q) {
     cons_t C; prim_t P = {0};
     load_cons(nv, n, U, q, &C);
-    int ok = c2p_point(sys, g, &C, &P);
+    int ok = c2p_point(sys, eos, g, &C, &P);
     prim[q] = P.rho; prim[n + q] = P.v[0]; prim[2 * n + q] = P.v[1];
     prim[3 * n + q] = P.v[2]; prim[4 * n + q] = P.p;
     if (fail) fail[q] = ok ? 0 : 1;
@@ -612,12 +620,16 @@ typedef struct {
   double lo[3], hi[3];
   /* per direction: 0 periodic; 1 both box faces take a fixed exterior state
    * (the analytic boundary condition for a solution that is constant
-   * outside the box), supplied below */
+   * outside the box), supplied below; 2 the exterior state is the isentropic
+   * vortex (eq. isen_vortex) at the face node and the current time (NE) */
   int32_t bc[3];
   int32_t limiter; /* 0 none; 1 minmod (beta = 2); 2 MUSCL (beta = 1); applied after every RK stage */
   double lim_M;    /* constant M of the minmodB function (eq. MinModB) */
   double bc_u[6][9]; /* exterior conserved state of box face 2d + side */
   double bc_p[6][5]; /* its primitives (rho, v, p) */
+  double time;       /* time of the state the operator is applied to */
+  double vortex[6];  /* beta, X0, Y0, U, V, W of eq. isen_vortex */
+  int32_t eos;       /* NE: 0 ideal gas, 1 polytropic p = rho^gamma */
 } ora_mesh;
 
 typedef struct {
@@ -629,8 +641,11 @@ typedef struct {
 
 static int make_geom(const ora_mesh *m, geom_t *G) {
   if (m->nx < 1 || m->ny < 1 || m->nz < 1) return ORA_EINVAL;
-  for (int d = 0; d < 3; ++d)
-    if (m->bc[d] != 0 && m->bc[d] != 1) return ORA_EINVAL;
+  if (m->eos < 0 || m->eos > 1 || (m->eos == 1 && m->sys != 0)) return ORA_EINVAL;
+  for (int d = 0; d < 3; ++d) {
+    if (m->bc[d] < 0 || m->bc[d] > 2) return ORA_EINVAL;
+    if (m->bc[d] == 2 && m->sys != 0) return ORA_EINVAL;
+  }
   if (m->limiter < 0 || m->limiter > 2 || !(m->lim_M >= 0.0)) return ORA_EINVAL;
   int ne[3] = {m->nx, m->ny, m->nz};
   for (int d = 0; d < 3; ++d) {
@@ -689,13 +704,53 @@ static int64_t neighbour(const ora_mesh *m, int64_t e, int d, int side) {
   return c[0] + ne[0] * (c[1] + ne[1] * c[2]);
 }
 
+/* Isentropic vortex of eq. isen_vortex at the point x and time t: with
+ * xt = x - X0 - U t, yt = y - Y0 - V t, r^2 = xt^2 + yt^2,
+ *   rho = (1 - (gamma-1) beta^2 / (8 gamma pi^2) e^(1 - r^2))^(1/(gamma-1)),
+ *   v = (U - yt beta/(2 pi) e^((1-r^2)/2), V + xt beta/(2 pi) e^((1-r^2)/2), W),
+ * and the isentropic pressure p = rho^gamma.                               */
+static void isentropic_vortex(double g, const double *par, const double *x, double t, prim_t *P) {
+  const double pi = 3.14159265358979323846;
+  double beta = par[0], xt = x[0] - par[1] - par[3] * t, yt = x[1] - par[2] - par[4] * t;
+  double r2 = xt * xt + yt * yt;
+  P->rho = pow(1.0 - (g - 1.0) * beta * beta / (8.0 * g * pi * pi) * exp(1.0 - r2), 1.0 / (g - 1.0));
+  double s = beta / (2.0 * pi) * exp(0.5 * (1.0 - r2));
+  P->v[0] = par[3] - yt * s;
+  P->v[1] = par[4] + xt * s;
+  P->v[2] = par[5];
+  P->p = pow(P->rho, g);
+}
+
+int ora_isentropic_vortex(double g, const double *par, int64_t n, const double *xyz, double t, double *prim) {
+  for (int64_t q = 0; q < n; ++q) {
+    double x[3] = {xyz[q], xyz[n + q], xyz[2 * n + q]};
+    prim_t P;
+    isentropic_vortex(g, par, x, t, &P);
+    prim[q] = P.rho; prim[n + q] = P.v[0]; prim[2 * n + q] = P.v[1]; prim[3 * n + q] = P.v[2]; prim[4 * n + q] = P.p;
+  }
+  return ORA_OK;
+}
+
+/* Physical coordinates of node (i, j, k) of element e. */
+static void node_xyz(const ora_mesh *m, const geom_t *G, int64_t e, int i, int j, int k, double *x) {
+  int64_t c[3] = {e % m->nx, (e / m->nx) % m->ny, e / ((int64_t)m->nx * m->ny)};
+  int ijk[3] = {i, j, k};
+  for (int d = 0; d < 3; ++d) x[d] = m->lo[d] + c[d] * G->dx[d] + 0.5 * (1.0 + G->x[d][ijk[d]]) * G->dx[d];
+}
+
 /* Exterior state of face (d, side) of element e at the neighbour's node b:
- * the neighbour's node, or the box face's fixed state.                     */
+ * the neighbour's node, the box face's fixed state, or the analytic
+ * solution at the face node x and the mesh's time.                         */
 static void exterior(const ora_mesh *m, int nv, int64_t N, int64_t npe, const double *U, const double *prim,
-                     int64_t en, int64_t b, int d, int side, cons_t *Ce, prim_t *Pe) {
+                     int64_t en, int64_t b, int d, int side, const double *x, cons_t *Ce, prim_t *Pe) {
   if (en >= 0) {
     load_cons(nv, N, U, en * npe + b, Ce);
     load_prim(N, prim, en * npe + b, Pe);
+    return;
+  }
+  if (m->bc[d] == 2) {
+    isentropic_vortex(m->gamma, m->vortex, x, m->time, Pe);
+    ne_p2c(m->gamma, Pe, Ce);
     return;
   }
   const double *u = m->bc_u[2 * d + side], *p = m->bc_p[2 * d + side];
@@ -773,7 +828,9 @@ static int rhs_strong(const ora_mesh *m, const geom_t *G, const double *U, const
               cons_t Ci, Ce; prim_t Pi, Pe;
               load_cons(nv, N, U, e * npe + a, &Ci);
               load_prim(N, prim, e * npe + a, &Pi);
-              exterior(m, nv, N, npe, U, prim, en, b, d, side, &Ce, &Pe);
+              double xf[3];
+              node_xyz(m, G, e, i, j, k, xf);
+              exterior(m, nv, N, npe, U, prim, en, b, d, side, xf, &Ce, &Pe);
               double Fs[9], Fi[9];
               numflux(m->flux, sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
               double wend = G->w[d][side ? Nd : 0];
@@ -845,7 +902,9 @@ static int rhs_weak(const ora_mesh *m, const geom_t *G, const double *U, const d
               cons_t Ci, Ce; prim_t Pi, Pe;
               load_cons(nv, N, U, e * npe + a, &Ci);
               load_prim(N, prim, e * npe + a, &Pi);
-              exterior(m, nv, N, npe, U, prim, en, b, d, side, &Ce, &Pe);
+              double xf[3];
+              node_xyz(m, G, e, i, j, k, xf);
+              exterior(m, nv, N, npe, U, prim, en, b, d, side, xf, &Ce, &Pe);
               double Fs[9], Fi[9];
               numflux(m->flux, sys, g, d, side ? 1.0 : -1.0, &Ci, &Pi, &Ce, &Pe, Fs, Fi);
               double sc = 2.0 / G->dx[d];
@@ -866,7 +925,7 @@ int64_t ora_rhs(const ora_mesh *m, const double *U, double *prim_out, double *dU
   geom_t G;
   if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
   double *prim = prim_out ? prim_out : (double *)malloc(sizeof(double) * 5 * G.nnodes);
-  int64_t nf = ora_cons2prim(m->sys, m->gamma, G.nnodes, U, prim, NULL);
+  int64_t nf = cons2prim_eos(m->sys, m->eos, m->gamma, G.nnodes, U, prim, NULL);
   int rc = rhs_strong(m, &G, U, prim, G.nelem, NULL, dUdt);
   if (!prim_out) free(prim);
   return rc == ORA_OK ? nf : rc;
@@ -887,7 +946,7 @@ int64_t ora_rhs_weak(const ora_mesh *m, const double *U, double *dUdt) {
   geom_t G;
   if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
   double *prim = (double *)malloc(sizeof(double) * 5 * G.nnodes);
-  int64_t nf = ora_cons2prim(m->sys, m->gamma, G.nnodes, U, prim, NULL);
+  int64_t nf = cons2prim_eos(m->sys, m->eos, m->gamma, G.nnodes, U, prim, NULL);
   rhs_weak(m, &G, U, prim, dUdt);
   free(prim);
   return nf;
@@ -964,7 +1023,7 @@ static void element_moments(const ora_mesh *m, const geom_t *G, const double *U,
         double h[3] = {G->w[0][i] / 2.0, G->w[1][j] / 2.0, G->w[2][k] / 2.0};
         cons_t C; prim_t P;
         load_cons(nv, N, U, q, &C);
-        if (!c2p_point(m->sys, m->gamma, &C, &P)) M->bad = 1;
+        if (!c2p_point(m->sys, m->eos, m->gamma, &C, &P)) M->bad = 1;
         for (int v = 0; v < nv; ++v) {
           double u = U[(int64_t)v * N + q];
           M->mean[v] += h[0] * h[1] * h[2] * u;
@@ -1011,6 +1070,7 @@ int64_t ora_limit(const ora_mesh *m, double *U) {
   geom_t G;
   if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
   if (m->limiter == 0) return 0;
+  if (m->bc[0] == 2 || m->bc[1] == 2 || m->bc[2] == 2) return ORA_EINVAL; /* ghost means need fixed states */
   int nv = nvars_of(m->sys);
   double beta = m->limiter == 1 ? 2.0 : 1.0;
   double mu[3][33];
@@ -1120,14 +1180,18 @@ int64_t ora_step(const ora_mesh *m, double *U, double dt) {
   double *U2 = (double *)malloc(sizeof(double) * n);
   int64_t nf = 0;
   /* with a limiter, every stage result is limited before its primitives
-   * are recovered for the next stage */
-  nf += ora_rhs(m, U, NULL, L);
+   * are recovered for the next stage; the stages act at the times t, t + dt
+   * and t + dt/2 of their inputs (time-dependent boundary states) */
+  ora_mesh ms = *m;
+  nf += ora_rhs(&ms, U, NULL, L);
   ora_rk3_combine(1, dt, n, U, U, L, U1);
   ora_limit(m, U1);
-  nf += ora_rhs(m, U1, NULL, L);
+  ms.time = m->time + dt;
+  nf += ora_rhs(&ms, U1, NULL, L);
   ora_rk3_combine(2, dt, n, U, U1, L, U2);
   ora_limit(m, U2);
-  nf += ora_rhs(m, U2, NULL, L);
+  ms.time = m->time + 0.5 * dt;
+  nf += ora_rhs(&ms, U2, NULL, L);
   ora_rk3_combine(3, dt, n, U, U2, L, U);
   ora_limit(m, U);
   free(L); free(U1); free(U2);
@@ -1136,8 +1200,10 @@ int64_t ora_step(const ora_mesh *m, double *U, double dt) {
 
 int64_t ora_evolve(const ora_mesh *m, double *U, double dt, int64_t nsteps) {
   int64_t nf = 0;
+  ora_mesh ms = *m;
   for (int64_t s = 0; s < nsteps; ++s) {
-    int64_t r = ora_step(m, U, dt);
+    ms.time = m->time + s * dt;
+    int64_t r = ora_step(&ms, U, dt);
     if (r < 0) return r;
     nf += r;
   }
@@ -1281,7 +1347,7 @@ static int face_node(int N, int d, int side, int a, int b) {
 /* Mixed-degree strong-form operator.  The mesh's deg[] field is ignored;
  * deg[e] gives each element's degree.  Returns failed recoveries or <0. */
 int64_t ora_rhs_mixed(const ora_mesh *m, const int32_t *deg, const double *U, double *prim_out, double *dUdt) {
-  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter) return ORA_EINVAL; /* periodic, unlimited only */
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos) return ORA_EINVAL; /* periodic, unlimited, ideal gas */
   int sys = m->sys, nv = nvars_of(sys);
   double g = m->gamma;
   int64_t ne = (int64_t)m->nx * m->ny * m->nz;
@@ -1463,7 +1529,7 @@ int ora_mixed_integrate(const ora_mesh *m, const int32_t *deg, int ncomp, const 
 
 /* SSP-RK3 step on a mixed-degree mesh. */
 int64_t ora_step_mixed(const ora_mesh *m, const int32_t *deg, double *U, double dt) {
-  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter) return ORA_EINVAL;
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos) return ORA_EINVAL;
   int64_t ne = (int64_t)m->nx * m->ny * m->nz;
   int nv = nvars_of(m->sys);
   int64_t n = (int64_t)nv * ora_mixed_num_nodes((int)ne, deg);

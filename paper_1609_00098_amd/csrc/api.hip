@@ -160,8 +160,12 @@ struct dgmi_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   const void *gU = nullptr, *gP = nullptr;
-  // box faces with fixed exterior states (uniform meshes)
-  int bc[3] = {0, 0, 0};          // per direction: 0 periodic, 1 fixed states
+  // box faces with fixed or analytic exterior states (uniform meshes)
+  int bc[3] = {0, 0, 0};          // per direction: 0 periodic, 1 fixed states, 2 analytic
+  double time = 0.0;              // time of the state (analytic boundaries)
+  double vortex[6] = {0};         // isentropic vortex parameters
+  double *d_bface = nullptr;      // analytic exterior states per boundary face node
+  int64_t boff[7] = {0};
   double hbc[6 * 16] = {0};       // per box face: conserved [0, nv), primitives [9, 14)
   double *d_bc = nullptr;         // device copy
   // slope limiter (uniform meshes)
@@ -535,6 +539,7 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_facebuf);
   (void)hipFree(c->d_dt);
   (void)hipFree(c->d_bc);
+  (void)hipFree(c->d_bface);
   (void)hipFree(c->d_limtab);
   (void)hipFree(c->d_mom);
   (void)hipFree(c->d_bad);
@@ -565,6 +570,9 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
     return fail(DGMI_EINVAL, "dgmi_create: degree 0 needs degrees_host");
   if (desc->degree == 0 && (desc->flags & DGMI_FLAG_HLL))
     return fail(DGMI_EUNSUPPORTED, "dgmi_create: the HLL flux is implemented for uniform degrees only");
+  if ((desc->flags & DGMI_FLAG_POLYTROPIC) && (desc->system != 0 || desc->degree == 0))
+    return fail(DGMI_EUNSUPPORTED, "dgmi_create: the polytropic equation of state is for Newtonian Euler on uniform "
+                                   "degrees");
   dgmi_ctx *c = new (std::nothrow) dgmi_ctx();
   if (!c) return fail(DGMI_ENOMEM, "dgmi_create: out of host memory");
   (void)hipGetDevice(&c->device);
@@ -684,6 +692,10 @@ static dgmi::RhsArgs rhs_args(dgmi_ctx *c) {
   dgmi::RhsArgs a{};
   a.nbr = c->d_nbr;
   a.bcs = c->d_bc;
+  for (int d = 0; d < 3; ++d) a.bckind[d] = c->bc[d];
+  a.bface = c->d_bface;
+  for (int f = 0; f < 7; ++f) a.boff[f] = c->boff[f];
+  a.poly = (c->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0;
   a.Dmat = c->d_D + 64 * c->degree;
   a.nfail = c->d_nfail;
   a.nelem = c->nelem;
@@ -696,6 +708,29 @@ static dgmi::RhsArgs rhs_args(dgmi_ctx *c) {
   a.ny = c->ny;
   a.nz = c->nz;
   return a;
+}
+
+// Analytic exterior states at time t for every box face of an analytic direction.
+static dgmi_status boundary_pass(dgmi_ctx *c, double t, hipStream_t s) {
+  if (c->bc[0] != 2 && c->bc[1] != 2 && c->bc[2] != 2) return DGMI_OK;
+  dgmi::BoundaryArgs b{};
+  b.bface = c->d_bface;
+  for (int f = 0; f < 7; ++f) b.boff[f] = c->boff[f];
+  for (int d = 0; d < 3; ++d) {
+    b.kind[d] = c->bc[d];
+    b.lo[d] = c->lo[d];
+    b.dx[d] = c->dx[d];
+  }
+  b.N = c->degree;
+  b.nx = c->nx;
+  b.ny = c->ny;
+  b.nz = c->nz;
+  b.xi = c->d_x + 8 * c->degree;
+  b.gamma = c->gamma;
+  b.time = t;
+  for (int k = 0; k < 6; ++k) b.par[k] = c->vortex[k];
+  HIP_TRY(dgmi::launch_boundary_states(b, s));
+  return DGMI_OK;
 }
 
 static dgmi::LimArgs lim_args(dgmi_ctx *c, double *U, const double *Pseed, double *Pout) {
@@ -718,6 +753,7 @@ static dgmi::LimArgs lim_args(dgmi_ctx *c, double *U, const double *Pseed, doubl
   for (int d = 0; d < 3; ++d) a.dx[d] = c->dx[d];
   a.nlim = c->d_nlim;
   a.nfail = c->d_nfail;
+  a.poly = (c->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0;
   return a;
 }
 
@@ -729,6 +765,7 @@ static dgmi_status recover_all(dgmi_ctx *c, const double *U, double *prim, int g
   a.gamma = c->gamma;
   a.tol = 0.0;
   a.nfail = c->d_nfail;
+  a.poly = (c->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0;
   HIP_TRY(dgmi::launch_con2prim(c->sys, guess, a, s));
   return DGMI_OK;
 }
@@ -743,6 +780,7 @@ dgmi_status dg_rhs(dgmi_ctx *ctx, const double *U, double *prim_inout, double *d
   dgmi_status st = recover_all(ctx, U, prim_inout, guess, s);
   if (st != DGMI_OK) return st;
   if (ctx->mixed) return mixed_pass(ctx, 0, U, prim_inout, dUdt, nullptr, nullptr, 0.0, 0.0, 0, s);
+  if ((st = boundary_pass(ctx, ctx->time, s)) != DGMI_OK) return st;
   dgmi::RhsArgs a = rhs_args(ctx);
   a.U = U;
   a.P = prim_inout;
@@ -757,6 +795,8 @@ dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, doub
     return fail(DGMI_EINVAL, "dg_operator: U, prim and dUdt must be device pointers");
   if (dUdt == U || dUdt == prim) return fail(DGMI_EINVAL, "dg_operator: dUdt must not alias its inputs");
   if (ctx->mixed) return mixed_pass(ctx, 0, U, prim, dUdt, nullptr, nullptr, 0.0, 0.0, 0, (hipStream_t)stream);
+  dgmi_status st = boundary_pass(ctx, ctx->time, (hipStream_t)stream);
+  if (st != DGMI_OK) return st;
   dgmi::RhsArgs a = rhs_args(ctx);
   a.U = U;
   a.P = prim;
@@ -783,7 +823,11 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
       HIP_TRY(dgmi::launch_set_scalar(ctx->d_dt, dt, s));
       ctx->last_dt = dt;
     }
-    if ((ctx->flags & DGMI_FLAG_NO_GRAPH) || s == nullptr) return mixed_step_enqueue(ctx, U, prim_inout, s);
+    if ((ctx->flags & DGMI_FLAG_NO_GRAPH) || s == nullptr) {
+      const dgmi_status st = mixed_step_enqueue(ctx, U, prim_inout, s);
+      if (st == DGMI_OK) ctx->time += dt;
+      return st;
+    }
     if (!ctx->gexec || ctx->gU != U || ctx->gP != prim_inout) {
       if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
       if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -803,6 +847,7 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
       ctx->gP = prim_inout;
     }
     HIP_TRY(hipGraphLaunch(ctx->gexec, s));
+    ctx->time += dt;
     return DGMI_OK;
   }
   dgmi::RhsArgs a = rhs_args(ctx);
@@ -812,9 +857,11 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
   // and writes the element moments; the limiter's decide and apply kernels
   // follow (the apply kernel re-recovers the nodes it changes)
   const bool limit = ctx->lim_kind != DGMI_LIMITER_NONE;
-  auto stage = [&](double *out, double *Pout) -> dgmi_status {
+  auto stage = [&](double *out, double *Pout, double t) -> dgmi_status {
     a.out = out;
     a.Pout = Pout;
+    dgmi_status bs = boundary_pass(ctx, t, s);
+    if (bs != DGMI_OK) return bs;
     if (!limit) {
       HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 1, flux_of(ctx), a, s));
       return DGMI_OK;
@@ -828,16 +875,20 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
     return DGMI_OK;
   };
   dgmi_status st;
+  // the stages apply the operator at the times of their inputs: t, t + dt, t + dt/2
+  const double t0 = ctx->time;
   // stage 1: U1 = U + dt L(U)
   a.U = U; a.P = prim_inout; a.a = 0.0; a.b = 1.0;
-  if ((st = stage(ctx->d_U1, ctx->d_P1)) != DGMI_OK) return st;
+  if ((st = stage(ctx->d_U1, ctx->d_P1, t0)) != DGMI_OK) return st;
   // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
   a.U = ctx->d_U1; a.P = ctx->d_P1; a.a = 0.75; a.b = 0.25;
-  if ((st = stage(ctx->d_U2, ctx->d_P2)) != DGMI_OK) return st;
+  if ((st = stage(ctx->d_U2, ctx->d_P2, t0 + dt)) != DGMI_OK) return st;
   // stage 3: U <- 1/3 U + 2/3 (U2 + dt L(U2))  (each thread reads U^n at its own node before writing it)
   a.U = ctx->d_U2; a.P = ctx->d_P2; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
   a.full_prims = 1;
-  return stage(U, prim_inout);
+  if ((st = stage(U, prim_inout, t0 + 0.5 * dt)) != DGMI_OK) return st;
+  ctx->time = t0 + dt;
+  return DGMI_OK;
 }
 
 dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *state_lo_host,
@@ -861,6 +912,7 @@ dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *st
         return fail(DGMI_EINVAL, "dgmi_set_boundary: state is not physical (rho, p > 0, |v| < 1)");
       dgmi::Prim P;
       P.rho = st[0]; P.v[0] = st[1]; P.v[1] = st[2]; P.v[2] = st[3]; P.p = st[4];
+      if (ctx->flags & DGMI_FLAG_POLYTROPIC) P.p = std::pow(P.rho, ctx->gamma);  // the state's own pressure
       double *row = hbc + (2 * direction + side) * 16;
       for (int k = 0; k < 16; ++k) row[k] = 0.0;
       switch (ctx->sys) {
@@ -868,7 +920,7 @@ dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *st
         case 1: dgmi::prim_to_cons<dgmi::kSR>(P, nullptr, ctx->gamma, row); break;
         default: dgmi::prim_to_cons<dgmi::kMHD>(P, st + 5, ctx->gamma, row); break;
       }
-      for (int k = 0; k < 5; ++k) row[9 + k] = st[k];
+      row[9] = P.rho; row[10] = P.v[0]; row[11] = P.v[1]; row[12] = P.v[2]; row[13] = P.p;
     }
     bc = 1;
   }
@@ -884,12 +936,69 @@ dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *st
   return DGMI_OK;
 }
 
+dgmi_status dgmi_set_analytic_boundary(dgmi_ctx *ctx, int32_t direction, int32_t solution, const double *params_host,
+                                       int32_t nparams) {
+  if (!ctx) return fail(DGMI_EINVAL, "dgmi_set_analytic_boundary: null context");
+  if (ctx->mixed) return fail(DGMI_EUNSUPPORTED, "dgmi_set_analytic_boundary: mixed-degree meshes are periodic only");
+  if (direction < 0 || direction > 2) return fail(DGMI_EINVAL, "dgmi_set_analytic_boundary: direction must be 0, 1 or 2");
+  if (solution != DGMI_SOLUTION_ISENTROPIC_VORTEX)
+    return fail(DGMI_EINVAL, "dgmi_set_analytic_boundary: unknown solution %d", solution);
+  if (ctx->sys != 0)
+    return fail(DGMI_EUNSUPPORTED, "dgmi_set_analytic_boundary: the isentropic vortex is a Newtonian Euler solution");
+  if (ctx->lim_kind != DGMI_LIMITER_NONE)
+    return fail(DGMI_EUNSUPPORTED, "dgmi_set_analytic_boundary: not combined with the slope limiter");
+  if (!params_host || nparams != 6) return fail(DGMI_EINVAL, "dgmi_set_analytic_boundary: 6 parameters expected");
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(params_host[k])) return fail(DGMI_EINVAL, "dgmi_set_analytic_boundary: non-finite parameter");
+  if (!ctx->d_bface) {
+    const int64_t ne[3] = {ctx->nx, ctx->ny, ctx->nz};
+    const int64_t nf = (int64_t)(ctx->degree + 1) * (ctx->degree + 1);
+    int64_t boff[7];
+    boff[0] = 0;
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1, da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+      boff[f + 1] = boff[f] + ne[da] * ne[db] * nf;
+    }
+    if (hipMalloc(&ctx->d_bface, sizeof(double) * 16 * boff[6]) != hipSuccess ||
+        hipMemset(ctx->d_bface, 0, sizeof(double) * 16 * boff[6]) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(ctx->d_bface);
+      ctx->d_bface = nullptr;
+      return fail(DGMI_ENOMEM, "dgmi_set_analytic_boundary: device allocation failed");
+    }
+    std::memcpy(ctx->boff, boff, sizeof(boff));
+  }
+  for (int k = 0; k < 6; ++k) ctx->vortex[k] = params_host[k];
+  const int old = ctx->bc[direction];
+  ctx->bc[direction] = 2;
+  const std::vector<int32_t> nbr = neighbour_table(ctx);
+  if (hipMemcpy(ctx->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    ctx->bc[direction] = old;
+    return fail(DGMI_EHIP, "dgmi_set_analytic_boundary: table upload failed");
+  }
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_set_time(dgmi_ctx *ctx, double t) {
+  if (!ctx || !std::isfinite(t)) return fail(DGMI_EINVAL, "dgmi_set_time: bad argument");
+  ctx->time = t;
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_get_time(const dgmi_ctx *ctx, double *t_host) {
+  if (!ctx || !t_host) return fail(DGMI_EINVAL, "dgmi_get_time: null argument");
+  *t_host = ctx->time;
+  return DGMI_OK;
+}
+
 dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M) {
   if (!ctx) return fail(DGMI_EINVAL, "dgmi_set_limiter: null context");
   if (kind < DGMI_LIMITER_NONE || kind > DGMI_LIMITER_MUSCL) return fail(DGMI_EINVAL, "dgmi_set_limiter: unknown kind");
   if (!(M >= 0.0) || !std::isfinite(M)) return fail(DGMI_EINVAL, "dgmi_set_limiter: M must be finite and >= 0");
   if (ctx->mixed && kind != DGMI_LIMITER_NONE)
     return fail(DGMI_EUNSUPPORTED, "dgmi_set_limiter: the limiter is implemented for uniform degrees only");
+  if (kind != DGMI_LIMITER_NONE && (ctx->bc[0] == 2 || ctx->bc[1] == 2 || ctx->bc[2] == 2))
+    return fail(DGMI_EUNSUPPORTED, "dgmi_set_limiter: not combined with analytic boundaries");
   if (kind != DGMI_LIMITER_NONE && !ctx->d_mom) {
     if (hipMalloc(&ctx->d_mom, sizeof(double) * 10 * ctx->nv * ctx->nelem) != hipSuccess ||
         hipMalloc(&ctx->d_bad, sizeof(int32_t) * ctx->nelem) != hipSuccess) {

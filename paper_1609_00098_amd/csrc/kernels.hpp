@@ -33,14 +33,20 @@ struct RhsArgs {
   const double *facebuf;
   int nblocks;         // logical blocks (set at launch)
   // uniform meshes: a face whose neighbour index is negative lies on a box
-  // face with a fixed exterior state, bcs[f][0..nv) conserved and
-  // bcs[f][9..14) primitives (16 doubles per box face f)
+  // face; its exterior state is, by direction (bckind), a fixed state
+  // bcs[f][0..nv) conserved and bcs[f][9..14) primitives (16 doubles per box
+  // face f), or (bckind 2) the analytic state of its node in bface, node
+  // (boff[f] + element-on-face * (N+1)^2 + face node) * 16
   const double *bcs;
+  int bckind[3];
+  const double *bface;
+  int64_t boff[7];
   // limited stage kernel: element moments [nelem][10][nv] and unphysical flags
   // of U^(s) for the slope limiter; lim_h, lim_mu: w/2 and 3/2 int(ell xi)
   double *mom;
   int32_t *bad;
   const double *lim_h, *lim_mu;
+  int poly;            // NE: polytropic equation of state p = rho^gamma
 };
 
 // Numerical fluxes of the uniform-mesh element kernels.
@@ -71,6 +77,7 @@ struct LimArgs {
   double gamma, beta, M;
   double dx[3];
   unsigned long long *nlim, *nfail;
+  int poly;                   // NE: polytropic equation of state p = rho^gamma
 };
 // moments = false: the moments (and the primitives of every node) are
 // already in place, written by the limited RK stage kernel.
@@ -78,6 +85,20 @@ hipError_t launch_limiter(int sys, int N, bool moments, const LimArgs &a, hipStr
 // RK stage (uniform mesh) that also writes the limiter's element moments and
 // unphysical-node flags of its result (RhsArgs::mom, bad, lim_h, lim_mu).
 hipError_t launch_rhs_stage_moments(int sys, int N, int flux, const RhsArgs &a, hipStream_t s);
+
+// Analytic exterior states of the box faces (uniform meshes): one thread per
+// boundary face node of the directions with kind 2.
+struct BoundaryArgs {
+  double *bface;
+  int64_t boff[7];      // node offsets of the six box faces (boff[6]: total)
+  int kind[3];          // per direction: 2 analytic (others are skipped)
+  int N, nx, ny, nz;
+  double lo[3], dx[3];
+  const double *xi;     // GLL nodes of degree N
+  double gamma, time;
+  double par[6];        // isentropic vortex: beta, X0, Y0, U, V, W
+};
+hipError_t launch_boundary_states(const BoundaryArgs &b, hipStream_t s);
 
 // Highest degree of the mixed-degree path (mortars of up to 8x8 nodes).
 constexpr int kMaxMixedDegree = 7;
@@ -133,6 +154,7 @@ struct C2PArgs {
   uint8_t *fail;
   unsigned long long *nfail;
   const float *mlp;    // learned-guess parameters (device), or null
+  int poly;            // NE: polytropic equation of state p = rho^gamma
 };
 
 // Records msg as the thread's last error (dgmi_last_error) and returns st.

@@ -83,7 +83,7 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_moments_ker
       u[v] = A.U[v * nn + q];
       su[(le * NV + v) * NPE + a] = u[v];
     }
-    const C2PResult R = recover<SYS>(u, A.gamma, A.Pseed[4 * nn + q], 0.0, 100);
+    const C2PResult R = recover<SYS>(u, A.gamma, A.Pseed[4 * nn + q], 0.0, 100, A.poly);
     store_prims(A.Pout, nn, q, R.P);
     if (!R.ok) sbad[le] = 1;
   }
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_apply_kerne
       u[v] = A.U[v * nn + q];
     }
   }
-  const C2PResult R = recover<SYS>(u, A.gamma, A.Pout[4 * nn + q], 0.0, 100);
+  const C2PResult R = recover<SYS>(u, A.gamma, A.Pout[4 * nn + q], 0.0, 100, A.poly);
   store_prims(A.Pout, nn, q, R.P);
   if (!R.ok) atomicAdd(A.nfail, 1ull);
 }

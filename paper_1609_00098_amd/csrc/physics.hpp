@@ -307,8 +307,10 @@ DG_HD double step_rcp(double x) {
 // sqrt((z - |S|)(z + |S|)) / z.  (MHD needs the root of its cubic and is not
 // handled here.)  The recovery returns exactly these values for its final
 // pressure, so a kernel that stores only p can rebuild the rest.
+// NE with poly: the polytropic equation of state p = rho^gamma (K = 1)
+// instead of the ideal gas.
 template <int SYS>
-DG_HD Prim prims_at_pressure(const double *u, double g, double p) {
+DG_HD Prim prims_at_pressure(const double *u, double g, double p, bool poly = false) {
   Prim P;
   if (SYS == kNE) {
     const double irho = fast_rcp(u[0]);
@@ -317,7 +319,7 @@ DG_HD Prim prims_at_pressure(const double *u, double g, double p) {
     P.v[1] = u[2] * irho;
     P.v[2] = u[3] * irho;
     const double m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
-    P.p = (g - 1.0) * (u[4] - 0.5 * m2 * irho);
+    P.p = poly ? pow(u[0], g) : (g - 1.0) * (u[4] - 0.5 * m2 * irho);
     return P;
   }
   const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
@@ -389,14 +391,14 @@ DG_HD bool pressure_function(const double *u, double g, double p, double *f) {
 // |f| W^2 / ((g-1) E) <= tol at the evaluated pressure; tol <= 0: iterate
 // Newton until the step is below 1e-14 p (rounding level).
 template <int SYS>
-DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int maxit) {
+DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int maxit, bool poly = false) {
   C2PResult R;
   R.iters = 0;
   R.ok = 0;
   const double D = u[0];
   const double tau = u[4];
   if (SYS == kNE) {
-    R.P = prims_at_pressure<kNE>(u, g, 0.0);
+    R.P = prims_at_pressure<kNE>(u, g, 0.0, poly);
     R.ok = (D > 0.0) && (R.P.p > 0.0);
     return R;
   }

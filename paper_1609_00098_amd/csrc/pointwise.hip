@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(256) con2prim_kernel(const C2PArgs A) {
     if (GUESS == 0 && valid) p0 = A.prim[4 * n + q];
     if (GUESS == 2) p0 = mlp_seed_wave<SYS>(sm, ws, u, A.gamma);
     if (!valid) continue;
-    const C2PResult R = recover<SYS>(u, A.gamma, p0, A.tol, 100);
+    const C2PResult R = recover<SYS>(u, A.gamma, p0, A.tol, 100, A.poly);
     A.prim[q] = R.P.rho;
     A.prim[n + q] = R.P.v[0];
     A.prim[2 * n + q] = R.P.v[1];

@@ -102,7 +102,7 @@ struct RhsCfg {
 // follows from U (and p) in closed form, exactly as the recovery returned it.
 template <int SYS>
 __device__ __forceinline__ void load_node(const double *U, const double *Pr, int64_t nn, int64_t q, double g,
-                                          double *u, Prim &P) {
+                                          double *u, Prim &P, bool poly = false) {
 #pragma unroll
   for (int v = 0; v < SysTraits<SYS>::nv; ++v) u[v] = U[v * nn + q];
   if (SYS == kMHD) {
@@ -112,7 +112,7 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
     P.v[2] = Pr[3 * nn + q];
     P.p = Pr[4 * nn + q];
   } else {
-    P = prims_at_pressure<SYS>(u, g, SYS == kSR ? Pr[4 * nn + q] : 0.0);
+    P = prims_at_pressure<SYS>(u, g, SYS == kSR ? Pr[4 * nn + q] : 0.0, poly);
   }
 }
 
@@ -152,7 +152,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   if (active) {
-    load_node<SYS>(A.U, A.P, nn, q, A.gamma, u, P);
+    load_node<SYS>(A.U, A.P, nn, q, A.gamma, u, P, A.poly);
     if (SYS == kMHD) acc[8] = -A.kappa * u[8];
 #pragma unroll
     for (int v = 0; v < NV; ++v) sown[(le * NV + v) * NPE + a] = u[v];
@@ -242,14 +242,19 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     const int ai = c0 + NP * (c1 + NP * c2);
     double ue[NV], Fe[NV];
     Prim Pe;
-    if (!MIXED && en < 0) {  // box face with a fixed exterior state
+    if (!MIXED && en < 0) {  // box face: fixed or analytic exterior state
       const double *bs = A.bcs + f * 16;
+      if (A.bckind[d] == 2) {
+        const int64_t ex = fe % A.nx, ey = (fe / A.nx) % A.ny, ez = fe / ((int64_t)A.nx * A.ny);
+        const int64_t ef = d == 0 ? ey + (int64_t)A.ny * ez : (d == 1 ? ex + (int64_t)A.nx * ez : ex + (int64_t)A.nx * ey);
+        bs = A.bface + (A.boff[f] + ef * NF + fn) * 16;
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) ue[v] = bs[v];
       Pe.rho = bs[9]; Pe.v[0] = bs[10]; Pe.v[1] = bs[11]; Pe.v[2] = bs[12]; Pe.p = bs[13];
     } else {
       const int64_t ebase = MIXED ? A.off[en] : en * NPE;
-      load_node<SYS>(A.U, A.P, nn, ebase + n0 + NP * (n1 + NP * n2), A.gamma, ue, Pe);
+      load_node<SYS>(A.U, A.P, nn, ebase + n0 + NP * (n1 + NP * n2), A.gamma, ue, Pe, A.poly);
     }
     flux_normal<SYS>(d, ue, Pe, Fe);
     const double *own = sown + fle * NV * NPE + ai;
@@ -325,7 +330,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
         A.out[v * nn + q] = us[v];
         su[(le * NV + v) * NPE + a] = us[v];
       }
-      const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100);
+      const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100, A.poly);
       A.Pout[q] = R.P.rho;
       A.Pout[nn + q] = R.P.v[0];
       A.Pout[2 * nn + q] = R.P.v[1];
@@ -352,7 +357,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     us[v] = A.a * A.Un[v * nn + q] + A.b * (u[v] + dt * acc[v]);
     A.out[v * nn + q] = us[v];
   }
-  const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100);
+  const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100, A.poly);
   // intermediate stages of NE / SR keep only the pressure (the next stage
   // rebuilds the rest); SRMHD and the caller's buffers get all five rows
   if (SYS == kMHD || A.full_prims) {

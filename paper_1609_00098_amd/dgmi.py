@@ -18,8 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libdgmi.so")
 
 NEWTONIAN_EULER, SR_HYDRO, SR_MHD = 0, 1, 2
 GUESS_INPUT, GUESS_PLAIN, GUESS_LEARNED = 0, 1, 2
-FLAG_PLAIN_GUESS, FLAG_RECOVER_FIRST, FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_HLL = 1, 2, 4, 8, 16
+FLAG_PLAIN_GUESS, FLAG_RECOVER_FIRST, FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_HLL, FLAG_POLYTROPIC = 1, 2, 4, 8, 16, 32
 LIMITER_NONE, LIMITER_MINMOD, LIMITER_MUSCL = 0, 1, 2
+SOLUTION_ISENTROPIC_VORTEX = 1
 NVARS = {NEWTONIAN_EULER: 5, SR_HYDRO: 5, SR_MHD: 9}
 MLP_NUM_WEIGHTS = 4609
 MLP_NUM_PARAMS = 4621
@@ -59,6 +60,9 @@ _SIGS = {
     "dgmi_failures": (_I32, [_P, ctypes.POINTER(_I64), _P]),
     "dgmi_set_boundary": (_I32, [_P, _I32, _P, _P]),
     "dgmi_set_limiter": (_I32, [_P, _I32, _D]),
+    "dgmi_set_analytic_boundary": (_I32, [_P, _I32, _I32, _P, _I32]),
+    "dgmi_set_time": (_I32, [_P, _D]),
+    "dgmi_get_time": (_I32, [_P, ctypes.POINTER(_D)]),
     "dg_limit": (_I32, [_P, _P, _P, _P]),
     "dgmi_limited": (_I32, [_P, ctypes.POINTER(_I64), _P]),
     "con2prim": (_I32, [_I32, _D, _P, _P, _I64, _I32, _P, _D, _P, _P, _P, _P]),
@@ -210,6 +214,23 @@ def dgmi_set_boundary(mesh, direction, state_lo=None, state_hi=None):
         raise ValueError(f"states must have {need} entries")
     _check(_lib.dgmi_set_boundary(mesh.handle, direction, lo.ctypes.data_as(ctypes.c_void_p),
                                   hi.ctypes.data_as(ctypes.c_void_p)), "dgmi_set_boundary")
+
+
+def dgmi_set_analytic_boundary(mesh, direction, solution, params):
+    import numpy as np
+    par = np.ascontiguousarray(params, dtype=np.float64)
+    _check(_lib.dgmi_set_analytic_boundary(mesh.handle, direction, solution, par.ctypes.data_as(ctypes.c_void_p),
+                                           par.size), "dgmi_set_analytic_boundary")
+
+
+def dgmi_set_time(mesh, t):
+    _check(_lib.dgmi_set_time(mesh.handle, float(t)), "dgmi_set_time")
+
+
+def dgmi_get_time(mesh):
+    v = _D(0.0)
+    _check(_lib.dgmi_get_time(mesh.handle, ctypes.byref(v)), "dgmi_get_time")
+    return float(v.value)
 
 
 def dgmi_set_limiter(mesh, kind, M=0.0):

@@ -71,6 +71,22 @@ def smooth_flow(xyz, t=0.0, amplitude=0.2, wavenumber=2.0 * math.pi, velocity=(0
     return xp.stack([rho, velocity[0] * ones, velocity[1] * ones, velocity[2] * ones, pressure * ones])
 
 
+def isentropic_vortex(xyz, t=0.0, beta=5.0, center=(4.0, 4.0), velocity=(1.0, 1.0, 0.0), gamma=1.4):
+    """Primitives (rho, v, p) of the isentropic vortex (eq. isen_vortex) at the
+    points xyz[3][n] and time t, with the isentropic pressure p = rho^gamma:
+    the initial data and exact solution of the three-dimensional Newtonian
+    test.  Returns prim[5][n]."""
+    xp = np if isinstance(xyz, np.ndarray) else _torch()
+    xt = xyz[0] - center[0] - velocity[0] * t
+    yt = xyz[1] - center[1] - velocity[1] * t
+    r2 = xt * xt + yt * yt
+    rho = (1.0 - (gamma - 1.0) * beta ** 2 / (8.0 * gamma * math.pi ** 2) * xp.exp(1.0 - r2)) ** (1.0 / (gamma - 1.0))
+    s = beta / (2.0 * math.pi) * xp.exp(0.5 * (1.0 - r2))
+    vx = velocity[0] - yt * s
+    vy = velocity[1] + xt * s
+    return xp.stack([rho, vx, vy, velocity[2] + 0.0 * rho, rho ** gamma])
+
+
 def _torch():
     import torch
     return torch
