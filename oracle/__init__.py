@@ -146,6 +146,10 @@ def _load():
         "ora_limit": (I64, [MP, D]),
         "ora_limiter_moments": (ctypes.c_int, [MP, D, D, U8]),
         "ora_isentropic_vortex": (ctypes.c_int, [ctypes.c_double, D, I64, D, ctypes.c_double, D]),
+        "ora_max_char_speed": (ctypes.c_double, [MP, D]),
+        "ora_min_node_spacing": (ctypes.c_double, [MP]),
+        "ora_stable_dt": (ctypes.c_double, [MP, D, ctypes.c_double]),
+        "ora_evolve_ab3": (I64, [MP, D, ctypes.c_double, I64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -374,6 +378,26 @@ def step(m, U, dt):
 def evolve(m, U, dt, nsteps):
     U = _c(U).copy()
     nf = _load().ora_evolve(ctypes.byref(m), _p(U), dt, nsteps)
+    return U, int(nf)
+
+
+def max_char_speed(m, U):
+    return float(_load().ora_max_char_speed(ctypes.byref(m), _p(_c(U))))
+
+
+def min_node_spacing(m):
+    return float(_load().ora_min_node_spacing(ctypes.byref(m)))
+
+
+def stable_dt(m, U, cfl):
+    return float(_load().ora_stable_dt(ctypes.byref(m), _p(_c(U)), cfl))
+
+
+def evolve_ab3(m, U, dt, nsteps):
+    U = _c(U).copy()
+    nf = _load().ora_evolve_ab3(ctypes.byref(m), _p(U), dt, nsteps)
+    if nf < 0:
+        raise ValueError("bad mesh")
     return U, int(nf)
 
 

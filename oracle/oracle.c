@@ -1210,6 +1210,91 @@ int64_t ora_evolve(const ora_mesh *m, double *U, double dt, int64_t nsteps) {
   return nf;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Time step from the CFL scaling (section on initial data, boundary        */
+/* conditions and time steppers): dt = C dx_min / lambda_max, dx_min the     */
+/* smallest distance between neighbouring GLL nodes on the physical grid,   */
+/* lambda_max the largest characteristic speed over all nodes, directions   */
+/* and components.                                                          */
+/* ------------------------------------------------------------------------ */
+double ora_max_char_speed(const ora_mesh *m, const double *U) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return -1.0;
+  int nv = nvars_of(m->sys);
+  double *prim = (double *)malloc(sizeof(double) * 5 * G.nnodes);
+  if (cons2prim_eos(m->sys, m->eos, m->gamma, G.nnodes, U, prim, NULL) != 0) {
+    free(prim);
+    return -1.0;
+  }
+  double lam = 0.0;
+  for (int64_t q = 0; q < G.nnodes; ++q) {
+    cons_t C; prim_t P; double a[9];
+    load_cons(nv, G.nnodes, U, q, &C);
+    load_prim(G.nnodes, prim, q, &P);
+    for (int d = 0; d < 3; ++d) {
+      if (G.n[d] < 2) continue;
+      max_speed(m->sys, m->gamma, d, &C, &P, a);
+      for (int c = 0; c < nv; ++c) lam = fmax(lam, a[c]);
+    }
+  }
+  free(prim);
+  return lam;
+}
+
+double ora_min_node_spacing(const ora_mesh *m) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return -1.0;
+  double h = INFINITY;
+  for (int d = 0; d < 3; ++d)
+    for (int i = 0; i + 1 < G.n[d]; ++i) h = fmin(h, 0.5 * G.dx[d] * (G.x[d][i + 1] - G.x[d][i]));
+  return h;
+}
+
+double ora_stable_dt(const ora_mesh *m, const double *U, double cfl) {
+  double lam = ora_max_char_speed(m, U), h = ora_min_node_spacing(m);
+  if (!(lam > 0.0) || !(h > 0.0)) return -1.0;
+  return cfl * h / lam;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Third-order Adams-Bashforth (section on initial data, boundary           */
+/* conditions and time steppers), constant dt:                              */
+/*   U^{n+1} = U^n + dt (23/12 L^n - 16/12 L^{n-1} + 5/12 L^{n-2}),          */
+/* L^k = L(U^k) at t_k.  The two missing past values are made by two SSP-RK3 */
+/* steps (the paper does not say how the history starts).  With a limiter   */
+/* the new state is limited.  Returns the failed recoveries.                */
+/* ------------------------------------------------------------------------ */
+int64_t ora_evolve_ab3(const ora_mesh *m, double *U, double dt, int64_t nsteps) {
+  geom_t G;
+  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
+  int nv = nvars_of(m->sys);
+  int64_t n = (int64_t)nv * G.nnodes;
+  double *L[3];
+  for (int k = 0; k < 3; ++k) L[k] = (double *)malloc(sizeof(double) * n);
+  int64_t nf = 0;
+  ora_mesh ms = *m;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    ms.time = m->time + s * dt;
+    double *Ln = L[s % 3];
+    int64_t r = ora_rhs(&ms, U, NULL, Ln);
+    if (r < 0) { nf = r; break; }
+    nf += r;
+    if (s < 2) {
+      r = ora_step(&ms, U, dt);
+      if (r < 0) { nf = r; break; }
+      nf += r;
+      continue;
+    }
+    const double *L1 = L[(s - 1) % 3], *L2 = L[(s - 2) % 3];
+#pragma omp parallel for schedule(static) if (n > 65536)
+    for (int64_t q = 0; q < n; ++q)
+      U[q] = U[q] + dt * (23.0 / 12.0 * Ln[q] - 16.0 / 12.0 * L1[q] + 5.0 / 12.0 * L2[q]);
+    ora_limit(m, U);
+  }
+  for (int k = 0; k < 3; ++k) free(L[k]);
+  return nf;
+}
+
 /* L1 norm of eq. L1 with the GLL rule of each element:
  * sum over components of sum_e sum_ijk w_i w_j w_k (dx dy dz / 8) |a - b|.
  * (collapsed directions contribute weight 2 and length dx, i.e. unit
