@@ -199,6 +199,32 @@ def learned_vs_plain(dg, synth, torch, npts, ntrain):
     return res
 
 
+def timestepping(dg, torch, U0, P0, steps):
+    """The headline state advanced by SSP-RK3 and by third-order
+    Adams-Bashforth steps (one operator evaluation per step once its history
+    is full), and the CFL time step (largest characteristic speed reduced on
+    the device)."""
+    G = dg.Mesh(SR, NEL, DEG, GAMMA)
+    U = U0.clone()
+    P = P0.clone()
+    dt_t = dg.dgmi_stable_dt(G, U, P, 0.3)
+    ms_cfl = time_loop(torch, lambda i: dg.dgmi_stable_dt(G, U, P, 0.3, out=dt_t), steps, 4)
+    dt = float(dt_t.item())
+    ms_rk3 = time_loop(torch, lambda i: dg.dg_step(G, U, P, dt), max(steps // 4, 10), 2)
+    U.copy_(U0)
+    P.copy_(P0)
+    for _ in range(2):
+        dg.dg_step_ab3(G, U, P, dt)  # the starting RK3 steps
+    ms_ab3 = time_loop(torch, lambda i: dg.dg_step_ab3(G, U, P, dt), max(steps // 4, 10), 2)
+    nn = G.nnodes
+    out = {"workload": "the dg_rhs workload above, stepped with dt = 0.3 dx_min / lambda_max",
+           "dt": dt, "stable_dt_ms": ms_cfl, "rk3_ms_per_step": ms_rk3, "ab3_ms_per_step": ms_ab3,
+           "ab3_dof_updates_per_s": nn * NV / (ms_ab3 * 1e-3), "failed_recoveries": dg.dgmi_failures(G)}
+    del G, U, P
+    torch.cuda.empty_cache()
+    return out
+
+
 def hll_flux(dg, torch, Ua, Ub, P, dUa, dUb, steps, ms_llf, ms_op_llf):
     """The headline workload with the HLL flux (eq. HLL) instead of LLF:
     dg_rhs and the operator alone, same inputs and alternation."""
@@ -404,6 +430,8 @@ def main():
     }
     if not args.no_extras:
         out["hll_flux_dg_rhs"] = hll_flux(dg, torch, Ua, Ub, P, dUa, dUb, args.steps, ms, ms_op)
+        dg.dg_rhs(G, Ua, P, dUa)  # P <- the primitives of Ua
+        out["time_stepping"] = timestepping(dg, torch, Ua, P, args.steps)
         del Ua, Ub, P, dUa, dUb, G
         torch.cuda.empty_cache()
         out["srmhd_blast_dg_step"] = srmhd_blast_steps(dg, synth, torch)

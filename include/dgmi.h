@@ -217,6 +217,33 @@ dgmi_status dgmi_limited(dgmi_ctx *ctx, int64_t *n_limited_host, void *stream);
  * then resets the counter). */
 dgmi_status dgmi_failures(dgmi_ctx *ctx, int64_t *n_failed_host, void *stream);
 
+/* Largest characteristic speed of U (section on initial data, boundary
+ * conditions and time steppers: the lambda_max of the CFL scaling) over
+ * every node, direction and component, written to the device double
+ * *lambda_device: |v_d| + c_s (NE), the larger modulus of the acoustic pair
+ * (SR), and 1 for SRMHD (its normal field and cleaning scalar move at the
+ * light speed).  prim: primitives of U (NE ignores them; SR reads p).
+ * Asynchronous; the result is a device value (no host synchronisation). */
+dgmi_status dgmi_max_speed(dgmi_ctx *ctx, const double *U, const double *prim, double *lambda_device, void *stream);
+
+/* dt = cfl * dx_min / lambda_max into the device double *dt_device, dx_min the
+ * smallest distance between neighbouring GLL nodes on the physical grid
+ * (over the degrees present), lambda_max as dgmi_max_speed.  cfl > 0. */
+dgmi_status dgmi_stable_dt(dgmi_ctx *ctx, const double *U, const double *prim, double cfl, double *dt_device,
+                           void *stream);
+
+/* One step of the third-order Adams-Bashforth method (section on initial
+ * data, boundary conditions and time steppers) in place:
+ *   U <- U + dt (23/12 L^n - 16/12 L^{n-1} + 5/12 L^{n-2}),  L^k = L(U^k) at t_k,
+ * one operator evaluation per step.  The context keeps the last three
+ * operator values (24 nv bytes per node, allocated on first use); the first
+ * two calls with a given dt are SSP-RK3 steps (dg_step) that start the
+ * history, and a call with another dt starts it again.  prim_inout as for
+ * dg_step (on exit the primitives of the new U; failures counted); with a
+ * slope limiter the new U is limited.  Advances the context's time by dt.
+ * Uniform degrees only (DGMI_EUNSUPPORTED otherwise). */
+dgmi_status dg_step_ab3(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream);
+
 /* Pointwise recovery of the primitives (conservation-laws section; the
  * relativistic systems solve f(p) = (gamma-1) rho eps(p) - p = 0 by a
  * bracketed Newton iteration on [0, p_hi], p_hi = (gamma-1) tau, or

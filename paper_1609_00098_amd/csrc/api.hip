@@ -175,6 +175,12 @@ struct dgmi_ctx {
   double *d_mom = nullptr;        // [nelem][10][nv]
   int32_t *d_bad = nullptr;       // [nelem]
   unsigned long long *d_nlim = nullptr;
+  // time stepping helpers
+  double hmin = 0.0;              // smallest GLL node spacing on the physical grid
+  double *d_lam = nullptr;        // device scalar: largest characteristic speed
+  double *d_L = nullptr;          // Adams-Bashforth history: three operator values [3][nv][nnodes]
+  int64_t ab_count = 0;           // steps taken with ab_dt
+  double ab_dt = NAN;
 };
 
 // Neighbour table [nelem][6] (-x,+x,-y,+y,-z,+z): periodic wrap, or -1 on the
@@ -540,6 +546,8 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_dt);
   (void)hipFree(c->d_bc);
   (void)hipFree(c->d_bface);
+  (void)hipFree(c->d_lam);
+  (void)hipFree(c->d_L);
   (void)hipFree(c->d_limtab);
   (void)hipFree(c->d_mom);
   (void)hipFree(c->d_bad);
@@ -612,6 +620,15 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
     diff_matrix(N, &hx[N * 8], &hD[N * 64]);
     c->wend[N] = w[0];
   }
+  // smallest node spacing over the degrees present
+  c->hmin = INFINITY;
+  for (int N = 1; N <= 7; ++N) {
+    bool present = false;
+    for (int64_t e = 0; e < c->nelem && !present; ++e) present = c->deg[e] == N;
+    if (!present) continue;
+    for (int d = 0; d < 3; ++d)
+      for (int i = 0; i < N; ++i) c->hmin = std::fmin(c->hmin, 0.5 * c->dx[d] * (hx[N * 8 + i + 1] - hx[N * 8 + i]));
+  }
   const std::vector<int32_t> nbr = neighbour_table(c);
   const size_t ubytes = sizeof(double) * (size_t)c->nv * c->nnodes;
   const size_t pbytes = sizeof(double) * 5 * (size_t)c->nnodes;
@@ -622,7 +639,8 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
       hipMalloc(&c->d_U1, ubytes) != hipSuccess || hipMalloc(&c->d_U2, ubytes) != hipSuccess ||
       hipMalloc(&c->d_P1, pbytes) != hipSuccess || hipMalloc(&c->d_P2, pbytes) != hipSuccess ||
       hipMalloc(&c->d_bc, sizeof(c->hbc)) != hipSuccess || hipMalloc(&c->d_limtab, 24 * sizeof(double)) != hipSuccess ||
-      hipMalloc(&c->d_nlim, sizeof(unsigned long long)) != hipSuccess) {
+      hipMalloc(&c->d_nlim, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&c->d_lam, sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     ctx_free(c);
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation failed (%lld nodes)", (long long)c->nnodes);
@@ -1045,6 +1063,91 @@ dgmi_status dgmi_limited(dgmi_ctx *ctx, int64_t *n_limited_host, void *stream) {
   HIP_TRY(hipMemsetAsync(ctx->d_nlim, 0, sizeof(v), s));
   HIP_TRY(hipStreamSynchronize(s));
   *n_limited_host = (int64_t)v;
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_max_speed(dgmi_ctx *ctx, const double *U, const double *prim, double *lambda_device, void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dgmi_max_speed: null context");
+  if (!is_device_ptr(U) || !is_device_ptr(prim) || !is_device_ptr(lambda_device))
+    return fail(DGMI_EINVAL, "dgmi_max_speed: U, prim and lambda must be device pointers");
+  HIP_TRY(dgmi::launch_max_speed(ctx->sys, U, prim, ctx->nnodes, ctx->gamma,
+                                 (ctx->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0, lambda_device, (hipStream_t)stream));
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_stable_dt(dgmi_ctx *ctx, const double *U, const double *prim, double cfl, double *dt_device,
+                           void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dgmi_stable_dt: null context");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DGMI_EINVAL, "dgmi_stable_dt: cfl must be positive");
+  if (!is_device_ptr(U) || !is_device_ptr(prim) || !is_device_ptr(dt_device))
+    return fail(DGMI_EINVAL, "dgmi_stable_dt: U, prim and dt must be device pointers");
+  if (ctx->nnodes == 0) return fail(DGMI_EINVAL, "dgmi_stable_dt: empty mesh");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(dgmi::launch_max_speed(ctx->sys, U, prim, ctx->nnodes, ctx->gamma,
+                                 (ctx->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0, ctx->d_lam, s));
+  HIP_TRY(dgmi::launch_cfl_dt(ctx->d_lam, cfl * ctx->hmin, dt_device, s));
+  return DGMI_OK;
+}
+
+dgmi_status dg_step_ab3(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dg_step_ab3: null context");
+  if (ctx->mixed) return fail(DGMI_EUNSUPPORTED, "dg_step_ab3: uniform degrees only");
+  if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
+    return fail(DGMI_EINVAL, "dg_step_ab3: U and prim_inout must be distinct device pointers");
+  if (!std::isfinite(dt)) return fail(DGMI_EINVAL, "dg_step_ab3: dt must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nvn = (int64_t)ctx->nv * ctx->nnodes;
+  if (!ctx->d_L) {
+    if (hipMalloc(&ctx->d_L, sizeof(double) * 3 * nvn) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->d_L = nullptr;
+      return fail(DGMI_ENOMEM, "dg_step_ab3: device allocation failed");
+    }
+  }
+  if (!(dt == ctx->ab_dt)) {  // a new step size restarts the history
+    ctx->ab_dt = dt;
+    ctx->ab_count = 0;
+  }
+  const int64_t k = ctx->ab_count;
+  double *Ln = ctx->d_L + (k % 3) * nvn;
+  if (ctx->flags & DGMI_FLAG_RECOVER_FIRST) {
+    const int guess = (ctx->flags & DGMI_FLAG_PLAIN_GUESS) ? DGMI_GUESS_PLAIN : DGMI_GUESS_INPUT;
+    dgmi_status st = recover_all(ctx, U, prim_inout, guess, s);
+    if (st != DGMI_OK) return st;
+  }
+  // L^n = L(U^n) at the current time
+  dgmi_status st = boundary_pass(ctx, ctx->time, s);
+  if (st != DGMI_OK) return st;
+  dgmi::RhsArgs a = rhs_args(ctx);
+  a.U = U;
+  a.P = prim_inout;
+  a.out = Ln;
+  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 0, flux_of(ctx), a, s));
+  if (k < 2) {
+    // the history starts with SSP-RK3 steps (prim_inout still holds U^n's primitives)
+    const int flags = ctx->flags;
+    ctx->flags &= ~DGMI_FLAG_RECOVER_FIRST;
+    st = dg_step(ctx, U, prim_inout, dt, stream);
+    ctx->flags = flags;
+    if (st != DGMI_OK) return st;
+  } else {
+    dgmi::AB3Args b{};
+    b.U = U;
+    b.P = prim_inout;
+    b.L0 = Ln;
+    b.L1 = ctx->d_L + ((k - 1) % 3) * nvn;
+    b.L2 = ctx->d_L + ((k - 2) % 3) * nvn;
+    b.nnodes = ctx->nnodes;
+    b.dt = dt;
+    b.gamma = ctx->gamma;
+    b.nfail = ctx->d_nfail;
+    b.poly = (ctx->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0;
+    HIP_TRY(dgmi::launch_ab3(ctx->sys, b, s));
+    if (ctx->lim_kind != DGMI_LIMITER_NONE)
+      HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, true, lim_args(ctx, U, prim_inout, prim_inout), s));
+    ctx->time += dt;
+  }
+  ctx->ab_count = k + 1;
   return DGMI_OK;
 }
 

@@ -100,6 +100,25 @@ struct BoundaryArgs {
 };
 hipError_t launch_boundary_states(const BoundaryArgs &b, hipStream_t s);
 
+// Largest characteristic speed over all nodes, directions and components
+// into the device double *lam (non-negative; written with a 64-bit atomic
+// maximum after *lam is set to 0); dt = cfl_h / *lam into *dt.
+hipError_t launch_max_speed(int sys, const double *U, const double *P, int64_t nn, double g, int poly, double *lam,
+                            hipStream_t s);
+hipError_t launch_cfl_dt(const double *lam, double cfl_h, double *dt, hipStream_t s);
+
+// Third-order Adams-Bashforth update in place, with the primitives of the
+// result (P: in, the pressure seeds; out, the primitives).
+struct AB3Args {
+  double *U, *P;
+  const double *L0, *L1, *L2;  // L^n, L^{n-1}, L^{n-2}
+  int64_t nnodes;
+  double dt, gamma;
+  unsigned long long *nfail;
+  int poly;
+};
+hipError_t launch_ab3(int sys, const AB3Args &a, hipStream_t s);
+
 // Highest degree of the mixed-degree path (mortars of up to 8x8 nodes).
 constexpr int kMaxMixedDegree = 7;
 

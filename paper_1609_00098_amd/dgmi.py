@@ -62,6 +62,9 @@ _SIGS = {
     "dgmi_set_limiter": (_I32, [_P, _I32, _D]),
     "dgmi_set_analytic_boundary": (_I32, [_P, _I32, _I32, _P, _I32]),
     "dgmi_set_time": (_I32, [_P, _D]),
+    "dgmi_max_speed": (_I32, [_P, _P, _P, _P, _P]),
+    "dgmi_stable_dt": (_I32, [_P, _P, _P, _D, _P, _P]),
+    "dg_step_ab3": (_I32, [_P, _P, _P, _D, _P]),
     "dgmi_get_time": (_I32, [_P, ctypes.POINTER(_D)]),
     "dg_limit": (_I32, [_P, _P, _P, _P]),
     "dgmi_limited": (_I32, [_P, ctypes.POINTER(_I64), _P]),
@@ -248,6 +251,34 @@ def dgmi_limited(mesh, stream=None):
     v = _I64(0)
     _check(_lib.dgmi_limited(mesh.handle, ctypes.byref(v), _stream(stream)), "dgmi_limited")
     return int(v.value)
+
+
+def dgmi_max_speed(mesh, U, prim, out=None, stream=None):
+    """Largest characteristic speed as a one-element device tensor."""
+    n = mesh.nnodes
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+    _check(_lib.dgmi_max_speed(mesh.handle, _ptr(U, numel=mesh.nv * n, name="U"), _ptr(prim, numel=5 * n, name="prim"),
+                               _ptr(out, numel=1, name="out"), _stream(stream)), "dgmi_max_speed")
+    return out
+
+
+def dgmi_stable_dt(mesh, U, prim, cfl, out=None, stream=None):
+    """cfl * dx_min / lambda_max as a one-element device tensor."""
+    n = mesh.nnodes
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+    _check(_lib.dgmi_stable_dt(mesh.handle, _ptr(U, numel=mesh.nv * n, name="U"), _ptr(prim, numel=5 * n, name="prim"),
+                               float(cfl), _ptr(out, numel=1, name="out"), _stream(stream)), "dgmi_stable_dt")
+    return out
+
+
+def dg_step_ab3(mesh, U, prim_inout, dt, stream=None):
+    n = mesh.nnodes
+    _check(_lib.dg_step_ab3(mesh.handle, _ptr(U, numel=mesh.nv * n, name="U"),
+                            _ptr(prim_inout, numel=5 * n, name="prim_inout"), float(dt), _stream(stream)),
+           "dg_step_ab3")
+    return U
 
 
 def dg_step(mesh, U, prim_inout, dt, stream=None):
