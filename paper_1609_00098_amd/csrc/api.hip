@@ -183,8 +183,10 @@ struct dgmi_ctx {
   double ab_dt = NAN;
 };
 
-// Neighbour table [nelem][6] (-x,+x,-y,+y,-z,+z): periodic wrap, or -1 on the
-// box faces of a direction with fixed exterior states.
+// Neighbour table [nelem][6] (-x,+x,-y,+y,-z,+z): periodic wrap, or on the
+// box faces of a non-periodic direction -1 - (index of the element on that
+// box face: a + n_a b over the two other directions in increasing order),
+// which locates the face's exterior states in the boundary buffer.
 static std::vector<int32_t> neighbour_table(const dgmi_ctx *c) {
   const int64_t ne[3] = {c->nx, c->ny, c->nz};
   std::vector<int32_t> nbr(c->nelem * 6);
@@ -194,7 +196,8 @@ static std::vector<int32_t> neighbour_table(const dgmi_ctx *c) {
       int64_t k[3] = {cc[0], cc[1], cc[2]};
       const int d = f >> 1;
       if (c->bc[d] && ((f & 1) ? k[d] == ne[d] - 1 : k[d] == 0)) {
-        nbr[e * 6 + f] = -1;
+        const int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+        nbr[e * 6 + f] = (int32_t)(-1 - (k[da] + ne[da] * k[db]));
         continue;
       }
       k[d] = (k[d] + ((f & 1) ? 1 : ne[d] - 1)) % ne[d];
@@ -709,8 +712,6 @@ dgmi_status dgmi_prim2cons(int32_t system, double gamma, const double *prim, con
 static dgmi::RhsArgs rhs_args(dgmi_ctx *c) {
   dgmi::RhsArgs a{};
   a.nbr = c->d_nbr;
-  a.bcs = c->d_bc;
-  for (int d = 0; d < 3; ++d) a.bckind[d] = c->bc[d];
   a.bface = c->d_bface;
   for (int f = 0; f < 7; ++f) a.boff[f] = c->boff[f];
   a.poly = (c->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0;
@@ -909,6 +910,29 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
   return DGMI_OK;
 }
 
+// Exterior states of every box-face node (16 doubles each), allocated on
+// first use; face f's nodes start at node boff[f].
+static dgmi_status ensure_bface(dgmi_ctx *ctx) {
+  if (ctx->d_bface) return DGMI_OK;
+  const int64_t ne[3] = {ctx->nx, ctx->ny, ctx->nz};
+  const int64_t nf = (int64_t)(ctx->degree + 1) * (ctx->degree + 1);
+  int64_t boff[7];
+  boff[0] = 0;
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+    boff[f + 1] = boff[f] + ne[da] * ne[db] * nf;
+  }
+  if (hipMalloc(&ctx->d_bface, sizeof(double) * 16 * boff[6]) != hipSuccess ||
+      hipMemset(ctx->d_bface, 0, sizeof(double) * 16 * boff[6]) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(ctx->d_bface);
+    ctx->d_bface = nullptr;
+    return fail(DGMI_ENOMEM, "boundary states: device allocation failed");
+  }
+  std::memcpy(ctx->boff, boff, sizeof(boff));
+  return DGMI_OK;
+}
+
 dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *state_lo_host,
                               const double *state_hi_host) {
   if (!ctx) return fail(DGMI_EINVAL, "dgmi_set_boundary: null context");
@@ -942,6 +966,19 @@ dgmi_status dgmi_set_boundary(dgmi_ctx *ctx, int32_t direction, const double *st
     }
     bc = 1;
   }
+  if (bc) {
+    // every node of the two box faces gets the face's state
+    dgmi_status st = ensure_bface(ctx);
+    if (st != DGMI_OK) return st;
+    for (int side = 0; side < 2; ++side) {
+      const int f = 2 * direction + side;
+      std::vector<double> rows((size_t)(ctx->boff[f + 1] - ctx->boff[f]) * 16);
+      for (size_t r = 0; r < rows.size() / 16; ++r) std::memcpy(&rows[r * 16], hbc + f * 16, 16 * sizeof(double));
+      if (hipMemcpy(ctx->d_bface + ctx->boff[f] * 16, rows.data(), rows.size() * sizeof(double),
+                    hipMemcpyHostToDevice) != hipSuccess)
+        return fail(DGMI_EHIP, "dgmi_set_boundary: state upload failed");
+    }
+  }
   const int old = ctx->bc[direction];
   ctx->bc[direction] = bc;
   const std::vector<int32_t> nbr = neighbour_table(ctx);
@@ -968,24 +1005,8 @@ dgmi_status dgmi_set_analytic_boundary(dgmi_ctx *ctx, int32_t direction, int32_t
   if (!params_host || nparams != 6) return fail(DGMI_EINVAL, "dgmi_set_analytic_boundary: 6 parameters expected");
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(params_host[k])) return fail(DGMI_EINVAL, "dgmi_set_analytic_boundary: non-finite parameter");
-  if (!ctx->d_bface) {
-    const int64_t ne[3] = {ctx->nx, ctx->ny, ctx->nz};
-    const int64_t nf = (int64_t)(ctx->degree + 1) * (ctx->degree + 1);
-    int64_t boff[7];
-    boff[0] = 0;
-    for (int f = 0; f < 6; ++f) {
-      const int d = f >> 1, da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
-      boff[f + 1] = boff[f] + ne[da] * ne[db] * nf;
-    }
-    if (hipMalloc(&ctx->d_bface, sizeof(double) * 16 * boff[6]) != hipSuccess ||
-        hipMemset(ctx->d_bface, 0, sizeof(double) * 16 * boff[6]) != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hipFree(ctx->d_bface);
-      ctx->d_bface = nullptr;
-      return fail(DGMI_ENOMEM, "dgmi_set_analytic_boundary: device allocation failed");
-    }
-    std::memcpy(ctx->boff, boff, sizeof(boff));
-  }
+  dgmi_status st = ensure_bface(ctx);
+  if (st != DGMI_OK) return st;
   for (int k = 0; k < 6; ++k) ctx->vortex[k] = params_host[k];
   const int old = ctx->bc[direction];
   ctx->bc[direction] = 2;

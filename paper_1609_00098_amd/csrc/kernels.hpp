@@ -32,13 +32,10 @@ struct RhsArgs {
   const int64_t *foff;
   const double *facebuf;
   int nblocks;         // logical blocks (set at launch)
-  // uniform meshes: a face whose neighbour index is negative lies on a box
-  // face; its exterior state is, by direction (bckind), a fixed state
-  // bcs[f][0..nv) conserved and bcs[f][9..14) primitives (16 doubles per box
-  // face f), or (bckind 2) the analytic state of its node in bface, node
-  // (boff[f] + element-on-face * (N+1)^2 + face node) * 16
-  const double *bcs;
-  int bckind[3];
+  // uniform meshes: a face whose neighbour index en is negative lies on box
+  // face f; its nodes' exterior states (fixed or analytic) are the 16-double
+  // rows bface[(boff[f] + (-1 - en) * (N+1)^2 + face node) * 16 + ...]:
+  // conserved [0, nv), primitives [9, 14)
   const double *bface;
   int64_t boff[7];
   // limited stage kernel: element moments [nelem][10][nv] and unphysical flags

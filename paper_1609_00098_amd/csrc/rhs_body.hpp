@@ -21,8 +21,8 @@
 //      a U^n + b (U + dt L) and recovers the primitives of the result with
 //      the previous stage's pressure as the Newton seed (tail recovery), so
 //      the next stage finds neighbour primitives ready.
-// A face on a box face with a fixed exterior state (negative neighbour
-// index, uniform meshes) takes that state as its exterior.
+// A face on a box face of a non-periodic direction (negative neighbour
+// index, uniform meshes) takes its nodes' states from the boundary buffer.
 // Workgroups are mapped XCD-major: consecutive element groups land on the
 // same XCD (and L2), so face neighbours along x and y are usually L2 hits.
 //
@@ -242,13 +242,8 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     const int ai = c0 + NP * (c1 + NP * c2);
     double ue[NV], Fe[NV];
     Prim Pe;
-    if (!MIXED && en < 0) {  // box face: fixed or analytic exterior state
-      const double *bs = A.bcs + f * 16;
-      if (A.bckind[d] == 2) {
-        const int64_t ex = fe % A.nx, ey = (fe / A.nx) % A.ny, ez = fe / ((int64_t)A.nx * A.ny);
-        const int64_t ef = d == 0 ? ey + (int64_t)A.ny * ez : (d == 1 ? ex + (int64_t)A.nx * ez : ex + (int64_t)A.nx * ey);
-        bs = A.bface + (A.boff[f] + ef * NF + fn) * 16;
-      }
+    if (!MIXED && en < 0) {  // box face: its node's fixed or analytic exterior state
+      const double *bs = A.bface + (A.boff[f] + (-1 - en) * NF + fn) * 16;
 #pragma unroll
       for (int v = 0; v < NV; ++v) ue[v] = bs[v];
       Pe.rho = bs[9]; Pe.v[0] = bs[10]; Pe.v[1] = bs[11]; Pe.v[2] = bs[12]; Pe.p = bs[13];

@@ -3,9 +3,9 @@
 //
 //   max_speed_kernel   the largest characteristic speed over every node,
 //       direction and component: per node the largest over the three
-//       directions, per wave a shuffle-free LDS reduction, per workgroup one
-//       atomic maximum on the 64-bit pattern of the (non-negative) double,
-//       whose integer order is the numeric order.
+//       directions, per workgroup an LDS tree reduction and one atomic
+//       maximum on the 64-bit pattern of the (non-negative) double, whose
+//       integer order is the numeric order.
 //   cfl_dt_kernel      dt = C dx_min / lambda_max on the device.
 //   ab3_kernel         U <- U + dt (23/12 L^n - 16/12 L^{n-1} + 5/12 L^{n-2})
 //       and the primitives of the result, one thread per node.
@@ -84,7 +84,10 @@ hipError_t launch_max_speed(int sys, const double *U, const double *P, int64_t n
   hipError_t err = launch_set_scalar(lam, 0.0, s);
   if (err != hipSuccess || nn <= 0) return err;
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(lam);
-  const dim3 grid(grid_for(nn)), block(256);
+  // at most 1024 workgroups (a grid-stride loop covers the rest): one atomic
+  // per workgroup on a single address serialises in L2, so few of them
+  const int64_t b = (nn + 255) / 256;
+  const dim3 grid((unsigned)(b < 1024 ? b : 1024)), block(256);
   switch (sys) {
     case kNE: hipLaunchKernelGGL(max_speed_kernel<kNE>, grid, block, 0, s, U, P, nn, g, poly, acc); break;
     case kSR: hipLaunchKernelGGL(max_speed_kernel<kSR>, grid, block, 0, s, U, P, nn, g, poly, acc); break;
