@@ -62,21 +62,22 @@ enum {
                                      replaying a captured graph */
 #define DGMI_FLAG_AUTOTUNE 8      /* mixed degrees: dgmi_create times every tile option per degree and
                                      keeps the fastest (results do not depend on the choice) */
+#define DGMI_FLAG_HLL 16          /* numerical flux HLL (eq. HLL) instead of local Lax-Friedrichs
+                                     (eq. LLF); uniform degrees only, a mixed-degree mesh with it
+                                     returns DGMI_EUNSUPPORTED */
 #define DGMI_FLAG_POLYTROPIC 32   /* Newtonian Euler with the polytropic equation of state p = rho^gamma
                                      (K = 1; the adiabatic one of the isentropic vortex test) instead of
                                      the ideal gas; uniform degrees only.  The energy is still evolved;
                                      the standalone con2prim call stays ideal-gas.  Fixed boundary states
                                      take p = rho^gamma. */
-#define DGMI_FLAG_HLL 16          /* numerical flux HLL (eq. HLL) instead of local Lax-Friedrichs
-                                     (eq. LLF); uniform degrees only, a mixed-degree mesh with it
-                                     returns DGMI_EUNSUPPORTED */
 
 typedef struct dgmi_ctx dgmi_ctx;
 typedef struct dgmi_mlp dgmi_mlp;
 
 typedef struct {
   int32_t system;         /* DGMI_NEWTONIAN_EULER, DGMI_SR_HYDRO or DGMI_SR_MHD */
-  int32_t nx, ny, nz;     /* elements per direction (>= 1 each); periodic box */
+  int32_t nx, ny, nz;     /* elements per direction (>= 1 each); a periodic box unless
+                             dgmi_set_boundary / dgmi_set_analytic_boundary say otherwise */
   int32_t degree;         /* 1..7: uniform polynomial degree N (N+1 GLL nodes per
                              direction); 0: per-element degrees from degrees_host */
   int32_t flags;          /* DGMI_FLAG_* */

@@ -118,6 +118,11 @@ int dgmi::set_error(int st, const char *msg) {
   return st;
 }
 
+// The limiter counts limited components into this many counters (workgroup b
+// adds to counter b mod kLimCounters), so that its atomics do not all meet on
+// one address.
+constexpr int kLimCounters = 64;
+
 struct dgmi_ctx {
   int device = 0;
   int sys = 0, nv = 5;
@@ -174,7 +179,7 @@ struct dgmi_ctx {
   double *d_limtab = nullptr;     // [3][8]: w/2, 3/2 int(ell xi), GLL node of the mesh degree
   double *d_mom = nullptr;        // [nelem][10][nv]
   int32_t *d_bad = nullptr;       // [nelem]
-  unsigned long long *d_nlim = nullptr;
+  unsigned long long *d_nlim = nullptr;  // [kLimCounters] limited-component counters (summed when read)
   // time stepping helpers
   double hmin = 0.0;              // smallest GLL node spacing on the physical grid
   double *d_lam = nullptr;        // device scalar: largest characteristic speed
@@ -642,7 +647,7 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
       hipMalloc(&c->d_U1, ubytes) != hipSuccess || hipMalloc(&c->d_U2, ubytes) != hipSuccess ||
       hipMalloc(&c->d_P1, pbytes) != hipSuccess || hipMalloc(&c->d_P2, pbytes) != hipSuccess ||
       hipMalloc(&c->d_bc, sizeof(c->hbc)) != hipSuccess || hipMalloc(&c->d_limtab, 24 * sizeof(double)) != hipSuccess ||
-      hipMalloc(&c->d_nlim, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&c->d_nlim, kLimCounters * sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->d_lam, sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     ctx_free(c);
@@ -652,7 +657,7 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
       hipMemcpy(c->d_x, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->d_nfail, 0, sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_nlim, 0, sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_nlim, 0, kLimCounters * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->d_bc, 0, sizeof(c->hbc)) != hipSuccess) {
     ctx_free(c);
     return fail(DGMI_EHIP, "dgmi_create: table upload failed");
@@ -1079,10 +1084,12 @@ dgmi_status dgmi_limited(dgmi_ctx *ctx, int64_t *n_limited_host, void *stream) {
   if (!ctx || !n_limited_host) return fail(DGMI_EINVAL, "dgmi_limited: null argument");
   unsigned long long v = 0;
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(hipMemcpyAsync(&v, ctx->d_nlim, sizeof(v), hipMemcpyDeviceToHost, s));
+  unsigned long long parts[kLimCounters];
+  HIP_TRY(hipMemcpyAsync(parts, ctx->d_nlim, sizeof(parts), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  HIP_TRY(hipMemsetAsync(ctx->d_nlim, 0, sizeof(v), s));
+  HIP_TRY(hipMemsetAsync(ctx->d_nlim, 0, sizeof(parts), s));
   HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < kLimCounters; ++k) v += parts[k];
   *n_limited_host = (int64_t)v;
   return DGMI_OK;
 }

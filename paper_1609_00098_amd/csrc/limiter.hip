@@ -128,9 +128,10 @@ __global__ void __launch_bounds__(256) limiter_decide_kernel(const LimArgs A) {
     for (int d = 0; d < 3; ++d) me[(1 + d) * NV + v] = ad[d];
     me[4 * NV + v] = troubled ? 1.0 : 0.0;
   }
-  // one counter update per wave
+  // one counter update per wave, spread over 64 counters (A.nlim[64], summed
+  // by the host) so that the atomics do not serialise on one address
   const unsigned long long bal = __ballot(troubled);
-  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(A.nlim, (unsigned long long)__popcll(bal));
+  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(A.nlim + (blockIdx.x & 63), (unsigned long long)__popcll(bal));
 }
 
 template <int SYS, int N>
