@@ -57,7 +57,8 @@ def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), k
          bc=None, limiter="none", M=0.0, vortex=None, time=0.0, eos="ideal"):
     """Box of nelem=(nx,ny,nz) affine elements, periodic unless ``bc`` says
     otherwise.  degree is an int or a per-direction triple; a 0 entry
-    collapses that direction.  flux: "llf" (eq. LLF) or "hll" (eq. HLL).
+    collapses that direction.  flux: "llf" (eq. LLF), "hll" (eq. HLL) or, for the
+    Newtonian ideal gas, "roe" (eq. Roe).
     bc: {d: (state_lo, state_hi)} gives direction d fixed exterior states on
     its two box faces, each state a primitive 5-vector (rho, v, p), or for
     SRMHD a 9-vector (rho, v, p, B, Phi); {d: "vortex"} makes the exterior
@@ -74,7 +75,7 @@ def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), k
     m.sys = system
     m.nx, m.ny, m.nz = nelem
     m.deg[:] = list(degree)
-    m.flux = {"llf": 0, "hll": 1}[flux]
+    m.flux = {"llf": 0, "hll": 1, "roe": 2}[flux]
     m.limiter = LIMITERS[limiter]
     m.lim_M = M
     m.time = time
@@ -147,6 +148,7 @@ def _load():
         "ora_limiter_moments": (ctypes.c_int, [MP, D, D, U8]),
         "ora_isentropic_vortex": (ctypes.c_int, [ctypes.c_double, D, I64, D, ctypes.c_double, D]),
         "ora_max_char_speed": (ctypes.c_double, [MP, D]),
+        "ora_roe": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_double, D, D, D, D, D]),
         "ora_min_node_spacing": (ctypes.c_double, [MP]),
         "ora_stable_dt": (ctypes.c_double, [MP, D, ctypes.c_double]),
         "ora_evolve_ab3": (I64, [MP, D, ctypes.c_double, I64]),
@@ -322,6 +324,12 @@ def rhs_weak(m, U):
     dU = np.zeros_like(U)
     _load().ora_rhs_weak(ctypes.byref(m), _p(U), _p(dU))
     return dU
+
+
+def roe(gamma, d, sgn, ui, pi, ue, pe):
+    out = np.zeros(5)
+    _load().ora_roe(gamma, d, sgn, _p(_c(ui)), _p(_c(pi)), _p(_c(ue)), _p(_c(pe)), _p(out))
+    return out
 
 
 def isentropic_vortex(gamma, params, xyz, t):

@@ -576,13 +576,74 @@ static void hll(int sys, double g, int d, double sgn, const cons_t *Ci, const pr
   }
 }
 
+/* Roe flux (eq. Roe) for the Newtonian ideal gas, interior state L, exterior
+ * R, outward normal n = sgn e_d:
+ *   F*.n = (F(U_L).n + F(U_R).n)/2 - 1/2 sum_i |lambda_i| alpha_i e_i,
+ * eigenvalues, right eigenvectors e_i and wave strengths alpha_i of the flux
+ * Jacobian along n at the Roe-averaged state (eqs. RoeAverages and
+ * RoeMatrixIdealEOS; h there is the total specific enthalpy (E + p)/rho,
+ * the average that makes the Jacobian a Roe matrix).  Along n the waves are
+ * u_n - a, u_n (three: entropy and the two shears), u_n + a, with
+ * a^2 = (gamma - 1)(h - |v|^2/2); the strengths follow from expanding the
+ * jump U_R - U_L in the right eigenvectors, written in the components
+ * (rho, rho v_n, rho v_t1, rho v_t2, E).                                   */
+static void roe(double g, int d, double sgn, const cons_t *Ci, const prim_t *Pi, const cons_t *Ce, const prim_t *Pe,
+                double *Fstar_n, double *Fint_n) {
+  double fi[9], fe[9];
+  flux(0, g, d, Ci, Pi, fi);
+  flux(0, g, d, Ce, Pe, fe);
+  double sl = sqrt(Pi->rho), sr = sqrt(Pe->rho);
+  double hl = (Ci->u[4] + Pi->p) / Pi->rho, hr = (Ce->u[4] + Pe->p) / Pe->rho;
+  double vh[3];
+  for (int k = 0; k < 3; ++k) vh[k] = (sl * Pi->v[k] + sr * Pe->v[k]) / (sl + sr);
+  double hh = (sl * hl + sr * hr) / (sl + sr);
+  double q2 = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
+  double a2 = (g - 1.0) * (hh - 0.5 * q2), a = sqrt(a2);
+  int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  double un = sgn * vh[d], w1 = vh[t1], w2 = vh[t2];
+  double dr = Ce->u[0] - Ci->u[0];
+  double dmn = sgn * (Ce->u[1 + d] - Ci->u[1 + d]);
+  double dm1 = Ce->u[1 + t1] - Ci->u[1 + t1], dm2 = Ce->u[1 + t2] - Ci->u[1 + t2];
+  double dE = Ce->u[4] - Ci->u[4];
+  double al3 = dm1 - w1 * dr, al4 = dm2 - w2 * dr;
+  double dEp = dE - al3 * w1 - al4 * w2;
+  double al2 = (g - 1.0) / a2 * (dr * (hh - un * un) + un * dmn - dEp);
+  double al1 = (dr * (un + a) - dmn - a * al2) / (2.0 * a);
+  double al5 = dr - (al1 + al2);
+  double l1 = fabs(un - a), l2 = fabs(un), l5 = fabs(un + a);
+  double s15 = l1 * al1 + l2 * al2 + l5 * al5;
+  double D[5];
+  D[0] = s15;
+  double Dn = l1 * al1 * (un - a) + l2 * al2 * un + l5 * al5 * (un + a);
+  D[1 + d] = sgn * Dn;
+  D[1 + t1] = s15 * w1 + l2 * al3;
+  D[1 + t2] = s15 * w2 + l2 * al4;
+  D[4] = l1 * al1 * (hh - un * a) + l2 * al2 * 0.5 * q2 + l2 * (al3 * w1 + al4 * w2) + l5 * al5 * (hh + un * a);
+  for (int c = 0; c < 5; ++c) {
+    Fint_n[c] = sgn * fi[c];
+    Fstar_n[c] = 0.5 * (sgn * fi[c] + sgn * fe[c]) - 0.5 * D[c];
+  }
+}
+
 /* The numerical flux selected by the mesh. */
 static void numflux(int kind, int sys, double g, int d, double sgn, const cons_t *Ci, const prim_t *Pi,
                     const cons_t *Ce, const prim_t *Pe, double *Fstar_n, double *Fint_n) {
   if (kind == 1)
     hll(sys, g, d, sgn, Ci, Pi, Ce, Pe, Fstar_n, Fint_n);
+  else if (kind == 2)
+    roe(g, d, sgn, Ci, Pi, Ce, Pe, Fstar_n, Fint_n);
   else
     llf(sys, g, d, sgn, Ci, Pi, Ce, Pe, Fstar_n, Fint_n);
+}
+
+int ora_roe(double g, int d, double sgn, const double *ui, const double *pi_, const double *ue, const double *pe,
+            double *fstar_n) {
+  cons_t Ci, Ce; prim_t Pi, Pe; double fin[9];
+  for (int v = 0; v < 5; ++v) { Ci.u[v] = ui[v]; Ce.u[v] = ue[v]; }
+  Pi.rho = pi_[0]; Pi.v[0] = pi_[1]; Pi.v[1] = pi_[2]; Pi.v[2] = pi_[3]; Pi.p = pi_[4];
+  Pe.rho = pe[0]; Pe.v[0] = pe[1]; Pe.v[1] = pe[2]; Pe.v[2] = pe[3]; Pe.p = pe[4];
+  roe(g, d, sgn, &Ci, &Pi, &Ce, &Pe, fstar_n, fin);
+  return ORA_OK;
 }
 
 int ora_hll(int sys, double g, int d, double sgn, const double *ui, const double *pi_, const double *ue,
@@ -615,7 +676,7 @@ typedef struct {
   int32_t sys;
   int32_t nx, ny, nz;
   int32_t deg[3];
-  int32_t flux; /* numerical flux: 0 local Lax-Friedrichs (eq. LLF), 1 HLL (eq. HLL) */
+  int32_t flux; /* numerical flux: 0 local Lax-Friedrichs (eq. LLF), 1 HLL (eq. HLL), 2 Roe (eq. Roe; NE) */
   double gamma, kappa;
   double lo[3], hi[3];
   /* per direction: 0 periodic; 1 both box faces take a fixed exterior state
@@ -642,6 +703,7 @@ typedef struct {
 static int make_geom(const ora_mesh *m, geom_t *G) {
   if (m->nx < 1 || m->ny < 1 || m->nz < 1) return ORA_EINVAL;
   if (m->eos < 0 || m->eos > 1 || (m->eos == 1 && m->sys != 0)) return ORA_EINVAL;
+  if (m->flux < 0 || m->flux > 2 || (m->flux == 2 && (m->sys != 0 || m->eos != 0))) return ORA_EINVAL;
   for (int d = 0; d < 3; ++d) {
     if (m->bc[d] < 0 || m->bc[d] > 2) return ORA_EINVAL;
     if (m->bc[d] == 2 && m->sys != 0) return ORA_EINVAL;
