@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgmi.so")
-SOURCES = ["api.hip", "rhs.hip", "rhs_hll.hip", "rhs_limited.hip", "mixed.hip", "limiter.hip", "boundary.hip", "timestep.hip", "pointwise.hip", "mlp.hip"]
+SOURCES = ["api.hip", "rhs.hip", "rhs_hll.hip", "rhs_roe.hip", "rhs_limited.hip", "mixed.hip", "limiter.hip", "boundary.hip", "timestep.hip", "pointwise.hip", "mlp.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

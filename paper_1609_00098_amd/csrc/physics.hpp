@@ -289,6 +289,43 @@ DG_HD void wave_bounds(int d, const double *u, const Prim P, double g, double &l
   lp = (a + b) * r;
 }
 
+// Roe dissipation for the Newtonian ideal gas (eq. Roe): D = sum_i |lambda_i|
+// alpha_i e_i of the flux Jacobian along the outward normal n = sgn e_d at
+// the Roe-averaged state (eq. RoeAverages, h the total specific enthalpy
+// (E + p)/rho), for the jump U_R - U_L from the interior state L to the
+// exterior state R; F*.n = (F_L + F_R).n / 2 - D / 2.  Waves along n:
+// v_n - a, v_n (entropy and two shears), v_n + a, a^2 = (gamma-1)(h - |v|^2/2).
+template <int D_>
+DG_HD void roe_dissipation(double sgn, const double *uL, const Prim &PL, const double *uR, const Prim &PR, double g,
+                           double *D) {
+  constexpr int T1 = (D_ + 1) % 3, T2 = (D_ + 2) % 3;
+  const double sl = sqrt(PL.rho), sr = sqrt(PR.rho);
+  const double iw = 1.0 / (sl + sr);
+  const double hl = (uL[4] + PL.p) / PL.rho, hr = (uR[4] + PR.p) / PR.rho;
+  const double vd = (sl * PL.v[D_] + sr * PR.v[D_]) * iw;
+  const double w1 = (sl * PL.v[T1] + sr * PR.v[T1]) * iw;
+  const double w2 = (sl * PL.v[T2] + sr * PR.v[T2]) * iw;
+  const double hh = (sl * hl + sr * hr) * iw;
+  const double q2 = vd * vd + w1 * w1 + w2 * w2;
+  const double a2 = (g - 1.0) * (hh - 0.5 * q2), a = sqrt(a2);
+  const double un = sgn * vd;
+  const double dr = uR[0] - uL[0];
+  const double dmn = sgn * (uR[1 + D_] - uL[1 + D_]);
+  const double dm1 = uR[1 + T1] - uL[1 + T1], dm2 = uR[1 + T2] - uL[1 + T2];
+  const double al3 = dm1 - w1 * dr, al4 = dm2 - w2 * dr;
+  const double dEp = (uR[4] - uL[4]) - al3 * w1 - al4 * w2;
+  const double al2 = (g - 1.0) / a2 * (dr * (hh - un * un) + un * dmn - dEp);
+  const double al1 = (dr * (un + a) - dmn - a * al2) / (2.0 * a);
+  const double al5 = dr - (al1 + al2);
+  const double l1 = fabs(un - a) * al1, l2 = fabs(un), l5 = fabs(un + a) * al5;
+  const double s = l1 + l2 * al2 + l5;
+  D[0] = s;
+  D[1 + D_] = sgn * (l1 * (un - a) + l2 * al2 * un + l5 * (un + a));
+  D[1 + T1] = s * w1 + l2 * al3;
+  D[1 + T2] = s * w2 + l2 * al4;
+  D[4] = l1 * (hh - un * a) + l2 * (al2 * 0.5 * q2 + al3 * w1 + al4 * w2) + l5 * (hh + un * a);
+}
+
 // ---------------------------------------------------------------- recovery
 // 1/x for a Newton step, where full accuracy is not needed: the hardware
 // reciprocal refined by one Newton-Raphson step on the device.

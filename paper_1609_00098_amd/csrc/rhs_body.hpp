@@ -12,9 +12,10 @@
 //      the exterior state (the coincident node of the periodic neighbour,
 //      from global memory), forms its flux and speed, and turns the slot into
 //      the difference F*.n - F.n of the numerical flux: local Lax-Friedrichs
-//      (eq. LLF; the interior parks its largest speed) or HLL (eq. HLL; the
+//      (eq. LLF; the interior parks its largest speed), HLL (eq. HLL; the
 //      interior parks its largest and smallest characteristic speed along
-//      the outward normal).
+//      the outward normal) or, for the Newtonian ideal gas, Roe (eq. Roe;
+//      from the interior state kept in LDS and the exterior one).
 //   3. Each volume thread adds -(2/dx_d)(1/w_end)(F*.n - F.n) for every face
 //      it lies on (edge and corner nodes receive two or three terms).
 //   4. RHS mode writes dU/dt; stage mode forms the Shu-Osher combination
@@ -255,6 +256,16 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     const double *own = sown + fle * NV * NPE + ai;
     double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
     const double hs = side ? 0.5 : -0.5;
+    if constexpr (FLUX == kRoe && SYS == kNE) {
+      double ui[5], D[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) ui[v] = own[v * NPE];
+      const Prim Pi = prims_at_pressure<kNE>(ui, A.gamma, 0.0);
+      roe_dissipation<d>(side ? 1.0 : -1.0, ui, Pi, ue, Pe, A.gamma, D);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) slot[v * 6 * NF] = hs * (Fe[v] - slot[v * 6 * NF]) - 0.5 * D[v];
+      return;
+    }
     if constexpr (FLUX == kHLL) {
       // F*.n - F_int.n = c [n_d (F_ext - F_int) - s+ (U_ext - U_int)] with
       // c = -s- / (s+ - s-), the two bounds clipped by zero

@@ -1,0 +1,13 @@
+// Uniform-mesh element kernels with the Roe flux (eq. Roe) for the Newtonian
+// ideal gas, in a translation unit of their own so that they compile in
+// parallel with the others.
+#include "rhs_body.hpp"
+
+namespace dgmi {
+
+hipError_t launch_rhs_roe(int sys, int N, int stage, const RhsArgs &a, hipStream_t s) {
+  if (sys != kNE) return hipErrorInvalidValue;
+  return launch_uniform<kNE, kRoe>(N, stage, a, s);
+}
+
+}  // namespace dgmi
