@@ -58,7 +58,7 @@ def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), k
     """Box of nelem=(nx,ny,nz) affine elements, periodic unless ``bc`` says
     otherwise.  degree is an int or a per-direction triple; a 0 entry
     collapses that direction.  flux: "llf" (eq. LLF), "hll" (eq. HLL) or, for the
-    Newtonian ideal gas, "roe" (eq. Roe).
+    Newtonian ideal gas, "roe" (eq. Roe) or "marquina".
     bc: {d: (state_lo, state_hi)} gives direction d fixed exterior states on
     its two box faces, each state a primitive 5-vector (rho, v, p), or for
     SRMHD a 9-vector (rho, v, p, B, Phi); {d: "vortex"} makes the exterior
@@ -75,7 +75,7 @@ def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), k
     m.sys = system
     m.nx, m.ny, m.nz = nelem
     m.deg[:] = list(degree)
-    m.flux = {"llf": 0, "hll": 1, "roe": 2}[flux]
+    m.flux = {"llf": 0, "hll": 1, "roe": 2, "marquina": 3}[flux]
     m.limiter = LIMITERS[limiter]
     m.lim_M = M
     m.time = time
@@ -149,6 +149,7 @@ def _load():
         "ora_isentropic_vortex": (ctypes.c_int, [ctypes.c_double, D, I64, D, ctypes.c_double, D]),
         "ora_max_char_speed": (ctypes.c_double, [MP, D]),
         "ora_roe": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_double, D, D, D, D, D]),
+        "ora_marquina": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_double, D, D, D, D, D]),
         "ora_min_node_spacing": (ctypes.c_double, [MP]),
         "ora_stable_dt": (ctypes.c_double, [MP, D, ctypes.c_double]),
         "ora_evolve_ab3": (I64, [MP, D, ctypes.c_double, I64]),
@@ -329,6 +330,12 @@ def rhs_weak(m, U):
 def roe(gamma, d, sgn, ui, pi, ue, pe):
     out = np.zeros(5)
     _load().ora_roe(gamma, d, sgn, _p(_c(ui)), _p(_c(pi)), _p(_c(ue)), _p(_c(pe)), _p(out))
+    return out
+
+
+def marquina(gamma, d, sgn, ui, pi, ue, pe):
+    out = np.zeros(5)
+    _load().ora_marquina(gamma, d, sgn, _p(_c(ui)), _p(_c(pi)), _p(_c(ue)), _p(_c(pe)), _p(out))
     return out
 
 

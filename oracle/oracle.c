@@ -625,6 +625,87 @@ static void roe(double g, int d, double sgn, const cons_t *Ci, const prim_t *Pi,
   }
 }
 
+/* Eigen-structure of the Newtonian ideal-gas flux Jacobian along n at one
+ * state, in the components (rho, rho v_n, rho v_t1, rho v_t2, E):
+ * eigenvalues v_n - c, v_n (three), v_n + c; right eigenvectors K[i][.]
+ *   K1 = (1, v_n - c, v_t1, v_t2, H - v_n c),  K2 = (1, v_n, v_t1, v_t2, q^2/2),
+ *   K3 = (0, 0, 1, 0, v_t1),  K4 = (0, 0, 0, 1, v_t2),
+ *   K5 = (1, v_n + c, v_t1, v_t2, H + v_n c),
+ * H = (E + p)/rho, q^2 = |v|^2; left eigenvectors Lt[i][.] the rows of
+ * K^{-1} (with b1 = (gamma-1)/c^2, b2 = b1 q^2/2):
+ *   L1 = ((b2 + v_n/c)/2, -(b1 v_n + 1/c)/2, -b1 v_t1/2, -b1 v_t2/2, b1/2),
+ *   L2 = (1 - b2, b1 v_n, b1 v_t1, b1 v_t2, -b1),
+ *   L3 = (-v_t1, 0, 1, 0, 0),  L4 = (-v_t2, 0, 0, 1, 0),
+ *   L5 = ((b2 - v_n/c)/2, -(b1 v_n - 1/c)/2, -b1 v_t1/2, -b1 v_t2/2, b1/2).   */
+static void euler_eigen(double g, const cons_t *C, const prim_t *P, int d, double sgn, double lam[5], double K[5][5],
+                        double Lt[5][5]) {
+  int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  double un = sgn * P->v[d], w1 = P->v[t1], w2 = P->v[t2];
+  double q2 = un * un + w1 * w1 + w2 * w2;
+  double c = sqrt(g * P->p / P->rho), H = (C->u[4] + P->p) / P->rho;
+  double b1 = (g - 1.0) / (c * c), b2 = 0.5 * q2 * b1;
+  double Kv[5][5] = {{1, un - c, w1, w2, H - un * c}, {1, un, w1, w2, 0.5 * q2}, {0, 0, 1, 0, w1}, {0, 0, 0, 1, w2},
+                     {1, un + c, w1, w2, H + un * c}};
+  double Lv[5][5] = {{0.5 * (b2 + un / c), -0.5 * (b1 * un + 1.0 / c), -0.5 * b1 * w1, -0.5 * b1 * w2, 0.5 * b1},
+                     {1.0 - b2, b1 * un, b1 * w1, b1 * w2, -b1},
+                     {-w1, 0, 1, 0, 0},
+                     {-w2, 0, 0, 1, 0},
+                     {0.5 * (b2 - un / c), -0.5 * (b1 * un - 1.0 / c), -0.5 * b1 * w1, -0.5 * b1 * w2, 0.5 * b1}};
+  double l[5] = {un - c, un, un, un, un + c};
+  for (int i = 0; i < 5; ++i) {
+    lam[i] = l[i];
+    for (int k = 0; k < 5; ++k) { K[i][k] = Kv[i][k]; Lt[i][k] = Lv[i][k]; }
+  }
+}
+
+/* Rotated components (rho, rho v_n, rho v_t1, rho v_t2, E) of a 5-vector
+ * given in Cartesian components, and back. */
+static void to_normal(const double *x, int d, double sgn, double *y) {
+  y[0] = x[0]; y[1] = sgn * x[1 + d]; y[2] = x[1 + (d + 1) % 3]; y[3] = x[1 + (d + 2) % 3]; y[4] = x[4];
+}
+static void from_normal(const double *y, int d, double sgn, double *x) {
+  x[0] = y[0]; x[1 + d] = sgn * y[1]; x[1 + (d + 1) % 3] = y[2]; x[1 + (d + 2) % 3] = y[3]; x[4] = y[4];
+}
+
+/* Marquina flux (Marquina subsection) for the Newtonian ideal gas, interior
+ * state L, exterior R, outward normal n = sgn e_d: with the eigen-structure
+ * of each side, omega_i = E_i . U and phi_i = E_i . F(U).n; per field i,
+ * upwind when lambda_i has one sign on both sides (phi+ = phi_i^L if both
+ * are >= 0, phi- = phi_i^R if both are <= 0), else the LLF split with
+ * alpha_i = max(|lambda_i^L|, |lambda_i^R|); F*.n = sum_i phi+_i e_i^L +
+ * phi-_i e_i^R.                                                            */
+static void marquina(double g, int d, double sgn, const cons_t *Ci, const prim_t *Pi, const cons_t *Ce,
+                     const prim_t *Pe, double *Fstar_n, double *Fint_n) {
+  double fi[9], fe[9], fin[5], fen[5], ui[5], ue[5], Fi[5], Fe[5];
+  flux(0, g, d, Ci, Pi, fi);
+  flux(0, g, d, Ce, Pe, fe);
+  for (int c = 0; c < 5; ++c) { fin[c] = sgn * fi[c]; fen[c] = sgn * fe[c]; }
+  to_normal(Ci->u, d, sgn, ui); to_normal(Ce->u, d, sgn, ue);
+  to_normal(fin, d, sgn, Fi); to_normal(fen, d, sgn, Fe);
+  double lL[5], KL[5][5], LL[5][5], lR[5], KR[5][5], LR[5][5];
+  euler_eigen(g, Ci, Pi, d, sgn, lL, KL, LL);
+  euler_eigen(g, Ce, Pe, d, sgn, lR, KR, LR);
+  double out[5] = {0, 0, 0, 0, 0};
+  for (int i = 0; i < 5; ++i) {
+    double wL = 0, wR = 0, pL = 0, pR = 0;
+    for (int k = 0; k < 5; ++k) {
+      wL += LL[i][k] * ui[k]; wR += LR[i][k] * ue[k];
+      pL += LL[i][k] * Fi[k]; pR += LR[i][k] * Fe[k];
+    }
+    double pp, pm;
+    if (lL[i] >= 0.0 && lR[i] >= 0.0) { pp = pL; pm = 0.0; }
+    else if (lL[i] <= 0.0 && lR[i] <= 0.0) { pp = 0.0; pm = pR; }
+    else {
+      double a = fmax(fabs(lL[i]), fabs(lR[i]));
+      pp = 0.5 * (pL + a * wL);
+      pm = 0.5 * (pR - a * wR);
+    }
+    for (int k = 0; k < 5; ++k) out[k] += pp * KL[i][k] + pm * KR[i][k];
+  }
+  from_normal(out, d, sgn, Fstar_n);
+  for (int c = 0; c < 5; ++c) Fint_n[c] = fin[c];
+}
+
 /* The numerical flux selected by the mesh. */
 static void numflux(int kind, int sys, double g, int d, double sgn, const cons_t *Ci, const prim_t *Pi,
                     const cons_t *Ce, const prim_t *Pe, double *Fstar_n, double *Fint_n) {
@@ -632,8 +713,20 @@ static void numflux(int kind, int sys, double g, int d, double sgn, const cons_t
     hll(sys, g, d, sgn, Ci, Pi, Ce, Pe, Fstar_n, Fint_n);
   else if (kind == 2)
     roe(g, d, sgn, Ci, Pi, Ce, Pe, Fstar_n, Fint_n);
+  else if (kind == 3)
+    marquina(g, d, sgn, Ci, Pi, Ce, Pe, Fstar_n, Fint_n);
   else
     llf(sys, g, d, sgn, Ci, Pi, Ce, Pe, Fstar_n, Fint_n);
+}
+
+int ora_marquina(double g, int d, double sgn, const double *ui, const double *pi_, const double *ue, const double *pe,
+                 double *fstar_n) {
+  cons_t Ci, Ce; prim_t Pi, Pe; double fin[9];
+  for (int v = 0; v < 5; ++v) { Ci.u[v] = ui[v]; Ce.u[v] = ue[v]; }
+  Pi.rho = pi_[0]; Pi.v[0] = pi_[1]; Pi.v[1] = pi_[2]; Pi.v[2] = pi_[3]; Pi.p = pi_[4];
+  Pe.rho = pe[0]; Pe.v[0] = pe[1]; Pe.v[1] = pe[2]; Pe.v[2] = pe[3]; Pe.p = pe[4];
+  marquina(g, d, sgn, &Ci, &Pi, &Ce, &Pe, fstar_n, fin);
+  return ORA_OK;
 }
 
 int ora_roe(double g, int d, double sgn, const double *ui, const double *pi_, const double *ue, const double *pe,
@@ -676,7 +769,8 @@ typedef struct {
   int32_t sys;
   int32_t nx, ny, nz;
   int32_t deg[3];
-  int32_t flux; /* numerical flux: 0 local Lax-Friedrichs (eq. LLF), 1 HLL (eq. HLL), 2 Roe (eq. Roe; NE) */
+  int32_t flux; /* numerical flux: 0 local Lax-Friedrichs (eq. LLF), 1 HLL (eq. HLL), 2 Roe (eq. Roe; NE),
+                 3 Marquina (NE) */
   double gamma, kappa;
   double lo[3], hi[3];
   /* per direction: 0 periodic; 1 both box faces take a fixed exterior state
@@ -703,7 +797,7 @@ typedef struct {
 static int make_geom(const ora_mesh *m, geom_t *G) {
   if (m->nx < 1 || m->ny < 1 || m->nz < 1) return ORA_EINVAL;
   if (m->eos < 0 || m->eos > 1 || (m->eos == 1 && m->sys != 0)) return ORA_EINVAL;
-  if (m->flux < 0 || m->flux > 2 || (m->flux == 2 && (m->sys != 0 || m->eos != 0))) return ORA_EINVAL;
+  if (m->flux < 0 || m->flux > 3 || (m->flux >= 2 && (m->sys != 0 || m->eos != 0))) return ORA_EINVAL;
   for (int d = 0; d < 3; ++d) {
     if (m->bc[d] < 0 || m->bc[d] > 2) return ORA_EINVAL;
     if (m->bc[d] == 2 && m->sys != 0) return ORA_EINVAL;

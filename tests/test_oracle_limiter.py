@@ -231,13 +231,14 @@ def sod_error(ora, nx, flux, limiter="muscl", N=1, dt_factor=0.05):
     return ora.l1_error(m, cons(riemann.sample(SOD_L, SOD_R, g, x, T)), U1), m, U0, T / nst
 
 
-SOD_ROWS = {"hll": ("hll", 1), "llf": ("llf", 1), "roe": ("roe", 1), "roe_NC3": ("roe", 2), "roe_NC4": ("roe", 3)}
+SOD_ROWS = {"hll": ("hll", 1), "llf": ("llf", 1), "roe": ("roe", 1), "mar": ("marquina", 1), "roe_NC3": ("roe", 2),
+            "roe_NC4": ("roe", 3)}
 
 
 @pytest.mark.parametrize("row", list(SOD_ROWS))
 def test_ne_sod_table(ora, row):
-    """tab:NE_sod, rows HLL-MinMod-2, LLF-MinMod-2, Roe-MinMod-2 (degree 1),
-    Roe-MinModN-3 and Roe-MinModN-4 (degrees 2 and 3, generalized
+    """tab:NE_sod, rows HLL-MinMod-2, LLF-MinMod-2, Roe-MinMod-2, Mar-MinMod-2
+    (degree 1), Roe-MinModN-3 and Roe-MinModN-4 (degrees 2 and 3, generalized
     troubled-cell test): each error within 6% of the printed two-digit value
     (n_x = 20, 40, 80; up to 640 with DGMI_SLOW=1).  Reproduced with beta = 1
     in the slope estimates (beta = 2 gives errors 15-30% below the printed
@@ -249,6 +250,39 @@ def test_ne_sod_table(ora, row):
     for nx, ref in zip(cols, gold["rows"][row]):
         err = sod_error(ora, nx, flux, N=N)[0]
         assert abs(err - ref) <= 0.06 * ref, (nx, err, ref)
+
+
+def test_marquina_flux_properties(ora):
+    """Marquina: with each side's left eigenvectors the rows of the inverse
+    of its right ones, equal states give F(U).n (sum_i (E_i . F) e_i = F);
+    every wave moving out of (into) the element gives the interior (exterior)
+    flux; the flux is single valued; a subsonic jump differs from Roe's."""
+    g = 1.4
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        d = trial % 3
+        pl = np.array([rng.uniform(0.5, 2), *rng.uniform(-0.3, 0.3, 3), rng.uniform(0.5, 2)])
+        pr = np.array([rng.uniform(0.5, 2), *rng.uniform(-0.3, 0.3, 3), rng.uniform(0.5, 2)])
+        ul = ora.prim2cons(NE, g, pl[:, None])[:, 0]
+        ur = ora.prim2cons(NE, g, pr[:, None])[:, 0]
+        fl = ora.flux(NE, g, d, ul[:, None], pl[:, None])[:, 0]
+        for sgn in (1.0, -1.0):
+            assert np.allclose(ora.marquina(g, d, sgn, ul, pl, ul, pl), sgn * fl, rtol=1e-13, atol=1e-13)
+        a = ora.marquina(g, d, 1.0, ul, pl, ur, pr)
+        b = ora.marquina(g, d, -1.0, ur, pr, ul, pl)
+        assert np.allclose(a, -b, rtol=1e-13, atol=1e-13)
+        for p_ in (pl, pr):
+            p_[1 + d] = 4.0
+        ul = ora.prim2cons(NE, g, pl[:, None])[:, 0]
+        ur = ora.prim2cons(NE, g, pr[:, None])[:, 0]
+        fl = ora.flux(NE, g, d, ul[:, None], pl[:, None])[:, 0]
+        fr = ora.flux(NE, g, d, ur[:, None], pr[:, None])[:, 0]
+        assert np.allclose(ora.marquina(g, d, 1.0, ul, pl, ur, pr), fl, rtol=1e-12, atol=1e-12)
+        assert np.allclose(ora.marquina(g, d, -1.0, ul, pl, ur, pr), -fr, rtol=1e-12, atol=1e-12)
+    pl = np.array([1.0, 0.1, 0.0, 0.0, 1.0])
+    pr = np.array([0.5, 0.0, 0.2, 0.0, 0.4])
+    ul, ur = ora.prim2cons(NE, g, pl[:, None])[:, 0], ora.prim2cons(NE, g, pr[:, None])[:, 0]
+    assert np.abs(ora.marquina(g, 0, 1.0, ul, pl, ur, pr) - ora.roe(g, 0, 1.0, ul, pl, ur, pr)).max() > 1e-4
 
 
 def test_roe_flux_properties(ora):
