@@ -66,9 +66,10 @@ enum {
                                      (eq. LLF); uniform degrees only, a mixed-degree mesh with it
                                      returns DGMI_EUNSUPPORTED */
 #define DGMI_FLAG_ROE 64          /* numerical flux Roe (eq. Roe, with the Roe averages of eq. RoeAverages)
-                                     for the Newtonian ideal gas on uniform degrees; not with
-                                     DGMI_FLAG_HLL (DGMI_EINVAL) nor another system, equation of
-                                     state or mixed degrees (DGMI_EUNSUPPORTED) */
+                                     for the Newtonian ideal gas on uniform degrees; not with another
+                                     flux flag (DGMI_EINVAL) nor another system, equation of state or
+                                     mixed degrees (DGMI_EUNSUPPORTED) */
+#define DGMI_FLAG_MARQUINA 128    /* numerical flux Marquina (Marquina subsection), same conditions */
 #define DGMI_FLAG_POLYTROPIC 32   /* Newtonian Euler with the polytropic equation of state p = rho^gamma
                                      (K = 1; the adiabatic one of the isentropic vortex test) instead of
                                      the ideal gas; uniform degrees only.  The energy is still evolved;

@@ -227,7 +227,10 @@ constexpr int kMixedLanes = 4;
 
 // Periodic neighbour of element e across face f (-x, +x, -y, +y, -z, +z).
 static int flux_of(const dgmi_ctx *c) {
-  return (c->flags & DGMI_FLAG_HLL) ? dgmi::kHLL : ((c->flags & DGMI_FLAG_ROE) ? dgmi::kRoe : dgmi::kLLF);
+  if (c->flags & DGMI_FLAG_HLL) return dgmi::kHLL;
+  if (c->flags & DGMI_FLAG_ROE) return dgmi::kRoe;
+  if (c->flags & DGMI_FLAG_MARQUINA) return dgmi::kMarquina;
+  return dgmi::kLLF;
 }
 
 static int64_t nbr_of(const dgmi_ctx *c, int64_t e, int f) {
@@ -588,11 +591,15 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
     return fail(DGMI_EINVAL, "dgmi_create: degree 0 needs degrees_host");
   if (desc->degree == 0 && (desc->flags & DGMI_FLAG_HLL))
     return fail(DGMI_EUNSUPPORTED, "dgmi_create: the HLL flux is implemented for uniform degrees only");
-  if ((desc->flags & DGMI_FLAG_ROE) && (desc->flags & DGMI_FLAG_HLL))
-    return fail(DGMI_EINVAL, "dgmi_create: choose one numerical flux");
-  if ((desc->flags & DGMI_FLAG_ROE) &&
+  {
+    const int nflux = !!(desc->flags & DGMI_FLAG_HLL) + !!(desc->flags & DGMI_FLAG_ROE) +
+                      !!(desc->flags & DGMI_FLAG_MARQUINA);
+    if (nflux > 1) return fail(DGMI_EINVAL, "dgmi_create: choose one numerical flux");
+  }
+  if ((desc->flags & (DGMI_FLAG_ROE | DGMI_FLAG_MARQUINA)) &&
       (desc->system != 0 || desc->degree == 0 || (desc->flags & DGMI_FLAG_POLYTROPIC)))
-    return fail(DGMI_EUNSUPPORTED, "dgmi_create: the Roe flux is for the Newtonian ideal gas on uniform degrees");
+    return fail(DGMI_EUNSUPPORTED,
+                "dgmi_create: the Roe and Marquina fluxes are for the Newtonian ideal gas on uniform degrees");
   if ((desc->flags & DGMI_FLAG_POLYTROPIC) && (desc->system != 0 || desc->degree == 0))
     return fail(DGMI_EUNSUPPORTED, "dgmi_create: the polytropic equation of state is for Newtonian Euler on uniform "
                                    "degrees");

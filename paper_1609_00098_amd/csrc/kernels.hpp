@@ -50,11 +50,13 @@ struct RhsArgs {
 constexpr int kLLF = 0;  // local Lax-Friedrichs (eq. LLF)
 constexpr int kHLL = 1;  // HLL (eq. HLL)
 constexpr int kRoe = 2;  // Roe (eq. Roe), Newtonian ideal gas only
+constexpr int kMarquina = 3;  // Marquina, Newtonian ideal gas only
 
 // Launch dg RHS (stage == 0) or RK stage (stage == 1) on a uniform mesh.
 hipError_t launch_rhs(int sys, int N, int stage, int flux, const RhsArgs &a, hipStream_t s);
 hipError_t launch_rhs_hll(int sys, int N, int stage, const RhsArgs &a, hipStream_t s);
 hipError_t launch_rhs_roe(int sys, int N, int stage, const RhsArgs &a, hipStream_t s);
+hipError_t launch_rhs_marquina(int sys, int N, int stage, const RhsArgs &a, hipStream_t s);
 // The same kernels over one degree's elements of a mixed-degree mesh, epb
 // elements per workgroup (one of mixed_tile_options).
 hipError_t launch_rhs_mixed(int sys, int N, int epb, int stage, const RhsArgs &a, hipStream_t s);

@@ -326,6 +326,93 @@ DG_HD void roe_dissipation(double sgn, const double *uL, const Prim &PL, const d
   D[4] = l1 * (hh - un * a) + l2 * (al2 * 0.5 * q2 + al3 * w1 + al4 * w2) + l5 * (hh + un * a);
 }
 
+// Marquina flux (Marquina subsection) for the Newtonian ideal gas along the
+// outward normal n = sgn e_d, interior state L, exterior R.  fL, fR: the
+// physical fluxes along +e_d.  Each side's eigen-structure of the flux
+// Jacobian along n, in the components (rho, rho v_n, rho v_t1, rho v_t2, E):
+// speeds v_n - c, v_n, v_n, v_n, v_n + c; right eigenvectors
+// (1, v_n - c, v_t1, v_t2, H - v_n c), (1, v_n, v_t1, v_t2, q^2/2),
+// (0, 0, 1, 0, v_t1), (0, 0, 0, 1, v_t2), (1, v_n + c, v_t1, v_t2, H + v_n c);
+// left eigenvectors the rows of their inverse (b1 = (gamma-1)/c^2,
+// b2 = b1 q^2/2).  Per field: upwind when the speed has one sign on both
+// sides, else the LLF split with the larger of the two speeds; Fn = F*.n.
+struct EulerSide {
+  double un, w1, w2, c, H, b1, b2, q2h;
+  double u[5], f[5];  // state and normal flux, rotated components
+};
+
+template <int D_>
+DG_HD EulerSide euler_side(double sgn, const double *u, const Prim &P, const double *fd, double g) {
+  constexpr int T1 = (D_ + 1) % 3, T2 = (D_ + 2) % 3;
+  EulerSide S;
+  S.un = sgn * P.v[D_];
+  S.w1 = P.v[T1];
+  S.w2 = P.v[T2];
+  S.c = sqrt(g * P.p / P.rho);
+  S.H = (u[4] + P.p) / P.rho;
+  S.b1 = (g - 1.0) / (S.c * S.c);
+  S.q2h = 0.5 * (S.un * S.un + S.w1 * S.w1 + S.w2 * S.w2);
+  S.b2 = S.q2h * S.b1;
+  S.u[0] = u[0]; S.u[1] = sgn * u[1 + D_]; S.u[2] = u[1 + T1]; S.u[3] = u[1 + T2]; S.u[4] = u[4];
+  S.f[0] = sgn * fd[0]; S.f[1] = fd[1 + D_]; S.f[2] = sgn * fd[1 + T1]; S.f[3] = sgn * fd[1 + T2]; S.f[4] = sgn * fd[4];
+  return S;
+}
+
+// left eigenvector i of side S applied to x
+DG_HD double euler_left(const EulerSide &S, int i, const double *x) {
+  const double cross = -S.b1 * (S.w1 * x[2] + S.w2 * x[3]);
+  if (i == 0) return 0.5 * ((S.b2 + S.un / S.c) * x[0] - (S.b1 * S.un + 1.0 / S.c) * x[1] + cross + S.b1 * x[4]);
+  if (i == 1) return (1.0 - S.b2) * x[0] + S.b1 * S.un * x[1] - cross - S.b1 * x[4];
+  if (i == 2) return x[2] - S.w1 * x[0];
+  if (i == 3) return x[3] - S.w2 * x[0];
+  return 0.5 * ((S.b2 - S.un / S.c) * x[0] - (S.b1 * S.un - 1.0 / S.c) * x[1] + cross + S.b1 * x[4]);
+}
+
+// out += a * (right eigenvector i of side S)
+DG_HD void euler_right_add(const EulerSide &S, int i, double a, double *out) {
+  if (i == 2) { out[2] += a; out[4] += a * S.w1; return; }
+  if (i == 3) { out[3] += a; out[4] += a * S.w2; return; }
+  const double s = i == 0 ? -1.0 : (i == 4 ? 1.0 : 0.0);
+  out[0] += a;
+  out[1] += a * (S.un + s * S.c);
+  out[2] += a * S.w1;
+  out[3] += a * S.w2;
+  out[4] += a * (i == 1 ? S.q2h : S.H + s * S.un * S.c);
+}
+
+template <int D_>
+DG_HD void marquina_flux(double sgn, const double *uL, const Prim &PL, const double *fL, const double *uR,
+                         const Prim &PR, const double *fR, double g, double *Fn) {
+  constexpr int T1 = (D_ + 1) % 3, T2 = (D_ + 2) % 3;
+  const EulerSide L = euler_side<D_>(sgn, uL, PL, fL, g), R = euler_side<D_>(sgn, uR, PR, fR, g);
+  double out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const double s = i == 0 ? -1.0 : (i == 4 ? 1.0 : 0.0);
+    const double lL = L.un + s * L.c, lR = R.un + s * R.c;
+    const double pL = euler_left(L, i, L.f), pR = euler_left(R, i, R.f);
+    double pp, pm;
+    if (lL >= 0.0 && lR >= 0.0) {
+      pp = pL;
+      pm = 0.0;
+    } else if (lL <= 0.0 && lR <= 0.0) {
+      pp = 0.0;
+      pm = pR;
+    } else {
+      const double a = fmax(fabs(lL), fabs(lR));
+      pp = 0.5 * (pL + a * euler_left(L, i, L.u));
+      pm = 0.5 * (pR - a * euler_left(R, i, R.u));
+    }
+    euler_right_add(L, i, pp, out);
+    euler_right_add(R, i, pm, out);
+  }
+  Fn[0] = out[0];
+  Fn[1 + D_] = sgn * out[1];
+  Fn[1 + T1] = out[2];
+  Fn[1 + T2] = out[3];
+  Fn[4] = out[4];
+}
+
 // ---------------------------------------------------------------- recovery
 // 1/x for a Newton step, where full accuracy is not needed: the hardware
 // reciprocal refined by one Newton-Raphson step on the device.

@@ -138,6 +138,7 @@ hipError_t launch_rhs_mixed(int sys, int N, int epb, int stage, const RhsArgs &a
 hipError_t launch_rhs(int sys, int N, int stage, int flux, const RhsArgs &a, hipStream_t s) {
   if (flux == kHLL) return launch_rhs_hll(sys, N, stage, a, s);
   if (flux == kRoe) return launch_rhs_roe(sys, N, stage, a, s);
+  if (flux == kMarquina) return launch_rhs_marquina(sys, N, stage, a, s);
   return launch_uniform_flux<kLLF>(sys, N, stage, a, s);
 }
 

@@ -14,8 +14,8 @@
 //      the difference F*.n - F.n of the numerical flux: local Lax-Friedrichs
 //      (eq. LLF; the interior parks its largest speed), HLL (eq. HLL; the
 //      interior parks its largest and smallest characteristic speed along
-//      the outward normal) or, for the Newtonian ideal gas, Roe (eq. Roe;
-//      from the interior state kept in LDS and the exterior one).
+//      the outward normal) or, for the Newtonian ideal gas, Roe (eq. Roe) or
+//      Marquina (from the interior state kept in LDS and the exterior one).
 //   3. Each volume thread adds -(2/dx_d)(1/w_end)(F*.n - F.n) for every face
 //      it lies on (edge and corner nodes receive two or three terms).
 //   4. RHS mode writes dU/dt; stage mode forms the Shu-Osher combination
@@ -256,6 +256,20 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     const double *own = sown + fle * NV * NPE + ai;
     double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
     const double hs = side ? 0.5 : -0.5;
+    if constexpr (FLUX == kMarquina && SYS == kNE) {
+      double ui[5], fi[5], Fs[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        ui[v] = own[v * NPE];
+        fi[v] = slot[v * 6 * NF];
+      }
+      const Prim Pi = prims_at_pressure<kNE>(ui, A.gamma, 0.0);
+      const double sg = side ? 1.0 : -1.0;
+      marquina_flux<d>(sg, ui, Pi, fi, ue, Pe, Fe, A.gamma, Fs);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) slot[v * 6 * NF] = Fs[v] - sg * fi[v];
+      return;
+    }
     if constexpr (FLUX == kRoe && SYS == kNE) {
       double ui[5], D[5];
 #pragma unroll

@@ -33,6 +33,7 @@ static hipError_t stage_moments_sys(int sys, int N, const RhsArgs &a, hipStream_
 
 hipError_t launch_rhs_stage_moments(int sys, int N, int flux, const RhsArgs &a, hipStream_t s) {
   if (flux == kRoe) return sys == kNE ? stage_moments_n<kNE, kRoe>(N, a, s) : hipErrorInvalidValue;
+  if (flux == kMarquina) return sys == kNE ? stage_moments_n<kNE, kMarquina>(N, a, s) : hipErrorInvalidValue;
   return flux == kHLL ? stage_moments_sys<kHLL>(sys, N, a, s) : stage_moments_sys<kLLF>(sys, N, a, s);
 }
 

@@ -170,7 +170,7 @@ def test_step_with_limiter_parity(ora, dg, system, N, lim, bc_dirs):
 SOD_L, SOD_R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
 
 
-SOD_FLAGS = {"llf": 0, "hll": "FLAG_HLL", "roe": "FLAG_ROE"}
+SOD_FLAGS = {"llf": 0, "hll": "FLAG_HLL", "roe": "FLAG_ROE", "marquina": "FLAG_MARQUINA"}
 
 
 def _sod_gpu(dg, nx, flux, N=1):
@@ -194,12 +194,13 @@ def _sod_gpu(dg, nx, flux, N=1):
     return G, x, to_host(U), T / nst, nst
 
 
-SOD_ROWS = {"hll": ("hll", 1), "llf": ("llf", 1), "roe": ("roe", 1), "roe_NC3": ("roe", 2), "roe_NC4": ("roe", 3)}
+SOD_ROWS = {"hll": ("hll", 1), "llf": ("llf", 1), "roe": ("roe", 1), "mar": ("marquina", 1), "roe_NC3": ("roe", 2),
+            "roe_NC4": ("roe", 3)}
 
 
 @pytest.mark.parametrize("row", list(SOD_ROWS))
 def test_sod_table_on_gpu(ora, dg, row):
-    """tab:NE_sod rows HLL-MinMod-2, LLF-MinMod-2, Roe-MinMod-2, Roe-MinModN-3
+    """tab:NE_sod rows HLL-MinMod-2, LLF-MinMod-2, Roe-MinMod-2, Mar-MinMod-2, Roe-MinModN-3
     and Roe-MinModN-4 (n_x = 20, 40, 80; within 6%) from GPU steps with the
     fixed-state boundary and the limiter; at n_x = 20 the whole run matches
     the oracle's run on the same mesh."""

@@ -1,8 +1,8 @@
-"""GPU parity of the Roe flux (eq. Roe, Newtonian ideal gas) against the
-oracle: dg_rhs at every degree 1..7 within 1e-12 norm-wise per variable on
-perturbed states (the two sides of every face differ), RK3 steps within the
-step bar, and the flag rules.  The Sod rows with the Roe flux run in
-test_gpu_limiter.py.
+"""GPU parity of the Roe (eq. Roe) and Marquina fluxes (Newtonian ideal
+gas) against the oracle: dg_rhs at every degree 1..7 within 1e-12
+norm-wise per variable on perturbed states (the two sides of every face
+differ), RK3 steps within the step bar, and the flag rules.  The Sod rows
+with these fluxes run in test_gpu_limiter.py.
 """
 import numpy as np
 import pytest
@@ -33,11 +33,15 @@ def _state(ora, m, seed):
     return ora.prim2cons(NE, m.gamma, prim), prim
 
 
+FLAGS = {"roe": "FLAG_ROE", "marquina": "FLAG_MARQUINA"}
+
+
+@pytest.mark.parametrize("flux", ["roe", "marquina"])
 @pytest.mark.parametrize("N", list(range(1, 8)))
-def test_roe_rhs_parity(ora, dg, N):
+def test_roe_rhs_parity(ora, dg, N, flux):
     nel = (3, 2, 2) if N <= 4 else (2, 2, 1)
-    m = ora.mesh(NE, nel, N, 1.4, lo=LO, hi=HI, flux="roe")
-    G = dg.Mesh(NE, nel, N, 1.4, lo=LO, hi=HI, flags=dg.FLAG_ROE)
+    m = ora.mesh(NE, nel, N, 1.4, lo=LO, hi=HI, flux=flux)
+    G = dg.Mesh(NE, nel, N, 1.4, lo=LO, hi=HI, flags=getattr(dg, FLAGS[flux]))
     U, prim = _state(ora, m, seed=30 + N)
     dUo, _, nf = ora.rhs(m, U)
     assert nf == 0
@@ -49,10 +53,11 @@ def test_roe_rhs_parity(ora, dg, N):
     assert np.abs(dUl - dUo).max() > 1e-6 * np.abs(dUo).max()
 
 
+@pytest.mark.parametrize("flux", ["roe", "marquina"])
 @pytest.mark.parametrize("N", [2, 4])
-def test_roe_step_parity(ora, dg, N):
-    m = ora.mesh(NE, (3, 2, 2), N, 1.4, lo=LO, hi=HI, flux="roe")
-    G = dg.Mesh(NE, (3, 2, 2), N, 1.4, lo=LO, hi=HI, flags=dg.FLAG_ROE)
+def test_roe_step_parity(ora, dg, N, flux):
+    m = ora.mesh(NE, (3, 2, 2), N, 1.4, lo=LO, hi=HI, flux=flux)
+    G = dg.Mesh(NE, (3, 2, 2), N, 1.4, lo=LO, hi=HI, flags=getattr(dg, FLAGS[flux]))
     U, prim = _state(ora, m, seed=40 + N)
     Lo, Po, _ = ora.rhs(m, U)
     dt = 1e-3 / max(np.abs(Lo[0] / U[0]).max(), np.abs(Lo[4] / U[4]).max())
@@ -72,3 +77,7 @@ def test_roe_flag_rules(dg):
         dg.Mesh(NE, (2, 2, 2), 2, 1.4, flags=dg.FLAG_ROE | dg.FLAG_HLL)
     with pytest.raises(dg.DgmiError):
         dg.Mesh(NE, (2, 2, 2), 2, 1.4, flags=dg.FLAG_ROE | dg.FLAG_POLYTROPIC)
+    with pytest.raises(dg.DgmiError):
+        dg.Mesh(NE, (2, 2, 2), 2, 1.4, flags=dg.FLAG_ROE | dg.FLAG_MARQUINA)
+    with pytest.raises(dg.DgmiError):
+        dg.Mesh(SR, (2, 2, 2), 2, 4.0 / 3.0, flags=dg.FLAG_MARQUINA)
