@@ -47,14 +47,15 @@ class Mesh(ctypes.Structure):
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("bc", ctypes.c_int32 * 3), ("limiter", ctypes.c_int32), ("lim_M", ctypes.c_double),
                 ("bc_u", (ctypes.c_double * 9) * 6), ("bc_p", (ctypes.c_double * 5) * 6),
-                ("time", ctypes.c_double), ("vortex", ctypes.c_double * 6), ("eos", ctypes.c_int32)]
+                ("time", ctypes.c_double), ("vortex", ctypes.c_double * 6), ("eos", ctypes.c_int32),
+                ("fix_D", ctypes.c_double), ("fix_tau", ctypes.c_double)]
 
 
 LIMITERS = {"none": 0, "minmod": 1, "muscl": 2}
 
 
 def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), kappa=0.0, flux="llf",
-         bc=None, limiter="none", M=0.0, vortex=None, time=0.0, eos="ideal"):
+         bc=None, limiter="none", M=0.0, vortex=None, time=0.0, eos="ideal", fix=None):
     """Box of nelem=(nx,ny,nz) affine elements, periodic unless ``bc`` says
     otherwise.  degree is an int or a per-direction triple; a 0 entry
     collapses that direction.  flux: "llf" (eq. LLF), "hll" (eq. HLL) or, for the
@@ -68,7 +69,9 @@ def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), k
     constant M, applied after every RK stage.  time: the time of the state
     rhs() is applied to, and of the first step of step() / evolve().
     eos: "ideal" (p = (gamma-1) rho eps) or, for NE, "polytropic"
-    (p = rho^gamma)."""
+    (p = rho^gamma).  fix: (D_min, tau_min) switches on the atmosphere floors
+    and conserved-variable fixing of limited elements (SR, SRMHD; see
+    fix_cons)."""
     if isinstance(degree, int):
         degree = (degree, degree, degree)
     m = Mesh()
@@ -80,6 +83,8 @@ def mesh(system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), k
     m.lim_M = M
     m.time = time
     m.eos = {"ideal": 0, "polytropic": 1}[eos]
+    if fix is not None:
+        m.fix_D, m.fix_tau = fix
     if vortex is not None:
         m.vortex[:] = list(vortex)
     for d, states in (bc or {}).items():
@@ -153,6 +158,8 @@ def _load():
         "ora_min_node_spacing": (ctypes.c_double, [MP]),
         "ora_stable_dt": (ctypes.c_double, [MP, D, ctypes.c_double]),
         "ora_evolve_ab3": (I64, [MP, D, ctypes.c_double, I64]),
+        "ora_limit_counts": (ctypes.c_int, [MP, D, ctypes.POINTER(I64)]),
+        "ora_fix_cons": (I64, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, I64, D]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -360,6 +367,27 @@ def limit(m, U):
     n = _load().ora_limit(ctypes.byref(m), _p(U))
     if n < 0:
         raise ValueError("bad mesh")
+    return U, int(n)
+
+
+def limit_counts(m, U):
+    """Returns (limited copy of U, limited element components, nodes changed
+    by the conserved-variable fixing)."""
+    U = _c(U).copy()
+    counts = np.zeros(2, dtype=np.int64)
+    if _load().ora_limit_counts(ctypes.byref(m), _p(U), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))) != 0:
+        raise ValueError("bad mesh")
+    return U, int(counts[0]), int(counts[1])
+
+
+def fix_cons(system, gamma, U, D_min, tau_min):
+    """Atmosphere floors and conserved-variable fixing (section on unphysical
+    conservative variables) of every column of U ([nv, n]); returns (fixed
+    copy, number of columns changed)."""
+    U = _c(U).copy()
+    n = _load().ora_fix_cons(system, gamma, D_min, tau_min, U.shape[1], _p(U))
+    if n < 0:
+        raise ValueError("bad arguments")
     return U, int(n)
 
 

@@ -290,6 +290,82 @@ static int c2p_point(int sys, int eos, double g, const cons_t *C, prim_t *P) {
   return 1;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Treatment of unphysical conserved variables (relativistic systems; the   */
+/* section on unphysical conservative variables).  Reading: the atmosphere  */
+/* keeps the density and the fluid's internal energy positive, D >= D_min   */
+/* and tau_f >= tau_min, where tau_f = tau (hydro) or tau - B^2/2 (MHD: the */
+/* energy of the fluid at rest in the field B); then the momentum is held   */
+/* one part in 10^12 below the largest value for which primitives exist,    */
+/* S^2 <= (1 - 1e-12) S^2_max.                                              */
+/*   Hydro: primitives exist iff (tau + D)^2 - S^2 > D^2, so                 */
+/*   S^2_max = tau (tau + 2 D) and S is rescaled onto the bound directly.    */
+/*   MHD: S is rescaled along itself.  A scale lambda is admissible when the */
+/*   state with momentum lambda S has a defined pressure function that is   */
+/*   positive at p = 0 (the lower end of the recovery's bracket; lambda = 0  */
+/*   always is, since f(0) = (gamma-1) tau_f there).  With s = (1-1e-12)^-1/2 */
+/*   the state is left alone when s is admissible; otherwise bisection on    */
+/*   [0, s] finds the admissible lambda_lo closest to the edge and S becomes */
+/*   (lambda_lo / s) S.  With B = 0 this is the hydro bound.                 */
+/* A state meeting every bound is returned bit for bit.  Returns 1 when the  */
+/* state changed.                                                           */
+static int mhd_admissible(double g, const double *u, double lambda) {
+  cons_t C;
+  for (int v = 0; v < 9; ++v) C.u[v] = u[v];
+  for (int i = 1; i <= 3; ++i) C.u[i] = lambda * u[i];
+  double f;
+  return c2p_eval(2, g, &C, 0.0, &f, NULL) && f > 0.0;
+}
+
+static int fix_cons(int sys, double g, double D_min, double tau_min, double *u) {
+  int changed = 0;
+  if (!(u[0] >= D_min)) { u[0] = D_min; changed = 1; }
+  double BB = 0.0;
+  if (sys == 2) BB = u[5] * u[5] + u[6] * u[6] + u[7] * u[7];
+  if (!(u[4] - 0.5 * BB >= tau_min)) { u[4] = 0.5 * BB + tau_min; changed = 1; }
+  double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+  if (!isfinite(S2)) {
+    u[1] = u[2] = u[3] = 0.0;
+    return 1;
+  }
+  double lambda;
+  if (sys == 1) {
+    double cap = (1.0 - 1e-12) * u[4] * (u[4] + 2.0 * u[0]);
+    if (S2 <= cap) return changed;
+    lambda = sqrt(cap / S2);
+  } else {
+    double s = 1.0 / sqrt(1.0 - 1e-12);
+    if (mhd_admissible(g, u, s)) return changed;
+    double lo = 0.0, hi = s;
+    for (int it = 0; it < 400; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi)) break;
+      if (mhd_admissible(g, u, mid)) lo = mid; else hi = mid;
+    }
+    lambda = lo / s;
+  }
+  for (int i = 1; i <= 3; ++i) u[i] *= lambda;
+  return 1;
+}
+
+/* Pointwise fixing of n conserved states (SoA, nv rows) in place; returns
+ * the number of states changed. */
+int64_t ora_fix_cons(int sys, double g, double D_min, double tau_min, int64_t n, double *U) {
+  if (sys != 1 && sys != 2) return ORA_EINVAL;
+  if (!(D_min > 0.0) || !(tau_min > 0.0)) return ORA_EINVAL;
+  int nv = nvars_of(sys);
+  int64_t nfix = 0;
+  for (int64_t q = 0; q < n; ++q) {
+    double u[9];
+    for (int v = 0; v < nv; ++v) u[v] = U[(int64_t)v * n + q];
+    if (fix_cons(sys, g, D_min, tau_min, u)) {
+      ++nfix;
+      for (int v = 0; v < nv; ++v) U[(int64_t)v * n + q] = u[v];
+    }
+  }
+  return nfix;
+}
+
 /* Physical fluxes in direction d (flat space, v_tr = v):
  * NE:  [rho v^d, rho v_i v^d + p delta, (E + p) v^d]
  * SR:  [D v^d, S_i v^d + p delta, tau v^d + p v^d]
@@ -785,6 +861,10 @@ typedef struct {
   double time;       /* time of the state the operator is applied to */
   double vortex[6];  /* beta, X0, Y0, U, V, W of eq. isen_vortex */
   int32_t eos;       /* NE: 0 ideal gas, 1 polytropic p = rho^gamma */
+  /* SR / SRMHD with a limiter: atmosphere floors D_min, tau_min (both > 0
+   * switch on the conserved-variable fixing of every node of a limited
+   * element, fix_cons below); 0, 0: off */
+  double fix_D, fix_tau;
 } ora_mesh;
 
 typedef struct {
@@ -803,6 +883,10 @@ static int make_geom(const ora_mesh *m, geom_t *G) {
     if (m->bc[d] == 2 && m->sys != 0) return ORA_EINVAL;
   }
   if (m->limiter < 0 || m->limiter > 2 || !(m->lim_M >= 0.0)) return ORA_EINVAL;
+  if (m->fix_D != 0.0 || m->fix_tau != 0.0) {
+    if (m->sys == 0 || !(m->fix_D > 0.0) || !(m->fix_tau > 0.0) || !isfinite(m->fix_D) || !isfinite(m->fix_tau))
+      return ORA_EINVAL;
+  }
   int ne[3] = {m->nx, m->ny, m->nz};
   for (int d = 0; d < 3; ++d) {
     if (m->deg[d] < 0 || m->deg[d] > 32) return ORA_EINVAL;
@@ -1220,10 +1304,15 @@ static void element_moments(const ora_mesh *m, const geom_t *G, const double *U,
   }
 }
 
-/* Limit U in place; returns the number of limited element components, or <0
- * on bad input.                                                            */
-int64_t ora_limit(const ora_mesh *m, double *U) {
+/* Limits every troubled element component (returns their number); with
+ * fixing on (fix_D, fix_tau > 0), every node of an element with a limited
+ * component is then passed through fix_cons (the paper limits unphysical
+ * cells first and fixes what the limited state still leaves unphysical;
+ * an element with an unphysical node is limited in every component, so no
+ * node of an unlimited element needs a fix).  *nfixed: nodes changed.    */
+static int64_t limit_impl(const ora_mesh *m, double *U, int64_t *nfixed) {
   geom_t G;
+  *nfixed = 0;
   if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
   if (m->limiter == 0) return 0;
   if (m->bc[0] == 2 || m->bc[1] == 2 || m->bc[2] == 2) return ORA_EINVAL; /* ghost means need fixed states */
@@ -1239,10 +1328,12 @@ int64_t ora_limit(const ora_mesh *m, double *U) {
   if (!Mo) return ORA_EINVAL;
 #pragma omp parallel for schedule(static) if (G.nnodes > 4096)
   for (int64_t e = 0; e < G.nelem; ++e) element_moments(m, &G, U, e, mu, &Mo[e]);
-  int64_t nlim = 0;
-#pragma omp parallel for schedule(static) reduction(+ : nlim) if (G.nnodes > 4096)
+  int64_t nlim = 0, nfix = 0;
+  const int fixing = m->fix_D > 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : nlim, nfix) if (G.nnodes > 4096)
   for (int64_t e = 0; e < G.nelem; ++e) {
     const moments_t *Me = &Mo[e];
+    int any = 0;
     for (int v = 0; v < nv; ++v) {
       double a[3] = {0.0, 0.0, 0.0};
       int troubled = Me->bad;
@@ -1267,6 +1358,7 @@ int64_t ora_limit(const ora_mesh *m, double *U) {
       }
       if (!troubled) continue;
       ++nlim;
+      any = 1;
       for (int k = 0; k < G.n[2]; ++k)
         for (int j = 0; j < G.n[1]; ++j)
           for (int i = 0; i < G.n[0]; ++i) {
@@ -1277,9 +1369,36 @@ int64_t ora_limit(const ora_mesh *m, double *U) {
             U[(int64_t)v * G.nnodes + e * G.npe + i + G.n[0] * (j + G.n[1] * k)] = u;
           }
     }
+    if (!fixing || !any) continue;
+    for (int a = 0; a < G.npe; ++a) {
+      double u[9];
+      int64_t q = e * G.npe + a;
+      for (int v = 0; v < nv; ++v) u[v] = U[(int64_t)v * G.nnodes + q];
+      if (fix_cons(m->sys, m->gamma, m->fix_D, m->fix_tau, u)) {
+        ++nfix;
+        for (int v = 0; v < nv; ++v) U[(int64_t)v * G.nnodes + q] = u[v];
+      }
+    }
   }
   free(Mo);
+  *nfixed = nfix;
   return nlim;
+}
+
+int64_t ora_limit(const ora_mesh *m, double *U) {
+  int64_t nfix;
+  return limit_impl(m, U, &nfix);
+}
+
+/* As ora_limit; counts[0] = limited element components, counts[1] = nodes
+ * changed by the fixing. */
+int ora_limit_counts(const ora_mesh *m, double *U, int64_t *counts) {
+  int64_t nfix = 0;
+  int64_t nlim = limit_impl(m, U, &nfix);
+  if (nlim < 0) return (int)nlim;
+  counts[0] = nlim;
+  counts[1] = nfix;
+  return ORA_OK;
 }
 
 /* Element means, Legendre slope coefficients c_d and face means of every
@@ -1588,7 +1707,7 @@ static int face_node(int N, int d, int side, int a, int b) {
 /* Mixed-degree strong-form operator.  The mesh's deg[] field is ignored;
  * deg[e] gives each element's degree.  Returns failed recoveries or <0. */
 int64_t ora_rhs_mixed(const ora_mesh *m, const int32_t *deg, const double *U, double *prim_out, double *dUdt) {
-  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos) return ORA_EINVAL; /* periodic, unlimited, ideal gas */
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos || m->fix_D != 0.0) return ORA_EINVAL; /* periodic, unlimited, ideal gas */
   int sys = m->sys, nv = nvars_of(sys);
   double g = m->gamma;
   int64_t ne = (int64_t)m->nx * m->ny * m->nz;
@@ -1770,7 +1889,7 @@ int ora_mixed_integrate(const ora_mesh *m, const int32_t *deg, int ncomp, const 
 
 /* SSP-RK3 step on a mixed-degree mesh. */
 int64_t ora_step_mixed(const ora_mesh *m, const int32_t *deg, double *U, double dt) {
-  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos) return ORA_EINVAL;
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos || m->fix_D != 0.0) return ORA_EINVAL;
   int64_t ne = (int64_t)m->nx * m->ny * m->nz;
   int nv = nvars_of(m->sys);
   int64_t n = (int64_t)nv * ora_mixed_num_nodes((int)ne, deg);
