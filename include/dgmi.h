@@ -223,6 +223,37 @@ dgmi_status dgmi_limited(dgmi_ctx *ctx, int64_t *n_limited_host, void *stream);
  * then resets the counter). */
 dgmi_status dgmi_failures(dgmi_ctx *ctx, int64_t *n_failed_host, void *stream);
 
+/* Atmosphere floors and conserved-variable fixing (relativistic systems;
+ * section on the treatment of unphysical conservative variables), read as:
+ * D >= D_min; tau_f >= tau_min with tau_f = tau (hydro) or tau - B^2/2
+ * (MHD); then the momentum held one part in 1e12 below the largest value for
+ * which primitives exist: S^2 <= (1 - 1e-12) tau (tau + 2D) for hydro; for
+ * MHD, S scaled along itself to 1 / (1 + 5e-13) of the largest scale at
+ * which the pressure function is defined and positive at p = 0 (found by
+ * bisection).  Only D, S and tau change; a state meeting every bound is left
+ * bit for bit.  A state whose margin 1e-12 S_max^2 is below rounding
+ * relative to (tau + D)^2 (very cold, slow flow) can stay unrecoverable.
+ *
+ * dgmi_set_fixing switches it on for dg_step / dg_limit (both floors > 0;
+ * both 0 switches it off; DGMI_EINVAL for Newtonian Euler or other values):
+ * after limiting, every node of an element with a limited component is
+ * fixed before its primitives are recovered.  The paper limits unphysical
+ * cells first; an element holding an unrecoverable node is limited in every
+ * component, so fixing acts only where a limiter is selected. */
+dgmi_status dgmi_set_fixing(dgmi_ctx *ctx, double D_min, double tau_min);
+
+/* Number of nodes changed by the fixing since the last call (synchronises
+ * `stream`, then resets the counter). */
+dgmi_status dgmi_fixed(dgmi_ctx *ctx, int64_t *n_fixed_host, void *stream);
+
+/* Pointwise fixing, as above, of n conserved states U (device, SoA: nv rows
+ * of n doubles; system DGMI_SR_HYDRO or DGMI_SR_MHD) in place.  n_fixed:
+ * optional device int64 to which the number of changed states is added.
+ * DGMI_EINVAL for another system, gamma outside (1, 2], floors not finite
+ * and > 0, or host pointers. */
+dgmi_status dgmi_fix_conserved(int32_t system, double gamma, double D_min, double tau_min, double *U, int64_t n,
+                               int64_t *n_fixed, void *stream);
+
 /* Largest characteristic speed of U (section on initial data, boundary
  * conditions and time steppers: the lambda_max of the CFL scaling) over
  * every node, direction and component, written to the device double

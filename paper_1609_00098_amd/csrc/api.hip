@@ -180,6 +180,9 @@ struct dgmi_ctx {
   double *d_mom = nullptr;        // [nelem][10][nv]
   int32_t *d_bad = nullptr;       // [nelem]
   unsigned long long *d_nlim = nullptr;  // [kLimCounters] limited-component counters (summed when read)
+  // atmosphere floors / conserved-variable fixing inside the limiter (0, 0: off)
+  double fix_D = 0.0, fix_tau = 0.0;
+  unsigned long long *d_nfix = nullptr;  // nodes changed by the fixing
   // time stepping helpers
   double hmin = 0.0;              // smallest GLL node spacing on the physical grid
   double *d_lam = nullptr;        // device scalar: largest characteristic speed
@@ -565,6 +568,7 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_mom);
   (void)hipFree(c->d_bad);
   (void)hipFree(c->d_nlim);
+  (void)hipFree(c->d_nfix);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   for (int k = 0; k < 8; ++k) {
@@ -662,6 +666,7 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
       hipMalloc(&c->d_P1, pbytes) != hipSuccess || hipMalloc(&c->d_P2, pbytes) != hipSuccess ||
       hipMalloc(&c->d_bc, sizeof(c->hbc)) != hipSuccess || hipMalloc(&c->d_limtab, 24 * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->d_nlim, kLimCounters * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&c->d_nfix, sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->d_lam, sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     ctx_free(c);
@@ -672,6 +677,7 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
       hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->d_nfail, 0, sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->d_nlim, 0, kLimCounters * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_nfix, 0, sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->d_bc, 0, sizeof(c->hbc)) != hipSuccess) {
     ctx_free(c);
     return fail(DGMI_EHIP, "dgmi_create: table upload failed");
@@ -792,6 +798,9 @@ static dgmi::LimArgs lim_args(dgmi_ctx *c, double *U, const double *Pseed, doubl
   a.nlim = c->d_nlim;
   a.nfail = c->d_nfail;
   a.poly = (c->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0;
+  a.fix_D = c->fix_D;
+  a.fix_tau = c->fix_tau;
+  a.nfix = c->d_nfix;
   return a;
 }
 
@@ -1190,6 +1199,49 @@ dgmi_status dg_step_ab3(dgmi_ctx *ctx, double *U, double *prim_inout, double dt,
     ctx->time += dt;
   }
   ctx->ab_count = k + 1;
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_set_fixing(dgmi_ctx *ctx, double D_min, double tau_min) {
+  if (!ctx) return fail(DGMI_EINVAL, "dgmi_set_fixing: null context");
+  if (D_min == 0.0 && tau_min == 0.0) {
+    ctx->fix_D = ctx->fix_tau = 0.0;
+    return DGMI_OK;
+  }
+  if (ctx->sys == DGMI_NEWTONIAN_EULER)
+    return fail(DGMI_EINVAL, "dgmi_set_fixing: conserved-variable fixing is for the relativistic systems");
+  if (!(D_min > 0.0) || !(tau_min > 0.0) || !std::isfinite(D_min) || !std::isfinite(tau_min))
+    return fail(DGMI_EINVAL, "dgmi_set_fixing: D_min and tau_min must be finite and > 0 (both 0: off)");
+  ctx->fix_D = D_min;
+  ctx->fix_tau = tau_min;
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_fixed(dgmi_ctx *ctx, int64_t *n_fixed_host, void *stream) {
+  if (!ctx || !n_fixed_host) return fail(DGMI_EINVAL, "dgmi_fixed: null argument");
+  unsigned long long v = 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(&v, ctx->d_nfix, sizeof(v), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemsetAsync(ctx->d_nfix, 0, sizeof(v), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *n_fixed_host = (int64_t)v;
+  return DGMI_OK;
+}
+
+dgmi_status dgmi_fix_conserved(int32_t system, double gamma, double D_min, double tau_min, double *U, int64_t n,
+                               int64_t *n_fixed, void *stream) {
+  if (system != DGMI_SR_HYDRO && system != DGMI_SR_MHD)
+    return fail(DGMI_EINVAL, "dgmi_fix_conserved: conserved-variable fixing is for the relativistic systems");
+  if (n < 0) return fail(DGMI_EINVAL, "dgmi_fix_conserved: negative size");
+  if (!(gamma > 1.0 && gamma <= 2.0)) return fail(DGMI_EINVAL, "dgmi_fix_conserved: gamma must be in (1, 2]");
+  if (!(D_min > 0.0) || !(tau_min > 0.0) || !std::isfinite(D_min) || !std::isfinite(tau_min))
+    return fail(DGMI_EINVAL, "dgmi_fix_conserved: D_min and tau_min must be finite and > 0");
+  if (n == 0) return DGMI_OK;
+  if (!is_device_ptr(U)) return fail(DGMI_EINVAL, "dgmi_fix_conserved: U must be a device pointer");
+  if (n_fixed && !is_device_ptr(n_fixed)) return fail(DGMI_EINVAL, "dgmi_fix_conserved: n_fixed must be a device pointer");
+  HIP_TRY(dgmi::launch_fix_conserved(system, gamma, D_min, tau_min, U, n, (unsigned long long *)n_fixed,
+                                     (hipStream_t)stream));
   return DGMI_OK;
 }
 

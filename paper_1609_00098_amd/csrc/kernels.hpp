@@ -79,7 +79,15 @@ struct LimArgs {
   double dx[3];
   unsigned long long *nlim, *nfail;
   int poly;                   // NE: polytropic equation of state p = rho^gamma
+  // SR / SRMHD: atmosphere floors (both > 0 switch on the conserved-variable
+  // fixing of every node of an element with a limited component)
+  double fix_D, fix_tau;
+  unsigned long long *nfix;   // nodes changed by the fixing
 };
+// Pointwise fixing of n conserved states in place (SoA rows of n); counts the
+// changed states into *nfix.
+hipError_t launch_fix_conserved(int sys, double gamma, double D_min, double tau_min, double *U, int64_t n,
+                                unsigned long long *nfix, hipStream_t s);
 // moments = false: the moments (and the primitives of every node) are
 // already in place, written by the limited RK stage kernel.
 hipError_t launch_limiter(int sys, int N, bool moments, const LimArgs &a, hipStream_t s);

@@ -16,9 +16,10 @@
 //       state), whether the component is troubled and its limited slopes,
 //       written over the element's moments.
 //   apply     one thread per node of an element with a troubled component:
-//       rewrite the troubled components as U0 + sum_d a_d (x_d - x_d0) and
-//       recover the node's primitives.  Other elements read one flag per
-//       component and touch no node data.
+//       rewrite the troubled components as U0 + sum_d a_d (x_d - x_d0), pass
+//       the node through the conserved-variable fixing when it is switched
+//       on (relativistic systems), and recover the node's primitives.  Other
+//       elements read one flag per component and touch no node data.
 //
 // Per component k of element e and direction d (every direction has degree
 // N >= 1 on a uniform mesh):
@@ -177,9 +178,54 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_apply_kerne
       u[v] = A.U[v * nn + q];
     }
   }
+  if (SYS != kNE && A.fix_D > 0.0) {
+    // fix what the limited state still leaves unphysical (only D, S, tau change)
+    if (fix_conserved<SYS>(u, A.gamma, A.fix_D, A.fix_tau)) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) A.U[v * nn + q] = u[v];
+      atomicAdd(A.nfix, 1ull);
+    }
+  }
   const C2PResult R = recover<SYS>(u, A.gamma, A.Pout[4 * nn + q], 0.0, 100, A.poly);
   store_prims(A.Pout, nn, q, R.P);
   if (!R.ok) atomicAdd(A.nfail, 1ull);
+}
+
+// Pointwise conserved-variable fixing, one thread per point; one counter
+// update per wave.
+template <int SYS>
+__global__ void __launch_bounds__(256) fix_conserved_kernel(double *U, int64_t n, double g, double D_min,
+                                                            double tau_min, unsigned long long *nfix) {
+  constexpr int NV = SysTraits<SYS>::nv;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool changed = false;
+  if (q < n) {
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[v * n + q];
+    changed = fix_conserved<SYS>(u, g, D_min, tau_min);
+    if (changed) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) U[v * n + q] = u[v];
+    }
+  }
+  const unsigned long long bal = __ballot(changed);
+  if (nfix && (threadIdx.x & 63) == 0 && bal) atomicAdd(nfix, (unsigned long long)__popcll(bal));
+}
+
+hipError_t launch_fix_conserved(int sys, double gamma, double D_min, double tau_min, double *U, int64_t n,
+                                unsigned long long *nfix, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + 255) / 256;
+  if (nb > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
+  switch (sys) {
+    case kSR: hipLaunchKernelGGL(fix_conserved_kernel<kSR>, dim3((unsigned)nb), dim3(256), 0, s, U, n, gamma, D_min,
+                                 tau_min, nfix); break;
+    case kMHD: hipLaunchKernelGGL(fix_conserved_kernel<kMHD>, dim3((unsigned)nb), dim3(256), 0, s, U, n, gamma, D_min,
+                                  tau_min, nfix); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int SYS, int N>

@@ -90,11 +90,16 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
 template <int SYS>
 __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   constexpr int NV = SysTraits<SYS>::nv, NS = Interp<SYS>::ns;
-  __shared__ double st[NS * 64];  // lower side's interpolation state, [c][node]
+  // two buffers serve two phases each (every phase ends at a barrier), which
+  // keeps the LDS per face at 15 x 64 doubles and the occupancy up
+  constexpr int NB = NS > NV ? NS : NV;
+  __shared__ double bufA[NB * 64];
+  __shared__ double bufB[NB * 64];
   __shared__ double fl[NV * 64];  // lower side's nodal normal fluxes, [v][node]
-  __shared__ double t1[NS * 64];  // state interpolated along a, [c][ma + nm ib]
-  __shared__ double jm[NV * 64];  // F*.n_lo at the mortar nodes, [v][m]
-  __shared__ double g1[NV * 64];  // projection along a, [v][a + nl mb]
+  double *const st = bufA;        // lower side's interpolation state, [c][node]      (L, I1)
+  double *const t1 = bufB;        // state interpolated along a, [c][ma + nm ib]       (I1, I2)
+  double *const jm = bufA;        // F*.n_lo at the mortar nodes, [v][m]               (I2, P1)
+  double *const g1 = bufB;        // projection along a, [v][a + nl mb]               (P1, P2)
   __shared__ double sI[64], sP[64], sQ[64];
   const int64_t t = blockIdx.x;
   if (t >= A.nfaces) return;

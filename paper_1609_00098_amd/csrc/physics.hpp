@@ -510,6 +510,69 @@ DG_HD bool pressure_function(const double *u, double g, double p, double *f) {
   return true;
 }
 
+// Atmosphere floors and conserved-variable fixing of one point (relativistic
+// systems; treatment of unphysical conservative variables): D >= D_min,
+// tau_f >= tau_min with tau_f = tau - B^2/2 (B = 0 for hydro), then the
+// momentum held one part in 1e12 below the largest value for which
+// primitives exist.  Hydro: S^2 <= (1 - 1e-12) tau (tau + 2D) in closed
+// form.  MHD: S is scaled along itself; with s = (1 - 1e-12)^-1/2 a state
+// whose momentum can grow by s while the pressure function stays defined and
+// positive at p = 0 is left alone, otherwise a bisection on [0, s] finds the
+// largest such scale lambda_lo and S becomes (lambda_lo / s) S.  A state
+// meeting every bound is left bit for bit; returns true when u changed.
+template <int SYS>
+DG_HD bool mhd_admissible(const double *u, double g, double lambda) {
+  double w[9];
+#pragma unroll
+  for (int v = 0; v < 9; ++v) w[v] = u[v];
+  w[1] *= lambda;
+  w[2] *= lambda;
+  w[3] *= lambda;
+  double f;
+  return pressure_function<kMHD>(w, g, 0.0, &f) && f > 0.0;
+}
+
+template <int SYS>
+DG_HD bool fix_conserved(double *u, double g, double D_min, double tau_min) {
+  bool changed = false;
+  if (!(u[0] >= D_min)) {
+    u[0] = D_min;
+    changed = true;
+  }
+  double BB = 0.0;
+  if (SYS == kMHD) BB = u[5] * u[5] + u[6] * u[6] + u[7] * u[7];
+  if (!(u[4] - 0.5 * BB >= tau_min)) {
+    u[4] = 0.5 * BB + tau_min;
+    changed = true;
+  }
+  const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+  if (!(S2 <= 1.7976931348623157e308)) {  // NaN or infinite momentum
+    u[1] = u[2] = u[3] = 0.0;
+    return true;
+  }
+  double lambda;
+  if (SYS == kSR) {
+    const double cap = (1.0 - 1e-12) * u[4] * (u[4] + 2.0 * u[0]);
+    if (S2 <= cap) return changed;
+    lambda = sqrt(cap / S2);
+  } else {
+    const double s = 1.0 / sqrt(1.0 - 1e-12);
+    if (mhd_admissible<SYS>(u, g, s)) return changed;
+    double lo = 0.0, hi = s;
+#pragma unroll 1
+    for (int it = 0; it < 400; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi)) break;
+      if (mhd_admissible<SYS>(u, g, mid)) lo = mid; else hi = mid;
+    }
+    lambda = lo / s;
+  }
+  u[1] *= lambda;
+  u[2] *= lambda;
+  u[3] *= lambda;
+  return true;
+}
+
 // Recovery of one point.  p0: initial pressure (outside the bracket => the
 // bracket's upper end).  tol > 0: stop when the backward residual
 // |f| W^2 / ((g-1) E) <= tol at the evaluated pressure; tol <= 0: iterate
@@ -551,6 +614,12 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
   double prev_step = 1e300;
   bool last_small = false;
   int conv = 0;
+  // the evaluated pressure with the smallest |f|, and whether that |f| lies
+  // within the rounding of f's terms (a last resort when the iteration runs
+  // out: for an extreme Lorentz factor 1 - v^2 cancels and f carries noise
+  // far above 1e-14 p, so neither the step tests nor the bracket settle)
+  double p_best = p, f_best = 1e300;
+  bool best_at_floor = false;
 #pragma unroll 1
   for (int it = 1; it <= maxit; ++it) {
     R.iters = it;
@@ -593,6 +662,12 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     }
     const double rho_eps = z * uu - D * sqw - p;
     const double f = gm1 * rho_eps - p;
+    if (fabs(f) < f_best) {
+      f_best = fabs(f);
+      p_best = p;
+      // |f| <= 32 eps (g-1) (z + D / sqrt(1 - v^2)), without the division
+      best_at_floor = f_best * sqw <= 7.105427357601002e-15 * gm1 * (z * sqw + D);
+    }
     if (tol > 0.0 && fabs(f) * W * W <= tol * gm1 * E) {
       conv = 1;
       break;
@@ -639,6 +714,10 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     }
     prev_step = newton ? step : 1e300;
     last_small = newton && step <= 1e-9 * p;
+  }
+  if (!conv && tol <= 0.0 && best_at_floor) {
+    p = p_best;
+    conv = 1;
   }
   // primitives at the final pressure
   if (SYS == kSR) {

@@ -69,6 +69,9 @@ _SIGS = {
     "dgmi_get_time": (_I32, [_P, ctypes.POINTER(_D)]),
     "dg_limit": (_I32, [_P, _P, _P, _P]),
     "dgmi_limited": (_I32, [_P, ctypes.POINTER(_I64), _P]),
+    "dgmi_set_fixing": (_I32, [_P, _D, _D]),
+    "dgmi_fixed": (_I32, [_P, ctypes.POINTER(_I64), _P]),
+    "dgmi_fix_conserved": (_I32, [_I32, _D, _D, _D, _P, _I64, _P, _P]),
     "con2prim": (_I32, [_I32, _D, _P, _P, _I64, _I32, _P, _D, _P, _P, _P, _P]),
     "dgmi_last_error": (ctypes.c_char_p, []),
     "mlp_create": (_I32, [ctypes.POINTER(_P), ctypes.c_uint64]),
@@ -252,6 +255,26 @@ def dgmi_limited(mesh, stream=None):
     v = _I64(0)
     _check(_lib.dgmi_limited(mesh.handle, ctypes.byref(v), _stream(stream)), "dgmi_limited")
     return int(v.value)
+
+
+def dgmi_set_fixing(mesh, D_min, tau_min):
+    _check(_lib.dgmi_set_fixing(mesh.handle, float(D_min), float(tau_min)), "dgmi_set_fixing")
+
+
+def dgmi_fixed(mesh, stream=None):
+    v = _I64(0)
+    _check(_lib.dgmi_fixed(mesh.handle, ctypes.byref(v), _stream(stream)), "dgmi_fixed")
+    return int(v.value)
+
+
+def dgmi_fix_conserved(system, gamma, D_min, tau_min, U, n_fixed=None, stream=None):
+    """Fixes the columns of U ([nv, n] device tensor) in place; n_fixed: optional
+    one-element int64 device tensor the number of changed columns is added to."""
+    n = U.shape[1]
+    _check(_lib.dgmi_fix_conserved(system, float(gamma), float(D_min), float(tau_min),
+                                   _ptr(U, numel=NVARS[system] * n if system in NVARS else None, name="U"), n,
+                                   _ptr(n_fixed, torch.int64, 1, "n_fixed"), _stream(stream)), "dgmi_fix_conserved")
+    return U
 
 
 def dgmi_max_speed(mesh, U, prim, out=None, stream=None):
