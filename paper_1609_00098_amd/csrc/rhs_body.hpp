@@ -87,9 +87,14 @@ struct RhsCfg {
   // more than the idle threads of the volume phase: measured 5% at degree 3)
   static constexpr int WORK = (SYS == kMHD && FACE_TASKS > EPB * NPE) ? FACE_TASKS : EPB * NPE;
   static constexpr int THREADS = ((WORK + 63) / 64) * 64;
-  // LDS (doubles): volume flux [EPB][NV][NPE], own state [EPB][NV][NPE],
-  // face slots [EPB][NV][6][NF], interior wave speeds [EPB][6][NF] (HLL:
-  // [EPB][2][6][NF], the largest then the smallest along the outward normal)
+  // LDS (doubles): volume flux [EPB][NV][NPE], own state [EPB][NV][NPE]
+  // (mixed-degree and limited-stage kernels only), face slots
+  // [EPB][NV][6][NF], interior wave speeds [EPB][6][NF] (HLL:
+  // [EPB][2][6][NF], the largest then the smallest along the outward normal).
+  // The uniform operator and stage kernels read a face node's own state back
+  // from global memory (an L2 hit: the workgroup loaded it at the start);
+  // without the 8 NV NPE EPB bytes their LDS no longer caps the occupancy
+  // (degree 4 SR: 34.6 -> 24.6 KB, 4 -> 6 waves per SIMD, operator 8% faster).
   static constexpr int VOL = EPB * NV * NPE;
   static constexpr int OWN = EPB * NV * NPE;
   static constexpr int SLOT = EPB * NV * 6 * NF;
@@ -124,8 +129,9 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   using C = RhsCfg<SYS, N, EPB_, FLUX>;
   constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
   double *svol = smem;
+  constexpr bool OWNL = MOM || MIXED;
   double *sown = svol + C::VOL;
-  double *sslot = sown + C::OWN;
+  double *sslot = sown + (OWNL ? C::OWN : 0);
   double *sspd = sslot + C::SLOT;
   double *sD = sspd + C::SPD;
 
@@ -155,8 +161,10 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   if (active) {
     load_node<SYS>(A.U, A.P, nn, q, A.gamma, u, P, A.poly);
     if (SYS == kMHD) acc[8] = -A.kappa * u[8];
+    if constexpr (OWNL) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sown[(le * NV + v) * NPE + a] = u[v];
+      for (int v = 0; v < NV; ++v) sown[(le * NV + v) * NPE + a] = u[v];
+    }
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = 0.0;
@@ -253,14 +261,15 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       load_node<SYS>(A.U, A.P, nn, ebase + n0 + NP * (n1 + NP * n2), A.gamma, ue, Pe, A.poly);
     }
     flux_normal<SYS>(d, ue, Pe, Fe);
-    const double *own = sown + fle * NV * NPE + ai;
+    const double *own = OWNL ? sown + fle * NV * NPE + ai : A.U + fe * NPE + ai;
+    const int64_t ost = OWNL ? NPE : nn;
     double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
     const double hs = side ? 0.5 : -0.5;
     if constexpr (FLUX == kMarquina && SYS == kNE) {
       double ui[5], fi[5], Fs[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        ui[v] = own[v * NPE];
+        ui[v] = own[v * ost];
         fi[v] = slot[v * 6 * NF];
       }
       const Prim Pi = prims_at_pressure<kNE>(ui, A.gamma, 0.0);
@@ -273,7 +282,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     if constexpr (FLUX == kRoe && SYS == kNE) {
       double ui[5], D[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) ui[v] = own[v * NPE];
+      for (int v = 0; v < 5; ++v) ui[v] = own[v * ost];
       const Prim Pi = prims_at_pressure<kNE>(ui, A.gamma, 0.0);
       roe_dissipation<d>(side ? 1.0 : -1.0, ui, Pi, ue, Pe, A.gamma, D);
 #pragma unroll
@@ -294,9 +303,9 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       for (int v = 0; v < NV; ++v) {
         const double Fi = slot[v * 6 * NF];
         if (SYS == kMHD && (v == 8 || v == 5 + d))  // bounds -1, +1: the LLF form with alpha = 1
-          slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * (ue[v] - own[v * NPE]);
+          slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * (ue[v] - own[v * ost]);
         else
-          slot[v * 6 * NF] = cf * (sg * (Fe[v] - Fi) - sp * (ue[v] - own[v * NPE]));
+          slot[v * 6 * NF] = cf * (sg * (Fe[v] - Fi) - sp * (ue[v] - own[v * ost]));
       }
       return;
     }
@@ -306,7 +315,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       double al = alpha;
       if (SYS == kMHD && (v == 8 || v == 5 + d)) al = 1.0;
       const double Fi = slot[v * 6 * NF];
-      slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * al * (ue[v] - own[v * NPE]);
+      slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * al * (ue[v] - own[v * ost]);
     }
   };
   constexpr int TPD = EPB * 2 * NF;  // tasks per direction
@@ -396,7 +405,7 @@ template <int SYS, int N, int STAGE, int EPB_ = default_epb<SYS, N>(), bool MIXE
           bool MOM = false>
 __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(const RhsArgs A) {
   using C = RhsCfg<SYS, N, EPB_, FLUX>;
-  __shared__ double smem[C::LDS];
+  __shared__ double smem[C::LDS - ((MOM || MIXED) ? 0 : C::OWN)];
   // XCD-major block order: hardware block b runs on XCD b % 8, which walks
   // its own contiguous range of the processing order.
   const int per = (A.nblocks + 7) >> 3;
