@@ -159,6 +159,8 @@ def _load():
         "ora_stable_dt": (ctypes.c_double, [MP, D, ctypes.c_double]),
         "ora_evolve_ab3": (I64, [MP, D, ctypes.c_double, I64]),
         "ora_limit_counts": (ctypes.c_int, [MP, D, ctypes.POINTER(I64)]),
+        "ora_evolve_ab3_mixed": (I64, [MP, ctypes.POINTER(ctypes.c_int32), D, ctypes.c_double, I64]),
+        "ora_stable_dt_mixed": (ctypes.c_double, [MP, ctypes.POINTER(ctypes.c_int32), D, ctypes.c_double]),
         "ora_fix_cons": (I64, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, I64, D]),
     }
     for name, (res, args) in sig.items():
@@ -501,3 +503,19 @@ def step_mixed(m, deg, U, dt):
     U = _c(U).copy()
     nf = _load().ora_step_mixed(ctypes.byref(m), dp, _p(U), dt)
     return U, int(nf)
+
+
+def evolve_ab3_mixed(m, deg, U, dt, nsteps):
+    """nsteps third-order Adams-Bashforth steps on a mixed-degree mesh (the
+    first two are SSP-RK3 steps); returns (U, failed recoveries)."""
+    d, dp = _deg(deg)
+    U = _c(U).copy()
+    nf = _load().ora_evolve_ab3_mixed(ctypes.byref(m), dp, _p(U), dt, nsteps)
+    if nf < 0:
+        raise ValueError("bad mesh")
+    return U, int(nf)
+
+
+def stable_dt_mixed(m, deg, U, cfl):
+    d, dp = _deg(deg)
+    return float(_load().ora_stable_dt_mixed(ctypes.byref(m), dp, _p(_c(U)), cfl))

@@ -1906,3 +1906,76 @@ int64_t ora_step_mixed(const ora_mesh *m, const int32_t *deg, double *U, double 
   free(L); free(U1); free(U2);
   return nf;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Time stepping on a mixed-degree mesh (periodic, ideal gas, unlimited):   */
+/* the same third-order Adams-Bashforth steps as ora_evolve_ab3 with the    */
+/* mixed-degree operator, its history started by two SSP-RK3 steps of       */
+/* ora_step_mixed; and the CFL step cfl * h_min / lambda_max with h_min the */
+/* smallest GLL node spacing over the degrees present and lambda_max the    */
+/* largest characteristic speed over every node (the section on initial     */
+/* data, boundary conditions and time steppers).                            */
+/* ------------------------------------------------------------------------ */
+int64_t ora_evolve_ab3_mixed(const ora_mesh *m, const int32_t *deg, double *U, double dt, int64_t nsteps) {
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos || m->fix_D != 0.0) return ORA_EINVAL;
+  int64_t ne = (int64_t)m->nx * m->ny * m->nz;
+  int nv = nvars_of(m->sys);
+  int64_t n = (int64_t)nv * ora_mixed_num_nodes((int)ne, deg);
+  double *L[3];
+  for (int k = 0; k < 3; ++k) L[k] = (double *)malloc(sizeof(double) * n);
+  int64_t nf = 0;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    double *Ln = L[s % 3];
+    int64_t r = ora_rhs_mixed(m, deg, U, NULL, Ln);
+    if (r < 0) { nf = r; break; }
+    nf += r;
+    if (s < 2) {
+      r = ora_step_mixed(m, deg, U, dt);
+      if (r < 0) { nf = r; break; }
+      nf += r;
+      continue;
+    }
+    const double *L1 = L[(s - 1) % 3], *L2 = L[(s - 2) % 3];
+    for (int64_t q = 0; q < n; ++q)
+      U[q] = U[q] + dt * (23.0 / 12.0 * Ln[q] - 16.0 / 12.0 * L1[q] + 5.0 / 12.0 * L2[q]);
+  }
+  for (int k = 0; k < 3; ++k) free(L[k]);
+  return nf;
+}
+
+double ora_stable_dt_mixed(const ora_mesh *m, const int32_t *deg, const double *U, double cfl) {
+  int64_t ne = (int64_t)m->nx * m->ny * m->nz;
+  int nv = nvars_of(m->sys);
+  int64_t nn = ora_mixed_num_nodes((int)ne, deg);
+  double dx[3] = {(m->hi[0] - m->lo[0]) / m->nx, (m->hi[1] - m->lo[1]) / m->ny, (m->hi[2] - m->lo[2]) / m->nz};
+  double h = INFINITY;
+  int seen[33] = {0};
+  for (int64_t e = 0; e < ne; ++e) {
+    int N = deg[e];
+    if (N < 1 || N > 32) return -1.0;
+    if (seen[N]) continue;
+    seen[N] = 1;
+    double x[33], w[33];
+    ora_gll(N, x, w);
+    for (int d = 0; d < 3; ++d)
+      for (int i = 0; i < N; ++i) h = fmin(h, 0.5 * dx[d] * (x[i + 1] - x[i]));
+  }
+  double *prim = (double *)malloc(sizeof(double) * 5 * nn);
+  if (cons2prim_eos(m->sys, 0, m->gamma, nn, U, prim, NULL) != 0) {
+    free(prim);
+    return -1.0;
+  }
+  double lam = 0.0;
+  for (int64_t q = 0; q < nn; ++q) {
+    cons_t C; prim_t P; double a[9];
+    load_cons(nv, nn, U, q, &C);
+    load_prim(nn, prim, q, &P);
+    for (int d = 0; d < 3; ++d) {
+      max_speed(m->sys, m->gamma, d, &C, &P, a);
+      for (int c = 0; c < nv; ++c) lam = fmax(lam, a[c]);
+    }
+  }
+  free(prim);
+  if (!(lam > 0.0) || !(h > 0.0)) return -1.0;
+  return cfl * h / lam;
+}

@@ -241,3 +241,79 @@ def test_mixed_rejects_bad_degrees(ora):
     m = _mesh(ora, SR, (2, 1, 1))
     with pytest.raises(ValueError):
         ora.rhs_mixed(m, np.array([0, 3], np.int32), np.zeros((5, 28)))
+
+
+def test_mixed_ab3_equal_degrees_match_uniform(ora):
+    """Adams-Bashforth 3 on a mixed-degree mesh whose degrees are all equal
+    reproduces the uniform-degree steps bit for bit (its operator and its
+    SSP-RK3 start both reduce to the uniform ones)."""
+    m = _mesh(ora, SR, (3, 2, 2), 3)
+    deg = np.full(12, 3, np.int32)
+    U = _state(ora, SR, m, deg)
+    # the random fields are steep on this coarse mesh (|L| ~ 1e5): a short step
+    a, nfa = ora.evolve_ab3(m, U, 1e-6, 5)
+    b, nfb = ora.evolve_ab3_mixed(m, deg, U, 1e-6, 5)
+    assert nfa == nfb == 0
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("system", [NE, SR, MHD])
+def test_mixed_ab3_conserves_totals(ora, system):
+    m = _mesh(ora, system, (3, 2, 2))
+    deg = synth.mixed_degrees(12, seed=1610)
+    U = _state(ora, system, m, deg)
+    before = ora.mixed_integrate(m, deg, U)
+    U1, nf = ora.evolve_ab3_mixed(m, deg, U, 1e-6, 6)
+    after = ora.mixed_integrate(m, deg, U1)
+    assert nf == 0
+    cons = slice(0, 8) if system == MHD else slice(0, 5)  # Phi is damped by kappa
+    assert np.all(np.abs(after - before)[cons] <= 1e-13 * np.abs(before).max())
+    assert np.abs(U1 - U).max() > 1e-3
+
+
+def test_mixed_ab3_third_order_in_time(ora):
+    """The advected SR wave on a checkerboard of degrees 3 and 4: against a
+    reference of SSP-RK3 steps at dt/4, the AB3 error at dt and dt/2 falls
+    by 2^3 (the spatial error is common to all three runs)."""
+    g = 5.0 / 3.0
+    K = 4
+    m = ora.mesh(SR, (K, K, K), 2, g)
+    e = np.arange(K ** 3)
+    deg = np.where(((e % K) + (e // K) % K + e // (K * K)) % 2 == 0, 3, 4).astype(np.int32)
+    xyz = ora.mixed_node_coords(m, deg)
+    U0 = ora.prim2cons(SR, g, synth.smooth_flow(xyz, 0.0, 0.2, 2 * math.pi, (0.2, 0.2, 0.2)))
+    # CFL ~ 0.05 at dt: measured ratios 1000, 18, 8 for dt = 0.008, 0.004,
+    # 0.002 against half of each (the asymptotic range starts below 0.004)
+    T, dt = 0.048, 0.002
+    ref = U0
+    for _ in range(192):
+        ref, nf = ora.step_mixed(m, deg, ref, T / 192)
+        assert nf == 0
+    errs = []
+    for h in (dt, dt / 2):
+        U, nf = ora.evolve_ab3_mixed(m, deg, U0, h, int(round(T / h)))
+        assert nf == 0
+        errs.append(np.abs(U - ref).max())
+    rate = math.log2(errs[0] / errs[1])
+    assert 2.6 < rate < 3.6, (errs, rate)
+
+
+def test_mixed_stable_dt(ora):
+    """cfl h_min / lambda_max: equal degrees give the uniform value; on a
+    checkerboard of degrees 2 and 5 with a constant state h_min is the
+    degree-5 GLL gap (x_1 - x_0 = 1 - sqrt(1/3 + 2 sqrt(7) / 21)) times dx/2
+    and lambda_max the constant state's speed."""
+    g = 4.0 / 3.0
+    m = _mesh(ora, SR, (3, 2, 2), 4)
+    deg = np.full(12, 4, np.int32)
+    U = _state(ora, SR, m, deg)
+    assert ora.stable_dt_mixed(m, deg, U, 0.3) == ora.stable_dt(m, U, 0.3)
+    deg = np.array([2, 5] * 6, np.int32)
+    n = int(((deg + 1) ** 3).sum())
+    prim = np.tile(np.array([[1.0], [0.3], [-0.2], [0.1], [0.5]]), (1, n))
+    Uc = ora.prim2cons(SR, g, prim)
+    mu = ora.mesh(SR, (1, 1, 1), 2, g)
+    lam = ora.max_char_speed(mu, ora.prim2cons(SR, g, np.tile(prim[:, :1], (1, 27))))
+    gap = 1.0 - math.sqrt(1.0 / 3.0 + 2.0 * math.sqrt(7.0) / 21.0)
+    dxmin = min((np.array(m.hi[:]) - np.array(m.lo[:])) / np.array([3, 2, 2]))
+    np.testing.assert_allclose(ora.stable_dt_mixed(m, deg, Uc, 0.3), 0.3 * 0.5 * dxmin * gap / lam, rtol=1e-14)
