@@ -278,7 +278,8 @@ dgmi_status dgmi_stable_dt(dgmi_ctx *ctx, const double *U, const double *prim, d
  * history, and a call with another dt starts it again.  prim_inout as for
  * dg_step (on exit the primitives of the new U; failures counted); with a
  * slope limiter the new U is limited.  Advances the context's time by dt.
- * Uniform degrees only (DGMI_EUNSUPPORTED otherwise). */
+ * Mixed-degree meshes: the operator is their mortar and element pass, the
+ * starting steps their RK3 steps. */
 dgmi_status dg_step_ab3(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream);
 
 /* Pointwise recovery of the primitives (conservation-laws section; the

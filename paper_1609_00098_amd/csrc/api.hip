@@ -1142,7 +1142,6 @@ dgmi_status dgmi_stable_dt(dgmi_ctx *ctx, const double *U, const double *prim, d
 
 dgmi_status dg_step_ab3(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream) {
   if (!ctx) return fail(DGMI_EINVAL, "dg_step_ab3: null context");
-  if (ctx->mixed) return fail(DGMI_EUNSUPPORTED, "dg_step_ab3: uniform degrees only");
   if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
     return fail(DGMI_EINVAL, "dg_step_ab3: U and prim_inout must be distinct device pointers");
   if (!std::isfinite(dt)) return fail(DGMI_EINVAL, "dg_step_ab3: dt must be finite");
@@ -1166,14 +1165,21 @@ dgmi_status dg_step_ab3(dgmi_ctx *ctx, double *U, double *prim_inout, double dt,
     dgmi_status st = recover_all(ctx, U, prim_inout, guess, s);
     if (st != DGMI_OK) return st;
   }
-  // L^n = L(U^n) at the current time
-  dgmi_status st = boundary_pass(ctx, ctx->time, s);
-  if (st != DGMI_OK) return st;
-  dgmi::RhsArgs a = rhs_args(ctx);
-  a.U = U;
-  a.P = prim_inout;
-  a.out = Ln;
-  HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 0, flux_of(ctx), a, s));
+  // L^n = L(U^n) at the current time (mixed degrees: mortar and element
+  // kernels in operator mode; their meshes are periodic and unlimited)
+  dgmi_status st;
+  if (ctx->mixed) {
+    st = mixed_pass(ctx, 0, U, prim_inout, Ln, nullptr, nullptr, 0.0, 0.0, 0, s);
+    if (st != DGMI_OK) return st;
+  } else {
+    st = boundary_pass(ctx, ctx->time, s);
+    if (st != DGMI_OK) return st;
+    dgmi::RhsArgs a = rhs_args(ctx);
+    a.U = U;
+    a.P = prim_inout;
+    a.out = Ln;
+    HIP_TRY(dgmi::launch_rhs(ctx->sys, ctx->degree, 0, flux_of(ctx), a, s));
+  }
   if (k < 2) {
     // the history starts with SSP-RK3 steps (prim_inout still holds U^n's primitives)
     const int flags = ctx->flags;

@@ -222,3 +222,37 @@ def test_mixed_full_size_rhs_and_step(ora, dg):
     assert dg.dgmi_failures(mesh) == 0
     stol = 2 * tol * dt * np.abs(L).max() + 8 * np.finfo(float).eps * np.abs(U).max()
     assert np.abs(to_host(Ud) - Uo).max() <= stol
+
+
+@pytest.mark.parametrize("system,nel,kind", CASES[:4])
+def test_mixed_ab3_parity(ora, dg, system, nel, kind):
+    """Adams-Bashforth 3 on mixed degrees (two RK3 starting steps, then one
+    mortar + element operator pass per step) against the oracle, within the
+    per-step operator budget times the number of steps."""
+    deg = _degrees(kind, int(np.prod(nel)))
+    m, mesh, U, prim, _ = _setup(ora, dg, system, nel, deg)
+    L, Po, _ = ora.rhs_mixed(m, deg, U)
+    dt = _dt(L, U)
+    n = 6
+    Uo, nf = ora.evolve_ab3_mixed(m, deg, U, dt, n)
+    assert nf == 0
+    Ud, Pd = to_dev(U), to_dev(Po)
+    for _ in range(n):
+        dg.dg_step_ab3(mesh, Ud, Pd, dt)
+    assert dg.dgmi_failures(mesh) == 0
+    assert abs(dg.dgmi_get_time(mesh) - n * dt) < 1e-15
+    eps = np.finfo(np.float64).eps
+    tol = n * (4e-12 * dt * np.maximum(np.abs(L).max(axis=1), 1e-3 * np.abs(L).max()) +
+               8 * eps * np.abs(U).max(axis=1))
+    diff = np.abs(to_host(Ud) - Uo).max(axis=1)
+    assert np.all(diff <= tol), (diff, tol)
+    assert np.all(np.abs(Uo - U).max(axis=1)[:5] > 1e2 * tol[:5])
+
+
+def test_mixed_stable_dt_parity(ora, dg):
+    deg = _degrees("random17", 36)
+    m, mesh, U, prim, _ = _setup(ora, dg, SR, (4, 3, 3), deg)
+    _, Po, _ = ora.rhs_mixed(m, deg, U)
+    dt_o = ora.stable_dt_mixed(m, deg, U, 0.3)
+    dt = float(to_host(dg.dgmi_stable_dt(mesh, to_dev(U), to_dev(Po), 0.3))[0])
+    assert abs(dt - dt_o) <= 1e-14 * dt_o

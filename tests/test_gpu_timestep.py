@@ -130,8 +130,3 @@ def test_ab3_with_analytic_boundary_and_polytropic_eos(ora, dg):
     e_ab3, e_rk3 = np.abs(Uo - ex).max(), np.abs(Ur - ex).max()
     assert abs(e_ab3 - e_rk3) <= 1e-3 * e_rk3, (e_ab3, e_rk3)
 
-
-def test_ab3_rejected_on_mixed_degrees(dg):
-    G = dg.Mesh(SR, (2, 2, 2), 0, 4.0 / 3.0, degrees=np.array([2, 3] * 4, dtype=np.int32))
-    with pytest.raises(dg.DgmiError):
-        dg.dg_step_ab3(G, G.empty_state(), G.empty_prims(), 1e-3)
