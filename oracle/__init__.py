@@ -159,6 +159,7 @@ def _load():
         "ora_stable_dt": (ctypes.c_double, [MP, D, ctypes.c_double]),
         "ora_evolve_ab3": (I64, [MP, D, ctypes.c_double, I64]),
         "ora_limit_counts": (ctypes.c_int, [MP, D, ctypes.POINTER(I64)]),
+        "ora_limit_mixed": (I64, [MP, ctypes.POINTER(ctypes.c_int32), D, ctypes.POINTER(I64)]),
         "ora_evolve_ab3_mixed": (I64, [MP, ctypes.POINTER(ctypes.c_int32), D, ctypes.c_double, I64]),
         "ora_stable_dt_mixed": (ctypes.c_double, [MP, ctypes.POINTER(ctypes.c_int32), D, ctypes.c_double]),
         "ora_fix_cons": (I64, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, I64, D]),
@@ -503,6 +504,18 @@ def step_mixed(m, deg, U, dt):
     U = _c(U).copy()
     nf = _load().ora_step_mixed(ctypes.byref(m), dp, _p(U), dt)
     return U, int(nf)
+
+
+def limit_mixed(m, deg, U):
+    """Limiter on a mixed-degree mesh: (limited copy of U, limited element
+    components, nodes changed by the fixing)."""
+    d, dp = _deg(deg)
+    U = _c(U).copy()
+    counts = np.zeros(2, dtype=np.int64)
+    r = _load().ora_limit_mixed(ctypes.byref(m), dp, _p(U), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if r < 0:
+        raise ValueError("bad mesh")
+    return U, int(counts[0]), int(counts[1])
 
 
 def evolve_ab3_mixed(m, deg, U, dt, nsteps):

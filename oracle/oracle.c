@@ -1249,17 +1249,17 @@ typedef struct {
   int bad;
 } moments_t;
 
-static void element_moments(const ora_mesh *m, const geom_t *G, const double *U, int64_t e, const double mu[3][33],
+static void element_moments(const ora_mesh *m, const geom_t *G, const double *U, int64_t base, const double mu[3][33],
                             moments_t *M) {
   int nv = nvars_of(m->sys);
-  int64_t N = G->nnodes, npe = G->npe;
+  int64_t N = G->nnodes;
   int n0 = G->n[0], n1 = G->n[1], n2 = G->n[2];
   memset(M, 0, sizeof(*M));
   for (int k = 0; k < n2; ++k)
     for (int j = 0; j < n1; ++j)
       for (int i = 0; i < n0; ++i) {
         int ijk[3] = {i, j, k};
-        int64_t q = e * npe + i + n0 * (j + n1 * k);
+        int64_t q = base + i + n0 * (j + n1 * k);
         double h[3] = {G->w[0][i] / 2.0, G->w[1][j] / 2.0, G->w[2][k] / 2.0};
         cons_t C; prim_t P;
         load_cons(nv, N, U, q, &C);
@@ -1294,8 +1294,8 @@ static void element_moments(const ora_mesh *m, const geom_t *G, const double *U,
             c_hi[d] = Nd - i; c_lo[d] = i;
             c_hi[da] = c_lo[da] = a;
             c_hi[db] = c_lo[db] = b;
-            int64_t qh = e * npe + c_hi[0] + n0 * (c_hi[1] + n1 * c_hi[2]);
-            int64_t ql = e * npe + c_lo[0] + n0 * (c_lo[1] + n1 * c_lo[2]);
+            int64_t qh = base + c_hi[0] + n0 * (c_hi[1] + n1 * c_hi[2]);
+            int64_t ql = base + c_lo[0] + n0 * (c_lo[1] + n1 * c_lo[2]);
             ls += mu[d][Nd - i] * (U[(int64_t)v * N + qh] - U[(int64_t)v * N + ql]);
           }
           M->c[d][v] += 1.5 * hab * ls;
@@ -1310,44 +1310,61 @@ static void element_moments(const ora_mesh *m, const geom_t *G, const double *U,
  * cells first and fixes what the limited state still leaves unphysical;
  * an element with an unphysical node is limited in every component, so no
  * node of an unlimited element needs a fix).  *nfixed: nodes changed.    */
-static int64_t limit_impl(const ora_mesh *m, double *U, int64_t *nfixed) {
+/* The geometry the limiter needs for elements of one degree: nodes,
+ * weights and spacing (G; G.nnodes is the stride of the whole state), the
+ * first moments mu of the GLL Lagrange polynomials, and whether the
+ * generalized troubled-cell test applies (degree >= 2 along some direction). */
+typedef struct {
   geom_t G;
-  *nfixed = 0;
-  if (make_geom(m, &G) != ORA_OK) return ORA_EINVAL;
-  if (m->limiter == 0) return 0;
-  if (m->bc[0] == 2 || m->bc[1] == 2 || m->bc[2] == 2) return ORA_EINVAL; /* ghost means need fixed states */
+  double mu[3][33];
+  int high;
+} limgeom_t;
+
+static void limgeom_finish(limgeom_t *L) {
+  L->high = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (L->G.n[d] >= 2) first_moments(L->G.n[d] - 1, L->G.x[d], L->mu[d]);
+    if (L->G.n[d] >= 3) L->high = 1;
+  }
+}
+
+/* Limits every troubled element component (returns their number); element e
+ * has the geometry Le[e] and its first node at base[e].  With fixing on
+ * (fix_D, fix_tau > 0), every node of an element with a limited component
+ * is then passed through fix_cons (the paper limits unphysical cells first
+ * and fixes what the limited state still leaves unphysical; an element with
+ * an unphysical node is limited in every component, so no node of an
+ * unlimited element needs a fix).  *nfixed: nodes changed.                */
+static int64_t limit_core(const ora_mesh *m, int64_t nelem, const limgeom_t *const *Le, const int64_t *base,
+                          double *U, int64_t *nfixed) {
   int nv = nvars_of(m->sys);
   double beta = m->limiter == 1 ? 2.0 : 1.0;
-  double mu[3][33];
-  int high = 0;
-  for (int d = 0; d < 3; ++d) {
-    if (G.n[d] >= 2) first_moments(G.n[d] - 1, G.x[d], mu[d]);
-    if (G.n[d] >= 3) high = 1;
-  }
-  moments_t *Mo = (moments_t *)malloc(sizeof(moments_t) * G.nelem);
+  int64_t stride = Le[0]->G.nnodes;
+  moments_t *Mo = (moments_t *)malloc(sizeof(moments_t) * nelem);
   if (!Mo) return ORA_EINVAL;
-#pragma omp parallel for schedule(static) if (G.nnodes > 4096)
-  for (int64_t e = 0; e < G.nelem; ++e) element_moments(m, &G, U, e, mu, &Mo[e]);
+#pragma omp parallel for schedule(static) if (stride > 4096)
+  for (int64_t e = 0; e < nelem; ++e) element_moments(m, &Le[e]->G, U, base[e], Le[e]->mu, &Mo[e]);
   int64_t nlim = 0, nfix = 0;
   const int fixing = m->fix_D > 0.0;
-#pragma omp parallel for schedule(static) reduction(+ : nlim, nfix) if (G.nnodes > 4096)
-  for (int64_t e = 0; e < G.nelem; ++e) {
+#pragma omp parallel for schedule(static) reduction(+ : nlim, nfix) if (stride > 4096)
+  for (int64_t e = 0; e < nelem; ++e) {
     const moments_t *Me = &Mo[e];
+    const geom_t *G = &Le[e]->G;
     int any = 0;
     for (int v = 0; v < nv; ++v) {
       double a[3] = {0.0, 0.0, 0.0};
       int troubled = Me->bad;
       for (int d = 0; d < 3; ++d) {
-        if (G.n[d] < 2) continue;
+        if (G->n[d] < 2) continue;
         double nb[2];
         for (int side = 0; side < 2; ++side) {
           int64_t en = neighbour(m, e, d, side);
           nb[side] = en >= 0 ? Mo[en].mean[v] : m->bc_u[2 * d + side][v];
         }
-        double u0 = Me->mean[v], dx = G.dx[d];
+        double u0 = Me->mean[v], dx = G->dx[d];
         double a1 = Me->c[d][v] * 2.0 / dx;
         a[d] = minmodB(a1, (nb[1] - u0) * beta / dx, (u0 - nb[0]) * beta / dx, m->lim_M, dx);
-        if (high) {
+        if (Le[e]->high) {
           double fl = Me->face[2 * d][v], fr = Me->face[2 * d + 1][v];
           double vl = u0 - minmod3(u0 - fl, u0 - nb[0], nb[1] - u0);
           double vr = u0 + minmod3(fr - u0, u0 - nb[0], nb[1] - u0);
@@ -1359,30 +1376,48 @@ static int64_t limit_impl(const ora_mesh *m, double *U, int64_t *nfixed) {
       if (!troubled) continue;
       ++nlim;
       any = 1;
-      for (int k = 0; k < G.n[2]; ++k)
-        for (int j = 0; j < G.n[1]; ++j)
-          for (int i = 0; i < G.n[0]; ++i) {
-            double xi[3] = {G.x[0][i], G.x[1][j], G.x[2][k]};
+      for (int k = 0; k < G->n[2]; ++k)
+        for (int j = 0; j < G->n[1]; ++j)
+          for (int i = 0; i < G->n[0]; ++i) {
+            double xi[3] = {G->x[0][i], G->x[1][j], G->x[2][k]};
             double u = Me->mean[v];
             for (int d = 0; d < 3; ++d)
-              if (G.n[d] >= 2) u += a[d] * 0.5 * G.dx[d] * xi[d];
-            U[(int64_t)v * G.nnodes + e * G.npe + i + G.n[0] * (j + G.n[1] * k)] = u;
+              if (G->n[d] >= 2) u += a[d] * 0.5 * G->dx[d] * xi[d];
+            U[(int64_t)v * stride + base[e] + i + G->n[0] * (j + G->n[1] * k)] = u;
           }
     }
     if (!fixing || !any) continue;
-    for (int a = 0; a < G.npe; ++a) {
+    for (int a = 0; a < G->npe; ++a) {
       double u[9];
-      int64_t q = e * G.npe + a;
-      for (int v = 0; v < nv; ++v) u[v] = U[(int64_t)v * G.nnodes + q];
+      int64_t q = base[e] + a;
+      for (int v = 0; v < nv; ++v) u[v] = U[(int64_t)v * stride + q];
       if (fix_cons(m->sys, m->gamma, m->fix_D, m->fix_tau, u)) {
         ++nfix;
-        for (int v = 0; v < nv; ++v) U[(int64_t)v * G.nnodes + q] = u[v];
+        for (int v = 0; v < nv; ++v) U[(int64_t)v * stride + q] = u[v];
       }
     }
   }
   free(Mo);
   *nfixed = nfix;
   return nlim;
+}
+
+static int64_t limit_impl(const ora_mesh *m, double *U, int64_t *nfixed) {
+  limgeom_t L;
+  *nfixed = 0;
+  if (make_geom(m, &L.G) != ORA_OK) return ORA_EINVAL;
+  if (m->limiter == 0) return 0;
+  if (m->bc[0] == 2 || m->bc[1] == 2 || m->bc[2] == 2) return ORA_EINVAL; /* ghost means need fixed states */
+  limgeom_finish(&L);
+  const limgeom_t **Le = (const limgeom_t **)malloc(sizeof(limgeom_t *) * L.G.nelem);
+  int64_t *base = (int64_t *)malloc(sizeof(int64_t) * L.G.nelem);
+  for (int64_t e = 0; e < L.G.nelem; ++e) {
+    Le[e] = &L;
+    base[e] = e * L.G.npe;
+  }
+  int64_t r = limit_core(m, L.G.nelem, Le, base, U, nfixed);
+  free(Le); free(base);
+  return r;
 }
 
 int64_t ora_limit(const ora_mesh *m, double *U) {
@@ -1413,7 +1448,7 @@ int ora_limiter_moments(const ora_mesh *m, const double *U, double *out, uint8_t
     if (G.n[d] >= 2) first_moments(G.n[d] - 1, G.x[d], mu[d]);
   for (int64_t e = 0; e < G.nelem; ++e) {
     moments_t M;
-    element_moments(m, &G, U, e, mu, &M);
+    element_moments(m, &G, U, e * G.npe, mu, &M);
     double *o = out + e * 10 * nv;
     for (int v = 0; v < nv; ++v) {
       o[v] = M.mean[v];
@@ -1707,7 +1742,7 @@ static int face_node(int N, int d, int side, int a, int b) {
 /* Mixed-degree strong-form operator.  The mesh's deg[] field is ignored;
  * deg[e] gives each element's degree.  Returns failed recoveries or <0. */
 int64_t ora_rhs_mixed(const ora_mesh *m, const int32_t *deg, const double *U, double *prim_out, double *dUdt) {
-  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos || m->fix_D != 0.0) return ORA_EINVAL; /* periodic, unlimited, ideal gas */
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->eos) return ORA_EINVAL; /* periodic, ideal gas (a limiter acts after a stage) */
   int sys = m->sys, nv = nvars_of(sys);
   double g = m->gamma;
   int64_t ne = (int64_t)m->nx * m->ny * m->nz;
@@ -1888,27 +1923,76 @@ int ora_mixed_integrate(const ora_mesh *m, const int32_t *deg, int ncomp, const 
 }
 
 /* SSP-RK3 step on a mixed-degree mesh. */
+/* The limiter on a mixed-degree mesh (periodic): each element takes the
+ * geometry of its own degree (its moments, the troubled-cell test for
+ * degree >= 2 or the slope test at degree 1, and its rewritten nodes); the
+ * neighbour means it compares with do not depend on the neighbours'
+ * degrees.  Returns the limited element components; *nfixed as ora_limit. */
+static int64_t limit_mixed_impl(const ora_mesh *m, const int32_t *deg, double *U, int64_t *nfixed) {
+  *nfixed = 0;
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->eos) return ORA_EINVAL;
+  if (m->limiter == 0) return 0;
+  int64_t ne = (int64_t)m->nx * m->ny * m->nz;
+  for (int64_t e = 0; e < ne; ++e)
+    if (deg[e] < 1 || deg[e] > 8) return ORA_EINVAL;
+  int64_t nn = ora_mixed_num_nodes((int)ne, deg);
+  limgeom_t *LG = (limgeom_t *)calloc(9, sizeof(limgeom_t));
+  int present[9] = {0};
+  for (int64_t e = 0; e < ne; ++e) present[deg[e]] = 1;
+  for (int N = 1; N <= 8; ++N) {
+    if (!present[N]) continue;
+    ora_mesh mN = *m;
+    mN.deg[0] = mN.deg[1] = mN.deg[2] = N;
+    if (make_geom(&mN, &LG[N].G) != ORA_OK) { free(LG); return ORA_EINVAL; }
+    LG[N].G.nnodes = nn;
+    limgeom_finish(&LG[N]);
+  }
+  const limgeom_t **Le = (const limgeom_t **)malloc(sizeof(limgeom_t *) * ne);
+  int64_t *base = (int64_t *)malloc(sizeof(int64_t) * ne);
+  int64_t b = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    Le[e] = &LG[deg[e]];
+    base[e] = b;
+    b += (int64_t)(deg[e] + 1) * (deg[e] + 1) * (deg[e] + 1);
+  }
+  int64_t r = limit_core(m, ne, Le, base, U, nfixed);
+  free(Le); free(base); free(LG);
+  return r;
+}
+
+int64_t ora_limit_mixed(const ora_mesh *m, const int32_t *deg, double *U, int64_t *counts) {
+  int64_t nfix = 0;
+  int64_t r = limit_mixed_impl(m, deg, U, &nfix);
+  if (r < 0) return r;
+  if (counts) { counts[0] = r; counts[1] = nfix; }
+  return r;
+}
+
 int64_t ora_step_mixed(const ora_mesh *m, const int32_t *deg, double *U, double dt) {
-  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos || m->fix_D != 0.0) return ORA_EINVAL;
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->eos) return ORA_EINVAL;
   int64_t ne = (int64_t)m->nx * m->ny * m->nz;
   int nv = nvars_of(m->sys);
   int64_t n = (int64_t)nv * ora_mixed_num_nodes((int)ne, deg);
   double *L = (double *)malloc(sizeof(double) * n);
   double *U1 = (double *)malloc(sizeof(double) * n);
   double *U2 = (double *)malloc(sizeof(double) * n);
-  int64_t nf = 0;
+  int64_t nf = 0, nfx;
+  /* with a limiter, each stage result is limited (as ora_step) */
   nf += ora_rhs_mixed(m, deg, U, NULL, L);
   ora_rk3_combine(1, dt, n, U, U, L, U1);
+  limit_mixed_impl(m, deg, U1, &nfx);
   nf += ora_rhs_mixed(m, deg, U1, NULL, L);
   ora_rk3_combine(2, dt, n, U, U1, L, U2);
+  limit_mixed_impl(m, deg, U2, &nfx);
   nf += ora_rhs_mixed(m, deg, U2, NULL, L);
   ora_rk3_combine(3, dt, n, U, U2, L, U);
+  limit_mixed_impl(m, deg, U, &nfx);
   free(L); free(U1); free(U2);
   return nf;
 }
 
 /* ------------------------------------------------------------------------ */
-/* Time stepping on a mixed-degree mesh (periodic, ideal gas, unlimited):   */
+/* Time stepping on a mixed-degree mesh (periodic, ideal gas):              */
 /* the same third-order Adams-Bashforth steps as ora_evolve_ab3 with the    */
 /* mixed-degree operator, its history started by two SSP-RK3 steps of       */
 /* ora_step_mixed; and the CFL step cfl * h_min / lambda_max with h_min the */
@@ -1917,7 +2001,7 @@ int64_t ora_step_mixed(const ora_mesh *m, const int32_t *deg, double *U, double 
 /* data, boundary conditions and time steppers).                            */
 /* ------------------------------------------------------------------------ */
 int64_t ora_evolve_ab3_mixed(const ora_mesh *m, const int32_t *deg, double *U, double dt, int64_t nsteps) {
-  if (m->bc[0] || m->bc[1] || m->bc[2] || m->limiter || m->eos || m->fix_D != 0.0) return ORA_EINVAL;
+  if (m->bc[0] || m->bc[1] || m->bc[2] || m->eos) return ORA_EINVAL;
   int64_t ne = (int64_t)m->nx * m->ny * m->nz;
   int nv = nvars_of(m->sys);
   int64_t n = (int64_t)nv * ora_mixed_num_nodes((int)ne, deg);
@@ -1938,6 +2022,8 @@ int64_t ora_evolve_ab3_mixed(const ora_mesh *m, const int32_t *deg, double *U, d
     const double *L1 = L[(s - 1) % 3], *L2 = L[(s - 2) % 3];
     for (int64_t q = 0; q < n; ++q)
       U[q] = U[q] + dt * (23.0 / 12.0 * Ln[q] - 16.0 / 12.0 * L1[q] + 5.0 / 12.0 * L2[q]);
+    int64_t nfx;
+    limit_mixed_impl(m, deg, U, &nfx);
   }
   for (int k = 0; k < 3; ++k) free(L[k]);
   return nf;

@@ -317,3 +317,86 @@ def test_mixed_stable_dt(ora):
     gap = 1.0 - math.sqrt(1.0 / 3.0 + 2.0 * math.sqrt(7.0) / 21.0)
     dxmin = min((np.array(m.hi[:]) - np.array(m.lo[:])) / np.array([3, 2, 2]))
     np.testing.assert_allclose(ora.stable_dt_mixed(m, deg, Uc, 0.3), 0.3 * 0.5 * dxmin * gap / lam, rtol=1e-14)
+
+
+def _jump_mixed(ora, system, m, deg, seed=5):
+    """x-only profile: smooth and monotone except for a drop across x = 0.37
+    (so that no limiter decision rests on a rounding-level slope)."""
+    xyz = ora.mixed_node_coords(m, deg)
+    lo, hi = np.array(m.lo[:]), np.array(m.hi[:])
+    x = (xyz[0] - lo[0]) / (hi[0] - lo[0])
+    c = np.random.default_rng(seed).uniform(0.3, 1.0, size=4)
+    step = x > 0.37
+    one = np.ones_like(x)
+    prim = np.stack([np.exp(c[0] * x) * np.where(step, 0.3, 1.0), 0.2 * np.exp(-c[1] * x), 0.1 * one,
+                     0.05 * one, np.exp(c[3] * x) * np.where(step, 0.2, 1.0)])
+    mag = None
+    if system == MHD:
+        mag = np.stack([one, 0.3 * np.exp(c[2] * x), 0.1 * one, 0.0 * one])
+    return ora.prim2cons(system, m.gamma, prim, mag)
+
+
+@pytest.mark.parametrize("system,N,lim", [(SR, 1, "minmod"), (NE, 3, "muscl"), (MHD, 2, "minmod")])
+def test_mixed_limiter_equal_degrees_is_uniform(ora, system, N, lim):
+    g = 4.0 / 3.0 if system else 1.4
+    m = ora.mesh(system, (6, 2, 2), N, g, limiter=lim)
+    deg = np.full(24, N, np.int32)
+    U = _jump_mixed(ora, system, m, deg)
+    a, na = ora.limit(m, U)
+    b, nb, _ = ora.limit_mixed(m, deg, U)
+    assert na == nb > 0
+    assert np.array_equal(a, b)
+    sa, _ = ora.step(m, U, 1e-4)
+    sb, _ = ora.step_mixed(m, deg, U, 1e-4)
+    assert np.array_equal(sa, sb)
+
+
+@pytest.mark.parametrize("system", [NE, SR, MHD])
+def test_mixed_limiter_invariants(ora, system):
+    """On a random degree mix: element means (totals) unchanged; a constant
+    state untouched; limited elements end up linear in their own nodes;
+    elements far from the jump and the periodic wrap are left alone."""
+    g = 4.0 / 3.0 if system else 1.4
+    nel = (8, 2, 2)
+    m = ora.mesh(system, nel, 2, g, limiter="minmod")
+    deg = synth.mixed_degrees(32, seed=77, lo=1, hi=6)
+    U = _jump_mixed(ora, system, m, deg)
+    V, nlim, _ = ora.limit_mixed(m, deg, U)
+    assert nlim > 0
+    # totals (element means times volumes) are kept
+    before, after = ora.mixed_integrate(m, deg, U), ora.mixed_integrate(m, deg, V)
+    assert np.all(np.abs(after - before) <= 1e-13 * np.abs(before).max())
+    # a constant state is never limited
+    C = np.tile(U[:, :1], (1, U.shape[1]))
+    W, nc, _ = ora.limit_mixed(m, deg, C)
+    assert nc == 0 and np.array_equal(W, C)
+    # changed components are linear along x (x-only data) in their element
+    off = np.concatenate([[0], np.cumsum((deg + 1) ** 3)])
+    xyz = ora.mixed_node_coords(m, deg)
+    changed = []
+    for e in range(32):
+        sl = slice(off[e], off[e + 1])
+        if np.array_equal(U[:, sl], V[:, sl]):
+            continue
+        changed.append(e % 8)
+        x = xyz[0, sl]
+        for v in range(U.shape[0]):
+            if np.array_equal(U[v, sl], V[v, sl]):
+                continue  # limiting acts per component
+            fit = np.polyfit(x, V[v, sl], 1)
+            assert np.abs(np.polyval(fit, x) - V[v, sl]).max() <= 1e-12 * max(1.0, np.abs(V[v, sl]).max())
+    # x = 0.37 lies in element column 2; columns 0 and 7 meet at the wrap
+    assert set(changed) <= {0, 1, 2, 3, 6, 7} and 2 in set(changed)
+
+
+def test_mixed_step_with_limiter_conserves(ora):
+    m = ora.mesh(SR, (8, 2, 2), 2, 4.0 / 3.0, limiter="muscl")
+    deg = synth.mixed_degrees(32, seed=78, lo=1, hi=5)
+    U = _jump_mixed(ora, SR, m, deg)
+    before = ora.mixed_integrate(m, deg, U)
+    V, nf = ora.step_mixed(m, deg, U, 2e-4)
+    W, nf2 = ora.evolve_ab3_mixed(m, deg, U, 2e-4, 4)
+    assert nf == nf2 == 0
+    for X in (V, W):
+        after = ora.mixed_integrate(m, deg, X)
+        assert np.all(np.abs(after - before) <= 1e-12 * np.abs(before).max())
