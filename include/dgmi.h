@@ -204,8 +204,11 @@ enum {
  * (the linear part keeps the Legendre modes 1, x, y, z).  Elements holding a
  * node whose primitives cannot be recovered are limited in every
  * component.  Allocates 80 nv bytes per element of device scratch on first
- * use; DGMI_EUNSUPPORTED on mixed-degree meshes and with analytic
- * boundaries (the limiter's exterior means need fixed states). */
+ * use; DGMI_EUNSUPPORTED with analytic boundaries (the limiter's exterior
+ * means need fixed states).  On mixed-degree meshes every element is limited
+ * with its own degree (its moments, the degree-1 slope test or the
+ * troubled-cell test from degree 2, its rewritten nodes) against its
+ * neighbours' means, after every RK3 stage and AB3 step. */
 dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M);
 
 /* Limit U in place with the selected limiter (DGMI_EINVAL if none).

@@ -177,6 +177,7 @@ struct dgmi_ctx {
   int lim_kind = 0;               // DGMI_LIMITER_*
   double lim_M = 0.0;
   double *d_limtab = nullptr;     // [3][8]: w/2, 3/2 int(ell xi), GLL node of the mesh degree
+  double *d_limtab_mix = nullptr; // mixed degrees: the same 24 doubles per degree, at 24 N
   double *d_mom = nullptr;        // [nelem][10][nv]
   int32_t *d_bad = nullptr;       // [nelem]
   unsigned long long *d_nlim = nullptr;  // [kLimCounters] limited-component counters (summed when read)
@@ -471,11 +472,37 @@ static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const dou
   return element_pass(c, stage, a, c->single_launch, s);
 }
 
+static dgmi::LimArgs lim_args(dgmi_ctx *c, double *U, const double *Pseed, double *Pout);
+
+// The limiter on a mixed-degree mesh (moments per degree, decisions, rewrite
+// per degree); P seeds the recoveries and receives the primitives.
+static dgmi_status mixed_limit(dgmi_ctx *c, double *U, double *P, hipStream_t s) {
+  dgmi::LimArgs a = lim_args(c, U, P, P);
+  a.off = c->d_off;
+  a.deg = c->d_deg;
+  HIP_TRY(dgmi::launch_limiter_mixed(c->sys, c->lstart, c->lcount, c->d_elist, c->d_limtab_mix, a, s));
+  return DGMI_OK;
+}
+
+// with a limiter, each stage result is limited before the next stage reads it
 static dgmi_status mixed_step_enqueue(dgmi_ctx *c, double *U, double *P, hipStream_t s) {
+  const bool limit = c->lim_kind != DGMI_LIMITER_NONE;
   dgmi_status st = mixed_pass(c, 1, U, P, c->d_U1, U, c->d_P1, 0.0, 1.0, 0, s);
+  if (st == DGMI_OK && limit) st = mixed_limit(c, c->d_U1, c->d_P1, s);
   if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U1, c->d_P1, c->d_U2, U, c->d_P2, 0.75, 0.25, 0, s);
+  if (st == DGMI_OK && limit) st = mixed_limit(c, c->d_U2, c->d_P2, s);
   if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U2, c->d_P2, U, U, P, 1.0 / 3.0, 2.0 / 3.0, 1, s);
+  if (st == DGMI_OK && limit) st = mixed_limit(c, U, P, s);
   return st;
+}
+
+// A captured mixed-degree step bakes in the limiter and fixing settings:
+// changing them drops it (the next step captures again).
+static void drop_graph(dgmi_ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
 }
 
 // Time every tile option of every degree present on a state at rest and keep
@@ -565,6 +592,7 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_lam);
   (void)hipFree(c->d_L);
   (void)hipFree(c->d_limtab);
+  (void)hipFree(c->d_limtab_mix);
   (void)hipFree(c->d_mom);
   (void)hipFree(c->d_bad);
   (void)hipFree(c->d_nlim);
@@ -1062,8 +1090,6 @@ dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M) {
   if (!ctx) return fail(DGMI_EINVAL, "dgmi_set_limiter: null context");
   if (kind < DGMI_LIMITER_NONE || kind > DGMI_LIMITER_MUSCL) return fail(DGMI_EINVAL, "dgmi_set_limiter: unknown kind");
   if (!(M >= 0.0) || !std::isfinite(M)) return fail(DGMI_EINVAL, "dgmi_set_limiter: M must be finite and >= 0");
-  if (ctx->mixed && kind != DGMI_LIMITER_NONE)
-    return fail(DGMI_EUNSUPPORTED, "dgmi_set_limiter: the limiter is implemented for uniform degrees only");
   if (kind != DGMI_LIMITER_NONE && (ctx->bc[0] == 2 || ctx->bc[1] == 2 || ctx->bc[2] == 2))
     return fail(DGMI_EUNSUPPORTED, "dgmi_set_limiter: not combined with analytic boundaries");
   if (kind != DGMI_LIMITER_NONE && !ctx->d_mom) {
@@ -1077,19 +1103,41 @@ dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M) {
     // per node index of the mesh degree: w/2, 3/2 int(ell_i xi), x_i; the
     // first moment int(ell_i xi) is w_i x_i (GLL quadrature is exact for the
     // degree N+1 integrand when N >= 2) and -+1/3 at degree 1
-    const int N = ctx->degree;
-    double x[8], w[8], tab[24] = {0};
-    gll_nodes(N, x, w);
-    for (int i = 0; i <= N; ++i) {
-      tab[i] = 0.5 * w[i];
-      tab[8 + i] = 1.5 * (N == 1 ? (i ? 1.0 / 3.0 : -1.0 / 3.0) : w[i] * x[i]);
-      tab[16 + i] = x[i];
+    double x[8], w[8];
+    if (!ctx->mixed) {
+      const int N = ctx->degree;
+      double tab[24] = {0};
+      gll_nodes(N, x, w);
+      for (int i = 0; i <= N; ++i) {
+        tab[i] = 0.5 * w[i];
+        tab[8 + i] = 1.5 * (N == 1 ? (i ? 1.0 / 3.0 : -1.0 / 3.0) : w[i] * x[i]);
+        tab[16 + i] = x[i];
+      }
+      if (hipMemcpy(ctx->d_limtab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(DGMI_EHIP, "dgmi_set_limiter: table upload failed");
+    } else {
+      // the same table for every degree a mixed mesh may hold
+      double mtab[24 * 8] = {0};
+      for (int Nm = 1; Nm <= dgmi::kMaxMixedDegree; ++Nm) {
+        gll_nodes(Nm, x, w);
+        for (int i = 0; i <= Nm; ++i) {
+          mtab[24 * Nm + i] = 0.5 * w[i];
+          mtab[24 * Nm + 8 + i] = 1.5 * (Nm == 1 ? (i ? 1.0 / 3.0 : -1.0 / 3.0) : w[i] * x[i]);
+          mtab[24 * Nm + 16 + i] = x[i];
+        }
+      }
+      if (hipMalloc(&ctx->d_limtab_mix, sizeof(mtab)) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->d_limtab_mix = nullptr;
+        return fail(DGMI_ENOMEM, "dgmi_set_limiter: device allocation failed");
+      }
+      if (hipMemcpy(ctx->d_limtab_mix, mtab, sizeof(mtab), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(DGMI_EHIP, "dgmi_set_limiter: table upload failed");
     }
-    if (hipMemcpy(ctx->d_limtab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess)
-      return fail(DGMI_EHIP, "dgmi_set_limiter: table upload failed");
   }
   ctx->lim_kind = kind;
   ctx->lim_M = M;
+  drop_graph(ctx);
   return DGMI_OK;
 }
 
@@ -1098,6 +1146,7 @@ dgmi_status dg_limit(dgmi_ctx *ctx, double *U, double *prim_inout, void *stream)
   if (ctx->lim_kind == DGMI_LIMITER_NONE) return fail(DGMI_EINVAL, "dg_limit: no limiter set (dgmi_set_limiter)");
   if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
     return fail(DGMI_EINVAL, "dg_limit: U and prim_inout must be distinct device pointers");
+  if (ctx->mixed) return mixed_limit(ctx, U, prim_inout, (hipStream_t)stream);
   HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, true, lim_args(ctx, U, prim_inout, prim_inout),
                                (hipStream_t)stream));
   return DGMI_OK;
@@ -1200,8 +1249,14 @@ dgmi_status dg_step_ab3(dgmi_ctx *ctx, double *U, double *prim_inout, double dt,
     b.nfail = ctx->d_nfail;
     b.poly = (ctx->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0;
     HIP_TRY(dgmi::launch_ab3(ctx->sys, b, s));
-    if (ctx->lim_kind != DGMI_LIMITER_NONE)
-      HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, true, lim_args(ctx, U, prim_inout, prim_inout), s));
+    if (ctx->lim_kind != DGMI_LIMITER_NONE) {
+      if (ctx->mixed) {
+        st = mixed_limit(ctx, U, prim_inout, s);
+        if (st != DGMI_OK) return st;
+      } else {
+        HIP_TRY(dgmi::launch_limiter(ctx->sys, ctx->degree, true, lim_args(ctx, U, prim_inout, prim_inout), s));
+      }
+    }
     ctx->time += dt;
   }
   ctx->ab_count = k + 1;
@@ -1212,6 +1267,7 @@ dgmi_status dgmi_set_fixing(dgmi_ctx *ctx, double D_min, double tau_min) {
   if (!ctx) return fail(DGMI_EINVAL, "dgmi_set_fixing: null context");
   if (D_min == 0.0 && tau_min == 0.0) {
     ctx->fix_D = ctx->fix_tau = 0.0;
+    drop_graph(ctx);
     return DGMI_OK;
   }
   if (ctx->sys == DGMI_NEWTONIAN_EULER)
@@ -1220,6 +1276,7 @@ dgmi_status dgmi_set_fixing(dgmi_ctx *ctx, double D_min, double tau_min) {
     return fail(DGMI_EINVAL, "dgmi_set_fixing: D_min and tau_min must be finite and > 0 (both 0: off)");
   ctx->fix_D = D_min;
   ctx->fix_tau = tau_min;
+  drop_graph(ctx);
   return DGMI_OK;
 }
 

@@ -83,7 +83,19 @@ struct LimArgs {
   // fixing of every node of an element with a limited component)
   double fix_D, fix_tau;
   unsigned long long *nfix;   // nodes changed by the fixing
+  // mixed-degree meshes: the elements of one degree (elist, nlist), every
+  // element's first node (off) and degree (deg; null on uniform meshes)
+  const int32_t *elist;
+  int64_t nlist;
+  const int64_t *off;
+  const int32_t *deg;
 };
+// The limiter on a mixed-degree mesh: moments per degree over the elements of
+// that degree (elist_all + lstart[N], lcount[N] of them), the decisions over
+// every element, the rewrite per degree.  tabs: per degree N the 24 doubles
+// w/2, 3/2 int(ell xi), GLL node at tabs + 24 N.
+hipError_t launch_limiter_mixed(int sys, const int64_t *lstart, const int64_t *lcount, const int32_t *elist_all,
+                                const double *tabs, const LimArgs &a, hipStream_t s);
 // Pointwise fixing of n conserved states in place (SoA rows of n); counts the
 // changed states into *nfix.
 hipError_t launch_fix_conserved(int sys, double gamma, double D_min, double tau_min, double *U, int64_t n,

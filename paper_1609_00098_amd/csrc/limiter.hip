@@ -58,7 +58,9 @@ __device__ __forceinline__ void store_prims(double *Pout, int64_t nn, int64_t q,
   Pout[4 * nn + q] = P.p;
 }
 
-template <int SYS, int N>
+// MIXED: the block's slots index the element list of this degree (A.elist,
+// A.nlist) and an element's nodes start at A.off[e]; otherwise slot = element.
+template <int SYS, int N, bool MIXED = false>
 __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_moments_kernel(const LimArgs A) {
   using C = LimCfg<SYS, N>;
   constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
@@ -74,10 +76,12 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_moments_ker
   if (tid < EPB) sbad[tid] = 0;
   __syncthreads();
   const int le = tid / NPE, a = tid - le * NPE;
-  const int64_t e0 = (int64_t)blockIdx.x * EPB, e = e0 + le;
+  const int64_t e0 = (int64_t)blockIdx.x * EPB, sl = e0 + le;
+  const int64_t cnt = MIXED ? A.nlist : A.nelem;
   const int64_t nn = A.nnodes;
-  if (le < EPB && e < A.nelem) {
-    const int64_t q = e * NPE + a;
+  if (le < EPB && sl < cnt) {
+    const int64_t e = MIXED ? (int64_t)A.elist[sl] : sl;
+    const int64_t q = (MIXED ? A.off[e] : e * NPE) + a;
     double u[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -89,8 +93,8 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_moments_ker
     if (!R.ok) sbad[le] = 1;
   }
   __syncthreads();
-  element_moments<N, NV, EPB, C::THREADS>(su, lines, sh, smu, A.mom, e0, A.nelem);
-  if (tid < EPB && e0 + tid < A.nelem) A.bad[e0 + tid] = sbad[tid];
+  element_moments<N, NV, EPB, C::THREADS>(su, lines, sh, smu, A.mom, e0, cnt, MIXED ? A.elist : nullptr);
+  if (tid < EPB && e0 + tid < cnt) A.bad[MIXED ? (int64_t)A.elist[e0 + tid] : e0 + tid] = sbad[tid];
 }
 
 // One thread per (element, component): troubled or not, and the limited
@@ -107,6 +111,8 @@ __global__ void __launch_bounds__(256) limiter_decide_kernel(const LimArgs A) {
     double *me = A.mom + e * 10 * NV;
     const double u0 = me[v];
     troubled = A.bad[e] != 0;
+    // the troubled-cell test from degree 2 on (per element on mixed meshes)
+    const bool high = A.deg ? A.deg[e] >= 2 : N >= 2;
     double ad[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -116,7 +122,7 @@ __global__ void __launch_bounds__(256) limiter_decide_kernel(const LimArgs A) {
       const double dx = A.dx[d];
       const double a1 = me[(1 + d) * NV + v] * (2.0 / dx);
       ad[d] = minmodB(a1, (nhi - u0) * A.beta / dx, (u0 - nlo) * A.beta / dx, A.M, dx);
-      if (N >= 2) {
+      if (high) {
         const double fl = me[(4 + 2 * d) * NV + v], fr = me[(5 + 2 * d) * NV + v];
         const double vl = u0 - minmod3(u0 - fl, u0 - nlo, nhi - u0);
         const double vr = u0 + minmod3(fr - u0, u0 - nlo, nhi - u0);
@@ -135,7 +141,7 @@ __global__ void __launch_bounds__(256) limiter_decide_kernel(const LimArgs A) {
   if ((threadIdx.x & 63) == 0 && bal) atomicAdd(A.nlim + (blockIdx.x & 63), (unsigned long long)__popcll(bal));
 }
 
-template <int SYS, int N>
+template <int SYS, int N, bool MIXED = false>
 __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_apply_kernel(const LimArgs A) {
   using C = LimCfg<SYS, N>;
   constexpr int NP = C::NP, NPE = C::NPE, NV = C::NV, EPB = C::EPB;
@@ -145,10 +151,12 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_apply_kerne
   if (tid < EPB) sany[tid] = 0;
   __syncthreads();
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
+  const int64_t cnt = MIXED ? A.nlist : A.nelem;
   for (int t = tid; t < EPB * NV; t += C::THREADS) {
     const int le = t / NV, v = t - le * NV;
-    const int64_t e = e0 + le;
-    if (e >= A.nelem) continue;
+    const int64_t sl = e0 + le;
+    if (sl >= cnt) continue;
+    const int64_t e = MIXED ? (int64_t)A.elist[sl] : sl;
     const double *me = A.mom + e * 10 * NV;
     const bool tr = me[4 * NV + v] != 0.0;
     strb[t] = tr;
@@ -162,9 +170,10 @@ __global__ void __launch_bounds__((LimCfg<SYS, N>::THREADS)) limiter_apply_kerne
   }
   __syncthreads();
   const int le = tid / NPE, a = tid - le * NPE;
-  const int64_t e = e0 + le;
-  if (le >= EPB || e >= A.nelem || !sany[le]) return;
-  const int64_t nn = A.nnodes, q = e * NPE + a;
+  const int64_t sl = e0 + le;
+  if (le >= EPB || sl >= cnt || !sany[le]) return;
+  const int64_t e = MIXED ? (int64_t)A.elist[sl] : sl;
+  const int64_t nn = A.nnodes, q = (MIXED ? A.off[e] : e * NPE) + a;
   const int i = a % NP, j = (a / NP) % NP, k = a / (NP * NP);
   const double xo = 0.5 * A.dx[0] * A.xi[i], yo = 0.5 * A.dx[1] * A.xi[j], zo = 0.5 * A.dx[2] * A.xi[k];
   double u[NV];
@@ -257,6 +266,62 @@ static hipError_t launch_lim_sys(int N, bool moments, const LimArgs &a, hipStrea
     case 5: return launch_lim_n<SYS, 5>(moments, a, s);
     case 6: return launch_lim_n<SYS, 6>(moments, a, s);
     case 7: return launch_lim_n<SYS, 7>(moments, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int SYS, int N>
+static hipError_t lim_mixed_n(bool apply, LimArgs a, const int64_t *lstart, const int64_t *lcount,
+                              const int32_t *elist_all, const double *tabs, hipStream_t s) {
+  using C = LimCfg<SYS, N>;
+  if (lcount[N] <= 0) return hipSuccess;
+  a.elist = elist_all + lstart[N];
+  a.nlist = lcount[N];
+  a.h = tabs + 24 * N;
+  a.mu = tabs + 24 * N + 8;
+  a.xi = tabs + 24 * N + 16;
+  const int64_t nb = (a.nlist + C::EPB - 1) / C::EPB;
+  if (nb > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+  if (apply)
+    hipLaunchKernelGGL((limiter_apply_kernel<SYS, N, true>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL((limiter_moments_kernel<SYS, N, true>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int SYS>
+static hipError_t lim_mixed_sys(const int64_t *lstart, const int64_t *lcount, const int32_t *elist_all,
+                                const double *tabs, const LimArgs &a, hipStream_t s) {
+  if (!a.deg || !a.off) return hipErrorInvalidValue;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool apply = pass == 1;
+    if (apply) {  // decisions over every element, each with its own degree
+      const int64_t nd = (a.nelem * SysTraits<SYS>::nv + 255) / 256;
+      if (nd > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+      if (nd > 0) {
+        hipLaunchKernelGGL((limiter_decide_kernel<2, SysTraits<SYS>::nv>), dim3((unsigned)nd), dim3(256), 0, s, a);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+      }
+    }
+    hipError_t err;
+    if ((err = lim_mixed_n<SYS, 1>(apply, a, lstart, lcount, elist_all, tabs, s)) != hipSuccess) return err;
+    if ((err = lim_mixed_n<SYS, 2>(apply, a, lstart, lcount, elist_all, tabs, s)) != hipSuccess) return err;
+    if ((err = lim_mixed_n<SYS, 3>(apply, a, lstart, lcount, elist_all, tabs, s)) != hipSuccess) return err;
+    if ((err = lim_mixed_n<SYS, 4>(apply, a, lstart, lcount, elist_all, tabs, s)) != hipSuccess) return err;
+    if ((err = lim_mixed_n<SYS, 5>(apply, a, lstart, lcount, elist_all, tabs, s)) != hipSuccess) return err;
+    if ((err = lim_mixed_n<SYS, 6>(apply, a, lstart, lcount, elist_all, tabs, s)) != hipSuccess) return err;
+    if ((err = lim_mixed_n<SYS, 7>(apply, a, lstart, lcount, elist_all, tabs, s)) != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_limiter_mixed(int sys, const int64_t *lstart, const int64_t *lcount, const int32_t *elist_all,
+                                const double *tabs, const LimArgs &a, hipStream_t s) {
+  switch (sys) {
+    case kNE: return lim_mixed_sys<kNE>(lstart, lcount, elist_all, tabs, a, s);
+    case kSR: return lim_mixed_sys<kSR>(lstart, lcount, elist_all, tabs, a, s);
+    case kMHD: return lim_mixed_sys<kMHD>(lstart, lcount, elist_all, tabs, a, s);
   }
   return hipErrorInvalidValue;
 }

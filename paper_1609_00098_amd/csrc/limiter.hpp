@@ -30,10 +30,13 @@ __device__ __forceinline__ double minmodB(double a1, double a2, double a3, doubl
 // which U is constant gives exactly zero) and its two end values; then each
 // moment is a sum over at most (N+1)^2 line results.  sh = w/2 and
 // smu = 3/2 int(ell xi) per node index (LDS); lines: LDS scratch of
-// 4 EPB NV (N+1)^2 doubles.  Every thread of the block must call it.
+// 4 EPB NV (N+1)^2 doubles.  The block holds slots e0 .. e0+EPB-1 of nelem;
+// slot k is element eids[k] (mixed-degree lists) or k itself (eids null).
+// Every thread of the block must call it.
 template <int N, int NV, int EPB, int BT>
 __device__ __forceinline__ void element_moments(const double *su, double *lines, const double *sh,
-                                                const double *smu, double *mom, int64_t e0, int64_t nelem) {
+                                                const double *smu, double *mom, int64_t e0, int64_t nelem,
+                                                const int32_t *eids = nullptr) {
   constexpr int NP = N + 1, NF = NP * NP, NPE = NP * NF;
   const int tid = threadIdx.x;
   for (int t = tid; t < EPB * NV * NF; t += BT) {
@@ -76,7 +79,8 @@ __device__ __forceinline__ void element_moments(const double *su, double *lines,
       const int sj = f < 2 ? 1 : NP, sk = f < 2 ? NP : 1;
       for (int k = 0; k < NP; ++k) s += sh[k] * A[(hi ? N : 0) * sj + k * sk];
     }
-    mom[((e0 + le) * 10 + kind) * NV + v] = s;
+    const int64_t eid = eids ? (int64_t)eids[e0 + le] : e0 + le;
+    mom[(eid * 10 + kind) * NV + v] = s;
   }
 }
 

@@ -256,3 +256,95 @@ def test_mixed_stable_dt_parity(ora, dg):
     dt_o = ora.stable_dt_mixed(m, deg, U, 0.3)
     dt = float(to_host(dg.dgmi_stable_dt(mesh, to_dev(U), to_dev(Po), 0.3))[0])
     assert abs(dt - dt_o) <= 1e-14 * dt_o
+
+
+def _jump_state(ora, system, m, deg, seed=5):
+    """x-only profile, smooth and monotone except for a drop across x = 0.37
+    (no limiter decision rests on a rounding-level slope)."""
+    xyz = ora.mixed_node_coords(m, deg)
+    lo, hi = np.array(m.lo[:]), np.array(m.hi[:])
+    x = (xyz[0] - lo[0]) / (hi[0] - lo[0])
+    c = np.random.default_rng(seed).uniform(0.3, 1.0, size=4)
+    step = x > 0.37
+    one = np.ones_like(x)
+    prim = np.stack([np.exp(c[0] * x) * np.where(step, 0.3, 1.0), 0.2 * np.exp(-c[1] * x), 0.1 * one,
+                     0.05 * one, np.exp(c[3] * x) * np.where(step, 0.2, 1.0)])
+    mag = None
+    if system == MHD:
+        mag = np.stack([one, 0.3 * np.exp(c[2] * x), 0.1 * one, 0.0 * one])
+    return ora.prim2cons(system, m.gamma, prim, mag), prim
+
+
+LIM_CASES = [(NE, "minmod", 77), (SR, "muscl", 78), (MHD, "minmod", 79)]
+
+
+@pytest.mark.parametrize("system,lim,seed", LIM_CASES)
+def test_mixed_limit_parity(ora, dg, system, lim, seed):
+    """Limiter on a random mix of degrees 1..6: decisions equal the oracle's,
+    limited U within 1e-13 norm-wise, primitives within 1e-12."""
+    g = G[system]
+    nel = (8, 2, 2)
+    deg = synth.mixed_degrees(32, seed=seed, lo=1, hi=6)
+    m = ora.mesh(system, nel, 2, g, kappa=0.5, limiter=lim)
+    mesh = dg.Mesh(system, nel, 0, g, kappa=0.5, degrees=deg)
+    dg.dgmi_set_limiter(mesh, {"minmod": dg.LIMITER_MINMOD, "muscl": dg.LIMITER_MUSCL}[lim], 0.0)
+    U, prim = _jump_state(ora, system, m, deg)
+    Uo, nlim, _ = ora.limit_mixed(m, deg, U)
+    assert nlim > 0
+    Po, _, nf = ora.cons2prim(system, g, Uo)
+    assert nf == 0
+    Ud, Pd = to_dev(U), to_dev(prim)
+    dg.dgmi_limited(mesh)
+    dg.dg_limit(mesh, Ud, Pd)
+    assert dg.dgmi_limited(mesh) == nlim
+    assert dg.dgmi_failures(mesh) == 0
+    assert np.all(normwise_err(to_host(Ud), Uo, floor_scale=1.0) <= 1e-13)
+    assert np.all(normwise_err(to_host(Pd), Po, floor_scale=1.0) <= 1e-12)
+
+
+@pytest.mark.parametrize("system,lim,seed", LIM_CASES)
+def test_mixed_step_with_limiter_parity(ora, dg, system, lim, seed):
+    """Limited RK3 steps (direct and graph-replayed) and limited AB3 steps on a
+    random degree mix against the oracle, within the step budget."""
+    import torch
+    g = G[system]
+    nel = (8, 2, 2)
+    deg = synth.mixed_degrees(32, seed=seed, lo=1, hi=6)
+    m = ora.mesh(system, nel, 2, g, kappa=0.5, limiter=lim)
+    U, prim = _jump_state(ora, system, m, deg)
+    U, _, _ = ora.limit_mixed(m, deg, U)
+    L, Po, _ = ora.rhs_mixed(m, deg, U)
+    dt = 2e-3 / float(max(np.abs(L[0] / U[0]).max(), np.abs(L[4] / U[4]).max()))
+    eps = np.finfo(np.float64).eps
+    budget = 4e-12 * dt * np.maximum(np.abs(L).max(axis=1), 1e-3 * np.abs(L).max()) + 32 * eps * np.abs(U).max(axis=1)
+    kind = {"minmod": dg.LIMITER_MINMOD, "muscl": dg.LIMITER_MUSCL}[lim]
+    Uo, nf = ora.step_mixed(m, deg, U, dt)
+    assert nf == 0
+    res = []
+    for use_graph in (False, True):
+        mesh = dg.Mesh(system, nel, 0, g, kappa=0.5, degrees=deg)
+        dg.dgmi_set_limiter(mesh, kind, 0.0)
+        Ud, Pd = to_dev(U), to_dev(Po)
+        s = torch.cuda.Stream() if use_graph else None
+        if s is not None:
+            s.wait_stream(torch.cuda.current_stream())
+        dg.dgmi_limited(mesh)
+        dg.dg_step(mesh, Ud, Pd, dt, stream=s)
+        torch.cuda.synchronize()
+        assert dg.dgmi_limited(mesh) > 0
+        assert dg.dgmi_failures(mesh) == 0
+        diff = np.abs(to_host(Ud) - Uo).max(axis=1)
+        assert np.all(diff <= budget), (use_graph, diff, budget)
+        res.append(to_host(Ud))
+    assert np.array_equal(res[0], res[1])
+    n = 5
+    Ua, nf = ora.evolve_ab3_mixed(m, deg, U, dt, n)
+    assert nf == 0
+    mesh = dg.Mesh(system, nel, 0, g, kappa=0.5, degrees=deg)
+    dg.dgmi_set_limiter(mesh, kind, 0.0)
+    Ud, Pd = to_dev(U), to_dev(Po)
+    for _ in range(n):
+        dg.dg_step_ab3(mesh, Ud, Pd, dt)
+    assert dg.dgmi_failures(mesh) == 0
+    diff = np.abs(to_host(Ud) - Ua).max(axis=1)
+    assert np.all(diff <= n * budget), (diff, n * budget)
