@@ -88,7 +88,8 @@ struct RhsCfg {
   static constexpr int WORK = (SYS == kMHD && FACE_TASKS > EPB * NPE) ? FACE_TASKS : EPB * NPE;
   static constexpr int THREADS = ((WORK + 63) / 64) * 64;
   // LDS (doubles): volume flux [EPB][NV][NPE], own state [EPB][NV][NPE]
-  // (mixed-degree and limited-stage kernels only), face slots
+  // (mixed-degree kernels only; the limited stage keeps [EPB][NPE] flags
+  // there), face slots
   // [EPB][NV][6][NF], interior wave speeds [EPB][6][NF] (HLL:
   // [EPB][2][6][NF], the largest then the smallest along the outward normal).
   // The uniform operator and stage kernels read a face node's own state back
@@ -129,9 +130,12 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   using C = RhsCfg<SYS, N, EPB_, FLUX>;
   constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
   double *svol = smem;
-  constexpr bool OWNL = MOM || MIXED;
+  // own state in LDS only for the mixed-degree kernels; the limited stage
+  // keeps one flag per node there (its recovery results)
+  constexpr bool OWNL = MIXED;
+  constexpr int OWN_SZ = MIXED ? C::OWN : (MOM ? EPB_ * C::NPE : 0);
   double *sown = svol + C::VOL;
-  double *sslot = sown + (OWNL ? C::OWN : 0);
+  double *sslot = sown + OWN_SZ;
   double *sspd = sslot + C::SLOT;
   double *sD = sspd + C::SPD;
 
@@ -405,7 +409,7 @@ template <int SYS, int N, int STAGE, int EPB_ = default_epb<SYS, N>(), bool MIXE
           bool MOM = false>
 __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(const RhsArgs A) {
   using C = RhsCfg<SYS, N, EPB_, FLUX>;
-  __shared__ double smem[C::LDS - ((MOM || MIXED) ? 0 : C::OWN)];
+  __shared__ double smem[C::LDS - C::OWN + (MIXED ? C::OWN : (MOM ? C::EPB * C::NPE : 0))];
   // XCD-major block order: hardware block b runs on XCD b % 8, which walks
   // its own contiguous range of the processing order.
   const int per = (A.nblocks + 7) >> 3;
