@@ -174,3 +174,61 @@ def test_fixing_arguments(dg):
         dg.dgmi_fix_conserved(SR, 3.0, DMIN, TMIN, U)
     with pytest.raises(dg.DgmiError):
         dg.dgmi_fix_conserved(SR, 4.0 / 3.0, 0.0, TMIN, U)
+
+
+def _komissarov(ora, dg, case, fix=True):
+    from tests.test_oracle_komissarov import states
+    g, T, ((pl, ml, UL), (pr, mr, UR)) = states(ora, case)
+    lo, hi, nx = -2.0, 2.0, 400  # element width 0.01, two GLL points per direction
+    bl, br = list(pl) + list(ml), list(pr) + list(mr)
+    G = dg.Mesh(MHD, (nx, 1, 1), 1, g, lo=(lo, 0, 0), hi=(hi, 1, 1))
+    dg.dgmi_set_boundary(G, 0, bl, br)
+    dg.dgmi_set_limiter(G, dg.LIMITER_MUSCL, 0.0)
+    if fix:
+        dg.dgmi_set_fixing(G, DMIN, TMIN)
+    m = ora.mesh(MHD, (nx, 1, 1), 1, g, lo=(lo, 0, 0), hi=(hi, 1, 1), limiter="muscl",
+                 fix=(DMIN, TMIN) if fix else None, bc={0: (bl, br)})
+    x = to_host(G.node_coords())[0]
+    left = x < 0
+    prim = np.where(left, pl[:, None], pr[:, None])
+    mag = np.where(left, ml[:, None], mr[:, None])
+    U = ora.prim2cons(MHD, g, prim, mag)
+    return G, m, U, prim, x, T, (UL, UR, pl, pr), (lo, hi)
+
+
+@pytest.mark.parametrize("case,speed,dtol", [("slow_shock", 0.5, 0.01), ("fast_shock", 0.2, 0.03)])
+def test_komissarov_shocks_on_gpu(ora, dg, case, speed, dtol):
+    """The RMHD fast and slow shock tests of tab:komissarov (element width
+    0.01, two GLL points per direction, SSP-RK3, MUSCL with unphysical
+    elements flagged, conserved-variable fixing): the first ten steps match
+    the oracle; at t_final the conserved D puts the shock at s t_final
+    (within 1%, measured 0.5%; fast shock 3%, measured 1.7%: the fixing
+    that its W = 25 inflow needs is not conservative) and the density crosses its mid value within 4
+    elements of s t_final (s from the Rankine-Hugoniot conditions of the
+    printed states: 0.5, 0.2)."""
+    G, m, U, prim, x, T, (UL, UR, pl, pr), (lo, hi) = _komissarov(ora, dg, case)
+    dt = 0.002
+    Ud, Pd = to_dev(U), to_dev(prim)
+    Uo = U
+    for _ in range(10):
+        dg.dg_step(G, Ud, Pd, dt)
+    for _ in range(10):
+        Uo, nf = ora.step(m, Uo, dt)
+        assert nf == 0
+    err = normwise_err(to_host(Ud), Uo, floor_scale=1.0)
+    assert np.all(err <= 1e-10), err
+    nst = int(round(T / dt))
+    for _ in range(nst - 10):
+        dg.dg_step(G, Ud, Pd, dt)
+    assert dg.dgmi_failures(G) == 0
+    Ug = to_host(Ud)
+    assert np.isfinite(Ug).all()
+    tot = ora.integrate(m, Ug)
+    xs = (tot[0] - UR[0] * hi + UL[0] * lo) / (UL[0] - UR[0])
+    rho = to_host(Pd)[0]
+    mid = 0.5 * (pl[0] + pr[0])
+    cross = x[np.where((rho[:-1] - mid) * (rho[1:] - mid) <= 0)[0]]
+    print(f"{case}: D-weighted shock position {xs:.4f}, density mid crossings {np.unique(cross)}, "
+          f"expected {speed * T}", flush=True)
+    assert abs(xs - speed * T) <= dtol * speed * T, (xs, speed * T)
+    assert len(cross) > 0 and np.all(np.abs(cross - speed * T) <= 0.04), (cross, speed * T)
