@@ -184,6 +184,9 @@ struct dgmi_ctx {
   // atmosphere floors / conserved-variable fixing inside the limiter (0, 0: off)
   double fix_D = 0.0, fix_tau = 0.0;
   unsigned long long *d_nfix = nullptr;  // nodes changed by the fixing
+  // recoveries that fail before a limiter pass (which recovers those nodes
+  // again and counts what still fails): counted here, never reported
+  unsigned long long *d_nfail_pre = nullptr;
   // time stepping helpers
   double hmin = 0.0;              // smallest GLL node spacing on the physical grid
   double *d_lam = nullptr;        // device scalar: largest characteristic speed
@@ -430,7 +433,7 @@ static dgmi_status element_pass(dgmi_ctx *c, int stage, const dgmi::RhsArgs &bas
     const int N = c->lane_order[i], k = c->lane_of[N];
     dgmi::RhsArgs a = mix_args(c, N);
     a.U = base.U; a.P = base.P; a.out = base.out; a.Un = base.Un; a.Pout = base.Pout;
-    a.a = base.a; a.b = base.b; a.full_prims = base.full_prims;
+    a.a = base.a; a.b = base.b; a.full_prims = base.full_prims; a.nfail = base.nfail;
     if (!used[k]) HIP_TRY(hipStreamWaitEvent(c->side[k], c->ev_fork, 0));
     used[k] = true;
     HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, c->epb[N], stage, a, c->side[k]));
@@ -469,6 +472,9 @@ static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const dou
   HIP_TRY(dgmi::launch_mortar(c->sys, mortar_args(c, U, P), s));
   dgmi::RhsArgs a = mix_args(c, dgmi::kMaxMixedDegree);
   a.U = U; a.P = P; a.out = out; a.Un = Un; a.Pout = Pout; a.a = wa; a.b = wb; a.full_prims = full_prims;
+  // with a limiter the stage's recoveries precede the limiter pass, which
+  // recovers those nodes again and reports what still fails
+  if (stage != 0 && c->lim_kind != DGMI_LIMITER_NONE) a.nfail = c->d_nfail_pre;
   return element_pass(c, stage, a, c->single_launch, s);
 }
 
@@ -597,6 +603,7 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_bad);
   (void)hipFree(c->d_nlim);
   (void)hipFree(c->d_nfix);
+  (void)hipFree(c->d_nfail_pre);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   for (int k = 0; k < 8; ++k) {
@@ -695,6 +702,7 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
       hipMalloc(&c->d_bc, sizeof(c->hbc)) != hipSuccess || hipMalloc(&c->d_limtab, 24 * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->d_nlim, kLimCounters * sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->d_nfix, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&c->d_nfail_pre, sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->d_lam, sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     ctx_free(c);
@@ -706,6 +714,7 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
       hipMemset(c->d_nfail, 0, sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->d_nlim, 0, kLimCounters * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->d_nfix, 0, sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_nfail_pre, 0, sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->d_bc, 0, sizeof(c->hbc)) != hipSuccess) {
     ctx_free(c);
     return fail(DGMI_EHIP, "dgmi_create: table upload failed");
@@ -1246,7 +1255,9 @@ dgmi_status dg_step_ab3(dgmi_ctx *ctx, double *U, double *prim_inout, double dt,
     b.nnodes = ctx->nnodes;
     b.dt = dt;
     b.gamma = ctx->gamma;
-    b.nfail = ctx->d_nfail;
+    // with a limiter the limiter pass recovers the new state again and
+    // reports what still fails
+    b.nfail = ctx->lim_kind != DGMI_LIMITER_NONE ? ctx->d_nfail_pre : ctx->d_nfail;
     b.poly = (ctx->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0;
     HIP_TRY(dgmi::launch_ab3(ctx->sys, b, s));
     if (ctx->lim_kind != DGMI_LIMITER_NONE) {

@@ -348,3 +348,41 @@ def test_mixed_step_with_limiter_parity(ora, dg, system, lim, seed):
     assert dg.dgmi_failures(mesh) == 0
     diff = np.abs(to_host(Ud) - Ua).max(axis=1)
     assert np.all(diff <= n * budget), (diff, n * budget)
+
+
+@pytest.mark.parametrize("system", [SR, MHD])
+def test_mixed_blast_with_limiter_and_fixing(ora, dg, system):
+    """A periodic blast (pressure 1000 against 0.01, gamma 5/3) on a mix of
+    degrees 1..3, MUSCL with the conserved-variable fixing: limited alone it
+    goes non-finite within eight steps; with the fixing every step matches
+    the oracle within 1e-10 per variable, the fixing acts, and no recovery
+    fails."""
+    g = 5.0 / 3.0
+    nx = 60
+    deg = synth.mixed_degrees(nx, seed=91, lo=1, hi=3)
+    m = ora.mesh(system, (nx, 1, 1), 2, g, lo=(-0.5, 0, 0), hi=(0.5, 1, 1), limiter="muscl", fix=(1e-10, 1e-12))
+    mesh = dg.Mesh(system, (nx, 1, 1), 0, g, lo=(-0.5, 0, 0), hi=(0.5, 1, 1), degrees=deg)
+    dg.dgmi_set_limiter(mesh, dg.LIMITER_MUSCL, 0.0)
+    dg.dgmi_set_fixing(mesh, 1e-10, 1e-12)
+    x = ora.mixed_node_coords(m, deg)[0]
+    n = len(x)
+    prim = np.vstack([np.ones(n), np.zeros((3, n)), np.where(np.abs(x) < 0.1, 1000.0, 0.01)])
+    mag = None
+    if system == MHD:
+        mag = np.zeros((4, n))
+        mag[0] = 0.5
+    U = ora.prim2cons(system, g, prim, mag)
+    dt = 0.1 / (3 * nx)
+    Ud, Pd = to_dev(U), to_dev(prim)
+    Uo = U
+    fixed = 0
+    dg.dgmi_failures(mesh)
+    for s in range(8):
+        dg.dg_step(mesh, Ud, Pd, dt)
+        Uo, nf = ora.step_mixed(m, deg, Uo, dt)
+        assert nf == 0
+        assert dg.dgmi_failures(mesh) == 0
+        fixed += dg.dgmi_fixed(mesh)
+        err = normwise_err(to_host(Ud), Uo, floor_scale=1.0)
+        assert np.all(err <= 1e-10), (s, err)
+    assert fixed > 0
