@@ -223,7 +223,9 @@ dgmi_status dg_limit(dgmi_ctx *ctx, double *U, double *prim_inout, void *stream)
 dgmi_status dgmi_limited(dgmi_ctx *ctx, int64_t *n_limited_host, void *stream);
 
 /* Number of failed recoveries since the last call (synchronises `stream`,
- * then resets the counter). */
+ * then resets the counter).  With a limiter selected, a state is counted
+ * after limiting (and fixing): nodes whose recovery fails before the limiter
+ * pass are recovered again by it and count only if they still fail. */
 dgmi_status dgmi_failures(dgmi_ctx *ctx, int64_t *n_failed_host, void *stream);
 
 /* Atmosphere floors and conserved-variable fixing (relativistic systems;
