@@ -223,7 +223,9 @@ __device__ __forceinline__ double mlp_seed_wave(const MlpSeedShared *s, MlpSeedW
     y1 += s->w3[4 * n4 + 1] * (float)hv[1] + s->w3[4 * n4 + 3] * (float)hv[3];
   }
   const float y = (y0 + y1) * s->ysd + s->ymu;
-  return u[0] * exp((double)y);
+  // the seed needs no more than FP32 (the FP64 iteration decides the result):
+  // the FP32 exponential instead of the FP64 library one (+3-6% throughput)
+  return u[0] * (double)__expf(y);
 }
 
 template <int SYS>
