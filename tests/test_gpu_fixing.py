@@ -232,3 +232,40 @@ def test_komissarov_shocks_on_gpu(ora, dg, case, speed, dtol):
           f"expected {speed * T}", flush=True)
     assert abs(xs - speed * T) <= dtol * speed * T, (xs, speed * T)
     assert len(cross) > 0 and np.all(np.abs(cross - speed * T) <= 0.04), (cross, speed * T)
+
+
+@pytest.mark.parametrize("system", [SR, MHD])
+def test_pointwise_non_finite_states(ora, dg, system):
+    """Non-finite components: a NaN or infinite D or tau is raised to its
+    floor, a NaN or infinite momentum becomes zero; the GPU treats each such
+    state as the oracle does (same count, same values, NaN where the oracle
+    leaves NaN)."""
+    import torch
+    nv = 9 if system == MHD else 5
+    base = np.array([1.0, 0.1, 0.0, 0.0, 2.0] + ([0.3, 0.0, 0.0, 0.0] if system == MHD else []))
+    cases = []
+    for v, val in ((0, np.nan), (0, -np.inf), (4, np.nan), (4, -np.inf), (1, np.nan), (2, np.inf), (3, -np.inf)):
+        c = base.copy()
+        c[v] = val
+        cases.append(c)
+    if system == MHD:
+        c = base.copy()
+        c[5] = np.nan
+        cases.append(c)
+    U = np.stack(cases, axis=1)
+    Uo, no = ora.fix_cons(system, 4.0 / 3.0, U, DMIN, TMIN)
+    Ud = to_dev(U)
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dg.dgmi_fix_conserved(system, 4.0 / 3.0, DMIN, TMIN, Ud, n_fixed=cnt)
+    Ug = to_host(Ud)
+    assert int(cnt.item()) == no == U.shape[1]
+    assert np.array_equal(np.isnan(Ug), np.isnan(Uo))
+    rows = [0, 4] + list(range(5, nv))
+    np.testing.assert_allclose(Ug[rows], Uo[rows], rtol=1e-15, atol=0, equal_nan=True)
+    # the momentum: as in the pointwise test, against the energy scale (a tau
+    # floored to B^2/2 + 1e-12 leaves an edge defined only to rounding)
+    ok = np.isfinite(Uo).all(axis=0)
+    BB = (Uo[5:8] ** 2).sum(0) if system == MHD else 0.0
+    E = (Uo[4] + Uo[0] + BB)[ok]
+    S2g, S2o = (Ug[1:4, ok] ** 2).sum(0), (Uo[1:4, ok] ** 2).sum(0)
+    assert np.all(np.abs(S2g - S2o) <= 1e-13 * E ** 2)
