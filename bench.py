@@ -366,7 +366,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+        print(json.dumps({"error": "this library runs on one GPU only; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
