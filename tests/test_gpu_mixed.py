@@ -280,11 +280,11 @@ LIM_CASES = [(NE, "minmod", 77), (SR, "muscl", 78), (MHD, "minmod", 79)]
 
 @pytest.mark.parametrize("system,lim,seed", LIM_CASES)
 def test_mixed_limit_parity(ora, dg, system, lim, seed):
-    """Limiter on a random mix of degrees 1..6: decisions equal the oracle's,
+    """Limiter on a random mix of degrees 1..7: decisions equal the oracle's,
     limited U within 1e-13 norm-wise, primitives within 1e-12."""
     g = G[system]
     nel = (8, 2, 2)
-    deg = synth.mixed_degrees(32, seed=seed, lo=1, hi=6)
+    deg = synth.mixed_degrees(32, seed=seed, lo=1, hi=7)
     m = ora.mesh(system, nel, 2, g, kappa=0.5, limiter=lim)
     mesh = dg.Mesh(system, nel, 0, g, kappa=0.5, degrees=deg)
     dg.dgmi_set_limiter(mesh, {"minmod": dg.LIMITER_MINMOD, "muscl": dg.LIMITER_MUSCL}[lim], 0.0)
@@ -309,7 +309,7 @@ def test_mixed_step_with_limiter_parity(ora, dg, system, lim, seed):
     import torch
     g = G[system]
     nel = (8, 2, 2)
-    deg = synth.mixed_degrees(32, seed=seed, lo=1, hi=6)
+    deg = synth.mixed_degrees(32, seed=seed, lo=1, hi=7)
     m = ora.mesh(system, nel, 2, g, kappa=0.5, limiter=lim)
     U, prim = _jump_state(ora, system, m, deg)
     U, _, _ = ora.limit_mixed(m, deg, U)
