@@ -131,6 +131,7 @@ def _load():
         "ora_backward_residual": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, I64, D, D, D]),
         "ora_flux": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, I64, D, D, D]),
         "ora_max_speed": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, I64, D, D, D]),
+        "ora_wave_speeds": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, I64, D, D, D, D]),
         "ora_llf": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, D, D, D, D, D]),
         "ora_num_nodes": (I64, [MP]),
         "ora_node_coords": (ctypes.c_int, [MP, D]),
@@ -279,6 +280,16 @@ def max_speed(system, gamma, d, U, prim):
     a = np.zeros_like(U)
     _load().ora_max_speed(system, gamma, d, U.shape[1], _p(U), _p(prim), _p(a))
     return a
+
+
+def wave_speeds(system, gamma, d, U, prim):
+    """Signed speed bounds (lm, lp), each [nv][n], of every component along +e_d."""
+    U = _c(U)
+    prim = _c(prim)
+    lm = np.zeros_like(U)
+    lp = np.zeros_like(U)
+    _load().ora_wave_speeds(system, gamma, d, U.shape[1], _p(U), _p(prim), _p(lm), _p(lp))
+    return lm, lp
 
 
 def llf(system, gamma, d, sgn, ui, pi, ue, pe):

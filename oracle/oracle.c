@@ -629,6 +629,24 @@ static void wave_speeds(int sys, double g, int d, const cons_t *C, const prim_t 
   }
 }
 
+/* Signed speed bounds lm <= lp of every component along +e_d (the HLL
+ * speeds of eq. HLL before clipping by zero), as computed above.            */
+int ora_wave_speeds(int sys, double g, int d, int64_t n, const double *U, const double *prim, double *lm,
+                    double *lp) {
+  int nv = nvars_of(sys);
+  for (int64_t q = 0; q < n; ++q) {
+    cons_t C; prim_t P; double a[9], b[9];
+    load_cons(nv, n, U, q, &C);
+    load_prim(n, prim, q, &P);
+    wave_speeds(sys, g, d, &C, &P, a, b);
+    for (int v = 0; v < nv; ++v) {
+      lm[(int64_t)v * n + q] = a[v];
+      lp[(int64_t)v * n + q] = b[v];
+    }
+  }
+  return ORA_OK;
+}
+
 /* HLL numerical flux (eq. HLL) for one face point with the element's
  * outward unit normal n = sgn e_d: with the speeds along n and
  *   s+ = max(0, lambda+_int, lambda+_ext),  s- = min(0, lambda-_int, lambda-_ext),

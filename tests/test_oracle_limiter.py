@@ -61,6 +61,54 @@ def test_moments_closed_forms(ora, N):
     assert abs(mom[8] - ((1 / 3 if N >= 2 else 1.0) - 2)) < 1e-13
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+def test_moments_of_random_polynomials_by_exact_integrals(ora, N):
+    """Random tensor polynomials of degree <= N per direction (exactly the
+    nodal space) on one element [-1,1]^3: the mean (1/8) int U, the slope
+    coefficients (3/8) int U xi_d and the face means (1/4) int U over each
+    face, from the monomial integrals int_{-1}^{1} t^k dt = 2/(k+1) (k even),
+    0 (k odd).  Independent of the quadrature and of the order in which the
+    oracle sums the line pairs."""
+    rng = np.random.default_rng(500 + N)
+    m = ora.mesh(NE, (1, 1, 1), N, 1.4, lo=(-1, -1, -1), hi=(1, 1, 1))
+    x = ora.node_coords(m)
+    a = rng.uniform(-1, 1, (N + 1, N + 1, N + 1))
+    U1 = np.zeros(x.shape[1])
+    for p in range(N + 1):
+        for q in range(N + 1):
+            for r in range(N + 1):
+                U1 += a[p, q, r] * x[0] ** p * x[1] ** q * x[2] ** r
+    U = np.tile(U1, (5, 1))
+    mo, _ = ora.limiter_moments(m, U)
+    mom = mo[0, :, 0]
+
+    def I(k):  # int_{-1}^{1} t^k dt
+        return 0.0 if k % 2 else 2.0 / (k + 1)
+
+    def E(k, side):  # t^k at t = -1 / +1
+        return (-1.0) ** k if side == 0 else 1.0
+
+    mean = sum(a[p, q, r] * I(p) * I(q) * I(r) for p in range(N + 1) for q in range(N + 1) for r in range(N + 1)) / 8
+    cx = sum(a[p, q, r] * I(p + 1) * I(q) * I(r) for p in range(N + 1) for q in range(N + 1) for r in range(N + 1))
+    cy = sum(a[p, q, r] * I(p) * I(q + 1) * I(r) for p in range(N + 1) for q in range(N + 1) for r in range(N + 1))
+    cz = sum(a[p, q, r] * I(p) * I(q) * I(r + 1) for p in range(N + 1) for q in range(N + 1) for r in range(N + 1))
+    faces = []
+    for d in range(3):
+        for side in (0, 1):
+            f = 0.0
+            for p in range(N + 1):
+                for q in range(N + 1):
+                    for r in range(N + 1):
+                        k = (p, q, r)
+                        t = [I(k[0]), I(k[1]), I(k[2])]
+                        t[d] = E(k[d], side)
+                        f += a[p, q, r] * t[0] * t[1] * t[2]
+            faces.append(f / 4)
+    want = np.array([mean, 3 * cx / 8, 3 * cy / 8, 3 * cz / 8, *faces])
+    scale = np.abs(a).sum()
+    assert np.abs(mom - want).max() <= 1e-14 * scale, (mom, want)
+
+
 def _ne_state(ora, m, rho):
     n = rho.size
     prim = np.zeros((5, n))

@@ -114,6 +114,96 @@ def test_mhd_speed_bounds_jacobian_and_cleaning_split(ora):
             assert a[0] < 1.0
 
 
+def _perpendicular_field_states(d, rng, n):
+    """SRMHD primitives with the velocity along e_d (zero for the first two)
+    and the field across it: magnetisation sigma = b^2/rho in [1e-2, 10],
+    p/rho in [1e-2, 10], |v| up to 0.9."""
+    prim = np.zeros((5, n))
+    mag = np.zeros((4, n))
+    for q in range(n):
+        rho = 10 ** rng.uniform(-1, 1)
+        p = rho * 10 ** rng.uniform(-2, 1)
+        vn = 0.0 if q < 2 else rng.uniform(-0.9, 0.9)
+        W = 1.0 / np.sqrt(1.0 - vn * vn)
+        sigma = 10 ** rng.uniform(-2, 1)
+        th = rng.uniform(0, 2 * np.pi)
+        t1, t2 = [k for k in range(3) if k != d]
+        Bhat = np.zeros(3)
+        Bhat[t1], Bhat[t2] = np.cos(th), np.sin(th)
+        # B.v = 0, so b^2 = B^2 / W^2
+        prim[:, q] = [rho, 0, 0, 0, p]
+        prim[1 + d, q] = vn
+        mag[:3, q] = W * np.sqrt(sigma * rho) * Bhat
+    return prim, mag
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_mhd_fast_speed_exact_for_field_across_the_normal(ora, d):
+    """With B perpendicular to e_d and v along e_d (or zero) the fast
+    magnetosonic wave crosses the field at a right angle in the fluid frame,
+    where its speed is exactly c_f^2 = v_A^2 + c_s^2 (1 - v_A^2) with
+    v_A^2 = b^2/(rho h + b^2), and the collinear boost makes the lab-frame
+    speeds (v_n +- c_f)/(1 +- v_n c_f).  So the fluid part's largest speed and
+    both signed bounds must equal the extreme eigenvalues of the
+    finite-difference Jacobian of the 7-variable sub-system exactly (to the
+    difference quotient's accuracy), which fails for a slip such as
+    v_A^2 = b^2/(rho h) or a fast speed without the (1 - v_A^2) factor."""
+    g = 4.0 / 3.0
+    rng = np.random.default_rng(40 + d)
+    prim, mag = _perpendicular_field_states(d, rng, 8)
+    U = ora.prim2cons(MHD, g, prim, mag)
+    a = ora.max_speed(MHD, g, d, U, prim)
+    lm, lp = ora.wave_speeds(MHD, g, d, U, prim)
+    sub = [5 + d, 8]
+    rest = [c for c in range(9) if c not in sub]
+    for q in range(U.shape[1]):
+        J = _fd_jacobian(ora, MHD, g, d, U[:, q])
+        ev = np.linalg.eigvals(J[np.ix_(rest, rest)])
+        assert np.abs(ev.imag).max() < 1e-6
+        ev = ev.real
+        for c in rest:
+            assert abs(a[c, q] - np.abs(ev).max()) <= 1e-6, (q, c, a[c, q], ev)
+            assert abs(lp[c, q] - ev.max()) <= 1e-6 and abs(lm[c, q] - ev.min()) <= 1e-6, (q, c, ev)
+        # the cleaning pair moves at the light speed
+        assert a[5 + d, q] == 1.0 and a[8, q] == 1.0
+        assert lm[5 + d, q] == -1.0 and lp[5 + d, q] == 1.0 and lm[8, q] == -1.0 and lp[8, q] == 1.0
+
+
+@pytest.mark.parametrize("system", [NE, SR])
+def test_signed_speed_bounds_are_the_extreme_eigenvalues(ora, system):
+    """NE and SR: the two acoustic speeds are the smallest and largest
+    eigenvalues of the flux Jacobian along e_d for every state."""
+    g = 5.0 / 3.0
+    rng = np.random.default_rng(17)
+    for q in range(5):
+        if system == NE:
+            prim = np.array([[rng.uniform(0.5, 2)], [rng.uniform(-1, 1)], [rng.uniform(-1, 1)],
+                             [rng.uniform(-1, 1)], [rng.uniform(0.5, 2)]])
+        else:
+            prim = synth.sr_samples(1, seed=200 + q, w_max=4.0)
+        U = ora.prim2cons(system, g, prim)
+        for d in range(3):
+            ev = np.linalg.eigvals(_fd_jacobian(ora, system, g, d, U[:, 0])).real
+            lm, lp = ora.wave_speeds(system, g, d, U, prim)
+            assert np.abs(lp[:, 0] - ev.max()).max() <= 1e-6 * max(1.0, abs(ev).max())
+            assert np.abs(lm[:, 0] - ev.min()).max() <= 1e-6 * max(1.0, abs(ev).max())
+
+
+def test_mhd_speeds_without_field_are_the_hydro_speeds(ora):
+    """B = 0: v_A = 0, so the fluid speeds of SRMHD are the SR acoustic ones."""
+    g = 4.0 / 3.0
+    prim = synth.sr_samples(300, seed=23, w_max=8.0)
+    Us = ora.prim2cons(SR, g, prim)
+    Um = ora.prim2cons(MHD, g, prim, np.zeros((4, 300)))
+    for d in range(3):
+        a_s = ora.max_speed(SR, g, d, Us, prim)
+        a_m = ora.max_speed(MHD, g, d, Um, prim)
+        assert np.abs(a_m[0] - a_s[0]).max() <= 1e-15
+        lms, lps = ora.wave_speeds(SR, g, d, Us, prim)
+        lmm, lpm = ora.wave_speeds(MHD, g, d, Um, prim)
+        assert np.abs(lmm[:5] - lms).max() <= 1e-15 and np.abs(lpm[:5] - lps).max() <= 1e-15
+
+
 @pytest.mark.parametrize("system", [NE, SR, MHD])
 def test_roundtrip(ora, system):
     g = 4.0 / 3.0
