@@ -93,8 +93,10 @@ typedef struct {
 } dgmi_mesh_desc;
 
 /* Build a mesh context: GLL nodes, weights and differentiation matrices
- * (eq. for D^{1bar}), neighbour tables, RK scratch.  Synchronous.  The
- * context is bound to the device current at creation.
+ * (eq. for D^{1bar}), neighbour tables, RK scratch.  The table uploads (and,
+ * with DGMI_FLAG_AUTOTUNE, the tile timings) run on `stream`, which is
+ * synchronised before the call returns; on failure nothing is left allocated
+ * and *out is NULL.  The context is bound to the device current at creation.
  *
  * Mixed degrees (degree == 0, degrees_host[e] in 1..7 for element e): the
  * paper defers the coupling of unequal degrees; a face between degrees Na and
@@ -106,7 +108,7 @@ typedef struct {
  * stream captures its three stages once per (U, prim_inout) pair and then
  * replays the graph (dt travels in a device scalar); the per-degree kernels
  * run concurrently on the context's own streams.                          */
-dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out);
+dgmi_status dgmi_create(const dgmi_mesh_desc *desc, void *stream, dgmi_ctx **out);
 dgmi_status dgmi_destroy(dgmi_ctx *ctx);
 
 int64_t dgmi_num_nodes(const dgmi_ctx *ctx);    /* sum over elements of (N_e+1)^3 */
@@ -142,7 +144,9 @@ dgmi_status dg_rhs(dgmi_ctx *ctx, const double *U, double *prim_inout, double *d
  * con2prim followed by this call).  dUdt must not alias U or prim. */
 dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, double *dUdt, void *stream);
 
-/* One third-order SSP Runge-Kutta step (Shu-Osher form) in place:
+/* One third-order SSP Runge-Kutta step in place (the RK3-SSP time stepper of
+ * the section on initial data, boundary conditions and time steppers), in
+ * Shu-Osher form:
  *   U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
  *   U <- 1/3 U + 2/3 (U2 + dt L(U2)).
  * prim_inout must hold the primitives of U on entry (or set
@@ -152,6 +156,18 @@ dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, doub
  * (as dg_limit does) before its primitives are final.  Advances the
  * context's time by dt. */
 dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream);
+
+/* Checked variants: the same work as dg_rhs / dg_step, then `stream` is
+ * synchronised and DGMI_ECON2PRIM is returned if any recovery of this call
+ * failed (an unphysical state, or no convergence within the iteration cap;
+ * the outputs are still written, failed nodes holding the last iterate).
+ * n_failed_host (nullable, host) receives this call's number of failures.
+ * The context's failure counter (dgmi_failures) still counts them.  Both
+ * synchronise `stream` before and after the work. */
+dgmi_status dg_rhs_checked(dgmi_ctx *ctx, const double *U, double *prim_inout, double *dUdt, int64_t *n_failed_host,
+                           void *stream);
+dgmi_status dg_step_checked(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, int64_t *n_failed_host,
+                            void *stream);
 
 /* Box faces with a fixed exterior state (the analytic boundary condition of
  * the section on initial data, boundary conditions and time steppers, for a
@@ -304,6 +320,14 @@ dgmi_status con2prim(int32_t system, double gamma, const double *U, double *prim
                      const dgmi_mlp *mlp, double tol, uint8_t *iters_out, uint8_t *fail_out, int64_t *n_failed,
                      void *stream);
 
+/* Checked recovery: as con2prim, with n_failed (device int64) required; it
+ * is set to this call's number of failures, `stream` is synchronised, the
+ * count is copied to n_failed_host (nullable, host) and DGMI_ECON2PRIM is
+ * returned if it is not zero (the outputs are written either way). */
+dgmi_status con2prim_checked(int32_t system, double gamma, const double *U, double *prim_inout, int64_t n,
+                             int32_t guess, const dgmi_mlp *mlp, double tol, uint8_t *iters_out, uint8_t *fail_out,
+                             int64_t *n_failed, int64_t *n_failed_host, void *stream);
+
 /* ---------------------------------------------------------------------
  * Learned pressure guess: a 5 -> 64 -> 64 -> 1 multilayer perceptron with
  * SiLU activations in FP32 that proposes the recovery's initial pressure
@@ -319,8 +343,9 @@ dgmi_status con2prim(int32_t system, double gamma, const double *U, double *prim
  * ------------------------------------------------------------------- */
 
 /* New network with weights drawn U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a
- * generator seeded by `seed`; identity normalisation.  Synchronous. */
-dgmi_status mlp_create(dgmi_mlp **out, uint64_t seed);
+ * generator seeded by `seed`; identity normalisation.  The upload runs on
+ * `stream`, which is synchronised before the call returns. */
+dgmi_status mlp_create(dgmi_mlp **out, uint64_t seed, void *stream);
 dgmi_status mlp_destroy(dgmi_mlp *mlp);
 /* Copy the 4621-float parameter vector out of / into the network
  * (device to device); mlp_set also resets the optimiser state. */

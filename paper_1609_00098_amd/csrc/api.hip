@@ -178,6 +178,7 @@ struct dgmi_ctx {
   double lim_M = 0.0;
   double *d_limtab = nullptr;     // [3][8]: w/2, 3/2 int(ell xi), GLL node of the mesh degree
   double *d_limtab_mix = nullptr; // mixed degrees: the same 24 doubles per degree, at 24 N
+  bool lim_tab_ready = false;     // the limiter table of the mesh's degree(s) is uploaded
   double *d_mom = nullptr;        // [nelem][10][nv]
   int32_t *d_bad = nullptr;       // [nelem]
   unsigned long long *d_nlim = nullptr;  // [kLimCounters] limited-component counters (summed when read)
@@ -229,7 +230,7 @@ static double lagrange(int n, const double *xs, int i, double y) {
   return v;
 }
 
-static dgmi_status autotune(dgmi_ctx *c);
+static dgmi_status autotune(dgmi_ctx *c, hipStream_t s);
 constexpr int kMixedLanes = 4;
 
 // Periodic neighbour of element e across face f (-x, +x, -y, +y, -z, +z).
@@ -249,7 +250,7 @@ static int64_t nbr_of(const dgmi_ctx *c, int64_t e, int f) {
 }
 
 // Degree lists, offsets, mortar tables, streams; optional tile autotuning.
-static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
+static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx, hipStream_t cs) {
   c->mixed = true;
   std::vector<int32_t> elist;
   elist.reserve(c->nelem);
@@ -296,12 +297,12 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
     (void)hipGetLastError();
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the mixed-degree tables failed");
   }
-  HIP_TRY(hipMemcpy(c->d_deg, c->deg.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_off, c->off.data(), sizeof(int64_t) * (c->nelem + 1), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_elist, elist.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_Itab, It.data(), tb, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_Ptab, Pt.data(), tb, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_Qtab, Qt.data(), tb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpyAsync(c->d_deg, c->deg.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice, cs));
+  HIP_TRY(hipMemcpyAsync(c->d_off, c->off.data(), sizeof(int64_t) * (c->nelem + 1), hipMemcpyHostToDevice, cs));
+  HIP_TRY(hipMemcpyAsync(c->d_elist, elist.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice, cs));
+  HIP_TRY(hipMemcpyAsync(c->d_Itab, It.data(), tb, hipMemcpyHostToDevice, cs));
+  HIP_TRY(hipMemcpyAsync(c->d_Ptab, Pt.data(), tb, hipMemcpyHostToDevice, cs));
+  HIP_TRY(hipMemcpyAsync(c->d_Qtab, Qt.data(), tb, hipMemcpyHostToDevice, cs));
   // faces between unequal degrees: each listed once (from the element whose
   // upper face it is); both sides get a block of lift terms in the face buffer
   std::vector<int64_t> foff(c->nelem * 6, -1);
@@ -325,9 +326,10 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
     (void)hipGetLastError();
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the mortar buffers failed");
   }
-  HIP_TRY(hipMemcpy(c->d_foff, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice));
-  if (!faces.empty()) HIP_TRY(hipMemcpy(c->d_faces, faces.data(), sizeof(int32_t) * faces.size(), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemset(c->d_dt, 0, sizeof(double)));
+  HIP_TRY(hipMemcpyAsync(c->d_foff, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice, cs));
+  if (!faces.empty())
+    HIP_TRY(hipMemcpyAsync(c->d_faces, faces.data(), sizeof(int32_t) * faces.size(), hipMemcpyHostToDevice, cs));
+  HIP_TRY(dgmi::launch_set_scalar(c->d_dt, 0.0, cs));
   for (int k = 0; k < 8; ++k) {
     HIP_TRY(hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
@@ -373,11 +375,14 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx) {
       return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the workgroup table failed");
     }
     if (c->nblk > 0) {
-      HIP_TRY(hipMemcpy(c->d_blk, bdeg.data(), sizeof(int32_t) * bdeg.size(), hipMemcpyHostToDevice));
-      HIP_TRY(hipMemcpy(c->d_blk + c->nblk, bgrp.data(), sizeof(int32_t) * bgrp.size(), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpyAsync(c->d_blk, bdeg.data(), sizeof(int32_t) * bdeg.size(), hipMemcpyHostToDevice, cs));
+      HIP_TRY(hipMemcpyAsync(c->d_blk + c->nblk, bgrp.data(), sizeof(int32_t) * bgrp.size(), hipMemcpyHostToDevice,
+                             cs));
     }
+    // the host tables above go out of scope here
+    HIP_TRY(hipStreamSynchronize(cs));
   }
-  if (c->flags & DGMI_FLAG_AUTOTUNE) return autotune(c);
+  if (c->flags & DGMI_FLAG_AUTOTUNE) return autotune(c, cs);
   return DGMI_OK;
 }
 
@@ -480,9 +485,18 @@ static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const dou
 
 static dgmi::LimArgs lim_args(dgmi_ctx *c, double *U, const double *Pseed, double *Pout);
 
+// The intermediate states of an SSP-RK3 step: U^(1), U^(2) [nv][nnodes] and
+// their primitives [5][nnodes].
+struct RkBufs {
+  double *U1, *U2, *P1, *P2;
+};
+static RkBufs ctx_bufs(dgmi_ctx *c) { return RkBufs{c->d_U1, c->d_U2, c->d_P1, c->d_P2}; }
+
 // The limiter on a mixed-degree mesh (moments per degree, decisions, rewrite
 // per degree); P seeds the recoveries and receives the primitives.
 static dgmi_status mixed_limit(dgmi_ctx *c, double *U, double *P, hipStream_t s) {
+  if (!c->lim_tab_ready || !c->d_limtab_mix || !c->d_mom || !c->d_bad)
+    return fail(DGMI_EINVAL, "limiter: tables or scratch missing (dgmi_set_limiter did not complete)");
   dgmi::LimArgs a = lim_args(c, U, P, P);
   a.off = c->d_off;
   a.deg = c->d_deg;
@@ -491,13 +505,13 @@ static dgmi_status mixed_limit(dgmi_ctx *c, double *U, double *P, hipStream_t s)
 }
 
 // with a limiter, each stage result is limited before the next stage reads it
-static dgmi_status mixed_step_enqueue(dgmi_ctx *c, double *U, double *P, hipStream_t s) {
+static dgmi_status mixed_step_enqueue(dgmi_ctx *c, double *U, double *P, const RkBufs &b, hipStream_t s) {
   const bool limit = c->lim_kind != DGMI_LIMITER_NONE;
-  dgmi_status st = mixed_pass(c, 1, U, P, c->d_U1, U, c->d_P1, 0.0, 1.0, 0, s);
-  if (st == DGMI_OK && limit) st = mixed_limit(c, c->d_U1, c->d_P1, s);
-  if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U1, c->d_P1, c->d_U2, U, c->d_P2, 0.75, 0.25, 0, s);
-  if (st == DGMI_OK && limit) st = mixed_limit(c, c->d_U2, c->d_P2, s);
-  if (st == DGMI_OK) st = mixed_pass(c, 1, c->d_U2, c->d_P2, U, U, P, 1.0 / 3.0, 2.0 / 3.0, 1, s);
+  dgmi_status st = mixed_pass(c, 1, U, P, b.U1, U, b.P1, 0.0, 1.0, 0, s);
+  if (st == DGMI_OK && limit) st = mixed_limit(c, b.U1, b.P1, s);
+  if (st == DGMI_OK) st = mixed_pass(c, 1, b.U1, b.P1, b.U2, U, b.P2, 0.75, 0.25, 0, s);
+  if (st == DGMI_OK && limit) st = mixed_limit(c, b.U2, b.P2, s);
+  if (st == DGMI_OK) st = mixed_pass(c, 1, b.U2, b.P2, U, U, P, 1.0 / 3.0, 2.0 / 3.0, 1, s);
   if (st == DGMI_OK && limit) st = mixed_limit(c, U, P, s);
   return st;
 }
@@ -513,8 +527,7 @@ static void drop_graph(dgmi_ctx *c) {
 
 // Time every tile option of every degree present on a state at rest and keep
 // the fastest (results do not depend on the choice).
-static dgmi_status autotune(dgmi_ctx *c) {
-  hipStream_t s = c->side[0];
+static dgmi_status autotune(dgmi_ctx *c, hipStream_t s) {
   const int64_t n = c->nnodes;
   // prims (1, 0, 0, 0, 1) in P1, field/Phi zero in U2, state in U1
   HIP_TRY(dgmi::launch_fill(c->d_P1, 5 * n, 0.0, s));
@@ -614,7 +627,7 @@ static void ctx_free(dgmi_ctx *c) {
   delete c;
 }
 
-dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
+dgmi_status dgmi_create(const dgmi_mesh_desc *desc, void *stream, dgmi_ctx **out) {
   if (!desc || !out) return fail(DGMI_EINVAL, "dgmi_create: null argument");
   *out = nullptr;
   if (desc->system < 0 || desc->system > 2) return fail(DGMI_EINVAL, "dgmi_create: unknown system %d", desc->system);
@@ -708,20 +721,25 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, dgmi_ctx **out) {
     ctx_free(c);
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation failed (%lld nodes)", (long long)c->nnodes);
   }
-  if (hipMemcpy(c->d_D, hD.data(), hD.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_x, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(c->d_nfail, 0, sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_nlim, 0, kLimCounters * sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_nfix, 0, sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_nfail_pre, 0, sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_bc, 0, sizeof(c->hbc)) != hipSuccess) {
+  const hipStream_t cs = (hipStream_t)stream;
+  if (hipMemcpyAsync(c->d_D, hD.data(), hD.size() * sizeof(double), hipMemcpyHostToDevice, cs) != hipSuccess ||
+      hipMemcpyAsync(c->d_x, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, cs) != hipSuccess ||
+      hipMemcpyAsync(c->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, cs) != hipSuccess ||
+      hipMemsetAsync(c->d_nfail, 0, sizeof(unsigned long long), cs) != hipSuccess ||
+      hipMemsetAsync(c->d_nlim, 0, kLimCounters * sizeof(unsigned long long), cs) != hipSuccess ||
+      hipMemsetAsync(c->d_nfix, 0, sizeof(unsigned long long), cs) != hipSuccess ||
+      hipMemsetAsync(c->d_nfail_pre, 0, sizeof(unsigned long long), cs) != hipSuccess ||
+      hipMemsetAsync(c->d_bc, 0, sizeof(c->hbc), cs) != hipSuccess || hipStreamSynchronize(cs) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(cs);
     ctx_free(c);
     return fail(DGMI_EHIP, "dgmi_create: table upload failed");
   }
   if (desc->degree == 0) {
-    dgmi_status st = mixed_setup(c, hx);
+    dgmi_status st = mixed_setup(c, hx, cs);
+    if (st == DGMI_OK && hipStreamSynchronize(cs) != hipSuccess) st = fail(DGMI_EHIP, "dgmi_create: stream error");
     if (st != DGMI_OK) {
+      (void)hipStreamSynchronize(cs);
       ctx_free(c);
       return st;
     }
@@ -889,12 +907,10 @@ dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, doub
   return DGMI_OK;
 }
 
-dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream) {
-  if (!ctx) return fail(DGMI_EINVAL, "dg_step: null context");
-  if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
-    return fail(DGMI_EINVAL, "dg_step: U and prim_inout must be distinct device pointers");
-  if (!std::isfinite(dt)) return fail(DGMI_EINVAL, "dg_step: dt must be finite");
-  hipStream_t s = (hipStream_t)stream;
+// One SSP-RK3 step with the intermediate states in b.  graph: a mixed-degree
+// step on a non-default stream is captured once and replayed.
+static dgmi_status step_impl(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, hipStream_t s, const RkBufs &b,
+                             bool graph) {
   if (ctx->flags & DGMI_FLAG_RECOVER_FIRST) {
     const int guess = (ctx->flags & DGMI_FLAG_PLAIN_GUESS) ? DGMI_GUESS_PLAIN : DGMI_GUESS_INPUT;
     dgmi_status st = recover_all(ctx, U, prim_inout, guess, s);
@@ -907,8 +923,8 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
       HIP_TRY(dgmi::launch_set_scalar(ctx->d_dt, dt, s));
       ctx->last_dt = dt;
     }
-    if ((ctx->flags & DGMI_FLAG_NO_GRAPH) || s == nullptr) {
-      const dgmi_status st = mixed_step_enqueue(ctx, U, prim_inout, s);
+    if (!graph || (ctx->flags & DGMI_FLAG_NO_GRAPH) || s == nullptr) {
+      const dgmi_status st = mixed_step_enqueue(ctx, U, prim_inout, b, s);
       if (st == DGMI_OK) ctx->time += dt;
       return st;
     }
@@ -918,7 +934,7 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
       ctx->gexec = nullptr;
       ctx->graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      dgmi_status st = mixed_step_enqueue(ctx, U, prim_inout, s);
+      dgmi_status st = mixed_step_enqueue(ctx, U, prim_inout, b, s);
       hipGraph_t g = nullptr;
       const hipError_t ce = hipStreamEndCapture(s, &g);
       if (st != DGMI_OK || ce != hipSuccess) {
@@ -963,16 +979,24 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
   const double t0 = ctx->time;
   // stage 1: U1 = U + dt L(U)
   a.U = U; a.P = prim_inout; a.a = 0.0; a.b = 1.0;
-  if ((st = stage(ctx->d_U1, ctx->d_P1, t0)) != DGMI_OK) return st;
+  if ((st = stage(b.U1, b.P1, t0)) != DGMI_OK) return st;
   // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
-  a.U = ctx->d_U1; a.P = ctx->d_P1; a.a = 0.75; a.b = 0.25;
-  if ((st = stage(ctx->d_U2, ctx->d_P2, t0 + dt)) != DGMI_OK) return st;
+  a.U = b.U1; a.P = b.P1; a.a = 0.75; a.b = 0.25;
+  if ((st = stage(b.U2, b.P2, t0 + dt)) != DGMI_OK) return st;
   // stage 3: U <- 1/3 U + 2/3 (U2 + dt L(U2))  (each thread reads U^n at its own node before writing it)
-  a.U = ctx->d_U2; a.P = ctx->d_P2; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
+  a.U = b.U2; a.P = b.P2; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
   a.full_prims = 1;
   if ((st = stage(U, prim_inout, t0 + 0.5 * dt)) != DGMI_OK) return st;
   ctx->time = t0 + dt;
   return DGMI_OK;
+}
+
+dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dg_step: null context");
+  if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
+    return fail(DGMI_EINVAL, "dg_step: U and prim_inout must be distinct device pointers");
+  if (!std::isfinite(dt)) return fail(DGMI_EINVAL, "dg_step: dt must be finite");
+  return step_impl(ctx, U, prim_inout, dt, (hipStream_t)stream, ctx_bufs(ctx), true);
 }
 
 // Exterior states of every box-face node (16 doubles each), allocated on
@@ -1101,14 +1125,24 @@ dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M) {
   if (!(M >= 0.0) || !std::isfinite(M)) return fail(DGMI_EINVAL, "dgmi_set_limiter: M must be finite and >= 0");
   if (kind != DGMI_LIMITER_NONE && (ctx->bc[0] == 2 || ctx->bc[1] == 2 || ctx->bc[2] == 2))
     return fail(DGMI_EUNSUPPORTED, "dgmi_set_limiter: not combined with analytic boundaries");
-  if (kind != DGMI_LIMITER_NONE && !ctx->d_mom) {
+  if (kind != DGMI_LIMITER_NONE && (!ctx->d_mom || !ctx->d_bad)) {
+    (void)hipFree(ctx->d_mom);
+    (void)hipFree(ctx->d_bad);
+    ctx->d_mom = nullptr;
+    ctx->d_bad = nullptr;
     if (hipMalloc(&ctx->d_mom, sizeof(double) * 10 * ctx->nv * ctx->nelem) != hipSuccess ||
         hipMalloc(&ctx->d_bad, sizeof(int32_t) * ctx->nelem) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipFree(ctx->d_mom);
+      (void)hipFree(ctx->d_bad);
       ctx->d_mom = nullptr;
+      ctx->d_bad = nullptr;
       return fail(DGMI_ENOMEM, "dgmi_set_limiter: device allocation failed");
     }
+  }
+  // the per-degree tables are set up once, independently of the scratch
+  // above, so that a failed upload is retried by the next call
+  if (kind != DGMI_LIMITER_NONE && !ctx->lim_tab_ready) {
     // per node index of the mesh degree: w/2, 3/2 int(ell_i xi), x_i; the
     // first moment int(ell_i xi) is w_i x_i (GLL quadrature is exact for the
     // degree N+1 integrand when N >= 2) and -+1/3 at degree 1
@@ -1135,7 +1169,7 @@ dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M) {
           mtab[24 * Nm + 16 + i] = x[i];
         }
       }
-      if (hipMalloc(&ctx->d_limtab_mix, sizeof(mtab)) != hipSuccess) {
+      if (!ctx->d_limtab_mix && hipMalloc(&ctx->d_limtab_mix, sizeof(mtab)) != hipSuccess) {
         (void)hipGetLastError();
         ctx->d_limtab_mix = nullptr;
         return fail(DGMI_ENOMEM, "dgmi_set_limiter: device allocation failed");
@@ -1143,6 +1177,7 @@ dgmi_status dgmi_set_limiter(dgmi_ctx *ctx, int32_t kind, double M) {
       if (hipMemcpy(ctx->d_limtab_mix, mtab, sizeof(mtab), hipMemcpyHostToDevice) != hipSuccess)
         return fail(DGMI_EHIP, "dgmi_set_limiter: table upload failed");
     }
+    ctx->lim_tab_ready = true;
   }
   ctx->lim_kind = kind;
   ctx->lim_M = M;
@@ -1331,25 +1366,70 @@ dgmi_status dgmi_failures(dgmi_ctx *ctx, int64_t *n_failed_host, void *stream) {
   return DGMI_OK;
 }
 
-dgmi_status con2prim(int32_t system, double gamma, const double *U, double *prim_inout, int64_t n, int32_t guess,
-                     const dgmi_mlp *mlp, double tol, uint8_t *iters_out, uint8_t *fail_out, int64_t *n_failed,
-                     void *stream) {
-  if (system < 0 || system > 2) return fail(DGMI_EINVAL, "con2prim: unknown system");
-  if (guess < 0 || guess > 2) return fail(DGMI_EINVAL, "con2prim: unknown guess mode");
-  if (n < 0) return fail(DGMI_EINVAL, "con2prim: negative size");
-  if (!(gamma > 1.0 && gamma <= 2.0)) return fail(DGMI_EINVAL, "con2prim: gamma must be in (1, 2]");
-  if (!std::isfinite(tol)) return fail(DGMI_EINVAL, "con2prim: tol must be finite");
+// Failed recoveries counted by the context so far (synchronises s).
+static dgmi_status read_failures(dgmi_ctx *c, hipStream_t s, unsigned long long *v) {
+  HIP_TRY(hipMemcpyAsync(v, c->d_nfail, sizeof(*v), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DGMI_OK;
+}
+
+dgmi_status dg_rhs_checked(dgmi_ctx *ctx, const double *U, double *prim_inout, double *dUdt, int64_t *n_failed_host,
+                           void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dg_rhs_checked: null context");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long before = 0, after = 0;
+  dgmi_status st = read_failures(ctx, s, &before);
+  if (st == DGMI_OK) st = dg_rhs(ctx, U, prim_inout, dUdt, stream);
+  if (st == DGMI_OK) st = read_failures(ctx, s, &after);
+  if (st != DGMI_OK) return st;
+  if (n_failed_host) *n_failed_host = (int64_t)(after - before);
+  if (after != before)
+    return fail(DGMI_ECON2PRIM, "dg_rhs_checked: %llu recoveries failed", (unsigned long long)(after - before));
+  return DGMI_OK;
+}
+
+dgmi_status dg_step_checked(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, int64_t *n_failed_host,
+                            void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dg_step_checked: null context");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long before = 0, after = 0;
+  dgmi_status st = read_failures(ctx, s, &before);
+  if (st == DGMI_OK) st = dg_step(ctx, U, prim_inout, dt, stream);
+  if (st == DGMI_OK) st = read_failures(ctx, s, &after);
+  if (st != DGMI_OK) return st;
+  if (n_failed_host) *n_failed_host = (int64_t)(after - before);
+  if (after != before)
+    return fail(DGMI_ECON2PRIM, "dg_step_checked: %llu recoveries failed", (unsigned long long)(after - before));
+  return DGMI_OK;
+}
+
+}  // extern "C"
+
+// Argument checks shared by con2prim and con2prim_checked (nothing enqueued).
+static dgmi_status c2p_args(const char *name, int32_t system, double gamma, const double *U, double *prim_inout,
+                            int64_t n, int32_t guess, const dgmi_mlp *mlp, double tol, uint8_t *iters_out,
+                            uint8_t *fail_out, int64_t *n_failed) {
+  if (system < 0 || system > 2) return fail(DGMI_EINVAL, "%s: unknown system", name);
+  if (guess < 0 || guess > 2) return fail(DGMI_EINVAL, "%s: unknown guess mode", name);
+  if (n < 0) return fail(DGMI_EINVAL, "%s: negative size", name);
+  if (!(gamma > 1.0 && gamma <= 2.0)) return fail(DGMI_EINVAL, "%s: gamma must be in (1, 2]", name);
+  if (!std::isfinite(tol)) return fail(DGMI_EINVAL, "%s: tol must be finite", name);
+  if (guess == DGMI_GUESS_LEARNED) {
+    if (system == 0) return fail(DGMI_EINVAL, "%s: the learned guess needs a relativistic system", name);
+    if (!mlp) return fail(DGMI_EINVAL, "%s: the learned guess needs an MLP handle", name);
+  }
   if (n == 0) return DGMI_OK;
-  if (!is_device_ptr(U) || !is_device_ptr(prim_inout)) return fail(DGMI_EINVAL, "con2prim: U/prim must be device pointers");
+  if (!is_device_ptr(U) || !is_device_ptr(prim_inout)) return fail(DGMI_EINVAL, "%s: U/prim must be device pointers", name);
   if ((iters_out && !is_device_ptr(iters_out)) || (fail_out && !is_device_ptr(fail_out)) ||
       (n_failed && !is_device_ptr(n_failed)))
-    return fail(DGMI_EINVAL, "con2prim: optional outputs must be device pointers");
-  const float *mp = nullptr;
-  if (guess == DGMI_GUESS_LEARNED) {
-    if (system == 0) return fail(DGMI_EINVAL, "con2prim: the learned guess needs a relativistic system");
-    if (!mlp) return fail(DGMI_EINVAL, "con2prim: the learned guess needs an MLP handle");
-    mp = mlp->params;
-  }
+    return fail(DGMI_EINVAL, "%s: optional outputs must be device pointers", name);
+  return DGMI_OK;
+}
+
+static dgmi_status c2p_launch(int32_t system, double gamma, const double *U, double *prim_inout, int64_t n,
+                              int32_t guess, const dgmi_mlp *mlp, double tol, uint8_t *iters_out, uint8_t *fail_out,
+                              int64_t *n_failed, hipStream_t s) {
+  if (n == 0) return DGMI_OK;
   dgmi::C2PArgs a{};
   a.U = U;
   a.prim = prim_inout;
@@ -1359,8 +1439,40 @@ dgmi_status con2prim(int32_t system, double gamma, const double *U, double *prim
   a.iters = iters_out;
   a.fail = fail_out;
   a.nfail = (unsigned long long *)n_failed;
-  a.mlp = mp;
-  HIP_TRY(dgmi::launch_con2prim(system, guess, a, (hipStream_t)stream));
+  a.mlp = guess == DGMI_GUESS_LEARNED ? mlp->params : nullptr;
+  HIP_TRY(dgmi::launch_con2prim(system, guess, a, s));
+  return DGMI_OK;
+}
+
+extern "C" {
+
+dgmi_status con2prim(int32_t system, double gamma, const double *U, double *prim_inout, int64_t n, int32_t guess,
+                     const dgmi_mlp *mlp, double tol, uint8_t *iters_out, uint8_t *fail_out, int64_t *n_failed,
+                     void *stream) {
+  const dgmi_status st =
+      c2p_args("con2prim", system, gamma, U, prim_inout, n, guess, mlp, tol, iters_out, fail_out, n_failed);
+  if (st != DGMI_OK) return st;
+  return c2p_launch(system, gamma, U, prim_inout, n, guess, mlp, tol, iters_out, fail_out, n_failed,
+                    (hipStream_t)stream);
+}
+
+dgmi_status con2prim_checked(int32_t system, double gamma, const double *U, double *prim_inout, int64_t n,
+                             int32_t guess, const dgmi_mlp *mlp, double tol, uint8_t *iters_out, uint8_t *fail_out,
+                             int64_t *n_failed, int64_t *n_failed_host, void *stream) {
+  if (!n_failed || !is_device_ptr(n_failed))
+    return fail(DGMI_EINVAL, "con2prim_checked: n_failed must be a device int64");
+  dgmi_status st =
+      c2p_args("con2prim_checked", system, gamma, U, prim_inout, n, guess, mlp, tol, iters_out, fail_out, n_failed);
+  if (st != DGMI_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(dgmi::launch_fill((double *)n_failed, 1, 0.0, s));  // all-zero bits: the counter starts at 0
+  st = c2p_launch(system, gamma, U, prim_inout, n, guess, mlp, tol, iters_out, fail_out, n_failed, s);
+  if (st != DGMI_OK) return st;
+  int64_t v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, n_failed, sizeof(v), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (n_failed_host) *n_failed_host = v;
+  if (v != 0) return fail(DGMI_ECON2PRIM, "con2prim_checked: %lld recoveries failed", (long long)v);
   return DGMI_OK;
 }
 

@@ -297,7 +297,7 @@ dgmi_status ensure_partials(dgmi_mlp *m, int64_t nblk) {
 
 extern "C" {
 
-dgmi_status mlp_create(dgmi_mlp **out, uint64_t seed) {
+dgmi_status mlp_create(dgmi_mlp **out, uint64_t seed, void *stream) {
   using namespace dgmi;
   if (!out) return merr(DGMI_EINVAL, "mlp_create: null argument");
   dgmi_mlp *m = new (std::nothrow) dgmi_mlp();
@@ -328,9 +328,15 @@ dgmi_status mlp_create(dgmi_mlp **out, uint64_t seed) {
     delete m;
     return merr(DGMI_ENOMEM, "mlp_create: device allocation failed");
   }
-  if (hipMemcpy(m->params, h.data(), sizeof(float) * kNumParams, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(m->adam_m, 0, sizeof(float) * kNumWeights) != hipSuccess ||
-      hipMemset(m->adam_v, 0, sizeof(float) * kNumWeights) != hipSuccess) {
+  const hipStream_t cs = (hipStream_t)stream;
+  if (hipMemcpyAsync(m->params, h.data(), sizeof(float) * kNumParams, hipMemcpyHostToDevice, cs) != hipSuccess ||
+      hipMemsetAsync(m->adam_m, 0, sizeof(float) * kNumWeights, cs) != hipSuccess ||
+      hipMemsetAsync(m->adam_v, 0, sizeof(float) * kNumWeights, cs) != hipSuccess ||
+      hipStreamSynchronize(cs) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(cs);
+    (void)hipFree(m->params); (void)hipFree(m->grad); (void)hipFree(m->adam_m); (void)hipFree(m->adam_v);
+    delete m;
     return merr(DGMI_EHIP, "mlp_create: upload failed");
   }
   *out = m;

@@ -47,7 +47,7 @@ class MeshDesc(ctypes.Structure):
 _P = ctypes.c_void_p
 _I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _SIGS = {
-    "dgmi_create": (_I32, [ctypes.POINTER(MeshDesc), ctypes.POINTER(_P)]),
+    "dgmi_create": (_I32, [ctypes.POINTER(MeshDesc), _P, ctypes.POINTER(_P)]),
     "dgmi_destroy": (_I32, [_P]),
     "dgmi_num_nodes": (_I64, [_P]),
     "dgmi_num_vars": (_I32, [_P]),
@@ -58,6 +58,9 @@ _SIGS = {
     "dg_rhs": (_I32, [_P, _P, _P, _P, _P]),
     "dg_step": (_I32, [_P, _P, _P, _D, _P]),
     "dg_operator": (_I32, [_P, _P, _P, _P, _P]),
+    "dg_rhs_checked": (_I32, [_P, _P, _P, _P, ctypes.POINTER(_I64), _P]),
+    "dg_step_checked": (_I32, [_P, _P, _P, _D, ctypes.POINTER(_I64), _P]),
+    "con2prim_checked": (_I32, [_I32, _D, _P, _P, _I64, _I32, _P, _D, _P, _P, _P, ctypes.POINTER(_I64), _P]),
     "dgmi_failures": (_I32, [_P, ctypes.POINTER(_I64), _P]),
     "dgmi_set_boundary": (_I32, [_P, _I32, _P, _P]),
     "dgmi_set_limiter": (_I32, [_P, _I32, _D]),
@@ -74,7 +77,7 @@ _SIGS = {
     "dgmi_fix_conserved": (_I32, [_I32, _D, _D, _D, _P, _I64, _P, _P]),
     "con2prim": (_I32, [_I32, _D, _P, _P, _I64, _I32, _P, _D, _P, _P, _P, _P]),
     "dgmi_last_error": (ctypes.c_char_p, []),
-    "mlp_create": (_I32, [ctypes.POINTER(_P), ctypes.c_uint64]),
+    "mlp_create": (_I32, [ctypes.POINTER(_P), ctypes.c_uint64, _P]),
     "mlp_destroy": (_I32, [_P]),
     "mlp_get": (_I32, [_P, _P, _P]),
     "mlp_set": (_I32, [_P, _P, _P]),
@@ -123,7 +126,7 @@ class Mesh:
     (nx*ny*nz ints in 1..7) selects the mixed-degree path."""
 
     def __init__(self, system, nelem, degree, gamma, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), kappa=0.0, flags=0,
-                 degrees=None):
+                 degrees=None, stream=None):
         d = MeshDesc()
         d.system = system
         d.nx, d.ny, d.nz = nelem
@@ -141,7 +144,7 @@ class Mesh:
         else:
             d.degree = degree
         h = ctypes.c_void_p()
-        _check(_lib.dgmi_create(ctypes.byref(d), ctypes.byref(h)), "dgmi_create")
+        _check(_lib.dgmi_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)), "dgmi_create")
         self.handle = h
         self.system = system
         self.gamma = gamma
@@ -312,6 +315,60 @@ def dg_step(mesh, U, prim_inout, dt, stream=None):
     return U
 
 
+class Con2PrimError(DgmiError):
+    """A checked call found failed recoveries; ``n_failed`` holds their number."""
+
+    def __init__(self, msg, n_failed):
+        super().__init__(msg)
+        self.n_failed = n_failed
+
+
+_ECON2PRIM = -4
+
+
+def _check_c2p(st, what, nf):
+    if st == _ECON2PRIM:
+        raise Con2PrimError(f"{what}: {_lib.dgmi_last_error().decode()}", int(nf.value))
+    _check(st, what)
+
+
+def dg_rhs_checked(mesh, U, prim_inout, dUdt, stream=None):
+    """dg_rhs, then a synchronisation; raises Con2PrimError if a recovery of
+    this call failed."""
+    n = mesh.nnodes
+    nf = _I64(0)
+    _check_c2p(_lib.dg_rhs_checked(mesh.handle, _ptr(U, numel=mesh.nv * n, name="U"),
+                                   _ptr(prim_inout, numel=5 * n, name="prim_inout"),
+                                   _ptr(dUdt, numel=mesh.nv * n, name="dUdt"), ctypes.byref(nf), _stream(stream)),
+               "dg_rhs_checked", nf)
+    return dUdt
+
+
+def dg_step_checked(mesh, U, prim_inout, dt, stream=None):
+    n = mesh.nnodes
+    nf = _I64(0)
+    _check_c2p(_lib.dg_step_checked(mesh.handle, _ptr(U, numel=mesh.nv * n, name="U"),
+                                    _ptr(prim_inout, numel=5 * n, name="prim_inout"), float(dt), ctypes.byref(nf),
+                                    _stream(stream)), "dg_step_checked", nf)
+    return U
+
+
+def con2prim_checked(system, gamma, U, prim_inout, n_failed, guess=GUESS_PLAIN, mlp=None, tol=0.0, iters_out=None,
+                     fail_out=None, stream=None):
+    """con2prim with the failure count of this call in n_failed (one-element
+    int64 device tensor); raises Con2PrimError if it is not zero."""
+    n = U.shape[1]
+    nf = _I64(0)
+    _check_c2p(_lib.con2prim_checked(system, gamma, _ptr(U, numel=NVARS[system] * n, name="U"),
+                                     _ptr(prim_inout, numel=5 * n, name="prim_inout"), n, guess,
+                                     mlp.handle if mlp is not None else None, float(tol),
+                                     _ptr(iters_out, torch.uint8, n, "iters_out"),
+                                     _ptr(fail_out, torch.uint8, n, "fail_out"),
+                                     _ptr(n_failed, torch.int64, 1, "n_failed"), ctypes.byref(nf), _stream(stream)),
+               "con2prim_checked", nf)
+    return prim_inout
+
+
 def dgmi_failures(mesh, stream=None):
     v = ctypes.c_int64()
     _check(_lib.dgmi_failures(mesh.handle, ctypes.byref(v), _stream(stream)), "dgmi_failures")
@@ -332,9 +389,9 @@ def con2prim(system, gamma, U, prim_inout, guess=GUESS_PLAIN, mlp=None, tol=0.0,
 class Mlp:
     """Owner of a dgmi_mlp (5 -> 64 -> 64 -> 1 SiLU pressure-guess network)."""
 
-    def __init__(self, seed=0):
+    def __init__(self, seed=0, stream=None):
         h = ctypes.c_void_p()
-        _check(_lib.mlp_create(ctypes.byref(h), seed), "mlp_create")
+        _check(_lib.mlp_create(ctypes.byref(h), seed, _stream(stream)), "mlp_create")
         self.handle = h
 
     def close(self):
