@@ -350,6 +350,93 @@ def test_config3_srmhd_blast_full_size_sampled(ora, dg):
     torch.cuda.empty_cache()
 
 
+def _face_ball(elems, n, r):
+    """Elements within r face-neighbour hops of elems on a periodic n^3 grid."""
+    cur = np.unique(np.asarray(elems))
+    for _ in range(r):
+        c = np.stack([cur % n, (cur // n) % n, cur // (n * n)])
+        nb = [cur]
+        for d in range(3):
+            for s_ in (-1, 1):
+                k = c.copy()
+                k[d] = (k[d] + s_) % n
+                nb.append(k[0] + n * (k[1] + n * k[2]))
+        cur = np.unique(np.concatenate(nb))
+    return cur
+
+
+def test_config3_srmhd_blast_dg_step_full_size_sampled(ora, dg):
+    """One SSP-RK3 step of the SRMHD blast (64^3 elements of degree 3,
+    16,777,216 nodes, the benchmark's state, dt = 4e-4) through dg_step in the
+    benchmark's launch configuration: stage kernels with their tail
+    recoveries and the brick processing order of the full mesh.  The oracle
+    follows the step on the sampled elements only: the operator couples face
+    neighbours, so U^(1) is needed three face hops around the samples, U^(2)
+    two hops and U^(3) on the samples themselves; every stage's primitives
+    are recovered by the oracle.  Bar per variable: the step bar
+    2e-12 dt max|L| + 8 ulp max|U| (with the flux scale for the rates that
+    vanish, B and Phi), and 1e-12 for the primitives of the new state."""
+    import torch
+    g, dt, n = 4.0 / 3.0, 4e-4, 64
+    lo, hi = (-0.5, -0.5, -0.5), (0.5, 0.5, 0.5)
+    m = ora.mesh(MHD, (n, n, n), 3, g, lo=lo, hi=hi, kappa=0.5)
+    G = dg.Mesh(MHD, (n, n, n), 3, g, lo=lo, hi=hi, kappa=0.5)
+    xyz = ora.node_coords(m)
+    prim, mag = synth.blast_wave(xyz, shell=(0.05, 0.15))
+    del xyz
+    U = ora.prim2cons(MHD, g, prim, mag)
+    del mag
+    Ud = to_dev(U)
+    Pd = to_dev(prim)
+    print("config 3 dg_step full size: GPU step", flush=True)
+    dg.dg_step(G, Ud, Pd, dt)
+    assert dg.dgmi_failures(G) == 0
+    rng = np.random.default_rng(11)
+    centre = 32 + 32 * n + 32 * n * n
+    shell = 32 + 36 * n + 32 * n * n
+    E3 = np.unique(np.concatenate([[0, n - 1, n ** 3 - 1, centre, shell], rng.choice(n ** 3, 59, replace=False)]))
+    H1, H2, H3 = (_face_ball(E3, n, r) for r in (1, 2, 3))
+
+    def nodes(el):
+        return (el[:, None] * 64 + np.arange(64)[None, :]).ravel()
+
+    # stage 1 from the given primitives (exactly what dg_step receives)
+    L0 = ora.rhs_elements(m, U, prim, H2)
+    i2, i1, i3 = nodes(H2), nodes(H1), nodes(E3)
+    U1 = np.zeros_like(U)
+    U1[:, i2] = ora.rk3_combine(1, dt, U[:, i2], U[:, i2], L0)
+    P1 = np.zeros_like(prim)
+    P1[:, i2], _, nf1 = ora.cons2prim(MHD, g, U1[:, i2])
+    L1 = ora.rhs_elements(m, U1, P1, H1)
+    U2 = np.zeros_like(U)
+    # H1 is a subset of H2: pick H1's columns out of the H2 block
+    pos = {e: k for k, e in enumerate(H2)}
+    sel1 = (np.array([pos[e] for e in H1])[:, None] * 64 + np.arange(64)[None, :]).ravel()
+    U2[:, i1] = ora.rk3_combine(2, dt, U[:, i1], U1[:, i1], L1)
+    P2 = np.zeros_like(prim)
+    P2[:, i1], _, nf2 = ora.cons2prim(MHD, g, U2[:, i1])
+    L2 = ora.rhs_elements(m, U2, P2, E3)
+    U3 = ora.rk3_combine(3, dt, U[:, i3], U2[:, i3], L2)
+    P3, _, nf3 = ora.cons2prim(MHD, g, U3)
+    assert nf1 == nf2 == nf3 == 0
+    del U1, U2, P1, P2
+    got = to_host(Ud)[:, i3]
+    gotP = to_host(Pd)[:, i3]
+    del Ud, Pd
+    torch.cuda.empty_cache()
+    eps = np.finfo(np.float64).eps
+    Lmax = np.maximum(np.abs(L0[:, sel1]).max(axis=1), np.abs(L2).max(axis=1))
+    fscale = np.max([np.abs(ora.flux(MHD, g, d, U[:, i3], prim[:, i3])).max(axis=1) for d in range(3)], axis=0)
+    Lscale = np.maximum(Lmax, fscale * 2.0 / (1.0 / n))
+    tol = 2e-12 * dt * Lscale + 8 * eps * np.abs(U[:, i3]).max(axis=1)
+    diff = np.abs(got - U3).max(axis=1)
+    assert np.all(diff <= tol), (diff, tol)
+    # the step moved the momentum (the bar is far below the change)
+    assert np.all(np.abs(U3 - U[:, i3]).max(axis=1)[1:4] > 1e3 * tol[1:4])
+    perr = normwise_err(gotP, P3)
+    assert np.all(perr <= 1e-12), perr
+
+
 @pytest.mark.parametrize("system,nel,N", [(SR, (1, 1, 1), 3), (MHD, (1, 1, 1), 2), (SR, (2, 1, 1), 4),
                                           (NE, (1, 2, 1), 5)])
 def test_self_neighbour_meshes(ora, dg, system, nel, N):
