@@ -157,6 +157,20 @@ dgmi_status dg_operator(dgmi_ctx *ctx, const double *U, const double *prim, doub
  * context's time by dt. */
 dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dg_step
+ * with the stage states U^(1), U^(2) and their primitives held in the
+ * library's statically allocated device scratch (one 64 MiB array per device,
+ * held until the process ends) instead of the context's buffers.  The call
+ * allocates nothing; mixed-degree meshes launch their kernels directly (no
+ * graph capture).  Results equal dg_step's bit for bit.  Capacity:
+ * 2 (nv + 5) nnodes <= 8 Mi doubles (419,430 nodes for NE / SR, 299,593
+ * for SRMHD); a larger mesh returns DGMI_EINVAL before any work.  Every call
+ * on a device shares its one scratch array, so calls that overlap on one
+ * device (on different streams or host threads) race; the context's device
+ * must be current (else DGMI_EINVAL). */
+dgmi_status dg_step_noalloc(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream);
+
 /* Checked variants: the same work as dg_rhs / dg_step, then `stream` is
  * synchronised and DGMI_ECON2PRIM is returned if any recovery of this call
  * failed (an unphysical state, or no convergence within the iteration cap;

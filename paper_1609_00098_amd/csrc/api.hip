@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -116,6 +117,39 @@ bool is_device_ptr(const void *p) {
 int dgmi::set_error(int st, const char *msg) {
   std::snprintf(g_err, sizeof(g_err), "%s", msg);
   return st;
+}
+
+// ------------------------------------------------- statically allocated scratch
+// The RK stage states of dg_step_noalloc live in this file-scope device array
+// (64 MiB on every device the library runs on, held until the process ends),
+// so that the call allocates nothing.  In host code `scratch` names a host-side
+// stand-in; its device address is looked up once per device, with that device
+// current, when the first context is created on it.
+constexpr int64_t kScratchDoubles = (int64_t)8 << 20;  // 64 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {nullptr};
+static bool g_scratch_tried[kMaxDevices] = {false};
+
+// Looks up (once) the device address of `scratch` on the current device.
+static void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_tried[device]) return;
+  g_scratch_tried[device] = true;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  g_scratch_ptr[device] = (double *)ptr;
+}
+
+static double *scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 // The limiter counts limited components into this many counters (workgroup b
@@ -658,6 +692,7 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, void *stream, dgmi_ctx **out
   dgmi_ctx *c = new (std::nothrow) dgmi_ctx();
   if (!c) return fail(DGMI_ENOMEM, "dgmi_create: out of host memory");
   (void)hipGetDevice(&c->device);
+  scratch_setup(c->device);
   c->sys = desc->system;
   c->nv = desc->system == 2 ? 9 : 5;
   c->nx = desc->nx; c->ny = desc->ny; c->nz = desc->nz;
@@ -997,6 +1032,26 @@ dgmi_status dg_step(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, voi
     return fail(DGMI_EINVAL, "dg_step: U and prim_inout must be distinct device pointers");
   if (!std::isfinite(dt)) return fail(DGMI_EINVAL, "dg_step: dt must be finite");
   return step_impl(ctx, U, prim_inout, dt, (hipStream_t)stream, ctx_bufs(ctx), true);
+}
+
+dgmi_status dg_step_noalloc(dgmi_ctx *ctx, double *U, double *prim_inout, double dt, void *stream) {
+  if (!ctx) return fail(DGMI_EINVAL, "dg_step_noalloc: null context");
+  if (!is_device_ptr(U) || !is_device_ptr(prim_inout) || U == prim_inout)
+    return fail(DGMI_EINVAL, "dg_step_noalloc: U and prim_inout must be distinct device pointers");
+  if (!std::isfinite(dt)) return fail(DGMI_EINVAL, "dg_step_noalloc: dt must be finite");
+  const int64_t ustride = (int64_t)ctx->nv * ctx->nnodes, pstride = 5 * ctx->nnodes;
+  if (2 * (ustride + pstride) > kScratchDoubles)
+    return fail(DGMI_EINVAL, "dg_step_noalloc: %lld nodes need %lld doubles of RK states, above the %lld of the "
+                "static scratch (at most %lld nodes for this system)", (long long)ctx->nnodes,
+                (long long)(2 * (ustride + pstride)), (long long)kScratchDoubles,
+                (long long)(kScratchDoubles / (2 * (ctx->nv + 5))));
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != ctx->device) return fail(DGMI_EINVAL, "dg_step_noalloc: the context's device is not current");
+  double *sp = scratch_of(dev);
+  if (!sp) return fail(DGMI_EHIP, "dg_step_noalloc: the device address of the static scratch is unknown");
+  const RkBufs b{sp, sp + ustride, sp + 2 * ustride, sp + 2 * ustride + pstride};
+  return step_impl(ctx, U, prim_inout, dt, (hipStream_t)stream, b, false);
 }
 
 // Exterior states of every box-face node (16 doubles each), allocated on

@@ -57,6 +57,7 @@ _SIGS = {
     "dgmi_prim2cons": (_I32, [_I32, _D, _P, _P, _P, _I64, _P]),
     "dg_rhs": (_I32, [_P, _P, _P, _P, _P]),
     "dg_step": (_I32, [_P, _P, _P, _D, _P]),
+    "dg_step_noalloc": (_I32, [_P, _P, _P, _D, _P]),
     "dg_operator": (_I32, [_P, _P, _P, _P, _P]),
     "dg_rhs_checked": (_I32, [_P, _P, _P, _P, ctypes.POINTER(_I64), _P]),
     "dg_step_checked": (_I32, [_P, _P, _P, _D, ctypes.POINTER(_I64), _P]),
@@ -367,6 +368,16 @@ def con2prim_checked(system, gamma, U, prim_inout, n_failed, guess=GUESS_PLAIN, 
                                      _ptr(n_failed, torch.int64, 1, "n_failed"), ctypes.byref(nf), _stream(stream)),
                "con2prim_checked", nf)
     return prim_inout
+
+
+def dg_step_noalloc(mesh, U, prim_inout, dt, stream=None):
+    """dg_step with the intermediate stage states in the library's static
+    device scratch (no allocation; meshes up to its capacity)."""
+    n = mesh.nnodes
+    _check(_lib.dg_step_noalloc(mesh.handle, _ptr(U, numel=mesh.nv * n, name="U"),
+                                _ptr(prim_inout, numel=5 * n, name="prim_inout"), float(dt), _stream(stream)),
+           "dg_step_noalloc")
+    return U
 
 
 def dgmi_failures(mesh, stream=None):
