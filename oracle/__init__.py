@@ -120,6 +120,7 @@ def _load():
     MP = ctypes.POINTER(Mesh)
     sig = {
         "ora_num_threads": (ctypes.c_int, []),
+        "ora_set_num_threads": (None, [ctypes.c_int]),
         "ora_gll": (ctypes.c_int, [ctypes.c_int, D, D]),
         "ora_legendre": (ctypes.c_double, [ctypes.c_int, ctypes.c_double]),
         "ora_diff_matrix": (ctypes.c_int, [ctypes.c_int, D, D]),
@@ -183,6 +184,10 @@ def _c(a, dtype=np.float64):
 
 def num_threads():
     return int(_load().ora_num_threads())
+
+
+def set_num_threads(n):
+    _load().ora_set_num_threads(int(n))
 
 
 # ----------------------------------------------------------------- tables

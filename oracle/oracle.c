@@ -37,6 +37,8 @@ static int nvars_of(int sys) { return sys == 2 ? 9 : 5; }
 
 /* Threads OpenMP regions of the oracle use. */
 int ora_num_threads(void) { return omp_get_max_threads(); }
+/* Threads of later OpenMP regions (n >= 1). */
+void ora_set_num_threads(int n) { if (n >= 1) omp_set_num_threads(n); }
 
 /* ------------------------------------------------------------------------ */
 /* Legendre polynomials and Gauss-Legendre-Lobatto quadrature               */

@@ -44,6 +44,8 @@ struct RhsArgs {
   int32_t *bad;
   const double *lim_h, *lim_mu;
   int poly;            // NE: polytropic equation of state p = rho^gamma
+  int periodic;        // uniform meshes periodic in every direction: face
+                       // neighbours by index arithmetic (else from nbr)
 };
 
 // Numerical fluxes of the uniform-mesh element kernels.

@@ -6,16 +6,21 @@
 //      time; the direction's nodal fluxes go through an LDS buffer and every
 //      thread contracts its pencil with its row of D (eq. for D^{1bar}),
 //      scaled by 2/dx_d.  A node on a face of that direction also parks its
-//      normal flux and its largest wave speed in the face slot: the interior
-//      half of the numerical flux is done by the node that owns it.
-//   2. The EPB*6*(N+1)^2 face nodes are handed out densely: each task reads
-//      the exterior state (the coincident node of the periodic neighbour,
-//      from global memory), forms its flux and speed, and turns the slot into
-//      the difference F*.n - F.n of the numerical flux: local Lax-Friedrichs
-//      (eq. LLF; the interior parks its largest speed), HLL (eq. HLL; the
-//      interior parks its largest and smallest characteristic speed along
-//      the outward normal) or, for the Newtonian ideal gas, Roe (eq. Roe) or
-//      Marquina (from the interior state kept in LDS and the exterior one).
+//      normal flux in the face slot.
+//      Once the last direction is done, the flux buffer takes every node's
+//      state (U and the primitives the node was given) for the face phase.
+//   2. The EPB*6*(N+1)^2 face nodes are handed out densely, each direction's
+//      tasks padded to whole waves so that a wave runs one direction's code:
+//      each task takes its own node's state from LDS and reads the exterior
+//      state (the coincident node of the periodic neighbour) from global
+//      memory, forms the exterior flux and the wave speeds of both sides,
+//      and turns the slot into the difference F*.n - F.n of the numerical
+//      flux: local Lax-Friedrichs (eq. LLF; the larger of the two sides'
+//      largest speeds), HLL (eq. HLL; both sides' largest and smallest
+//      characteristic speeds along the outward normal) or, for the Newtonian
+//      ideal gas, Roe (eq. Roe) or Marquina.  (The speeds are needed at face
+//      nodes only; computed in the volume phase they would cost every lane of
+//      every wave three evaluations.)
 //   3. Each volume thread adds -(2/dx_d)(1/w_end)(F*.n - F.n) for every face
 //      it lies on (edge and corner nodes receive two or three terms).
 //   4. RHS mode writes dU/dt; stage mode forms the Shu-Osher combination
@@ -82,26 +87,26 @@ struct RhsCfg {
   static constexpr int NV = SysTraits<SYS>::nv;
   static constexpr int EPB = EPB_;
   static constexpr int FACE_TASKS = EPB * 6 * NF;
-  // one thread per volume node; SRMHD gets one per face task when there are
-  // more of those (its face tasks are long, a second round of them costs
-  // more than the idle threads of the volume phase: measured 5% at degree 3)
-  static constexpr int WORK = (SYS == kMHD && FACE_TASKS > EPB * NPE) ? FACE_TASKS : EPB * NPE;
+  // face tasks per direction, and that count padded to whole waves (a wave
+  // then runs the code of a single direction)
+  static constexpr int TPD = EPB * 2 * NF;
+  static constexpr int TPDP = ((TPD + 63) / 64) * 64;
+  // one thread per volume node; SRMHD gets one per (padded) face task when
+  // there are more of those (its face tasks are long, a second round of them
+  // costs more than the idle threads of the volume phase: measured 5% at
+  // degree 3)
+  static constexpr int WORK = (SYS == kMHD && 3 * TPDP > EPB * NPE) ? 3 * TPDP : EPB * NPE;
   static constexpr int THREADS = ((WORK + 63) / 64) * 64;
-  // LDS (doubles): volume flux [EPB][NV][NPE], own state [EPB][NV][NPE]
-  // (mixed-degree kernels only; the limited stage keeps [EPB][NPE] flags
-  // there), face slots
-  // [EPB][NV][6][NF], interior wave speeds [EPB][6][NF] (HLL:
-  // [EPB][2][6][NF], the largest then the smallest along the outward normal).
-  // The uniform operator and stage kernels read a face node's own state back
-  // from global memory (an L2 hit: the workgroup loaded it at the start);
-  // without the 8 NV NPE EPB bytes their LDS no longer caps the occupancy
-  // (degree 4 SR: 34.6 -> 24.6 KB, 4 -> 6 waves per SIMD, operator 8% faster).
-  static constexpr int VOL = EPB * NV * NPE;
-  static constexpr int OWN = EPB * NV * NPE;
+  // primitive rows a node's state carries into the face phase: NE none (they
+  // follow from U), SR the pressure, SRMHD all five
+  static constexpr int NPR = SYS == kSR ? 1 : (SYS == kMHD ? 5 : 0);
+  static constexpr int RS = NV + NPR;  // rows per element in the volume buffer
+  // LDS (doubles): the volume buffer [EPB][RS][NPE] (one direction's nodal
+  // fluxes, then each node's state for the face phase), face slots
+  // [EPB][NV][6][NF], D.  (The limited stage adds [EPB][NPE] recovery flags.)
+  static constexpr int VOL = EPB * RS * NPE;
   static constexpr int SLOT = EPB * NV * 6 * NF;
-  static constexpr int SPDW = FLUX == kHLL ? 2 : 1;
-  static constexpr int SPD = EPB * SPDW * 6 * NF;
-  static constexpr int LDS = VOL + OWN + SLOT + SPD + NP * NP;  // doubles
+  static constexpr int LDS = VOL + SLOT + NP * NP;  // doubles
 };
 
 // A node's conserved state and primitives.  SRMHD reads all five primitive
@@ -128,16 +133,11 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
 template <int SYS, int N, int STAGE, int EPB_, bool MIXED, int BT, int FLUX = kLLF, bool MOM = false>
 __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem) {
   using C = RhsCfg<SYS, N, EPB_, FLUX>;
-  constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB;
+  constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB, RS = C::RS;
   double *svol = smem;
-  // own state in LDS only for the mixed-degree kernels; the limited stage
-  // keeps one flag per node there (its recovery results)
-  constexpr bool OWNL = MIXED;
-  constexpr int OWN_SZ = MIXED ? C::OWN : (MOM ? EPB_ * C::NPE : 0);
-  double *sown = svol + C::VOL;
-  double *sslot = sown + OWN_SZ;
-  double *sspd = sslot + C::SLOT;
-  double *sD = sspd + C::SPD;
+  double *sslot = svol + C::VOL;
+  double *sD = sslot + C::SLOT;
+  double *sflag = sD + NP * NP;  // the limited stage's recovery flags
 
   const int tid = threadIdx.x;
   for (int t = tid; t < NP * NP; t += BT) sD[t] = A.Dmat[t];
@@ -157,26 +157,260 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   const int ci = a % NP, cj = (a / NP) % NP, ck = a / NF;
   const int64_t nn = A.nnodes;
 
+  // ---- face tasks.  Task t (padded per direction to whole waves) belongs to
+  // direction d = t / TPDP; within it, element slot fle, side and face node fn.
+  // Its exterior state comes from a mesh node (kind 1), a box-face row
+  // (kind 2) or, on mixed meshes, the mortar kernel's lift terms (kind 3).
+  auto decode = [&](auto dc, int r, int &fle, int &f, int &fn, int &ai, int &kind, int64_t &src) {
+    constexpr int d = decltype(dc)::value;
+    fle = r / (2 * NF);
+    const int r2 = r - fle * 2 * NF;
+    const int side = r2 / NF;
+    fn = r2 - side * NF;
+    f = 2 * d + side;
+    kind = 0;
+    const int64_t fsl = (int64_t)grp * EPB + fle;
+    if (fsl >= (MIXED ? A.nlist : A.nelem)) return;
+    const int64_t fe = MIXED ? (int64_t)A.elist[fsl] : fsl;
+    const int ta = fn % NP, tb = fn / NP;
+    const int ce = side ? N : 0, cn = side ? 0 : N;  // own and exterior index along d
+    ai = d == 0 ? ce + NP * (ta + NP * tb) : (d == 1 ? ta + NP * (ce + NP * tb) : ta + NP * (tb + NP * ce));
+    const int an = d == 0 ? cn + NP * (ta + NP * tb) : (d == 1 ? ta + NP * (cn + NP * tb) : ta + NP * (tb + NP * cn));
+    if constexpr (MIXED) {
+      const int64_t fo = A.foff[fe * 6 + f];
+      if (fo >= 0) {  // neighbour of another degree: the mortar kernel's lift terms
+        kind = 3;
+        src = fo + fn;
+        return;
+      }
+      kind = 1;
+      src = A.off[A.nbr[fe * 6 + f]] + an;
+      return;
+    }
+    int64_t en;
+    if (A.periodic) {  // every direction periodic: the neighbour by arithmetic
+      const int64_t nxy = (int64_t)A.nx * A.ny;
+      const int64_t n_d = d == 0 ? A.nx : (d == 1 ? A.ny : A.nz);
+      const int64_t st = d == 0 ? 1 : (d == 1 ? (int64_t)A.nx : nxy);
+      const int64_t c = d == 0 ? fe % A.nx : (d == 1 ? (fe / A.nx) % A.ny : fe / nxy);
+      en = side ? (c == n_d - 1 ? fe - (n_d - 1) * st : fe + st) : (c == 0 ? fe + (n_d - 1) * st : fe - st);
+    } else {
+      en = A.nbr[fe * 6 + f];
+    }
+    if (en < 0) {  // box face: its node's fixed or analytic exterior state
+      kind = 2;
+      src = (A.boff[f] + (-1 - en) * NF + fn) * 16;
+      return;
+    }
+    kind = 1;
+    src = en * NPE + an;
+  };
+  // raw exterior values of a mesh node: U and the primitive rows it carries
+  auto load_raw = [&](int64_t qe, double *ue, double *pr) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ue[v] = A.U[v * nn + qe];
+    if (SYS == kSR) pr[0] = A.P[4 * nn + qe];
+    if (SYS == kMHD) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) pr[k] = A.P[k * nn + qe];
+    }
+  };
+  constexpr int NPRX = C::NPR > 0 ? C::NPR : 1;
+  // one face task: F*.n - F_int.n into the face slot (pre: the exterior
+  // state was loaded at the start of the kernel)
+  auto face_task = [&](auto dc, auto prec, int r, const double *ue_pre, const double *pr_pre) {
+    constexpr int d = decltype(dc)::value;
+    constexpr bool pre = decltype(prec)::value;
+    int fle, f, fn, ai, kind;
+    int64_t src;
+    decode(dc, r, fle, f, fn, ai, kind, src);
+    if (kind == 0) return;
+    double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
+    if (kind == 3) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) slot[v * 6 * NF] = A.facebuf[src + v * NF];
+      return;
+    }
+    const int side = f & 1;
+    const double hs = side ? 0.5 : -0.5;
+    // the interior node (its state in the volume buffer): park its normal
+    // flux in the slot and keep only its wave speeds in registers
+    const double *own = svol + fle * RS * NPE + ai;
+    double si = 0.0, lmi = 0.0, lpi = 0.0;
+    {
+      double ui[NV], Fi[NV];
+      Prim Pi;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ui[v] = own[v * NPE];
+      if (SYS == kMHD) {
+        Pi.rho = own[NV * NPE];
+        Pi.v[0] = own[(NV + 1) * NPE];
+        Pi.v[1] = own[(NV + 2) * NPE];
+        Pi.v[2] = own[(NV + 3) * NPE];
+        Pi.p = own[(NV + 4) * NPE];
+      } else {
+        Pi = prims_at_pressure<SYS>(ui, A.gamma, SYS == kSR ? own[NV * NPE] : 0.0, A.poly);
+      }
+      flux_normal<SYS>(d, ui, Pi, Fi);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) slot[v * 6 * NF] = Fi[v];
+      if constexpr (FLUX == kHLL) wave_bounds<SYS>(d, ui, Pi, A.gamma, lmi, lpi);
+      else if constexpr (FLUX == kLLF) si = max_speed<SYS>(d, ui, Pi, A.gamma);
+    }
+    // the exterior state
+    double ue[NV], Fe[NV];
+    Prim Pe;
+    if (kind == 2) {
+      const double *bs = A.bface + src;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ue[v] = bs[v];
+      Pe.rho = bs[9]; Pe.v[0] = bs[10]; Pe.v[1] = bs[11]; Pe.v[2] = bs[12]; Pe.p = bs[13];
+    } else {
+      double pr[NPRX];
+      if constexpr (pre) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ue[v] = ue_pre[v];
+#pragma unroll
+        for (int k = 0; k < NPRX; ++k) pr[k] = pr_pre[k];
+      } else {
+        load_raw(src, ue, pr);
+      }
+      if (SYS == kMHD) {
+        Pe.rho = pr[0]; Pe.v[0] = pr[1]; Pe.v[1] = pr[2]; Pe.v[2] = pr[3]; Pe.p = pr[4];
+      } else {
+        Pe = prims_at_pressure<SYS>(ue, A.gamma, SYS == kSR ? pr[0] : 0.0, A.poly);
+      }
+    }
+    flux_normal<SYS>(d, ue, Pe, Fe);
+    if constexpr ((FLUX == kMarquina || FLUX == kRoe) && SYS == kNE) {
+      double ui[5], fi[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        ui[v] = own[v * NPE];
+        fi[v] = slot[v * 6 * NF];
+      }
+      const Prim Pi = prims_at_pressure<kNE>(ui, A.gamma, 0.0, A.poly);
+      const double sg = side ? 1.0 : -1.0;
+      if constexpr (FLUX == kMarquina) {
+        double Fs[5];
+        marquina_flux<d>(sg, ui, Pi, fi, ue, Pe, Fe, A.gamma, Fs);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) slot[v * 6 * NF] = Fs[v] - sg * fi[v];
+      } else {
+        double D[5];
+        roe_dissipation<d>(sg, ui, Pi, ue, Pe, A.gamma, D);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) slot[v * 6 * NF] = hs * (Fe[v] - fi[v]) - 0.5 * D[v];
+      }
+      return;
+    }
+    if constexpr (FLUX == kHLL) {
+      // F*.n - F_int.n = c [n_d (F_ext - F_int) - s+ (U_ext - U_int)] with
+      // c = -s- / (s+ - s-), the bounds (largest and smallest speed along the
+      // outward normal of either side) clipped by zero
+      double lm, lp;
+      wave_bounds<SYS>(d, ue, Pe, A.gamma, lm, lp);
+      const double sp = fmax(0.0, side ? fmax(lpi, lp) : -fmin(lmi, lm));
+      const double sm = fmin(0.0, side ? fmin(lmi, lm) : -fmax(lpi, lp));
+      const double cf = -sm * fast_rcp(sp - sm);
+      const double sg = side ? 1.0 : -1.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double Fi = slot[v * 6 * NF];
+        if (SYS == kMHD && (v == 8 || v == 5 + d))  // bounds -1, +1: the LLF form with alpha = 1
+          slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * (ue[v] - own[v * NPE]);
+        else
+          slot[v * 6 * NF] = cf * (sg * (Fe[v] - Fi) - sp * (ue[v] - own[v * NPE]));
+      }
+      return;
+    }
+    const double alpha = fmax(si, max_speed<SYS>(d, ue, Pe, A.gamma));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double al = alpha;
+      if (SYS == kMHD && (v == 8 || v == 5 + d)) al = 1.0;
+      const double Fi = slot[v * 6 * NF];
+      slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * al * (ue[v] - own[v * NPE]);
+    }
+  };
+
+  // ---- loads: the node's own state and, issued together with it, the
+  // exterior state of this thread's first face task (SRMHD, whose face
+  // tasks are many and heavy, loads its exterior states in the face phase)
+  constexpr bool PREF = SYS != kMHD;
+  const int d0 = __builtin_amdgcn_readfirstlane(tid / C::TPDP);  // uniform across the wave
+  const int r0 = tid - d0 * C::TPDP;
+  const bool has0 = tid < 3 * C::TPDP && r0 < C::TPD;
+  double ue0[NV], pr0[NPRX];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ue0[v] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NPRX; ++k) pr0[k] = 1.0;
+  if (PREF && has0) {
+    int fle, f, fn, ai, kind;
+    int64_t src;
+    if (d0 == 0) decode(std::integral_constant<int, 0>{}, r0, fle, f, fn, ai, kind, src);
+    else if (d0 == 1) decode(std::integral_constant<int, 1>{}, r0, fle, f, fn, ai, kind, src);
+    else decode(std::integral_constant<int, 2>{}, r0, fle, f, fn, ai, kind, src);
+    if (kind == 1) load_raw(src, ue0, pr0);
+  }
+  double *mybuf = svol + le * RS * NPE;  // [row][node] for this element
+  double *myslot = sslot + le * NV * 6 * NF;
+  // every node's state (U and the primitive rows it was given) into the
+  // volume buffer, for the face phase
+  if (active) {
+    double ur[NV], prr[NPRX];
+    load_raw(q, ur, prr);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) mybuf[v * NPE + a] = ur[v];
+#pragma unroll
+    for (int k = 0; k < C::NPR; ++k) mybuf[(NV + k) * NPE + a] = prr[k];
+  }
+  __syncthreads();
+  // ---- face phase: the first round takes the exterior state loaded above
+  if (has0) {
+    using PF = std::integral_constant<bool, PREF>;
+    if (d0 == 0) face_task(std::integral_constant<int, 0>{}, PF{}, r0, ue0, pr0);
+    else if (d0 == 1) face_task(std::integral_constant<int, 1>{}, PF{}, r0, ue0, pr0);
+    else face_task(std::integral_constant<int, 2>{}, PF{}, r0, ue0, pr0);
+  }
+#pragma unroll 1
+  for (int t = tid + BT; t < 3 * C::TPDP; t += BT) {
+    const int d = __builtin_amdgcn_readfirstlane(t / C::TPDP);
+    const int r = t - d * C::TPDP;
+    using NP_ = std::integral_constant<bool, false>;
+    if (r < C::TPD) {
+      if (d == 0) face_task(std::integral_constant<int, 0>{}, NP_{}, r, ue0, pr0);
+      else if (d == 1) face_task(std::integral_constant<int, 1>{}, NP_{}, r, ue0, pr0);
+      else face_task(std::integral_constant<int, 2>{}, NP_{}, r, ue0, pr0);
+    }
+  }
+  __syncthreads();
+
+  // the node's own state back from the volume buffer
   double u[NV];
   Prim P;
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   if (active) {
-    load_node<SYS>(A.U, A.P, nn, q, A.gamma, u, P, A.poly);
-    if (SYS == kMHD) acc[8] = -A.kappa * u[8];
-    if constexpr (OWNL) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sown[(le * NV + v) * NPE + a] = u[v];
+    for (int v = 0; v < NV; ++v) u[v] = mybuf[v * NPE + a];
+    if (SYS == kMHD) {
+      P.rho = mybuf[NV * NPE + a];
+      P.v[0] = mybuf[(NV + 1) * NPE + a];
+      P.v[1] = mybuf[(NV + 2) * NPE + a];
+      P.v[2] = mybuf[(NV + 3) * NPE + a];
+      P.p = mybuf[(NV + 4) * NPE + a];
+      acc[8] = -A.kappa * u[8];
+    } else {
+      P = prims_at_pressure<SYS>(u, A.gamma, SYS == kSR ? mybuf[NV * NPE + a] : 0.0, A.poly);
     }
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = 0.0;
     P.rho = 1.0; P.v[0] = P.v[1] = P.v[2] = 0.0; P.p = 1.0;
   }
-  double *mybuf = svol + le * NV * NPE;  // [v][node] for this element
-  double *myslot = sslot + le * NV * 6 * NF;
-  double *myspd = sspd + le * C::SPDW * 6 * NF;
 
   // ---- volume term, one direction at a time
 #pragma unroll
@@ -186,22 +420,6 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       flux_normal<SYS>(d, u, P, F);
 #pragma unroll
       for (int v = 0; v < NV; ++v) mybuf[v * NPE + a] = F[v];
-      // a face node of this direction parks its half of the face flux
-      const int idx = sel3i(d, ci, cj, ck);
-      if (idx == 0 || idx == N) {
-        const int f = 2 * d + (idx == N ? 1 : 0);
-        const int fn = sel3i(d, cj + NP * ck, ci + NP * ck, ci + NP * cj);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) myslot[(v * 6 + f) * NF + fn] = F[v];
-        if constexpr (FLUX == kHLL) {
-          double lm, lp;
-          wave_bounds<SYS>(d, u, P, A.gamma, lm, lp);
-          myspd[f * NF + fn] = idx == N ? lp : -lm;        // largest along n
-          myspd[(6 + f) * NF + fn] = idx == N ? lm : -lp;  // smallest along n
-        } else {
-          myspd[f * NF + fn] = max_speed<SYS>(d, u, P, A.gamma);
-        }
-      }
     }
     __syncthreads();
     if (active) {
@@ -222,113 +440,6 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     }
     __syncthreads();
   }
-
-  // ---- face terms: dense assignment of the EPB*6*(N+1)^2 face nodes,
-  // ordered by direction so that each branch is compiled for a fixed d (no
-  // run-time selects in the fluxes and speeds); a wave spans at most two
-  // directions
-  auto face_task = [&](auto dc, int r) {
-    constexpr int d = decltype(dc)::value;
-    const int fle = r / (2 * NF);
-    const int r2 = r - fle * 2 * NF;
-    const int side = r2 / NF;
-    const int fn = r2 - side * NF;
-    const int f = 2 * d + side;
-    const int64_t fsl = (int64_t)grp * EPB + fle;
-    if (fsl >= (MIXED ? A.nlist : A.nelem)) return;
-    const int64_t fe = MIXED ? (int64_t)A.elist[fsl] : fsl;
-    if constexpr (MIXED) {
-      const int64_t fo = A.foff[fe * 6 + f];
-      if (fo >= 0) {  // neighbour of another degree: the mortar kernel's lift terms
-        double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) slot[v * 6 * NF] = A.facebuf[fo + v * NF + fn];
-        return;
-      }
-    }
-    const int ta = fn % NP, tb = fn / NP;
-    int c0, c1, c2, n0, n1, n2;
-    if constexpr (d == 0) { c0 = side ? N : 0; c1 = ta; c2 = tb; n0 = side ? 0 : N; n1 = ta; n2 = tb; }
-    else if constexpr (d == 1) { c0 = ta; c1 = side ? N : 0; c2 = tb; n0 = ta; n1 = side ? 0 : N; n2 = tb; }
-    else { c0 = ta; c1 = tb; c2 = side ? N : 0; n0 = ta; n1 = tb; n2 = side ? 0 : N; }
-    const int64_t en = A.nbr[fe * 6 + f];
-    const int ai = c0 + NP * (c1 + NP * c2);
-    double ue[NV], Fe[NV];
-    Prim Pe;
-    if (!MIXED && en < 0) {  // box face: its node's fixed or analytic exterior state
-      const double *bs = A.bface + (A.boff[f] + (-1 - en) * NF + fn) * 16;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) ue[v] = bs[v];
-      Pe.rho = bs[9]; Pe.v[0] = bs[10]; Pe.v[1] = bs[11]; Pe.v[2] = bs[12]; Pe.p = bs[13];
-    } else {
-      const int64_t ebase = MIXED ? A.off[en] : en * NPE;
-      load_node<SYS>(A.U, A.P, nn, ebase + n0 + NP * (n1 + NP * n2), A.gamma, ue, Pe, A.poly);
-    }
-    flux_normal<SYS>(d, ue, Pe, Fe);
-    const double *own = OWNL ? sown + fle * NV * NPE + ai : A.U + fe * NPE + ai;
-    const int64_t ost = OWNL ? NPE : nn;
-    double *slot = sslot + fle * NV * 6 * NF + f * NF + fn;
-    const double hs = side ? 0.5 : -0.5;
-    if constexpr (FLUX == kMarquina && SYS == kNE) {
-      double ui[5], fi[5], Fs[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        ui[v] = own[v * ost];
-        fi[v] = slot[v * 6 * NF];
-      }
-      const Prim Pi = prims_at_pressure<kNE>(ui, A.gamma, 0.0);
-      const double sg = side ? 1.0 : -1.0;
-      marquina_flux<d>(sg, ui, Pi, fi, ue, Pe, Fe, A.gamma, Fs);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) slot[v * 6 * NF] = Fs[v] - sg * fi[v];
-      return;
-    }
-    if constexpr (FLUX == kRoe && SYS == kNE) {
-      double ui[5], D[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) ui[v] = own[v * ost];
-      const Prim Pi = prims_at_pressure<kNE>(ui, A.gamma, 0.0);
-      roe_dissipation<d>(side ? 1.0 : -1.0, ui, Pi, ue, Pe, A.gamma, D);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) slot[v * 6 * NF] = hs * (Fe[v] - slot[v * 6 * NF]) - 0.5 * D[v];
-      return;
-    }
-    if constexpr (FLUX == kHLL) {
-      // F*.n - F_int.n = c [n_d (F_ext - F_int) - s+ (U_ext - U_int)] with
-      // c = -s- / (s+ - s-), the two bounds clipped by zero
-      double lm, lp;
-      wave_bounds<SYS>(d, ue, Pe, A.gamma, lm, lp);
-      const double *spd = sspd + fle * 2 * 6 * NF;
-      const double sp = fmax(0.0, fmax(spd[f * NF + fn], side ? lp : -lm));
-      const double sm = fmin(0.0, fmin(spd[(6 + f) * NF + fn], side ? lm : -lp));
-      const double cf = -sm * fast_rcp(sp - sm);
-      const double sg = side ? 1.0 : -1.0;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double Fi = slot[v * 6 * NF];
-        if (SYS == kMHD && (v == 8 || v == 5 + d))  // bounds -1, +1: the LLF form with alpha = 1
-          slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * (ue[v] - own[v * ost]);
-        else
-          slot[v * 6 * NF] = cf * (sg * (Fe[v] - Fi) - sp * (ue[v] - own[v * ost]));
-      }
-      return;
-    }
-    const double alpha = fmax(sspd[(fle * 6 + f) * NF + fn], max_speed<SYS>(d, ue, Pe, A.gamma));
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double al = alpha;
-      if (SYS == kMHD && (v == 8 || v == 5 + d)) al = 1.0;
-      const double Fi = slot[v * 6 * NF];
-      slot[v * 6 * NF] = hs * (Fe[v] - Fi) - 0.5 * al * (ue[v] - own[v * ost]);
-    }
-  };
-  constexpr int TPD = EPB * 2 * NF;  // tasks per direction
-  for (int t = tid; t < C::FACE_TASKS; t += BT) {
-    if (t < TPD) face_task(std::integral_constant<int, 0>{}, t);
-    else if (t < 2 * TPD) face_task(std::integral_constant<int, 1>{}, t - TPD);
-    else face_task(std::integral_constant<int, 2>{}, t - 2 * TPD);
-  }
-  __syncthreads();
 
   // (the limited stage, MOM, keeps every thread for the moment reduction)
   if (!MOM && !active) return;
@@ -355,7 +466,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   if constexpr (MOM) {
     // limited stage: recover every node of U^(s), then reduce each element to
     // the limiter's moments (the slope limiter runs next, over the grid)
-    double *su = svol, *okf = sown, *tabs = sD;
+    double *su = svol, *okf = sflag, *tabs = sD;
     if (active) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -409,7 +520,7 @@ template <int SYS, int N, int STAGE, int EPB_ = default_epb<SYS, N>(), bool MIXE
           bool MOM = false>
 __global__ void __launch_bounds__((RhsCfg<SYS, N, EPB_>::THREADS)) rhs_kernel(const RhsArgs A) {
   using C = RhsCfg<SYS, N, EPB_, FLUX>;
-  __shared__ double smem[C::LDS - C::OWN + (MIXED ? C::OWN : (MOM ? C::EPB * C::NPE : 0))];
+  __shared__ double smem[C::LDS + (MOM ? C::EPB * C::NPE : 0)];
   // XCD-major block order: hardware block b runs on XCD b % 8, which walks
   // its own contiguous range of the processing order.
   const int per = (A.nblocks + 7) >> 3;
