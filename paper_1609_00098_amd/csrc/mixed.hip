@@ -80,27 +80,26 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
 // interpolation and projection one direction at a time):
 //   L  lanes k < (Nlo+1)^2 load the lower side's face nodes: interpolation
 //      state and normal fluxes F_h;
-//   I1 interpolate the state along the first tangential direction;
+//   I1 interpolate the state and F_h along the first tangential direction;
 //   I2 finish the interpolation at the mortar nodes; each mortar lane (which
-//      loaded its higher-side node at the start) forms F*.n and writes the
-//      higher side's lift term F*.n - F.n;
-//   P1, P2 project F*.n_lo onto the lower side's nodes along each direction
-//      and subtract Q F_h, Q = P I (the projection of the interpolant of its
-//      own fluxes, a fixed (Nlo+1)^2 operator).
+//      loaded its higher-side node at the start) forms F*.n, writes the
+//      higher side's lift term F*.n - F.n and keeps F*.n_lo - I F_h.n_lo;
+//   P1, P2 project that difference onto the lower side's nodes along each
+//      direction.
 template <int SYS>
 __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   constexpr int NV = SysTraits<SYS>::nv, NS = Interp<SYS>::ns;
-  // two buffers serve two phases each (every phase ends at a barrier), which
-  // keeps the LDS per face at 15 x 64 doubles and the occupancy up
-  constexpr int NB = NS > NV ? NS : NV;
-  __shared__ double bufA[NB * 64];
-  __shared__ double bufB[NB * 64];
-  __shared__ double fl[NV * 64];  // lower side's nodal normal fluxes, [v][node]
-  double *const st = bufA;        // lower side's interpolation state, [c][node]      (L, I1)
-  double *const t1 = bufB;        // state interpolated along a, [c][ma + nm ib]       (I1, I2)
-  double *const jm = bufA;        // F*.n_lo at the mortar nodes, [v][m]               (I2, P1)
-  double *const g1 = bufB;        // projection along a, [v][a + nl mb]               (P1, P2)
-  __shared__ double sI[64], sP[64], sQ[64];
+  // channels interpolated to the mortar: the state, then the lower side's
+  // nodal normal fluxes
+  constexpr int NC = NS + NV;
+  // two buffers serve two phases each (every phase ends at a barrier)
+  __shared__ double bufA[NC * 64];
+  __shared__ double bufB[NC * 64];
+  double *const st = bufA;        // lower side's state and F_h, [c][node]              (L, I1)
+  double *const t1 = bufB;        // interpolated along a, [c][ma + nm ib]               (I1, I2)
+  double *const jm = bufA;        // F*.n_lo - I F_h.n_lo at the mortar nodes, [v][m]    (I2, P1)
+  double *const g1 = bufB;        // projection along a, [v][a + nl mb]                 (P1, P2)
+  __shared__ double sI[64], sP[64];
   const int64_t t = blockIdx.x;
   if (t >= A.nfaces) return;
   const int l = threadIdx.x;
@@ -120,7 +119,6 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   const int tab = (Nlo * 8 + Nm) * 64;
   sI[l] = A.Itab[tab + l];  // I[ma][ia] (row stride 8)
   sP[l] = A.Ptab[tab + l];  // P[a][ma]
-  sQ[l] = A.Qtab[tab + l];  // Q[a][ia]
 
   // the higher side's node of this lane's mortar position, loaded up front so
   // that its latency overlaps the lower side's loads
@@ -158,36 +156,36 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     double F[NV];
     flux_normal<SYS>(d, u, P, F);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) fl[v * 64 + l] = F[v];
+    for (int v = 0; v < NV; ++v) st[(NS + v) * 64 + l] = F[v];
   }
   __syncthreads();
 
   // I1: t1[c][ma + nm ib] = sum_ia I[ma][ia] st[c][ia + nl ib]
   if (l < nm * nl) {
     const int ma = l % nm, ib = l / nm;
-    double acc[NS];
+    double acc[NC];
 #pragma unroll
-    for (int c = 0; c < NS; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     for (int ia = 0; ia < nl; ++ia) {
       const double w = sI[ma * 8 + ia];
 #pragma unroll
-      for (int c = 0; c < NS; ++c) acc[c] += w * st[c * 64 + ia + nl * ib];
+      for (int c = 0; c < NC; ++c) acc[c] += w * st[c * 64 + ia + nl * ib];
     }
 #pragma unroll
-    for (int c = 0; c < NS; ++c) t1[c * 64 + l] = acc[c];
+    for (int c = 0; c < NC; ++c) t1[c * 64 + l] = acc[c];
   }
   __syncthreads();
 
   // I2 + flux at the mortar node
   if (l < nm * nm) {
     const int ma = l % nm, mb = l / nm;
-    double s[NS];
+    double s[NC];
 #pragma unroll
-    for (int c = 0; c < NS; ++c) s[c] = 0.0;
+    for (int c = 0; c < NC; ++c) s[c] = 0.0;
     for (int ib = 0; ib < nl; ++ib) {
       const double w = sI[mb * 8 + ib];
 #pragma unroll
-      for (int c = 0; c < NS; ++c) s[c] += w * t1[c * 64 + ma + nm * ib];
+      for (int c = 0; c < NC; ++c) s[c] += w * t1[c * 64 + ma + nm * ib];
     }
     double ul[NV], Fl[NV];
     Prim Pl;
@@ -203,7 +201,9 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
       // F*.n_hi with the higher side interior
       const double diss = 0.5 * al * (ul[v] - uh[v]);
       out_hi[v * nm * nm] = hs * (Fl[v] - Fh[v]) - diss;
-      jm[v * 64 + l] = diss - hs * (Fh[v] + Fl[v]);  // F*.n_lo = -F*.n_hi
+      // F*.n_lo = -F*.n_hi, less the interpolant of the lower side's own
+      // normal fluxes (s[NS + v] is along +e_d)
+      jm[v * 64 + l] = diss - hs * (Fh[v] + Fl[v]) - sgn_lo * s[NS + v];
     }
   }
   __syncthreads();
@@ -224,31 +224,20 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   }
   __syncthreads();
 
-  // P2: lower side's lift term P F*.n_lo - sgn_lo (Q x Q) F_h at node (a, b)
+  // P2: lower side's lift term P (F*.n_lo - I F_h.n_lo) at node (a, b)
   if (l < nl * nl) {
     const int a = l % nl, b = l / nl;
-    double g[NV], h[NV];
+    double g[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      g[v] = 0.0;
-      h[v] = 0.0;
-    }
+    for (int v = 0; v < NV; ++v) g[v] = 0.0;
     for (int mb = 0; mb < nm; ++mb) {
       const double w = sP[b * 8 + mb];
 #pragma unroll
       for (int v = 0; v < NV; ++v) g[v] += w * g1[v * 64 + a + nl * mb];
     }
-    for (int ib = 0; ib < nl; ++ib) {
-      const double wb = sQ[b * 8 + ib];
-      for (int ia = 0; ia < nl; ++ia) {
-        const double w = sQ[a * 8 + ia] * wb;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) h[v] += w * fl[v * 64 + ia + nl * ib];
-      }
-    }
     double *out_lo = A.facebuf + A.foff[elo * 6 + 2 * d + side_lo] + l;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out_lo[v * nl * nl] = g[v] - sgn_lo * h[v];
+    for (int v = 0; v < NV; ++v) out_lo[v * nl * nl] = g[v];
   }
 }
 
