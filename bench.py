@@ -202,10 +202,12 @@ def mixed_degree_steps(dg, synth, torch, steps=50, warmup=3):
 def learned_vs_plain(dg, synth, torch, npts, ntrain):
     """Recovery throughput on npts SRMHD states drawn like the training set
     (rho log-uniform [1e-3, 1e2], p/rho log-uniform [1e-4, 1e2], W up to 20,
-    magnetisation up to 10), at backward residual 1e-10, seeded three ways:
-    the bracket's upper end (plain), the trained network (learned), and the
-    true pressure times 1.01 (warm reference).  The network is trained
-    in-library on ntrain samples of a different seed."""
+    magnetisation up to 10), at backward residual 1e-10, seeded four ways:
+    the bracket's upper end (plain), the pressure function's value at zero
+    pressure f(0) (a closed form, one evaluation), the trained network
+    (learned, FP32), and the true pressure times 1.01 (warm reference).
+    Iteration counts include the seeds' evaluation of f(0).  The network is
+    trained in-library on ntrain samples of a different seed."""
     res = {"workload": f"SRMHD con2prim, {npts:.0e} points, tol 1e-10; MLP 5-64-64-1 SiLU trained on {ntrain:.0e}"}
     # training
     prim, mag = synth.srmhd_samples(ntrain, seed=1, xp="torch", device="cuda")
@@ -231,7 +233,8 @@ def learned_vs_plain(dg, synth, torch, npts, ntrain):
     P = torch.empty((5, npts), dtype=torch.float64, device="cuda")
     iters = torch.empty(npts, dtype=torch.uint8, device="cuda")
     nfail = torch.zeros(1, dtype=torch.int64, device="cuda")
-    for name, guess in (("plain", dg.GUESS_PLAIN), ("learned", dg.GUESS_LEARNED), ("warm_1pct", dg.GUESS_INPUT)):
+    for name, guess in (("plain", dg.GUESS_PLAIN), ("f0", dg.GUESS_F0), ("learned", dg.GUESS_LEARNED),
+                        ("warm_1pct", dg.GUESS_INPUT)):
         def run(i):
             if guess == dg.GUESS_INPUT:
                 P[4].copy_(ptrue).mul_(1.01)

@@ -52,7 +52,9 @@ enum { DGMI_NEWTONIAN_EULER = 0, DGMI_SR_HYDRO = 1, DGMI_SR_MHD = 2 };
 enum {
   DGMI_GUESS_INPUT = 0,   /* prim_inout[4][i] on entry */
   DGMI_GUESS_PLAIN = 1,   /* upper end of the bracket (ignores prim_inout on entry) */
-  DGMI_GUESS_LEARNED = 2  /* the pressure-guess MLP (needs an MLP handle) */
+  DGMI_GUESS_LEARNED = 2, /* the pressure-guess MLP (needs an MLP handle) */
+  DGMI_GUESS_F0 = 3       /* f(0) = (gamma-1) rho eps at zero pressure, the pressure function's value
+                             there (closed form; the bracket's top where it is not positive) */
 };
 
 /* dgmi_mesh_desc.flags */
@@ -325,7 +327,8 @@ dgmi_status dg_step_ab3(dgmi_ctx *ctx, double *U, double *prim_inout, double dt,
  *   and out.  tol > 0: stop once the backward residual
  *   max(|dD|/D, |dS|_inf/E, |dtau|/E) of the returned primitives is <= tol
  *   (E = tau + D); tol <= 0: polish to rounding level.
- *   iters_out (uint8[n], nullable): pressure-function evaluations used;
+ *   iters_out (uint8[n], nullable): pressure-function evaluations used
+ *   (the learned and f(0) seeds count their evaluation of f(0));
  *   fail_out (uint8[n], nullable): 1 where no physical state was found
  *   (prims then hold the last iterate); n_failed (device int64, nullable):
  *   incremented by the number of failures.

@@ -1466,7 +1466,7 @@ static dgmi_status c2p_args(const char *name, int32_t system, double gamma, cons
                             int64_t n, int32_t guess, const dgmi_mlp *mlp, double tol, uint8_t *iters_out,
                             uint8_t *fail_out, int64_t *n_failed) {
   if (system < 0 || system > 2) return fail(DGMI_EINVAL, "%s: unknown system", name);
-  if (guess < 0 || guess > 2) return fail(DGMI_EINVAL, "%s: unknown guess mode", name);
+  if (guess < 0 || guess > 3) return fail(DGMI_EINVAL, "%s: unknown guess mode", name);
   if (n < 0) return fail(DGMI_EINVAL, "%s: negative size", name);
   if (!(gamma > 1.0 && gamma <= 2.0)) return fail(DGMI_EINVAL, "%s: gamma must be in (1, 2]", name);
   if (!std::isfinite(tol)) return fail(DGMI_EINVAL, "%s: tol must be finite", name);

@@ -99,31 +99,29 @@ __device__ __forceinline__ float mlp_forward_one(const float *w, const float *xn
 }
 
 // ---------------------------------------------------------------------
-// Recovery seed on the matrix cores.  One wave evaluates the network for its
-// 64 points together: layer 1 (5 -> 64) and the activations on the vector
-// units in FP32, layer 2 (the 64 x 64 product, 90% of the flops) as
-// [64 points x 64] x [64 x 64] with v_mfma_f32_32x32x8_f16 (fp16 operands,
-// FP32 accumulation), layer 3 as a per-point dot product.  fp16 operands
-// move the predicted ln(p/D) by about 1e-3; the seed only starts the FP64
-// Newton iteration.
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+// Recovery seed on the matrix cores, all in FP32.  One wave evaluates the
+// network for its 64 points together:
+//   layer 1 (5 -> 64) and its activations on the vector units, two hidden
+//     units at a time, each lane for its own point;
+//   layer 2 (the 64 x 64 product, 90% of the flops) as [64 points x 64] x
+//     [64 x 64] with v_mfma_f32_32x32x2_f32 (FP32 operands and accumulation),
+//     fed straight from registers: for k step ks the A operand of lane l is
+//     unit 2 ks + l / 32 of point l % 32 (+32 for the second row tile), so
+//     one exchange of the two half-waves per step supplies it;
+//   layer 3 as a per-point dot product, summed over the units the lanes of a
+//     half-wave hold by a butterfly of half-wave exchanges.
+// No per-wave LDS: the block shares only the weights.
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
 
-constexpr int kSeedStride = kH + 4;  // fp16 row stride of the per-wave activation tiles
-
-struct MlpSeedShared {  // per block: the small weights in FP32, W2 as fp16 operand fragments
+struct MlpSeedShared {  // per block: the weights in FP32, W2 as operand fragments
   float w1[kH * kIn], b1[kH], b2[kH], w3[kH], b3, mu[kIn], sd[kIn], ymu, ysd;
-  half4_t w2f[2][8][64];  // [n tile][k step][lane]
-};
-struct MlpSeedWave {    // per wave: layer-1 and layer-2 activations, [point][unit]
-  alignas(16) _Float16 h1[64 * kSeedStride];
-  alignas(16) _Float16 h2[64 * kSeedStride];
+  float2_t w2f[32][64];  // [k step][lane]: W2[l % 32][2 ks + l / 32], W2[l % 32 + 32][2 ks + l / 32]
 };
 
 // Fills the block's shared weights.  The B operand of layer 2 is
-// B[k][n] = W2[n][k]; in the 32x32x8 operand layout lane l holds column
-// n = l % 32 (+32 per n tile) and rows k = 4 (l / 32) + 8 ks + {0..3}, stored
-// per (tile, step, lane) so that each lane reads one 8-byte fragment.
+// B[k][n] = W2[n][k]; in the 32x32x2 layout lane l holds column n = l % 32
+// (+32 for the second column tile) at row k = 2 ks + l / 32.
 __device__ __forceinline__ void mlp_seed_load_shared(const float *p, MlpSeedShared *s) {
   for (int t = threadIdx.x; t < kH * kIn; t += blockDim.x) s->w1[t] = p[kOffW1 + t];
   for (int t = threadIdx.x; t < kH; t += blockDim.x) {
@@ -140,91 +138,99 @@ __device__ __forceinline__ void mlp_seed_load_shared(const float *p, MlpSeedShar
     s->ymu = p[kOffYmu];
     s->ysd = p[kOffYsd];
   }
-  for (int t = threadIdx.x; t < 2 * 8 * 64; t += blockDim.x) {
-    const int l = t & 63, ks = (t >> 6) & 7, nt = t >> 9;
-    const float *src = p + kOffW2 + ((l & 31) + 32 * nt) * kH + 4 * (l >> 5) + 8 * ks;
-    half4_t b;
-    b[0] = (_Float16)src[0];
-    b[1] = (_Float16)src[1];
-    b[2] = (_Float16)src[2];
-    b[3] = (_Float16)src[3];
-    s->w2f[nt][ks][l] = b;
+  for (int t = threadIdx.x; t < 32 * 64; t += blockDim.x) {
+    const int l = t & 63, ks = t >> 6;
+    const int k = 2 * ks + (l >> 5), n = l & 31;
+    float2_t b;
+    b[0] = p[kOffW2 + n * kH + k];
+    b[1] = p[kOffW2 + (n + 32) * kH + k];
+    s->w2f[ks][l] = b;
   }
 }
 
 __device__ __forceinline__ float silu_seed(float x) { return x * __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// One step of a recursive-halving sum across lanes l and l ^ M: each keeps
+// the half of V[0 .. 2M) selected by bit M of its lane (moved to V[0 .. M))
+// plus the partner's copy of that half.
+template <int M>
+__device__ __forceinline__ void halving_step(float *V, int l) {
+  const bool keep_hi = (l & M) != 0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const float mine = keep_hi ? V[j + M] : V[j];
+    const float send = keep_hi ? V[j] : V[j + M];
+    V[j] = mine + __shfl_xor(send, M);
+  }
 }
 
 // Called by all 64 lanes of a wave together (every lane must take part);
 // returns this lane's seed D exp(y).
 template <int SYS>
-__device__ __forceinline__ double mlp_seed_wave(const MlpSeedShared *s, MlpSeedWave *ws, const double *u, double g) {
+__device__ __forceinline__ double mlp_seed_wave(const MlpSeedShared *s, const double *u, double g) {
   const int l = threadIdx.x & 63;
+  const bool lo = l < 32;
   float x[kIn];
   mlp_features<SYS>(u, g, x);
 #pragma unroll
   for (int i = 0; i < kIn; ++i) x[i] = (x[i] - s->mu[i]) / s->sd[i];
-  // layer 1: this lane's row of h1
-#pragma unroll 1
-  for (int j4 = 0; j4 < kH / 4; ++j4) {
-    half4_t hv;
+  // C[rt][nt]: points 32 rt .. 32 rt + 31 against units 32 nt .. 32 nt + 31;
+  // entry a of lane l is point 8 (a / 4) + 4 (l / 32) + a % 4 (+ 32 rt) and
+  // unit l % 32 (+ 32 nt)
+  floatx16_t C00, C01, C10, C11;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = 4 * j4 + c;
+  for (int a = 0; a < 16; ++a) {
+    C00[a] = 0.0f;
+    C01[a] = 0.0f;
+    C10[a] = 0.0f;
+    C11[a] = 0.0f;
+  }
+#pragma unroll 1
+  for (int ks = 0; ks < 32; ++ks) {
+    // layer 1: units 2 ks and 2 ks + 1 of this lane's point
+    float h[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int j = 2 * ks + c;
       float a = s->b1[j];
 #pragma unroll
       for (int i = 0; i < kIn; ++i) a += s->w1[j * kIn + i] * x[i];
-      hv[c] = (_Float16)silu_seed(a);
+      h[c] = silu_seed(a);
     }
-    *reinterpret_cast<half4_t *>(ws->h1 + l * kSeedStride + 4 * j4) = hv;
+    // the other half-wave's unit: lanes < 32 need unit 2 ks of point l + 32,
+    // lanes >= 32 unit 2 ks + 1 of point l - 32
+    const float other = __shfl_xor(lo ? h[1] : h[0], 32);
+    const float A0 = lo ? h[0] : other;  // row tile 0: points 0..31
+    const float A1 = lo ? other : h[1];  // row tile 1: points 32..63
+    const float2_t B = s->w2f[ks][l];
+    C00 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0, B[0], C00, 0, 0, 0);
+    C01 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0, B[1], C01, 0, 0, 0);
+    C10 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1, B[0], C10, 0, 0, 0);
+    C11 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1, B[1], C11, 0, 0, 0);
   }
-  wave_lds_sync();
-  // layer 2 on the matrix cores, one 32-unit column tile at a time: rows =
-  // points (two 32-row tiles), eight k steps of 8; accumulator a of lane l
-  // holds row 8 (a / 4) + 4 (l / 32) + a % 4 and column l % 32 of its tile
-#pragma unroll 1
-  for (int nt = 0; nt < 2; ++nt) {
-    floatx16_t C0, C1;
+  // layer 2 activations times the layer-3 weights, summed over this lane's
+  // two units: V[16 rt + a] belongs to point 32 rt + 8 (a / 4) + 4 (l / 32) + a % 4
+  const int n0 = l & 31, n1 = n0 + 32;
+  const float b20 = s->b2[n0], b21 = s->b2[n1], w30 = s->w3[n0], w31 = s->w3[n1];
+  float V[32];
 #pragma unroll
-    for (int a = 0; a < 16; ++a) {
-      C0[a] = 0.0f;
-      C1[a] = 0.0f;
-    }
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      const half4_t B = s->w2f[nt][ks][l];
-      const int k = 4 * (l >> 5) + 8 * ks;
-      const half4_t A0 = *reinterpret_cast<const half4_t *>(ws->h1 + (l & 31) * kSeedStride + k);
-      const half4_t A1 = *reinterpret_cast<const half4_t *>(ws->h1 + ((l & 31) + 32) * kSeedStride + k);
-      C0 = __builtin_amdgcn_mfma_f32_32x32x8f16(A0, B, C0, 0, 0, 0);
-      C1 = __builtin_amdgcn_mfma_f32_32x32x8f16(A1, B, C1, 0, 0, 0);
-    }
-    const int n = (l & 31) + 32 * nt;
-    const float bn = s->b2[n];
-#pragma unroll
-    for (int a = 0; a < 16; ++a) {
-      const int pt = 8 * (a >> 2) + 4 * (l >> 5) + (a & 3);
-      ws->h2[pt * kSeedStride + n] = (_Float16)silu_seed(C0[a] + bn);
-      ws->h2[(pt + 32) * kSeedStride + n] = (_Float16)silu_seed(C1[a] + bn);
-    }
+  for (int a = 0; a < 16; ++a) {
+    V[a] = w30 * silu_seed(C00[a] + b20) + w31 * silu_seed(C01[a] + b21);
+    V[16 + a] = w30 * silu_seed(C10[a] + b20) + w31 * silu_seed(C11[a] + b21);
   }
-  wave_lds_sync();
-  // layer 3: this lane's point
-  float y0 = s->b3, y1 = 0.0f;
-#pragma unroll 4
-  for (int n4 = 0; n4 < kH / 4; ++n4) {
-    const half4_t hv = *reinterpret_cast<const half4_t *>(ws->h2 + l * kSeedStride + 4 * n4);
-    y0 += s->w3[4 * n4] * (float)hv[0] + s->w3[4 * n4 + 2] * (float)hv[2];
-    y1 += s->w3[4 * n4 + 1] * (float)hv[1] + s->w3[4 * n4 + 3] * (float)hv[3];
-  }
-  const float y = (y0 + y1) * s->ysd + s->ymu;
-  // the seed needs no more than FP32 (the FP64 iteration decides the result):
-  // the FP32 exponential instead of the FP64 library one (+3-6% throughput)
+  // sum over the 32 lanes of the half-wave (their units): recursive halving,
+  // after which lane l holds the full sum of entry l % 32
+  halving_step<16>(V, l);
+  halving_step<8>(V, l);
+  halving_step<4>(V, l);
+  halving_step<2>(V, l);
+  halving_step<1>(V, l);
+  // entry v = l % 32 of half-wave h = l / 32 is point 32 (v / 16) +
+  // 8 ((v % 16) / 4) + 4 h + v % 4; fetch this lane's own point
+  const int src = 32 * ((l >> 2) & 1) + 16 * (l >> 5) + 4 * ((l >> 3) & 3) + (l & 3);
+  const float ysum = __shfl(V[0], src);
+  const float y = (s->b3 + ysum) * s->ysd + s->ymu;
+  // the seed needs no more than FP32 (the FP64 iteration decides the result)
   return u[0] * (double)__expf(y);
 }
 

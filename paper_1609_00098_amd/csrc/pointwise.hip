@@ -13,12 +13,9 @@ __global__ void __launch_bounds__(256) con2prim_kernel(const C2PArgs A) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   unsigned long long nbad = 0;
   MlpSeedShared *sm = nullptr;
-  MlpSeedWave *ws = nullptr;
   if (GUESS == 2) {
     __shared__ MlpSeedShared smem;
-    __shared__ MlpSeedWave wsm[4];
     sm = &smem;
-    ws = &wsm[threadIdx.x >> 6];
     mlp_seed_load_shared(A.mlp, sm);
     __syncthreads();
   }
@@ -38,10 +35,23 @@ __global__ void __launch_bounds__(256) con2prim_kernel(const C2PArgs A) {
       u[4] = 1.0;
     }
     double p0 = -1.0;
+    int extra = 0;  // pressure-function evaluations spent on the seed
     if (GUESS == 0 && valid) p0 = A.prim[4 * n + q];
-    if (GUESS == 2) p0 = mlp_seed_wave<SYS>(sm, ws, u, A.gamma);
+    if (GUESS == 2) {
+      p0 = mlp_seed_wave<SYS>(sm, u, A.gamma);
+      extra = 1;  // the network's f(0) feature
+    }
+    if (GUESS == 3 && valid) {
+      // f(0): the thermal energy left at zero pressure, an estimate of p
+      // from above for the states of interest (taken if it lies inside the
+      // bracket; the recovery falls back to the bracket's top otherwise)
+      double f0 = 0.0;
+      if (pressure_function<SYS>(u, A.gamma, 0.0, &f0) && f0 > 0.0) p0 = f0;
+      extra = 1;
+    }
     if (!valid) continue;
-    const C2PResult R = recover<SYS>(u, A.gamma, p0, A.tol, 100, A.poly);
+    C2PResult R = recover<SYS>(u, A.gamma, p0, A.tol, 100, A.poly);
+    R.iters += extra;
     A.prim[q] = R.P.rho;
     A.prim[n + q] = R.P.v[0];
     A.prim[2 * n + q] = R.P.v[1];
@@ -73,6 +83,10 @@ static hipError_t c2p_sys(int guess, const C2PArgs &a, hipStream_t s) {
       if (SYS == kNE) return hipErrorInvalidValue;
       hipLaunchKernelGGL((con2prim_kernel<SYS, 2>), dim3(grid), dim3(256), 0, s, a);
       break;
+    case 3:
+      if (SYS == kNE) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((con2prim_kernel<SYS, 3>), dim3(grid), dim3(256), 0, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -80,7 +94,7 @@ static hipError_t c2p_sys(int guess, const C2PArgs &a, hipStream_t s) {
 
 hipError_t launch_con2prim(int sys, int guess, const C2PArgs &a, hipStream_t s) {
   switch (sys) {
-    case kNE: return c2p_sys<kNE>(guess == 2 ? 1 : guess, a, s);
+    case kNE: return c2p_sys<kNE>(guess >= 2 ? 1 : guess, a, s);
     case kSR: return c2p_sys<kSR>(guess, a, s);
     case kMHD: return c2p_sys<kMHD>(guess, a, s);
   }

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgmi.so")
 
 NEWTONIAN_EULER, SR_HYDRO, SR_MHD = 0, 1, 2
-GUESS_INPUT, GUESS_PLAIN, GUESS_LEARNED = 0, 1, 2
+GUESS_INPUT, GUESS_PLAIN, GUESS_LEARNED, GUESS_F0 = 0, 1, 2, 3
 FLAG_PLAIN_GUESS, FLAG_RECOVER_FIRST, FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_HLL, FLAG_POLYTROPIC = 1, 2, 4, 8, 16, 32
 FLAG_ROE, FLAG_MARQUINA = 64, 128
 LIMITER_NONE, LIMITER_MINMOD, LIMITER_MUSCL = 0, 1, 2

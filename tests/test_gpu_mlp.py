@@ -129,7 +129,7 @@ def test_trained_guess_cuts_iterations_at_equal_residual(ora, dg):
     vp, vm = synth.srmhd_samples(50_000, seed=3)
     Uv = ora.prim2cons(MHD, G43, vp, vm)
     res = {}
-    for guess in (dg.GUESS_PLAIN, dg.GUESS_LEARNED):
+    for guess in (dg.GUESS_PLAIN, dg.GUESS_F0, dg.GUESS_LEARNED):
         P = torch.zeros((5, Uv.shape[1]), dtype=torch.float64, device="cuda")
         it = torch.zeros(Uv.shape[1], dtype=torch.uint8, device="cuda")
         nf = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -139,13 +139,17 @@ def test_trained_guess_cuts_iterations_at_equal_residual(ora, dg):
         r = ora.backward_residual(MHD, G43, Uv, to_host(P))
         assert r.max() <= 1e-10
         res[guess] = to_host(it).astype(np.float64).mean()
+    print("mean pressure-function evaluations (plain, f(0), learned):", res[dg.GUESS_PLAIN], res[dg.GUESS_F0],
+          res[dg.GUESS_LEARNED], flush=True)
+    # both counts include the seed's evaluation of f(0)
     assert res[dg.GUESS_LEARNED] < 0.8 * res[dg.GUESS_PLAIN], res
+    assert res[dg.GUESS_F0] < res[dg.GUESS_PLAIN], res
 
 
 def test_recovery_seed_matches_network(ora, dg):
-    """The recovery's learned seed (layer 2 on fp16 matrix cores, FP32
-    accumulation) against the FP64 network: with an unreachable tolerance the
-    recovery stops at its first evaluation and returns the seed itself
+    """The recovery's learned seed (FP32 throughout, layer 2 on the FP32
+    matrix cores) against the FP64 network: with an unreachable tolerance
+    the recovery stops at its first evaluation and returns the seed itself
     whenever the seed lies inside the bracket."""
     import torch
     U, prim = _samples(ora, 20000, 47)
@@ -166,4 +170,5 @@ def test_recovery_seed_matches_network(ora, dg):
     inside = np.exp(want) * U[0] < 0.9 * p_hi
     assert inside.sum() > 1000
     d = np.abs(got - want)[inside]
-    assert d.max() <= 0.05 and d.mean() <= 0.01, (d.max(), d.mean())
+    # FP32 arithmetic (features, 4,609 weights, the exponential of the seed)
+    assert d.max() <= 1e-4 and d.mean() <= 1e-5, (d.max(), d.mean())
