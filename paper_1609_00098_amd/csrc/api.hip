@@ -459,11 +459,20 @@ static dgmi::MixedAllArgs all_args(dgmi_ctx *c) {
 
 // The element kernels of one pass: all degrees in one launch on s, or the
 // per-degree kernels spread over the context's streams.
-static dgmi_status element_pass(dgmi_ctx *c, int stage, const dgmi::RhsArgs &base, bool single, hipStream_t s) {
-  if (single) {
+// mom: the limited stage (single launch only), which also recovers every node
+// and writes the limiter's moments and unphysical-node flags.
+static dgmi_status element_pass(dgmi_ctx *c, int stage, const dgmi::RhsArgs &base, bool single, hipStream_t s,
+                                bool mom = false) {
+  if (single || mom) {
     dgmi::RhsArgs a = base;
     a.elist = c->d_elist;
-    HIP_TRY(dgmi::launch_rhs_mixed_all(c->sys, stage, a, all_args(c), s));
+    dgmi::MixedAllArgs m = all_args(c);
+    if (mom) {
+      a.mom = c->d_mom;
+      a.bad = c->d_bad;
+      m.limtab = c->d_limtab_mix;
+    }
+    HIP_TRY(dgmi::launch_rhs_mixed_all(c->sys, stage, mom, a, m, s));
     return DGMI_OK;
   }
   HIP_TRY(hipEventRecord(c->ev_fork, s));
@@ -506,15 +515,17 @@ static dgmi::MortarArgs mortar_args(dgmi_ctx *c, const double *U, const double *
 
 // One operator / stage pass over every degree: the mortar kernel writes the
 // lift terms of the non-conforming faces, then the element kernels run.
+// mom: the limited stage (see element_pass).
 static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const double *P, double *out,
-                              const double *Un, double *Pout, double wa, double wb, int full_prims, hipStream_t s) {
+                              const double *Un, double *Pout, double wa, double wb, int full_prims, hipStream_t s,
+                              bool mom = false) {
   HIP_TRY(dgmi::launch_mortar(c->sys, mortar_args(c, U, P), s));
   dgmi::RhsArgs a = mix_args(c, dgmi::kMaxMixedDegree);
   a.U = U; a.P = P; a.out = out; a.Un = Un; a.Pout = Pout; a.a = wa; a.b = wb; a.full_prims = full_prims;
   // with a limiter the stage's recoveries precede the limiter pass, which
   // recovers those nodes again and reports what still fails
   if (stage != 0 && c->lim_kind != DGMI_LIMITER_NONE) a.nfail = c->d_nfail_pre;
-  return element_pass(c, stage, a, c->single_launch, s);
+  return element_pass(c, stage, a, c->single_launch, s, mom);
 }
 
 static dgmi::LimArgs lim_args(dgmi_ctx *c, double *U, const double *Pseed, double *Pout);
@@ -528,25 +539,31 @@ static RkBufs ctx_bufs(dgmi_ctx *c) { return RkBufs{c->d_U1, c->d_U2, c->d_P1, c
 
 // The limiter on a mixed-degree mesh (moments per degree, decisions, rewrite
 // per degree); P seeds the recoveries and receives the primitives.
-static dgmi_status mixed_limit(dgmi_ctx *c, double *U, double *P, hipStream_t s) {
+// moments = false: a limited stage kernel already wrote the moments, the
+// unphysical-node flags and every node's primitives.
+static dgmi_status mixed_limit(dgmi_ctx *c, double *U, double *P, hipStream_t s, bool moments = true) {
   if (!c->lim_tab_ready || !c->d_limtab_mix || !c->d_mom || !c->d_bad)
     return fail(DGMI_EINVAL, "limiter: tables or scratch missing (dgmi_set_limiter did not complete)");
   dgmi::LimArgs a = lim_args(c, U, P, P);
   a.off = c->d_off;
   a.deg = c->d_deg;
-  HIP_TRY(dgmi::launch_limiter_mixed(c->sys, c->lstart, c->lcount, c->d_elist, c->d_limtab_mix, a, s));
+  HIP_TRY(dgmi::launch_limiter_mixed(c->sys, moments, c->lstart, c->lcount, c->d_elist, c->d_limtab_mix, a, s));
   return DGMI_OK;
 }
 
-// with a limiter, each stage result is limited before the next stage reads it
+// With a limiter, each stage is the limited stage kernel (it recovers every
+// node of its result and reduces each element to the limiter's moments) and
+// the limiter's decide and apply kernels follow before the next stage.
 static dgmi_status mixed_step_enqueue(dgmi_ctx *c, double *U, double *P, const RkBufs &b, hipStream_t s) {
   const bool limit = c->lim_kind != DGMI_LIMITER_NONE;
-  dgmi_status st = mixed_pass(c, 1, U, P, b.U1, U, b.P1, 0.0, 1.0, 0, s);
-  if (st == DGMI_OK && limit) st = mixed_limit(c, b.U1, b.P1, s);
-  if (st == DGMI_OK) st = mixed_pass(c, 1, b.U1, b.P1, b.U2, U, b.P2, 0.75, 0.25, 0, s);
-  if (st == DGMI_OK && limit) st = mixed_limit(c, b.U2, b.P2, s);
-  if (st == DGMI_OK) st = mixed_pass(c, 1, b.U2, b.P2, U, U, P, 1.0 / 3.0, 2.0 / 3.0, 1, s);
-  if (st == DGMI_OK && limit) st = mixed_limit(c, U, P, s);
+  if (limit && (!c->lim_tab_ready || !c->d_limtab_mix || !c->d_mom || !c->d_bad))
+    return fail(DGMI_EINVAL, "limiter: tables or scratch missing (dgmi_set_limiter did not complete)");
+  dgmi_status st = mixed_pass(c, 1, U, P, b.U1, U, b.P1, 0.0, 1.0, 0, s, limit);
+  if (st == DGMI_OK && limit) st = mixed_limit(c, b.U1, b.P1, s, false);
+  if (st == DGMI_OK) st = mixed_pass(c, 1, b.U1, b.P1, b.U2, U, b.P2, 0.75, 0.25, 0, s, limit);
+  if (st == DGMI_OK && limit) st = mixed_limit(c, b.U2, b.P2, s, false);
+  if (st == DGMI_OK) st = mixed_pass(c, 1, b.U2, b.P2, U, U, P, 1.0 / 3.0, 2.0 / 3.0, 1, s, limit);
+  if (st == DGMI_OK && limit) st = mixed_limit(c, U, P, s, false);
   return st;
 }
 

@@ -96,8 +96,10 @@ struct LimArgs {
 // that degree (elist_all + lstart[N], lcount[N] of them), the decisions over
 // every element, the rewrite per degree.  tabs: per degree N the 24 doubles
 // w/2, 3/2 int(ell xi), GLL node at tabs + 24 N.
-hipError_t launch_limiter_mixed(int sys, const int64_t *lstart, const int64_t *lcount, const int32_t *elist_all,
-                                const double *tabs, const LimArgs &a, hipStream_t s);
+// moments = false: the limited mixed stage kernel already wrote the moments,
+// flags and primitives.
+hipError_t launch_limiter_mixed(int sys, bool moments, const int64_t *lstart, const int64_t *lcount,
+                                const int32_t *elist_all, const double *tabs, const LimArgs &a, hipStream_t s);
 // Pointwise fixing of n conserved states in place (SoA rows of n); counts the
 // changed states into *nfix.
 hipError_t launch_fix_conserved(int sys, double gamma, double D_min, double tau_min, double *U, int64_t n,
@@ -171,10 +173,13 @@ struct MixedAllArgs {
   int64_t lstart[8], lcount[8];  // per degree: start and length in the element list
   const double *D;               // [8][64] differentiation matrices
   double inv_wend[8];
+  const double *limtab;          // limited stages: per degree N the 24 doubles w/2, 3/2 int(ell xi), GLL
+                                 // node at limtab + 24 N
 };
 // Elements per workgroup of degree N in the single-launch kernel.
 int mixed_all_epb(int sys, int N);
-hipError_t launch_rhs_mixed_all(int sys, int stage, const RhsArgs &a, const MixedAllArgs &m, hipStream_t s);
+// mom: the limited stage (stage kernels only; needs a.mom, a.bad, m.limtab).
+hipError_t launch_rhs_mixed_all(int sys, int stage, bool mom, const RhsArgs &a, const MixedAllArgs &m, hipStream_t s);
 
 // Elements-per-workgroup options of the mixed-degree element kernel for
 // (system, degree); returns how many were written to epb_out (at most 2).

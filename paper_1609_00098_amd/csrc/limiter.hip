@@ -290,10 +290,10 @@ static hipError_t lim_mixed_n(bool apply, LimArgs a, const int64_t *lstart, cons
 }
 
 template <int SYS>
-static hipError_t lim_mixed_sys(const int64_t *lstart, const int64_t *lcount, const int32_t *elist_all,
+static hipError_t lim_mixed_sys(bool moments, const int64_t *lstart, const int64_t *lcount, const int32_t *elist_all,
                                 const double *tabs, const LimArgs &a, hipStream_t s) {
   if (!a.deg || !a.off) return hipErrorInvalidValue;
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = moments ? 0 : 1; pass < 2; ++pass) {
     const bool apply = pass == 1;
     if (apply) {  // decisions over every element, each with its own degree
       const int64_t nd = (a.nelem * SysTraits<SYS>::nv + 255) / 256;
@@ -316,12 +316,12 @@ static hipError_t lim_mixed_sys(const int64_t *lstart, const int64_t *lcount, co
   return hipSuccess;
 }
 
-hipError_t launch_limiter_mixed(int sys, const int64_t *lstart, const int64_t *lcount, const int32_t *elist_all,
-                                const double *tabs, const LimArgs &a, hipStream_t s) {
+hipError_t launch_limiter_mixed(int sys, bool moments, const int64_t *lstart, const int64_t *lcount,
+                                const int32_t *elist_all, const double *tabs, const LimArgs &a, hipStream_t s) {
   switch (sys) {
-    case kNE: return lim_mixed_sys<kNE>(lstart, lcount, elist_all, tabs, a, s);
-    case kSR: return lim_mixed_sys<kSR>(lstart, lcount, elist_all, tabs, a, s);
-    case kMHD: return lim_mixed_sys<kMHD>(lstart, lcount, elist_all, tabs, a, s);
+    case kNE: return lim_mixed_sys<kNE>(moments, lstart, lcount, elist_all, tabs, a, s);
+    case kSR: return lim_mixed_sys<kSR>(moments, lstart, lcount, elist_all, tabs, a, s);
+    case kMHD: return lim_mixed_sys<kMHD>(moments, lstart, lcount, elist_all, tabs, a, s);
   }
   return hipErrorInvalidValue;
 }

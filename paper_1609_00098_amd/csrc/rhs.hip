@@ -11,18 +11,28 @@ namespace dgmi {
 // 512 threads and the LDS budget of the largest degree.
 constexpr int kAllThreads = 512;
 template <int SYS>
-constexpr int all_budget() {  // doubles of LDS: 64 KB, or degree 7 alone if larger
-  return RhsCfg<SYS, 7, 1>::LDS > 8192 ? RhsCfg<SYS, 7, 1>::LDS : 8192;
+constexpr int all_budget() {  // doubles of LDS: 64 KB, or one degree-7 element with its flags if larger
+  return RhsCfg<SYS, 7, 1>::LDS + 512 > 8192 ? RhsCfg<SYS, 7, 1>::LDS + 512 : 8192;
 }
+// elements per workgroup: as many as fit 512 threads and the budget, with
+// room for the limited stage's recovery flags (one double per node)
 template <int SYS, int N>
 constexpr int all_epb() {
-  int e = kAllThreads / ((N + 1) * (N + 1) * (N + 1));
+  constexpr int NP = N + 1, NPE = NP * NP * NP;
+  int e = kAllThreads / NPE;
   if (e < 1) e = 1;
-  while (e > 1 && (e * (RhsCfg<SYS, N, 1>::LDS - (N + 1) * (N + 1)) + (N + 1) * (N + 1)) > all_budget<SYS>()) --e;
+  while (e > 1 && (e * (RhsCfg<SYS, N, 1>::LDS - NP * NP + NPE) + NP * NP) > all_budget<SYS>()) --e;
   return e;
 }
+// every degree's workgroup, flags included, fits the budget
+static_assert(RhsCfg<kMHD, 7, 1>::LDS + 512 <= all_budget<kMHD>(), "LDS budget");
+static_assert(RhsCfg<kSR, 7, 1>::LDS + 512 <= all_budget<kSR>(), "LDS budget");
+static_assert(RhsCfg<kNE, 7, 1>::LDS + 512 <= all_budget<kNE>(), "LDS budget");
 
-template <int SYS, int STAGE>
+// MOM: the limited RK stage (every node of U^(s) recovered, the limiter's
+// element moments and unphysical-node flags written; limiter tables of
+// degree N at M.limtab + 24 N).
+template <int SYS, int STAGE, bool MOM>
 __global__ void __launch_bounds__(kAllThreads) rhs_mixed_all_kernel(const RhsArgs A, const MixedAllArgs M) {
   __shared__ double smem[all_budget<SYS>()];
   const int b = blockIdx.x;
@@ -34,14 +44,18 @@ __global__ void __launch_bounds__(kAllThreads) rhs_mixed_all_kernel(const RhsArg
   a.nlist = M.lcount[N];
   a.Dmat = M.D + 64 * N;
   a.inv_wend = M.inv_wend[N];
+  if (MOM) {
+    a.lim_h = M.limtab + 24 * N;
+    a.lim_mu = M.limtab + 24 * N + 8;
+  }
   switch (N) {
-    case 1: rhs_body<SYS, 1, STAGE, all_epb<SYS, 1>(), true, kAllThreads>(a, grp, smem); break;
-    case 2: rhs_body<SYS, 2, STAGE, all_epb<SYS, 2>(), true, kAllThreads>(a, grp, smem); break;
-    case 3: rhs_body<SYS, 3, STAGE, all_epb<SYS, 3>(), true, kAllThreads>(a, grp, smem); break;
-    case 4: rhs_body<SYS, 4, STAGE, all_epb<SYS, 4>(), true, kAllThreads>(a, grp, smem); break;
-    case 5: rhs_body<SYS, 5, STAGE, all_epb<SYS, 5>(), true, kAllThreads>(a, grp, smem); break;
-    case 6: rhs_body<SYS, 6, STAGE, all_epb<SYS, 6>(), true, kAllThreads>(a, grp, smem); break;
-    case 7: rhs_body<SYS, 7, STAGE, all_epb<SYS, 7>(), true, kAllThreads>(a, grp, smem); break;
+    case 1: rhs_body<SYS, 1, STAGE, all_epb<SYS, 1>(), true, kAllThreads, kLLF, MOM>(a, grp, smem); break;
+    case 2: rhs_body<SYS, 2, STAGE, all_epb<SYS, 2>(), true, kAllThreads, kLLF, MOM>(a, grp, smem); break;
+    case 3: rhs_body<SYS, 3, STAGE, all_epb<SYS, 3>(), true, kAllThreads, kLLF, MOM>(a, grp, smem); break;
+    case 4: rhs_body<SYS, 4, STAGE, all_epb<SYS, 4>(), true, kAllThreads, kLLF, MOM>(a, grp, smem); break;
+    case 5: rhs_body<SYS, 5, STAGE, all_epb<SYS, 5>(), true, kAllThreads, kLLF, MOM>(a, grp, smem); break;
+    case 6: rhs_body<SYS, 6, STAGE, all_epb<SYS, 6>(), true, kAllThreads, kLLF, MOM>(a, grp, smem); break;
+    case 7: rhs_body<SYS, 7, STAGE, all_epb<SYS, 7>(), true, kAllThreads, kLLF, MOM>(a, grp, smem); break;
   }
 }
 
@@ -57,16 +71,20 @@ int mixed_all_epb(int sys, int N) {
   return t[sys][N];
 }
 
-hipError_t launch_rhs_mixed_all(int sys, int stage, const RhsArgs &a, const MixedAllArgs &m, hipStream_t s) {
+hipError_t launch_rhs_mixed_all(int sys, int stage, bool mom, const RhsArgs &a, const MixedAllArgs &m, hipStream_t s) {
   if (m.nblocks <= 0) return hipSuccess;
+  if (mom && (!stage || !m.limtab || !a.mom || !a.bad)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)m.nblocks), block(kAllThreads);
-  switch (sys * 2 + (stage ? 1 : 0)) {
-    case 0: hipLaunchKernelGGL((rhs_mixed_all_kernel<kNE, 0>), grid, block, 0, s, a, m); break;
-    case 1: hipLaunchKernelGGL((rhs_mixed_all_kernel<kNE, 1>), grid, block, 0, s, a, m); break;
-    case 2: hipLaunchKernelGGL((rhs_mixed_all_kernel<kSR, 0>), grid, block, 0, s, a, m); break;
-    case 3: hipLaunchKernelGGL((rhs_mixed_all_kernel<kSR, 1>), grid, block, 0, s, a, m); break;
-    case 4: hipLaunchKernelGGL((rhs_mixed_all_kernel<kMHD, 0>), grid, block, 0, s, a, m); break;
-    case 5: hipLaunchKernelGGL((rhs_mixed_all_kernel<kMHD, 1>), grid, block, 0, s, a, m); break;
+  switch (sys * 3 + (stage ? 1 : 0) + (mom ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((rhs_mixed_all_kernel<kNE, 0, false>), grid, block, 0, s, a, m); break;
+    case 1: hipLaunchKernelGGL((rhs_mixed_all_kernel<kNE, 1, false>), grid, block, 0, s, a, m); break;
+    case 2: hipLaunchKernelGGL((rhs_mixed_all_kernel<kNE, 1, true>), grid, block, 0, s, a, m); break;
+    case 3: hipLaunchKernelGGL((rhs_mixed_all_kernel<kSR, 0, false>), grid, block, 0, s, a, m); break;
+    case 4: hipLaunchKernelGGL((rhs_mixed_all_kernel<kSR, 1, false>), grid, block, 0, s, a, m); break;
+    case 5: hipLaunchKernelGGL((rhs_mixed_all_kernel<kSR, 1, true>), grid, block, 0, s, a, m); break;
+    case 6: hipLaunchKernelGGL((rhs_mixed_all_kernel<kMHD, 0, false>), grid, block, 0, s, a, m); break;
+    case 7: hipLaunchKernelGGL((rhs_mixed_all_kernel<kMHD, 1, false>), grid, block, 0, s, a, m); break;
+    case 8: hipLaunchKernelGGL((rhs_mixed_all_kernel<kMHD, 1, true>), grid, block, 0, s, a, m); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

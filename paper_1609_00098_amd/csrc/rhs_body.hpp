@@ -487,13 +487,15 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       tabs[NP + tid] = A.lim_mu[tid];
     }
     __syncthreads();
+    // slots e0 .. e0+EPB-1 of the element list (mixed degrees) or the mesh
     const int64_t e0 = (int64_t)grp * EPB;
-    if (tid < EPB && e0 + tid < A.nelem) {
+    const int64_t nl = MIXED ? A.nlist : A.nelem;
+    if (tid < EPB && e0 + tid < nl) {
       int bad = 0;
       for (int b = 0; b < NPE; ++b) bad |= okf[tid * NPE + b] == 0.0;
-      A.bad[e0 + tid] = bad;
+      A.bad[MIXED ? (int64_t)A.elist[e0 + tid] : e0 + tid] = bad;
     }
-    element_moments<N, NV, EPB, BT>(su, sslot, tabs, tabs + NP, A.mom, e0, A.nelem);
+    element_moments<N, NV, EPB, BT>(su, sslot, tabs, tabs + NP, A.mom, e0, nl, MIXED ? A.elist : nullptr);
     return;
   }
 #pragma unroll
