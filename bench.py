@@ -64,7 +64,8 @@ def parse():
 PROFILE = os.path.join(ROOT, "profiles", "dg_rhs_sr_hydro_32x32x32_deg4.md")
 KERNEL_SOURCES = ["paper_1609_00098_amd/csrc/rhs_body.hpp", "paper_1609_00098_amd/csrc/rhs.hip",
                   "paper_1609_00098_amd/csrc/physics.hpp", "paper_1609_00098_amd/csrc/kernels.hpp",
-                  "paper_1609_00098_amd/csrc/limiter.hpp"]
+                  "paper_1609_00098_amd/csrc/limiter.hpp", "paper_1609_00098_amd/csrc/pointwise.hip",
+                  "paper_1609_00098_amd/csrc/mlp.hpp"]
 
 
 def kernel_source_hash():
@@ -396,9 +397,10 @@ def time_calls(torch, fn, steps, warmup):
 
 
 def ramp_clocks(torch, fn, seconds=0.5):
-    """Untimed: keep the GPU busy with fn for about `seconds` before any
-    warm-up or timed call, so that the timed steps do not include the clock
-    ramp of an idle device (short loops otherwise measure up to ~18% slower)."""
+    """Untimed: keep the GPU busy with fn (the timed step itself, on the same
+    alternating inputs) for about `seconds` before the warm-up and timed
+    calls, so that the timed steps do not include the clock ramp of an idle
+    device (short loops otherwise measure up to ~18% slower)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     i = 0
@@ -493,7 +495,7 @@ def main():
         else:
             dg.dg_rhs(G, Ub, P, dUb)
 
-    ramp_clocks(torch, lambda i: dg.dg_operator(G, Ua, P, dUa))
+    ramp_clocks(torch, step)
     tm = time_calls(torch, step, args.steps, args.warmup)
     ms = tm["mean"]
     nfail = dg.dgmi_failures(G)
