@@ -196,18 +196,24 @@ def test_mixed_full_size_rhs_and_step(ora, dg):
     """16^3 elements of degrees 2..7 with the full-range fields (W up to 10,
     p over four decades).  Here the operator itself moves by ~1e-12 under a
     one-ulp change of U (the recovery is ill conditioned at W ~ 10 and the
-    degree-7 lift and derivative amplify it), so the bar is the larger of
-    1e-12 and twice that measured sensitivity."""
+    degree-7 lift and derivative amplify the rounding of fluxes far larger
+    than their divergence), so the bar is the larger of 1e-12 and twice that
+    measured sensitivity, for the operator on the oracle's primitives as for
+    dg_rhs; the same mesh with the fields the step is timed on meets 1e-12
+    itself (next test)."""
     import torch
     m, mesh, U, prim, _, deg = _cfg4(ora, dg)
     assert mesh.nnodes == 879747
     L, Po, nf = ora.rhs_mixed(m, deg, U)
     assert nf == 0
+    Ud = to_dev(U)
+    out = mesh.empty_state()
     tol = max(1e-12, 2.0 * _ulp_sensitivity(ora, m, deg, U, L))
     assert tol <= 5e-12
+    dg.dg_operator(mesh, Ud, to_dev(Po), out)
+    err = normwise_err(to_host(out), L)
+    assert err.max() <= tol, (err, tol)
     P = to_dev(prim * np.array([[1.0], [1.0], [1.0], [1.0], [1.001]]))
-    out = mesh.empty_state()
-    Ud = to_dev(U)
     dg.dg_rhs(mesh, Ud, P, out)
     err = normwise_err(to_host(out), L)
     assert err.max() <= tol, (err, tol)
@@ -222,6 +228,42 @@ def test_mixed_full_size_rhs_and_step(ora, dg):
     assert dg.dgmi_failures(mesh) == 0
     stol = 2 * tol * dt * np.abs(L).max() + 8 * np.finfo(float).eps * np.abs(U).max()
     assert np.abs(to_host(Ud) - Uo).max() <= stol
+
+
+def test_mixed_full_size_timed_fields_at_1e12(ora, dg):
+    """The same 16^3 mesh of degrees 2..7 with the fields its RK3 step is
+    timed on (seed 1609, rho, p in [0.5, 2], W up to 3, at every element's
+    own nodes of the unit box): dg_operator on the oracle's primitives,
+    dg_rhs with recovery from a 0.1%-off pressure seed, and one RK3 step,
+    all at the relative 1e-12 bar."""
+    import torch
+    deg = synth.mixed_degrees(4096, seed=1610)
+    m = ora.mesh(SR, (16, 16, 16), 2, G[SR], kappa=0.5)
+    mesh = dg.Mesh(SR, (16, 16, 16), 0, G[SR], kappa=0.5, degrees=deg)
+    xyz = ora.mixed_node_coords(m, deg)
+    prim = synth.fourier_random_prims(xyz, seed=1609, rho_range=(0.5, 2.0), p_range=(0.5, 2.0), w_max=3.0)
+    U = ora.prim2cons(SR, G[SR], prim)
+    L, Po, nf = ora.rhs_mixed(m, deg, U)
+    assert nf == 0
+    Ud = to_dev(U)
+    out = mesh.empty_state()
+    dg.dg_operator(mesh, Ud, to_dev(Po), out)
+    err = normwise_err(to_host(out), L)
+    assert err.max() <= 1e-12, err
+    dg.dg_rhs(mesh, Ud, to_dev(prim * np.array([[1.0], [1.0], [1.0], [1.0], [1.001]])), out)
+    assert dg.dgmi_failures(mesh) == 0
+    err = normwise_err(to_host(out), L)
+    assert err.max() <= 1e-12, err
+    dt = 2e-4
+    Uo, nf = ora.step_mixed(m, deg, U, dt)
+    assert nf == 0
+    Pd = to_dev(Po)
+    dg.dg_step(mesh, Ud, Pd, dt)
+    torch.cuda.synchronize()
+    assert dg.dgmi_failures(mesh) == 0
+    # each stage adds at most dt * (1e-12 of the operator's scale)
+    stol = 2e-12 * dt * np.abs(L).max(axis=1, keepdims=True) + 8 * np.finfo(float).eps * np.abs(U).max(axis=1, keepdims=True)
+    assert np.all(np.abs(to_host(Ud) - Uo) <= stol)
 
 
 @pytest.mark.parametrize("system,nel,kind", CASES[:4])
