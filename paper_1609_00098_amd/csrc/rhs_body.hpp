@@ -1,29 +1,29 @@
 // Uniform-degree DG right-hand side (eq. 411) and fused SSP-RK3 stage.
 //
 // One workgroup owns EPB whole elements, one thread per volume node.
-//   1. Each thread loads its node's U and primitives (coalesced), keeps U in
-//      LDS for the face phase, and forms the flux along one direction at a
-//      time; the direction's nodal fluxes go through an LDS buffer and every
-//      thread contracts its pencil with its row of D (eq. for D^{1bar}),
-//      scaled by 2/dx_d.  A node on a face of that direction also parks its
-//      normal flux in the face slot.
-//      Once the last direction is done, the flux buffer takes every node's
-//      state (U and the primitives the node was given) for the face phase.
-//   2. The EPB*6*(N+1)^2 face nodes are handed out densely, each direction's
-//      tasks padded to whole waves so that a wave runs one direction's code:
-//      each task takes its own node's state from LDS and reads the exterior
-//      state (the coincident node of the periodic neighbour) from global
-//      memory, forms the exterior flux and the wave speeds of both sides,
-//      and turns the slot into the difference F*.n - F.n of the numerical
-//      flux: local Lax-Friedrichs (eq. LLF; the larger of the two sides'
-//      largest speeds), HLL (eq. HLL; both sides' largest and smallest
-//      characteristic speeds along the outward normal) or, for the Newtonian
-//      ideal gas, Roe (eq. Roe) or Marquina.  (The speeds are needed at face
-//      nodes only; computed in the volume phase they would cost every lane of
-//      every wave three evaluations.)
-//   3. Each volume thread adds -(2/dx_d)(1/w_end)(F*.n - F.n) for every face
+//   1. Each thread loads its node's U and the primitive rows it carries
+//      (coalesced) into the volume buffer in LDS and, issued together with
+//      them, the exterior state of its first face task.
+//   2. Face phase.  The EPB*6*(N+1)^2 face nodes are handed out densely,
+//      each direction's tasks padded to whole waves so that a wave runs one
+//      direction's code: each task forms the interior node's normal flux and
+//      wave speeds from the volume buffer, takes the exterior state (the
+//      coincident node of the neighbour: loaded in step 1 for a thread's
+//      first task, from global memory for later ones), forms the exterior
+//      flux and speeds and writes the difference F*.n - F.n of the
+//      numerical flux into the face slot: local Lax-Friedrichs (eq. LLF; the
+//      larger of the two sides' largest speeds), HLL (eq. HLL; both sides'
+//      largest and smallest characteristic speeds along the outward normal)
+//      or, for the Newtonian ideal gas, Roe (eq. Roe) or Marquina.  (The
+//      speeds are needed at face nodes only.)  The exterior loads of the
+//      first round thus overlap the own-node loads instead of following the
+//      volume work.
+//   3. Volume term, one direction at a time: each thread takes its state
+//      back from the buffer, writes its flux along d there, and contracts
+//      its pencil with its row of D (eq. for D^{1bar}), scaled by 2/dx_d.
+//   4. Each volume thread adds -(2/dx_d)(1/w_end)(F*.n - F.n) for every face
 //      it lies on (edge and corner nodes receive two or three terms).
-//   4. RHS mode writes dU/dt; stage mode forms the Shu-Osher combination
+//   5. RHS mode writes dU/dt; stage mode forms the Shu-Osher combination
 //      a U^n + b (U + dt L) and recovers the primitives of the result with
 //      the previous stage's pressure as the Newton seed (tail recovery), so
 //      the next stage finds neighbour primitives ready.
