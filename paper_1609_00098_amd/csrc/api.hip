@@ -180,9 +180,9 @@ struct dgmi_ctx {
   int64_t *d_off = nullptr;       // [nelem + 1]
   int32_t *d_elist = nullptr;     // elements grouped by degree, highest first
   int64_t lstart[9] = {0}, lcount[9] = {0};
-  double *d_Itab = nullptr, *d_Ptab = nullptr, *d_Qtab = nullptr;  // [8][8][8][8] mortar tables
+  double *d_Itab = nullptr, *d_Ptab = nullptr;  // [8][8][8][8] mortar tables
   int64_t *d_foff = nullptr;      // [nelem][6] lift-term offsets of non-conforming faces (-1: conforming)
-  int32_t *d_faces = nullptr;     // [nfaces][2] non-conforming faces, each once
+  int64_t *d_fdesc = nullptr;     // [nfaces][5] descriptors of the non-conforming faces, each once
   int64_t nfaces = 0;
   double *d_facebuf = nullptr;    // lift terms written by the mortar kernel
   double *d_dt = nullptr;         // device scalar read by captured stages
@@ -311,22 +311,11 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx, hipSt
           It[((lo * 8 + m) * 8 + ma) * 8 + ia] = l;
           Pt[((lo * 8 + m) * 8 + ia) * 8 + ma] = w[8 * m + ma] * l / w[8 * lo + ia];
         }
-  // Q = P I: the projection of the interpolant of the lower side's own fluxes
-  std::vector<double> Qt(8 * 8 * 8 * 8, 0.0);
-  for (int lo = 1; lo <= 7; ++lo)
-    for (int m = lo; m <= 7; ++m)
-      for (int a = 0; a <= lo; ++a)
-        for (int ia = 0; ia <= lo; ++ia) {
-          double q = 0.0;
-          for (int ma = 0; ma <= m; ++ma)
-            q += Pt[((lo * 8 + m) * 8 + a) * 8 + ma] * It[((lo * 8 + m) * 8 + ma) * 8 + ia];
-          Qt[((lo * 8 + m) * 8 + a) * 8 + ia] = q;
-        }
   const size_t tb = It.size() * sizeof(double);
   if (hipMalloc(&c->d_deg, sizeof(int32_t) * c->nelem) != hipSuccess ||
       hipMalloc(&c->d_off, sizeof(int64_t) * (c->nelem + 1)) != hipSuccess ||
       hipMalloc(&c->d_elist, sizeof(int32_t) * c->nelem) != hipSuccess || hipMalloc(&c->d_Itab, tb) != hipSuccess ||
-      hipMalloc(&c->d_Ptab, tb) != hipSuccess || hipMalloc(&c->d_Qtab, tb) != hipSuccess ||
+      hipMalloc(&c->d_Ptab, tb) != hipSuccess ||
       hipMalloc(&c->d_dt, sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the mixed-degree tables failed");
@@ -336,11 +325,9 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx, hipSt
   HIP_TRY(hipMemcpyAsync(c->d_elist, elist.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice, cs));
   HIP_TRY(hipMemcpyAsync(c->d_Itab, It.data(), tb, hipMemcpyHostToDevice, cs));
   HIP_TRY(hipMemcpyAsync(c->d_Ptab, Pt.data(), tb, hipMemcpyHostToDevice, cs));
-  HIP_TRY(hipMemcpyAsync(c->d_Qtab, Qt.data(), tb, hipMemcpyHostToDevice, cs));
   // faces between unequal degrees: each listed once (from the element whose
   // upper face it is); both sides get a block of lift terms in the face buffer
   std::vector<int64_t> foff(c->nelem * 6, -1);
-  std::vector<int32_t> faces;
   int64_t cursor = 0;
   for (int64_t e = 0; e < c->nelem; ++e)
     for (int f = 0; f < 6; ++f) {
@@ -348,21 +335,34 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx, hipSt
       if (c->deg[en] == c->deg[e]) continue;
       foff[e * 6 + f] = cursor;
       cursor += (int64_t)c->nv * (c->deg[e] + 1) * (c->deg[e] + 1);
-      if (f & 1) {
-        faces.push_back((int32_t)e);
-        faces.push_back(f);
-      }
     }
-  c->nfaces = (int64_t)faces.size() / 2;
+  // one descriptor per face, from the element whose upper face it is (the
+  // layout is MortarArgs::fdesc's)
+  std::vector<int64_t> fdesc;
+  for (int64_t e = 0; e < c->nelem; ++e)
+    for (int f = 1; f < 6; f += 2) {
+      if (foff[e * 6 + f] < 0) continue;
+      const int64_t en = nbr_of(c, e, f);
+      const int d = f >> 1;
+      const bool e_hi = c->deg[e] > c->deg[en];
+      const int64_t ehi = e_hi ? e : en, elo = e_hi ? en : e;
+      const int side_hi = e_hi ? 1 : 0;
+      fdesc.push_back(c->off[ehi]);
+      fdesc.push_back(c->off[elo]);
+      fdesc.push_back(foff[ehi * 6 + 2 * d + side_hi]);
+      fdesc.push_back(foff[elo * 6 + 2 * d + 1 - side_hi]);
+      fdesc.push_back(d | side_hi << 2 | c->deg[ehi] << 3 | c->deg[elo] << 6);
+    }
+  c->nfaces = (int64_t)fdesc.size() / 5;
   if (hipMalloc(&c->d_foff, sizeof(int64_t) * foff.size()) != hipSuccess ||
-      hipMalloc(&c->d_faces, sizeof(int32_t) * (faces.size() + 2)) != hipSuccess ||
+      hipMalloc(&c->d_fdesc, sizeof(int64_t) * (fdesc.size() + 5)) != hipSuccess ||
       hipMalloc(&c->d_facebuf, sizeof(double) * (cursor + 1)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the mortar buffers failed");
   }
   HIP_TRY(hipMemcpyAsync(c->d_foff, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice, cs));
-  if (!faces.empty())
-    HIP_TRY(hipMemcpyAsync(c->d_faces, faces.data(), sizeof(int32_t) * faces.size(), hipMemcpyHostToDevice, cs));
+  if (!fdesc.empty())
+    HIP_TRY(hipMemcpyAsync(c->d_fdesc, fdesc.data(), sizeof(int64_t) * fdesc.size(), hipMemcpyHostToDevice, cs));
   HIP_TRY(dgmi::launch_set_scalar(c->d_dt, 0.0, cs));
   for (int k = 0; k < 8; ++k) {
     HIP_TRY(hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));
@@ -498,16 +498,11 @@ static dgmi::MortarArgs mortar_args(dgmi_ctx *c, const double *U, const double *
   dgmi::MortarArgs m{};
   m.U = U;
   m.P = P;
-  m.faces = c->d_faces;
+  m.fdesc = c->d_fdesc;
   m.nfaces = c->nfaces;
-  m.nbr = c->d_nbr;
-  m.deg = c->d_deg;
-  m.off = c->d_off;
-  m.foff = c->d_foff;
   m.facebuf = c->d_facebuf;
   m.Itab = c->d_Itab;
   m.Ptab = c->d_Ptab;
-  m.Qtab = c->d_Qtab;
   m.nnodes = c->nnodes;
   m.gamma = c->gamma;
   return m;
@@ -651,10 +646,9 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_elist);
   (void)hipFree(c->d_Itab);
   (void)hipFree(c->d_Ptab);
-  (void)hipFree(c->d_Qtab);
   (void)hipFree(c->d_foff);
   (void)hipFree(c->d_blk);
-  (void)hipFree(c->d_faces);
+  (void)hipFree(c->d_fdesc);
   (void)hipFree(c->d_facebuf);
   (void)hipFree(c->d_dt);
   (void)hipFree(c->d_bc);

@@ -149,18 +149,19 @@ constexpr int kMaxMixedDegree = 7;
 
 // Arguments of the mortar kernel: one wave per face between elements of
 // unequal degree (each such face listed once, from its lower-x/y/z element).
+// A face's descriptor holds everything its wave needs to start loading, so
+// that no load waits on another: [nfaces][5] int64
+//   0: first node of the higher-degree element, 1: of the lower-degree one,
+//   2, 3: offsets of the two sides' lift terms in facebuf (higher, lower),
+//   4: d | side_hi << 2 | N_hi << 3 | N_lo << 6 (side_hi: 1 if the face is
+//      the higher element's upper face along d).
 struct MortarArgs {
   const double *U, *P;     // state and primitives (NE/SR: only p is read)
-  const int32_t *faces;    // [nfaces][2]: element e and its upper face f (1, 3 or 5)
+  const int64_t *fdesc;    // [nfaces][5] face descriptors
   int64_t nfaces;
-  const int32_t *nbr;      // [nelem][6]
-  const int32_t *deg;      // [nelem]
-  const int64_t *off;      // [nelem + 1]
-  const int64_t *foff;     // [nelem][6] start of each face's lift terms in facebuf
   double *facebuf;         // lift terms [v][(N_e+1)^2] per non-conforming face side
   const double *Itab;      // I[lo][m][ma][ia] = l^lo_ia(x^m_ma), [8][8][8][8]
   const double *Ptab;      // P[lo][m][a][ma] = w^m_ma l^lo_a(x^m_ma) / w^lo_a
-  const double *Qtab;      // Q[lo][m][a][ia] = sum_ma P[a][ma] I[ma][ia]
   int64_t nnodes;
   double gamma;
 };

@@ -86,33 +86,32 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
 //      higher side's lift term F*.n - F.n and keeps F*.n_lo - I F_h.n_lo;
 //   P1, P2 project that difference onto the lower side's nodes along each
 //      direction.
+// Workgroups are mapped XCD-major (hardware block b runs on XCD b % 8 and
+// walks its own contiguous range of the face list), so that faces of nearby
+// elements, which share cache lines of the node blocks, share an L2.
 template <int SYS>
 __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   constexpr int NV = SysTraits<SYS>::nv, NS = Interp<SYS>::ns;
   // channels interpolated to the mortar: the state, then the lower side's
   // nodal normal fluxes
   constexpr int NC = NS + NV;
-  // two buffers serve two phases each (every phase ends at a barrier)
-  __shared__ double bufA[NC * 64];
-  __shared__ double bufB[NC * 64];
-  double *const st = bufA;        // lower side's state and F_h, [c][node]              (L, I1)
-  double *const t1 = bufB;        // interpolated along a, [c][ma + nm ib]               (I1, I2)
-  double *const jm = bufA;        // F*.n_lo - I F_h.n_lo at the mortar nodes, [v][m]    (I2, P1)
-  double *const g1 = bufB;        // projection along a, [v][a + nl mb]                 (P1, P2)
+  // one buffer serves every phase: a phase reads it into registers and
+  // writes its results back only after a barrier
+  __shared__ double buf[NC * 64];
+  double *const st = buf;  // lower side's state and F_h, [c][node]            (L, I1)
+  double *const t1 = buf;  // interpolated along a, [c][ma + nm ib]             (I1, I2)
+  double *const jm = buf;  // F*.n_lo - I F_h.n_lo at the mortar nodes, [v][m]  (I2, P1)
+  double *const g1 = buf;  // projection along a, [v][a + nl mb]               (P1, P2)
   __shared__ double sI[64], sP[64];
-  const int64_t t = blockIdx.x;
+  const int64_t per = (A.nfaces + 7) >> 3;
+  const int64_t t = (int64_t)(blockIdx.x & 7) * per + (int64_t)(blockIdx.x >> 3);
   if (t >= A.nfaces) return;
   const int l = threadIdx.x;
-  const int64_t e = A.faces[2 * t];
-  const int f = A.faces[2 * t + 1];  // upper face of e along d
-  const int d = f >> 1;
-  const int64_t en = A.nbr[e * 6 + f];
-  const int Ne = A.deg[e], Nn = A.deg[en];
-  // e sees the face as its upper (side 1) face, en as its lower
-  const bool e_hi = Ne > Nn;
-  const int64_t ehi = e_hi ? e : en, elo = e_hi ? en : e;
-  const int Nm = e_hi ? Ne : Nn, Nlo = e_hi ? Nn : Ne;
-  const int side_hi = e_hi ? 1 : 0, side_lo = 1 - side_hi;
+  const int64_t *fd = A.fdesc + 5 * t;
+  const int64_t qhi = fd[0], qlo = fd[1], ohi = fd[2], olo = fd[3];
+  const int info = (int)fd[4];
+  const int d = info & 3, side_hi = (info >> 2) & 1, Nm = (info >> 3) & 7, Nlo = (info >> 6) & 7;
+  const int side_lo = 1 - side_hi;
   const int nm = Nm + 1, nl = Nlo + 1;
   const double sgn_hi = side_hi ? 1.0 : -1.0, sgn_lo = -sgn_hi;
   const int64_t nn = A.nnodes;
@@ -130,7 +129,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   }
   if (l < nm * nm) {
     Prim Ph;
-    load_node<SYS>(A.U, A.P, nn, A.off[ehi] + face_idx(nm, d, side_hi ? Nm : 0, l % nm, l / nm), A.gamma, uh, Ph);
+    load_node<SYS>(A.U, A.P, nn, qhi + face_idx(nm, d, side_hi ? Nm : 0, l % nm, l / nm), A.gamma, uh, Ph);
     flux_normal<SYS>(d, uh, Ph, Fh);
     ah = max_speed<SYS>(d, uh, Ph, A.gamma);
   }
@@ -138,7 +137,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   // L: lower side's face nodes
   if (l < nl * nl) {
     const int ka = l % nl, kb = l / nl;
-    const int64_t q = A.off[elo] + face_idx(nl, d, side_lo ? Nlo : 0, ka, kb);
+    const int64_t q = qlo + face_idx(nl, d, side_lo ? Nlo : 0, ka, kb);
     double u[NV];
     Prim P;
     load_node<SYS>(A.U, A.P, nn, q, A.gamma, u, P);
@@ -161,22 +160,28 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   __syncthreads();
 
   // I1: t1[c][ma + nm ib] = sum_ia I[ma][ia] st[c][ia + nl ib]
-  if (l < nm * nl) {
-    const int ma = l % nm, ib = l / nm;
+  {
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int ia = 0; ia < nl; ++ia) {
-      const double w = sI[ma * 8 + ia];
+    if (l < nm * nl) {
+      const int ma = l % nm, ib = l / nm;
+      for (int ia = 0; ia < nl; ++ia) {
+        const double w = sI[ma * 8 + ia];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] += w * st[c * 64 + ia + nl * ib];
+        for (int c = 0; c < NC; ++c) acc[c] += w * st[c * 64 + ia + nl * ib];
+      }
     }
+    __syncthreads();
+    if (l < nm * nl) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) t1[c * 64 + l] = acc[c];
+      for (int c = 0; c < NC; ++c) t1[c * 64 + l] = acc[c];
+    }
   }
   __syncthreads();
 
   // I2 + flux at the mortar node
+  double jr[NV];
   if (l < nm * nm) {
     const int ma = l % nm, mb = l / nm;
     double s[NC];
@@ -193,7 +198,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     flux_normal<SYS>(d, ul, Pl, Fl);
     const double alpha = fmax(ah, max_speed<SYS>(d, ul, Pl, A.gamma));
     const double hs = 0.5 * sgn_hi;
-    double *out_hi = A.facebuf + A.foff[ehi * 6 + 2 * d + side_hi] + l;
+    double *out_hi = A.facebuf + ohi + l;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double al = alpha;
@@ -203,24 +208,34 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
       out_hi[v * nm * nm] = hs * (Fl[v] - Fh[v]) - diss;
       // F*.n_lo = -F*.n_hi, less the interpolant of the lower side's own
       // normal fluxes (s[NS + v] is along +e_d)
-      jm[v * 64 + l] = diss - hs * (Fh[v] + Fl[v]) - sgn_lo * s[NS + v];
+      jr[v] = diss - hs * (Fh[v] + Fl[v]) - sgn_lo * s[NS + v];
     }
+  }
+  __syncthreads();
+  if (l < nm * nm) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) jm[v * 64 + l] = jr[v];
   }
   __syncthreads();
 
   // P1: g1[v][a + nl mb] = sum_ma P[a][ma] jm[v][ma + nm mb]
-  if (l < nl * nm) {
-    const int a = l % nl, mb = l / nl;
+  {
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    for (int ma = 0; ma < nm; ++ma) {
-      const double w = sP[a * 8 + ma];
+    if (l < nl * nm) {
+      const int a = l % nl, mb = l / nl;
+      for (int ma = 0; ma < nm; ++ma) {
+        const double w = sP[a * 8 + ma];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += w * jm[v * 64 + ma + nm * mb];
+        for (int v = 0; v < NV; ++v) acc[v] += w * jm[v * 64 + ma + nm * mb];
+      }
     }
+    __syncthreads();
+    if (l < nl * nm) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) g1[v * 64 + l] = acc[v];
+      for (int v = 0; v < NV; ++v) g1[v * 64 + l] = acc[v];
+    }
   }
   __syncthreads();
 
@@ -235,7 +250,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) g[v] += w * g1[v * 64 + a + nl * mb];
     }
-    double *out_lo = A.facebuf + A.foff[elo * 6 + 2 * d + side_lo] + l;
+    double *out_lo = A.facebuf + olo + l;
 #pragma unroll
     for (int v = 0; v < NV; ++v) out_lo[v * nl * nl] = g[v];
   }
@@ -272,7 +287,7 @@ __global__ void __launch_bounds__(256) fill_kernel(double *p, int64_t n, double 
 hipError_t launch_mortar(int sys, const MortarArgs &a, hipStream_t s) {
   if (a.nfaces <= 0) return hipSuccess;
   if (a.nfaces > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)a.nfaces), block(64);
+  const dim3 grid((unsigned)(((a.nfaces + 7) >> 3) << 3)), block(64);
   switch (sys) {
     case kNE: hipLaunchKernelGGL(mortar_kernel<kNE>, grid, block, 0, s, a); break;
     case kSR: hipLaunchKernelGGL(mortar_kernel<kSR>, grid, block, 0, s, a); break;
