@@ -182,6 +182,7 @@ struct dgmi_ctx {
   int64_t lstart[9] = {0}, lcount[9] = {0};
   double *d_Itab = nullptr, *d_Ptab = nullptr;  // [8][8][8][8] mortar tables
   int64_t *d_foff = nullptr;      // [nelem][6] lift-term offsets of non-conforming faces (-1: conforming)
+  int64_t *d_mtab = nullptr;      // [nelem][7] per element-list slot: node block, exterior sources (RhsArgs::mtab)
   int64_t *d_fdesc = nullptr;     // [nfaces][5] descriptors of the non-conforming faces, each once
   int64_t nfaces = 0;
   double *d_facebuf = nullptr;    // lift terms written by the mortar kernel
@@ -354,13 +355,25 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx, hipSt
       fdesc.push_back(d | side_hi << 2 | c->deg[ehi] << 3 | c->deg[elo] << 6);
     }
   c->nfaces = (int64_t)fdesc.size() / 5;
+  // per slot of the degree-sorted element list: the element's first node,
+  // then per face the neighbour's first node or, across a face between
+  // unequal degrees, -1 - the offset of its lift terms
+  std::vector<int64_t> mtab(c->nelem * 7);
+  for (int64_t i = 0; i < c->nelem; ++i) {
+    const int64_t e = elist[i];
+    mtab[7 * i] = c->off[e];
+    for (int f = 0; f < 6; ++f)
+      mtab[7 * i + 1 + f] = foff[e * 6 + f] >= 0 ? -1 - foff[e * 6 + f] : c->off[nbr_of(c, e, f)];
+  }
   if (hipMalloc(&c->d_foff, sizeof(int64_t) * foff.size()) != hipSuccess ||
+      hipMalloc(&c->d_mtab, sizeof(int64_t) * mtab.size()) != hipSuccess ||
       hipMalloc(&c->d_fdesc, sizeof(int64_t) * (fdesc.size() + 5)) != hipSuccess ||
       hipMalloc(&c->d_facebuf, sizeof(double) * (cursor + 1)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the mortar buffers failed");
   }
   HIP_TRY(hipMemcpyAsync(c->d_foff, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice, cs));
+  HIP_TRY(hipMemcpyAsync(c->d_mtab, mtab.data(), sizeof(int64_t) * mtab.size(), hipMemcpyHostToDevice, cs));
   if (!fdesc.empty())
     HIP_TRY(hipMemcpyAsync(c->d_fdesc, fdesc.data(), sizeof(int64_t) * fdesc.size(), hipMemcpyHostToDevice, cs));
   HIP_TRY(dgmi::launch_set_scalar(c->d_dt, 0.0, cs));
@@ -423,6 +436,7 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx, hipSt
 static dgmi::RhsArgs mix_args(dgmi_ctx *c, int N) {
   dgmi::RhsArgs a{};
   a.elist = c->d_elist + c->lstart[N];
+  a.mtab = c->d_mtab + 7 * c->lstart[N];
   a.nlist = c->lcount[N];
   a.off = c->d_off;
   a.foff = c->d_foff;
@@ -466,6 +480,7 @@ static dgmi_status element_pass(dgmi_ctx *c, int stage, const dgmi::RhsArgs &bas
   if (single || mom) {
     dgmi::RhsArgs a = base;
     a.elist = c->d_elist;
+    a.mtab = c->d_mtab;
     dgmi::MixedAllArgs m = all_args(c);
     if (mom) {
       a.mom = c->d_mom;
@@ -647,6 +662,7 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_Itab);
   (void)hipFree(c->d_Ptab);
   (void)hipFree(c->d_foff);
+  (void)hipFree(c->d_mtab);
   (void)hipFree(c->d_blk);
   (void)hipFree(c->d_fdesc);
   (void)hipFree(c->d_facebuf);

@@ -31,6 +31,10 @@ struct RhsArgs {
   const int64_t *off;
   const int64_t *foff;
   const double *facebuf;
+  // the same per slot of elist, so that no load waits on another: [7] int64
+  // per slot, the element's first node, then per face the neighbour's first
+  // node or, across a face between unequal degrees, -1 - foff
+  const int64_t *mtab;
   int nblocks;         // logical blocks (set at launch)
   // uniform meshes: a face whose neighbour index en is negative lies on box
   // face f; its nodes' exterior states (fixed or analytic) are the 16-double

@@ -41,6 +41,7 @@ __global__ void __launch_bounds__(kAllThreads) rhs_mixed_all_kernel(const RhsArg
   const int grp = M.blk_grp[b];
   RhsArgs a = A;
   a.elist = A.elist + M.lstart[N];
+  a.mtab = A.mtab + 7 * M.lstart[N];
   a.nlist = M.lcount[N];
   a.Dmat = M.D + 64 * N;
   a.inv_wend = M.inv_wend[N];

@@ -149,7 +149,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   int64_t q;
   if constexpr (MIXED) {
     active = (le < EPB) && (sl < A.nlist);
-    q = active ? A.off[A.elist[sl]] + a : 0;
+    q = active ? A.mtab[7 * sl] + a : 0;
   } else {
     active = (le < EPB) && (sl < A.nelem);
     q = sl * NPE + a;
@@ -171,22 +171,22 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     kind = 0;
     const int64_t fsl = (int64_t)grp * EPB + fle;
     if (fsl >= (MIXED ? A.nlist : A.nelem)) return;
-    const int64_t fe = MIXED ? (int64_t)A.elist[fsl] : fsl;
     const int ta = fn % NP, tb = fn / NP;
     const int ce = side ? N : 0, cn = side ? 0 : N;  // own and exterior index along d
     ai = d == 0 ? ce + NP * (ta + NP * tb) : (d == 1 ? ta + NP * (ce + NP * tb) : ta + NP * (tb + NP * ce));
     const int an = d == 0 ? cn + NP * (ta + NP * tb) : (d == 1 ? ta + NP * (cn + NP * tb) : ta + NP * (tb + NP * cn));
     if constexpr (MIXED) {
-      const int64_t fo = A.foff[fe * 6 + f];
-      if (fo >= 0) {  // neighbour of another degree: the mortar kernel's lift terms
+      const int64_t xs = A.mtab[7 * fsl + 1 + f];
+      if (xs < 0) {  // neighbour of another degree: the mortar kernel's lift terms
         kind = 3;
-        src = fo + fn;
+        src = -1 - xs + fn;
         return;
       }
       kind = 1;
-      src = A.off[A.nbr[fe * 6 + f]] + an;
+      src = xs + an;
       return;
     }
+    const int64_t fe = fsl;
     int64_t en;
     if (A.periodic) {  // every direction periodic: the neighbour by arithmetic
       const int64_t nxy = (int64_t)A.nx * A.ny;
