@@ -858,6 +858,8 @@ static dgmi::RhsArgs rhs_args(dgmi_ctx *c) {
   for (int f = 0; f < 7; ++f) a.boff[f] = c->boff[f];
   a.poly = (c->flags & DGMI_FLAG_POLYTROPIC) ? 1 : 0;
   a.periodic = (c->bc[0] == 0 && c->bc[1] == 0 && c->bc[2] == 0) ? 1 : 0;
+  a.div_nx = dgmi::make_fastdiv((uint32_t)c->nx);
+  a.div_ny = dgmi::make_fastdiv((uint32_t)c->ny);
   a.Dmat = c->d_D + 64 * c->degree;
   a.nfail = c->d_nfail;
   a.nelem = c->nelem;

@@ -5,6 +5,23 @@
 
 namespace dgmi {
 
+// Division by a run-time divisor 1 <= d < 2^31 of any 0 <= n < 2^31 as a
+// multiply and a shift: with l = ceil(log2 d), m = floor(2^(31+l) / d) + 1
+// fits 32 bits and floor(m n / 2^(31+l)) = floor(n / d) (Granlund and
+// Montgomery, division by invariant integers using multiplication, 1994).
+struct FastDiv {
+  uint32_t m;
+  uint32_t s;  // 31 + l
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while (((uint64_t)1 << l) < d) ++l;
+  return FastDiv{(uint32_t)((((uint64_t)1 << (31 + l)) / d) + 1), 31 + l};
+}
+__device__ __forceinline__ uint32_t fastdiv(uint32_t n, FastDiv f) {
+  return (uint32_t)(((uint64_t)n * f.m) >> f.s);
+}
+
 // Arguments of the uniform-degree RHS / RK-stage kernel.
 struct RhsArgs {
   const double *U;     // state the operator is applied to, [nv][nnodes]
@@ -50,6 +67,7 @@ struct RhsArgs {
   int poly;            // NE: polytropic equation of state p = rho^gamma
   int periodic;        // uniform meshes periodic in every direction: face
                        // neighbours by index arithmetic (else from nbr)
+  FastDiv div_nx, div_ny;  // division by nx and ny (periodic neighbours)
 };
 
 // Numerical fluxes of the uniform-mesh element kernels.

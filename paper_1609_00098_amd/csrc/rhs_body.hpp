@@ -189,10 +189,19 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     const int64_t fe = fsl;
     int64_t en;
     if (A.periodic) {  // every direction periodic: the neighbour by arithmetic
-      const int64_t nxy = (int64_t)A.nx * A.ny;
-      const int64_t n_d = d == 0 ? A.nx : (d == 1 ? A.ny : A.nz);
-      const int64_t st = d == 0 ? 1 : (d == 1 ? (int64_t)A.nx : nxy);
-      const int64_t c = d == 0 ? fe % A.nx : (d == 1 ? (fe / A.nx) % A.ny : fe / nxy);
+      // (element indices are below 2^31: the neighbour table holds int32)
+      const uint32_t e32 = (uint32_t)fe, q1 = fastdiv(e32, A.div_nx);
+      int64_t n_d, st, c;
+      if constexpr (d == 0) {
+        n_d = A.nx;
+        st = 1;
+        c = e32 - q1 * (uint32_t)A.nx;
+      } else {
+        const uint32_t q2 = fastdiv(q1, A.div_ny);
+        n_d = d == 1 ? A.ny : A.nz;
+        st = d == 1 ? (int64_t)A.nx : (int64_t)A.nx * A.ny;
+        c = d == 1 ? q1 - q2 * (uint32_t)A.ny : q2;
+      }
       en = side ? (c == n_d - 1 ? fe - (n_d - 1) * st : fe + st) : (c == 0 ? fe + (n_d - 1) * st : fe - st);
     } else {
       en = A.nbr[fe * 6 + f];
