@@ -65,8 +65,8 @@ enum {
 #define DGMI_FLAG_AUTOTUNE 8      /* mixed degrees: dgmi_create times every tile option per degree and
                                      keeps the fastest (results do not depend on the choice) */
 #define DGMI_FLAG_HLL 16          /* numerical flux HLL (eq. HLL) instead of local Lax-Friedrichs
-                                     (eq. LLF); uniform degrees only, a mixed-degree mesh with it
-                                     returns DGMI_EUNSUPPORTED */
+                                     (eq. LLF), on uniform and mixed-degree meshes (on a face between
+                                     unequal degrees at every mortar node) */
 #define DGMI_FLAG_ROE 64          /* numerical flux Roe (eq. Roe, with the Roe averages of eq. RoeAverages)
                                      for the Newtonian ideal gas on uniform degrees; not with another
                                      flux flag (DGMI_EINVAL) nor another system, equation of state or

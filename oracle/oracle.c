@@ -1677,7 +1677,8 @@ int ora_integrate(const ora_mesh *m, int ncomp, const double *q, double *out) {
 /*    and B, Phi for MHD) to the mortar nodes with the tensor Lagrange matrix */
 /*    I(m,i) = l_i^(Nlo)(x_m^(Nm)) and maps them to conserved variables;     */
 /*    the higher-degree side's face nodes are the mortar nodes.              */
-/*  - One LLF flux F*.n per mortar node from the two mortar states.          */
+/*  - One numerical flux F*.n (LLF or HLL) per mortar node from the two     */
+/*    mortar states.                                                        */
 /*  - The higher-degree side lifts as in the uniform operator; the lower side */
 /*    uses P (F*.n - I F_h.n) with I the interpolation of its own nodal      */
 /*    fluxes to the mortar and P(i,m) = w_m^(Nm) l_i^(Nlo)(x_m) / w_i^(Nlo)  */

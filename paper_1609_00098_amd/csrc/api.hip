@@ -268,7 +268,7 @@ static double lagrange(int n, const double *xs, int i, double y) {
 static dgmi_status autotune(dgmi_ctx *c, hipStream_t s);
 constexpr int kMixedLanes = 4;
 
-// Periodic neighbour of element e across face f (-x, +x, -y, +y, -z, +z).
+// The numerical flux the context's flags select.
 static int flux_of(const dgmi_ctx *c) {
   if (c->flags & DGMI_FLAG_HLL) return dgmi::kHLL;
   if (c->flags & DGMI_FLAG_ROE) return dgmi::kRoe;
@@ -276,6 +276,7 @@ static int flux_of(const dgmi_ctx *c) {
   return dgmi::kLLF;
 }
 
+// Periodic neighbour of element e across face f (-x, +x, -y, +y, -z, +z).
 static int64_t nbr_of(const dgmi_ctx *c, int64_t e, int f) {
   const int64_t ne[3] = {c->nx, c->ny, c->nz};
   int64_t k[3] = {e % c->nx, (e / c->nx) % c->ny, e / ((int64_t)c->nx * c->ny)};
@@ -487,7 +488,7 @@ static dgmi_status element_pass(dgmi_ctx *c, int stage, const dgmi::RhsArgs &bas
       a.bad = c->d_bad;
       m.limtab = c->d_limtab_mix;
     }
-    HIP_TRY(dgmi::launch_rhs_mixed_all(c->sys, stage, mom, a, m, s));
+    HIP_TRY(dgmi::launch_rhs_mixed_all(c->sys, stage, mom, flux_of(c), a, m, s));
     return DGMI_OK;
   }
   HIP_TRY(hipEventRecord(c->ev_fork, s));
@@ -499,7 +500,7 @@ static dgmi_status element_pass(dgmi_ctx *c, int stage, const dgmi::RhsArgs &bas
     a.a = base.a; a.b = base.b; a.full_prims = base.full_prims; a.nfail = base.nfail;
     if (!used[k]) HIP_TRY(hipStreamWaitEvent(c->side[k], c->ev_fork, 0));
     used[k] = true;
-    HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, c->epb[N], stage, a, c->side[k]));
+    HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, c->epb[N], stage, flux_of(c), a, c->side[k]));
   }
   for (int k = 0; k < kMixedLanes; ++k) {
     if (!used[k]) continue;
@@ -529,7 +530,7 @@ static dgmi::MortarArgs mortar_args(dgmi_ctx *c, const double *U, const double *
 static dgmi_status mixed_pass(dgmi_ctx *c, int stage, const double *U, const double *P, double *out,
                               const double *Un, double *Pout, double wa, double wb, int full_prims, hipStream_t s,
                               bool mom = false) {
-  HIP_TRY(dgmi::launch_mortar(c->sys, mortar_args(c, U, P), s));
+  HIP_TRY(dgmi::launch_mortar(c->sys, flux_of(c), mortar_args(c, U, P), s));
   dgmi::RhsArgs a = mix_args(c, dgmi::kMaxMixedDegree);
   a.U = U; a.P = P; a.out = out; a.Un = Un; a.Pout = Pout; a.a = wa; a.b = wb; a.full_prims = full_prims;
   // with a limiter the stage's recoveries precede the limiter pass, which
@@ -596,7 +597,7 @@ static dgmi_status autotune(dgmi_ctx *c, hipStream_t s) {
   HIP_TRY(dgmi::launch_fill(c->d_P1 + 4 * n, n, 1.0, s));
   HIP_TRY(dgmi::launch_fill(c->d_U2, 4 * n, 0.0, s));
   HIP_TRY(dgmi::launch_prim2cons(c->sys, c->gamma, c->d_P1, c->d_U2, c->d_U1, n, s));
-  HIP_TRY(dgmi::launch_mortar(c->sys, mortar_args(c, c->d_U1, c->d_P1), s));
+  HIP_TRY(dgmi::launch_mortar(c->sys, flux_of(c), mortar_args(c, c->d_U1, c->d_P1), s));
   hipEvent_t t0, t1;
   HIP_TRY(hipEventCreate(&t0));
   HIP_TRY(hipEventCreate(&t1));
@@ -608,9 +609,9 @@ static dgmi_status autotune(dgmi_ctx *c, hipStream_t s) {
     for (int o = 0; o < no; ++o) {
       dgmi::RhsArgs a = mix_args(c, N);
       a.U = c->d_U1; a.P = c->d_P1; a.out = c->d_U2;
-      HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, opts[o], 0, a, s));
+      HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, opts[o], 0, flux_of(c), a, s));
       HIP_TRY(hipEventRecord(t0, s));
-      for (int r = 0; r < 5; ++r) HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, opts[o], 0, a, s));
+      for (int r = 0; r < 5; ++r) HIP_TRY(dgmi::launch_rhs_mixed(c->sys, N, opts[o], 0, flux_of(c), a, s));
       HIP_TRY(hipEventRecord(t1, s));
       HIP_TRY(hipEventSynchronize(t1));
       float ms = 0.f;
@@ -702,8 +703,6 @@ dgmi_status dgmi_create(const dgmi_mesh_desc *desc, void *stream, dgmi_ctx **out
   if (desc->degree < 0 || desc->degree > 7) return fail(DGMI_EINVAL, "dgmi_create: degree must be 1..7 or 0");
   if (desc->degree == 0 && !desc->degrees_host)
     return fail(DGMI_EINVAL, "dgmi_create: degree 0 needs degrees_host");
-  if (desc->degree == 0 && (desc->flags & DGMI_FLAG_HLL))
-    return fail(DGMI_EUNSUPPORTED, "dgmi_create: the HLL flux is implemented for uniform degrees only");
   {
     const int nflux = !!(desc->flags & DGMI_FLAG_HLL) + !!(desc->flags & DGMI_FLAG_ROE) +
                       !!(desc->flags & DGMI_FLAG_MARQUINA);

@@ -82,8 +82,9 @@ hipError_t launch_rhs_hll(int sys, int N, int stage, const RhsArgs &a, hipStream
 hipError_t launch_rhs_roe(int sys, int N, int stage, const RhsArgs &a, hipStream_t s);
 hipError_t launch_rhs_marquina(int sys, int N, int stage, const RhsArgs &a, hipStream_t s);
 // The same kernels over one degree's elements of a mixed-degree mesh, epb
-// elements per workgroup (one of mixed_tile_options).
-hipError_t launch_rhs_mixed(int sys, int N, int epb, int stage, const RhsArgs &a, hipStream_t s);
+// elements per workgroup (one of mixed_tile_options); flux kLLF or kHLL.
+hipError_t launch_rhs_mixed(int sys, int N, int epb, int stage, int flux, const RhsArgs &a, hipStream_t s);
+hipError_t launch_rhs_mixed_hll(int sys, int N, int epb, int stage, const RhsArgs &a, hipStream_t s);
 
 // Minmod-family slope limiter on a uniform mesh of degree N: moments and
 // primitives of U (prims seeded from Pseed's pressure, written to Pout,
@@ -201,13 +202,18 @@ struct MixedAllArgs {
 };
 // Elements per workgroup of degree N in the single-launch kernel.
 int mixed_all_epb(int sys, int N);
-// mom: the limited stage (stage kernels only; needs a.mom, a.bad, m.limtab).
-hipError_t launch_rhs_mixed_all(int sys, int stage, bool mom, const RhsArgs &a, const MixedAllArgs &m, hipStream_t s);
+// mom: the limited stage (stage kernels only; needs a.mom, a.bad, m.limtab);
+// flux kLLF or kHLL.
+hipError_t launch_rhs_mixed_all(int sys, int stage, bool mom, int flux, const RhsArgs &a, const MixedAllArgs &m,
+                                hipStream_t s);
+hipError_t launch_rhs_mixed_all_hll(int sys, int stage, bool mom, const RhsArgs &a, const MixedAllArgs &m,
+                                    hipStream_t s);
 
 // Elements-per-workgroup options of the mixed-degree element kernel for
 // (system, degree); returns how many were written to epb_out (at most 2).
 int mixed_tile_options(int sys, int N, int *epb_out);
-hipError_t launch_mortar(int sys, const MortarArgs &a, hipStream_t s);
+// flux kLLF or kHLL at the mortar nodes.
+hipError_t launch_mortar(int sys, int flux, const MortarArgs &a, hipStream_t s);
 hipError_t launch_mixed_coords(const int32_t *deg, const int64_t *off, const double *xtab, int nx, int ny,
                                int64_t nelem, const double *lo, const double *dx, double *xyz, int64_t nn,
                                hipStream_t s);

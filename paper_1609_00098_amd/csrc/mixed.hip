@@ -5,7 +5,7 @@
 //   - the lower-degree side is interpolated there in (rho, W v, p [, B, Phi])
 //     (the spatial four-velocity W v cannot be interpolated past the light
 //     speed) and mapped to conserved variables;
-//   - one LLF flux F*.n per mortar node;
+//   - one numerical flux F*.n per mortar node (LLF, or HLL);
 //   - the higher side's lift term is F*.n - F.n at its nodes, as on a
 //     conforming face; the lower side's is P (F*.n - I F_h.n): the difference
 //     between F* and the interpolant of its own nodal fluxes, integrated
@@ -89,7 +89,7 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
 // Workgroups are mapped XCD-major (hardware block b runs on XCD b % 8 and
 // walks its own contiguous range of the face list), so that faces of nearby
 // elements, which share cache lines of the node blocks, share an L2.
-template <int SYS>
+template <int SYS, int FLUX>
 __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   constexpr int NV = SysTraits<SYS>::nv, NS = Interp<SYS>::ns;
   // channels interpolated to the mortar: the state, then the lower side's
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
 
   // the higher side's node of this lane's mortar position, loaded up front so
   // that its latency overlaps the lower side's loads
-  double uh[NV], Fh[NV], ah = 0.0;
+  double uh[NV], Fh[NV], ah = 0.0, lmh = 0.0, lph = 0.0;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     uh[v] = 0.0;
@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     Prim Ph;
     load_node<SYS>(A.U, A.P, nn, qhi + face_idx(nm, d, side_hi ? Nm : 0, l % nm, l / nm), A.gamma, uh, Ph);
     flux_normal<SYS>(d, uh, Ph, Fh);
-    ah = max_speed<SYS>(d, uh, Ph, A.gamma);
+    if constexpr (FLUX == kHLL) wave_bounds<SYS>(d, uh, Ph, A.gamma, lmh, lph);
+    else ah = max_speed<SYS>(d, uh, Ph, A.gamma);
   }
 
   // L: lower side's face nodes
@@ -196,19 +197,42 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     Prim Pl;
     interp_to_state<SYS>(s, A.gamma, ul, Pl);
     flux_normal<SYS>(d, ul, Pl, Fl);
-    const double alpha = fmax(ah, max_speed<SYS>(d, ul, Pl, A.gamma));
     const double hs = 0.5 * sgn_hi;
     double *out_hi = A.facebuf + ohi + l;
+    if constexpr (FLUX == kHLL) {
+      // the higher side as the interior: F*.n - F_h.n = c [sg (F_l - F_h) -
+      // s+ (U_l - U_h)], c = -s- / (s+ - s-), with the largest and smallest
+      // speeds along its outward normal of either side, clipped by zero
+      double lml, lpl;
+      wave_bounds<SYS>(d, ul, Pl, A.gamma, lml, lpl);
+      const double sp = fmax(0.0, side_hi ? fmax(lph, lpl) : -fmin(lmh, lml));
+      const double sm = fmin(0.0, side_hi ? fmin(lmh, lml) : -fmax(lph, lpl));
+      const double cf = -sm * fast_rcp(sp - sm);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double al = alpha;
-      if (SYS == kMHD && (v == 8 || v == 5 + d)) al = 1.0;
-      // F*.n_hi with the higher side interior
-      const double diss = 0.5 * al * (ul[v] - uh[v]);
-      out_hi[v * nm * nm] = hs * (Fl[v] - Fh[v]) - diss;
-      // F*.n_lo = -F*.n_hi, less the interpolant of the lower side's own
-      // normal fluxes (s[NS + v] is along +e_d)
-      jr[v] = diss - hs * (Fh[v] + Fl[v]) - sgn_lo * s[NS + v];
+      for (int v = 0; v < NV; ++v) {
+        double oh;
+        if (SYS == kMHD && (v == 8 || v == 5 + d))  // bounds -1, +1: the LLF form with alpha = 1
+          oh = hs * (Fl[v] - Fh[v]) - 0.5 * (ul[v] - uh[v]);
+        else
+          oh = cf * (sgn_hi * (Fl[v] - Fh[v]) - sp * (ul[v] - uh[v]));
+        out_hi[v * nm * nm] = oh;
+        // F*.n_lo = -(F*.n_hi), less the interpolant of the lower side's own
+        // normal fluxes (s[NS + v] is along +e_d)
+        jr[v] = -(oh + sgn_hi * Fh[v]) - sgn_lo * s[NS + v];
+      }
+    } else {
+      const double alpha = fmax(ah, max_speed<SYS>(d, ul, Pl, A.gamma));
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double al = alpha;
+        if (SYS == kMHD && (v == 8 || v == 5 + d)) al = 1.0;
+        // F*.n_hi with the higher side interior
+        const double diss = 0.5 * al * (ul[v] - uh[v]);
+        out_hi[v * nm * nm] = hs * (Fl[v] - Fh[v]) - diss;
+        // F*.n_lo = -F*.n_hi, less the interpolant of the lower side's own
+        // normal fluxes (s[NS + v] is along +e_d)
+        jr[v] = diss - hs * (Fh[v] + Fl[v]) - sgn_lo * s[NS + v];
+      }
     }
   }
   __syncthreads();
@@ -284,14 +308,25 @@ __global__ void __launch_bounds__(256) fill_kernel(double *p, int64_t n, double 
 }
 
 // ------------------------------------------------------------ launchers
-hipError_t launch_mortar(int sys, const MortarArgs &a, hipStream_t s) {
+hipError_t launch_mortar(int sys, int flux, const MortarArgs &a, hipStream_t s) {
   if (a.nfaces <= 0) return hipSuccess;
   if (a.nfaces > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(((a.nfaces + 7) >> 3) << 3)), block(64);
+  if (flux != kLLF && flux != kHLL) return hipErrorInvalidValue;
+  const bool hll = flux == kHLL;
   switch (sys) {
-    case kNE: hipLaunchKernelGGL(mortar_kernel<kNE>, grid, block, 0, s, a); break;
-    case kSR: hipLaunchKernelGGL(mortar_kernel<kSR>, grid, block, 0, s, a); break;
-    case kMHD: hipLaunchKernelGGL(mortar_kernel<kMHD>, grid, block, 0, s, a); break;
+    case kNE:
+      if (hll) hipLaunchKernelGGL((mortar_kernel<kNE, kHLL>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((mortar_kernel<kNE, kLLF>), grid, block, 0, s, a);
+      break;
+    case kSR:
+      if (hll) hipLaunchKernelGGL((mortar_kernel<kSR, kHLL>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((mortar_kernel<kSR, kLLF>), grid, block, 0, s, a);
+      break;
+    case kMHD:
+      if (hll) hipLaunchKernelGGL((mortar_kernel<kMHD, kHLL>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((mortar_kernel<kMHD, kLLF>), grid, block, 0, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -130,12 +130,6 @@ def test_hll_free_stream_and_conservation_on_gpu(ora, dg, system):
     assert np.all(np.abs(tot) <= 1e-13 * absint.max())
 
 
-def test_hll_rejected_on_mixed_degrees(dg):
-    deg = np.array([2, 3] * 4, dtype=np.int32)
-    with pytest.raises(dg.DgmiError):
-        dg.Mesh(SR, (2, 2, 2), 0, 4.0 / 3.0, flags=dg.FLAG_HLL, degrees=deg)
-
-
 def test_hll_full_size_sampled(ora, dg):
     """3D SR hydro at the benchmark size (32^3 elements of degree 4) with the
     HLL flux, in the benchmark's launch configuration, on the perturbed

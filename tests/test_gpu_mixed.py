@@ -22,7 +22,8 @@ def dg():
     return dgmi
 
 
-def _setup(ora, dg, system, nel, deg, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), seed=1609, flags=0, mild=True):
+def _setup(ora, dg, system, nel, deg, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), seed=1609, flags=0, mild=True,
+           flux="llf"):
     """Seeded smooth random state.  Small meshes get mild fields (rho, p in
     [0.5, 2], W <= 2): interpolating badly under-resolved data onto a finer
     mortar can overshoot to negative density or pressure, which the method
@@ -30,7 +31,9 @@ def _setup(ora, dg, system, nel, deg, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), se
     compare two treatments of unphysical states."""
     g = G[system]
     kw = dict(w_max=2.0, rho_range=(0.5, 2.0), p_range=(0.5, 2.0)) if mild else {}
-    m = ora.mesh(system, nel, 2, g, lo=lo, hi=hi, kappa=0.5)
+    m = ora.mesh(system, nel, 2, g, lo=lo, hi=hi, kappa=0.5, flux=flux)
+    if flux == "hll":
+        flags |= dg.FLAG_HLL
     mesh = dg.Mesh(system, nel, 0, g, lo=lo, hi=hi, kappa=0.5, flags=flags, degrees=deg)
     xyz = ora.mixed_node_coords(m, deg)
     unit = (xyz - np.array(lo)[:, None]) / (np.array(hi) - np.array(lo))[:, None]
@@ -109,6 +112,92 @@ def test_equal_degrees_match_uniform_kernels(ora, dg, system, N):
     dg.dg_operator(uni, Ud, Pd, b)
     err = normwise_err(to_host(a), to_host(b))
     assert err.max() <= 1e-14, err
+
+
+@pytest.mark.parametrize("system,nel,kind", CASES)
+def test_mixed_hll_rhs_parity(ora, dg, system, nel, kind):
+    """The HLL flux (eq. HLL) on mixed degrees: the mortar kernel's flux at the
+    mortar nodes and the element kernels' on conforming faces, against the
+    oracle's mixed operator with the same flux."""
+    deg = _degrees(kind, int(np.prod(nel)))
+    m, mesh, U, prim, _ = _setup(ora, dg, system, nel, deg, flux="hll")
+    L, Po, nf = ora.rhs_mixed(m, deg, U)
+    assert nf == 0
+    Llf, _, _ = ora.rhs_mixed(ora.mesh(system, nel, 2, G[system], kappa=0.5), deg, U)
+    assert normwise_err(Llf, L).max() > 1e-6  # the two fluxes differ here
+    P = to_dev(prim * np.array([[1.0], [1.0], [1.0], [1.0], [1.001]]))
+    out = mesh.empty_state()
+    dg.dg_rhs(mesh, to_dev(U), P, out)
+    assert dg.dgmi_failures(mesh) == 0
+    err = normwise_err(to_host(out), L)
+    assert err.max() <= 1e-12, err
+
+
+@pytest.mark.parametrize("system,N", [(SR, 4), (NE, 3), (MHD, 3)])
+def test_hll_equal_degrees_match_uniform_hll_kernels(ora, dg, system, N):
+    nel = (3, 2, 2)
+    deg = np.full(12, N, np.int32)
+    m, mixed, U, prim, _ = _setup(ora, dg, system, nel, deg, flux="hll")
+    uni = dg.Mesh(system, nel, N, G[system], kappa=0.5, flags=dg.FLAG_HLL)
+    Ud, Pd = to_dev(U), to_dev(prim)
+    a, b = mixed.empty_state(), uni.empty_state()
+    dg.dg_operator(mixed, Ud, Pd, a)
+    dg.dg_operator(uni, Ud, Pd, b)
+    err = normwise_err(to_host(a), to_host(b))
+    assert err.max() <= 1e-14, err
+
+
+@pytest.mark.parametrize("system,nel,kind", CASES[:4])
+def test_mixed_hll_step_parity(ora, dg, system, nel, kind):
+    """RK3 steps with the HLL flux, direct and graph-replayed, and with the
+    MUSCL limiter after every stage, against the oracle."""
+    import torch
+    deg = _degrees(kind, int(np.prod(nel)))
+    m, mesh, U, prim, _ = _setup(ora, dg, system, nel, deg, flux="hll")
+    L, Po, _ = ora.rhs_mixed(m, deg, U)
+    dt = _dt(L, U)
+    Uo, nf = ora.step_mixed(m, deg, U, dt)
+    assert nf == 0
+    tol = 2e-12 * dt * np.abs(L).max() + 8 * np.finfo(float).eps * np.abs(U).max()
+    res = []
+    for use_graph in (False, True):
+        Ud, Pd = to_dev(U), to_dev(Po)
+        s = torch.cuda.Stream() if use_graph else None
+        if s is not None:
+            s.wait_stream(torch.cuda.current_stream())
+        dg.dg_step(mesh, Ud, Pd, dt, stream=s)
+        torch.cuda.synchronize()
+        assert dg.dgmi_failures(mesh) == 0
+        res.append(to_host(Ud))
+        assert np.abs(res[-1] - Uo).max() <= tol, (np.abs(res[-1] - Uo).max(), tol)
+    assert np.array_equal(res[0], res[1])
+
+
+@pytest.mark.parametrize("system,lim,seed", [(SR, "muscl", 81), (MHD, "minmod", 82)])
+def test_mixed_hll_step_with_limiter_parity(ora, dg, system, lim, seed):
+    """Limited RK3 steps with the HLL flux on a random mix of degrees 1..7
+    (the limited stage kernel in its HLL instantiation)."""
+    g = G[system]
+    nel = (8, 2, 2)
+    deg = synth.mixed_degrees(32, seed=seed, lo=1, hi=7)
+    m = ora.mesh(system, nel, 2, g, kappa=0.5, limiter=lim, flux="hll")
+    U, prim = _jump_state(ora, system, m, deg)
+    U, _, _ = ora.limit_mixed(m, deg, U)
+    L, Po, _ = ora.rhs_mixed(m, deg, U)
+    dt = 2e-3 / float(max(np.abs(L[0] / U[0]).max(), np.abs(L[4] / U[4]).max()))
+    eps = np.finfo(np.float64).eps
+    budget = 4e-12 * dt * np.maximum(np.abs(L).max(axis=1), 1e-3 * np.abs(L).max()) + 32 * eps * np.abs(U).max(axis=1)
+    Uo, nf = ora.step_mixed(m, deg, U, dt)
+    assert nf == 0
+    mesh = dg.Mesh(system, nel, 0, g, kappa=0.5, degrees=deg, flags=dg.FLAG_HLL)
+    dg.dgmi_set_limiter(mesh, {"minmod": dg.LIMITER_MINMOD, "muscl": dg.LIMITER_MUSCL}[lim], 0.0)
+    Ud, Pd = to_dev(U), to_dev(Po)
+    dg.dgmi_limited(mesh)
+    dg.dg_step(mesh, Ud, Pd, dt)
+    assert dg.dgmi_limited(mesh) > 0
+    assert dg.dgmi_failures(mesh) == 0
+    diff = np.abs(to_host(Ud) - Uo).max(axis=1)
+    assert np.all(diff <= budget), (diff, budget)
 
 
 def _dt(L, U):
