@@ -607,7 +607,7 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
   R.P.p = hi;
   if (!(D > 0.0) || !(hi > 0.0) || !(E > 0.0)) return R;
   if (SYS == kSR && !(E * E - S2 > D * D)) return R;  // f(0) <= 0: no physical state
-  const double Sabs = sqrt(S2);
+  const double Sabs = fast_sqrt(S2);
   double p = (p0 > lo && p0 < hi) ? p0 : hi;
   double em_prev = -1.0, e_prev = 0.0;
   double z = 0.0, em = 0.0, W = 1.0;
@@ -719,12 +719,17 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
     p = p_best;
     conv = 1;
   }
-  // primitives at the final pressure
+  // primitives at the final pressure (as prims_at_pressure forms them, with
+  // |S| from above); rho > 0 holds exactly when z > |S|, i.e. v^2 < 1
   if (SYS == kSR) {
-    R.P = prims_at_pressure<kSR>(u, g, p);
-    const double iz = 1.0 / (tau + D + p);
-    const double v2 = S2 * iz * iz;
-    R.ok = conv && (v2 < 1.0) && (p > 0.0) && (R.P.rho > 0.0);
+    const double zf = tau + D + p;
+    const double izf = fast_rcp(zf);
+    R.P.v[0] = S0 * izf;
+    R.P.v[1] = S1 * izf;
+    R.P.v[2] = S2c * izf;
+    R.P.rho = D * (fast_sqrt((zf - Sabs) * (zf + Sabs)) * izf);
+    R.P.p = p;
+    R.ok = conv && (zf > 0.0) && (p > 0.0) && (R.P.rho > 0.0);
     return R;
   }
   double v2;
