@@ -86,7 +86,7 @@ typedef struct {
   int32_t nx, ny, nz;     /* elements per direction (>= 1 each); a periodic box unless
                              dgmi_set_boundary / dgmi_set_analytic_boundary say otherwise */
   int32_t degree;         /* 1..7: uniform polynomial degree N (N+1 GLL nodes per
-                             direction); 0: per-element degrees from degrees_host */
+                             direction); 0 (or -1): per-element degrees from degrees_host */
   int32_t flags;          /* DGMI_FLAG_* */
   double gamma;           /* ideal-gas adiabatic index, 1 < gamma <= 2 */
   double kappa;           /* divergence-cleaning damping (MHD source -kappa Phi) */
@@ -103,8 +103,8 @@ typedef struct {
  * Mixed degrees (degree == 0, degrees_host[e] in 1..7 for element e): the
  * paper defers the coupling of unequal degrees; a face between degrees Na and
  * Nb carries a mortar with the GLL nodes of degree max(Na, Nb).  The lower
- * side is interpolated there in (rho, W v, p [, B, Phi]), one LLF flux is
- * formed per mortar node, the higher side lifts F*.n - F.n at its nodes and
+ * side is interpolated there in (rho, W v, p [, B, Phi]), one numerical flux
+ * (LLF, or HLL with DGMI_FLAG_HLL) is formed per mortar node, the higher side lifts F*.n - F.n at its nodes and
  * the lower side lifts P (F*.n - I F_h.n), P(i,m) = w_m l_i(x_m) / w_i, with
  * I F_h the interpolant of its own nodal fluxes.  dg_step on a non-default
  * stream captures its three stages once per (U, prim_inout) pair and then
@@ -118,6 +118,10 @@ int32_t dgmi_num_vars(const dgmi_ctx *ctx);     /* 5 or 9 */
 int64_t dgmi_num_elements(const dgmi_ctx *ctx);
 /* off_host[nelem+1]: first node of every element (host copy). */
 dgmi_status dgmi_elem_offsets(const dgmi_ctx *ctx, int64_t *off_host);
+/* The same nelem+1 offsets as a host array owned by the context (valid until
+ * dgmi_destroy; do not free); NULL, with the last error set, for a NULL
+ * context. */
+const int64_t *dgmi_elem_offsets_host(const dgmi_ctx *ctx);
 
 /* xyz[3][nnodes]: physical coordinates of every node through the affine map
  * x = a + (1 + xbar)(b - a)/2 (eq. AffineMap). */

@@ -689,9 +689,12 @@ static void ctx_free(dgmi_ctx *c) {
   delete c;
 }
 
-dgmi_status dgmi_create(const dgmi_mesh_desc *desc, void *stream, dgmi_ctx **out) {
-  if (!desc || !out) return fail(DGMI_EINVAL, "dgmi_create: null argument");
+dgmi_status dgmi_create(const dgmi_mesh_desc *desc_in, void *stream, dgmi_ctx **out) {
+  if (!desc_in || !out) return fail(DGMI_EINVAL, "dgmi_create: null argument");
   *out = nullptr;
+  dgmi_mesh_desc dcopy = *desc_in;
+  if (dcopy.degree == -1) dcopy.degree = 0;  // -1: per-element degrees, as 0
+  const dgmi_mesh_desc *desc = &dcopy;
   if (desc->system < 0 || desc->system > 2) return fail(DGMI_EINVAL, "dgmi_create: unknown system %d", desc->system);
   if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1)
     return fail(DGMI_EINVAL, "dgmi_create: element counts must be >= 1");
@@ -819,6 +822,14 @@ dgmi_status dgmi_destroy(dgmi_ctx *ctx) {
 int64_t dgmi_num_nodes(const dgmi_ctx *ctx) { return ctx ? ctx->nnodes : -1; }
 int32_t dgmi_num_vars(const dgmi_ctx *ctx) { return ctx ? ctx->nv : -1; }
 int64_t dgmi_num_elements(const dgmi_ctx *ctx) { return ctx ? ctx->nelem : -1; }
+
+const int64_t *dgmi_elem_offsets_host(const dgmi_ctx *ctx) {
+  if (!ctx) {
+    fail(DGMI_EINVAL, "dgmi_elem_offsets_host: null context");
+    return nullptr;
+  }
+  return ctx->off.data();
+}
 
 dgmi_status dgmi_elem_offsets(const dgmi_ctx *ctx, int64_t *off_host) {
   if (!ctx || !off_host) return fail(DGMI_EINVAL, "dgmi_elem_offsets: null argument");

@@ -53,6 +53,7 @@ _SIGS = {
     "dgmi_num_vars": (_I32, [_P]),
     "dgmi_num_elements": (_I64, [_P]),
     "dgmi_elem_offsets": (_I32, [_P, _P]),
+    "dgmi_elem_offsets_host": (_P, [_P]),
     "dgmi_node_coords": (_I32, [_P, _P, _P]),
     "dgmi_prim2cons": (_I32, [_I32, _D, _P, _P, _P, _I64, _P]),
     "dg_rhs": (_I32, [_P, _P, _P, _P, _P]),
@@ -140,7 +141,7 @@ class Mesh:
         if degrees is not None:
             import numpy as np
             self._deg = np.ascontiguousarray(degrees, dtype=np.int32)
-            d.degree = 0
+            d.degree = -1 if degree == -1 else 0  # both select degrees_host
             d.degrees_host = self._deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         else:
             d.degree = degree
@@ -171,6 +172,15 @@ class Mesh:
         off = np.zeros(ne + 1, dtype=np.int64)
         _check(_lib.dgmi_elem_offsets(self.handle, off.ctypes.data_as(ctypes.c_void_p)), "dgmi_elem_offsets")
         return off
+
+    def elem_offsets_host(self):
+        """The context's own host array of element offsets (a copy of it)."""
+        import numpy as np
+        ne = int(_lib.dgmi_num_elements(self.handle))
+        p = _lib.dgmi_elem_offsets_host(self.handle)
+        if not p:
+            raise DgmiError("dgmi_elem_offsets_host: " + _lib.dgmi_last_error().decode())
+        return np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_int64)), shape=(ne + 1,)).copy()
 
     def node_coords(self, stream=None):
         xyz = torch.empty((3, self.nnodes), dtype=torch.float64, device="cuda")

@@ -76,7 +76,16 @@ def test_mixed_node_coords_and_offsets(ora, dg, system, nel, kind):
     assert mesh.nnodes == ora.mixed_num_nodes(deg)
     off = mesh.elem_offsets()
     assert np.array_equal(np.diff(off), (deg.astype(np.int64) + 1) ** 3)
+    assert np.array_equal(mesh.elem_offsets_host(), off)
     assert np.abs(to_host(mesh.node_coords()) - xyz).max() <= 1e-15
+
+
+def test_degree_minus_one_selects_per_element_degrees(dg):
+    deg = _degrees("random27", 18)
+    a = dg.Mesh(SR, (3, 3, 2), 0, G[SR], degrees=deg)
+    b = dg.Mesh(SR, (3, 3, 2), -1, G[SR], degrees=deg)
+    assert a.nnodes == b.nnodes
+    assert np.array_equal(a.elem_offsets_host(), b.elem_offsets())
 
 
 @pytest.mark.parametrize("system,nel,kind", CASES)
