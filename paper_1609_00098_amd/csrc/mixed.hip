@@ -76,46 +76,27 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
 }  // namespace
 
 
-// One wave per non-conforming face, in separable passes (tensor-product
-// interpolation and projection one direction at a time):
-//   L  lanes k < (Nlo+1)^2 load the lower side's face nodes: interpolation
-//      state and normal fluxes F_h;
-//   I1 interpolate the state and F_h along the first tangential direction;
-//   I2 finish the interpolation at the mortar nodes; each mortar lane (which
-//      loaded its higher-side node at the start) forms F*.n, writes the
-//      higher side's lift term F*.n - F.n and keeps F*.n_lo - I F_h.n_lo;
-//   P1, P2 project that difference onto the lower side's nodes along each
-//      direction.
-// Workgroups are mapped XCD-major (hardware block b runs on XCD b % 8 and
-// walks its own contiguous range of the face list), so that faces of nearby
-// elements, which share cache lines of the node blocks, share an L2.
-template <int SYS, int FLUX>
-__global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
+// The work of one face (wave) between degrees NLO < NMX, every loop bound a
+// compile-time constant.
+template <int SYS, int FLUX, int NLO, int NMX>
+__device__ __forceinline__ void mortar_face(const MortarArgs &A, int64_t qhi, int64_t qlo, int64_t ohi, int64_t olo,
+                                            int d, int side_hi, double *buf, double *sI, double *sP) {
   constexpr int NV = SysTraits<SYS>::nv, NS = Interp<SYS>::ns;
   // channels interpolated to the mortar: the state, then the lower side's
   // nodal normal fluxes
   constexpr int NC = NS + NV;
+  constexpr int nm = NMX + 1, nl = NLO + 1;
   // one buffer serves every phase: a phase reads it into registers and
   // writes its results back only after a barrier
-  __shared__ double buf[NC * 64];
   double *const st = buf;  // lower side's state and F_h, [c][node]            (L, I1)
   double *const t1 = buf;  // interpolated along a, [c][ma + nm ib]             (I1, I2)
   double *const jm = buf;  // F*.n_lo - I F_h.n_lo at the mortar nodes, [v][m]  (I2, P1)
   double *const g1 = buf;  // projection along a, [v][a + nl mb]               (P1, P2)
-  __shared__ double sI[64], sP[64];
-  const int64_t per = (A.nfaces + 7) >> 3;
-  const int64_t t = (int64_t)(blockIdx.x & 7) * per + (int64_t)(blockIdx.x >> 3);
-  if (t >= A.nfaces) return;
   const int l = threadIdx.x;
-  const int64_t *fd = A.fdesc + 5 * t;
-  const int64_t qhi = fd[0], qlo = fd[1], ohi = fd[2], olo = fd[3];
-  const int info = (int)fd[4];
-  const int d = info & 3, side_hi = (info >> 2) & 1, Nm = (info >> 3) & 7, Nlo = (info >> 6) & 7;
   const int side_lo = 1 - side_hi;
-  const int nm = Nm + 1, nl = Nlo + 1;
   const double sgn_hi = side_hi ? 1.0 : -1.0, sgn_lo = -sgn_hi;
   const int64_t nn = A.nnodes;
-  const int tab = (Nlo * 8 + Nm) * 64;
+  constexpr int tab = (NLO * 8 + NMX) * 64;
   sI[l] = A.Itab[tab + l];  // I[ma][ia] (row stride 8)
   sP[l] = A.Ptab[tab + l];  // P[a][ma]
 
@@ -129,7 +110,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   }
   if (l < nm * nm) {
     Prim Ph;
-    load_node<SYS>(A.U, A.P, nn, qhi + face_idx(nm, d, side_hi ? Nm : 0, l % nm, l / nm), A.gamma, uh, Ph);
+    load_node<SYS>(A.U, A.P, nn, qhi + face_idx(nm, d, side_hi ? NMX : 0, l % nm, l / nm), A.gamma, uh, Ph);
     flux_normal<SYS>(d, uh, Ph, Fh);
     if constexpr (FLUX == kHLL) wave_bounds<SYS>(d, uh, Ph, A.gamma, lmh, lph);
     else ah = max_speed<SYS>(d, uh, Ph, A.gamma);
@@ -138,7 +119,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
   // L: lower side's face nodes
   if (l < nl * nl) {
     const int ka = l % nl, kb = l / nl;
-    const int64_t q = qlo + face_idx(nl, d, side_lo ? Nlo : 0, ka, kb);
+    const int64_t q = qlo + face_idx(nl, d, side_lo ? NLO : 0, ka, kb);
     double u[NV];
     Prim P;
     load_node<SYS>(A.U, A.P, nn, q, A.gamma, u, P);
@@ -167,6 +148,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     if (l < nm * nl) {
       const int ma = l % nm, ib = l / nm;
+      #pragma unroll
       for (int ia = 0; ia < nl; ++ia) {
         const double w = sI[ma * 8 + ia];
 #pragma unroll
@@ -188,6 +170,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     double s[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) s[c] = 0.0;
+    #pragma unroll
     for (int ib = 0; ib < nl; ++ib) {
       const double w = sI[mb * 8 + ib];
 #pragma unroll
@@ -249,6 +232,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     if (l < nl * nm) {
       const int a = l % nl, mb = l / nl;
+      #pragma unroll
       for (int ma = 0; ma < nm; ++ma) {
         const double w = sP[a * 8 + ma];
 #pragma unroll
@@ -269,6 +253,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
     double g[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) g[v] = 0.0;
+    #pragma unroll
     for (int mb = 0; mb < nm; ++mb) {
       const double w = sP[b * 8 + mb];
 #pragma unroll
@@ -278,6 +263,47 @@ __global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) out_lo[v * nl * nl] = g[v];
   }
+}
+
+// One wave per non-conforming face, in separable passes (tensor-product
+// interpolation and projection one direction at a time):
+//   L  lanes k < (Nlo+1)^2 load the lower side's face nodes: interpolation
+//      state and normal fluxes F_h;
+//   I1 interpolate the state and F_h along the first tangential direction;
+//   I2 finish the interpolation at the mortar nodes; each mortar lane (which
+//      loaded its higher-side node at the start) forms F*.n, writes the
+//      higher side's lift term F*.n - F.n and keeps F*.n_lo - I F_h.n_lo;
+//   P1, P2 project that difference onto the lower side's nodes along each
+//      direction.
+// Workgroups are mapped XCD-major (hardware block b runs on XCD b % 8 and
+// walks its own contiguous range of the face list), so that faces of nearby
+// elements, which share cache lines of the node blocks, share an L2.  The
+// degree pair selects a body compiled for it (every face of a wave has the
+// same pair, so the branch is uniform).
+template <int SYS, int FLUX>
+__global__ void __launch_bounds__(64) mortar_kernel(const MortarArgs A) {
+  constexpr int NC = Interp<SYS>::ns + SysTraits<SYS>::nv;
+  __shared__ double buf[NC * 64];
+  __shared__ double sI[64], sP[64];
+  const int64_t per = (A.nfaces + 7) >> 3;
+  const int64_t t = (int64_t)(blockIdx.x & 7) * per + (int64_t)(blockIdx.x >> 3);
+  if (t >= A.nfaces) return;
+  const int64_t *fd = A.fdesc + 5 * t;
+  const int64_t qhi = fd[0], qlo = fd[1], ohi = fd[2], olo = fd[3];
+  const int info = (int)fd[4];
+  const int d = info & 3, side_hi = (info >> 2) & 1, Nm = (info >> 3) & 7, Nlo = (info >> 6) & 7;
+#define DGMI_MORTAR_CASE(LO, HI) \
+  case LO * 8 + HI: mortar_face<SYS, FLUX, LO, HI>(A, qhi, qlo, ohi, olo, d, side_hi, buf, sI, sP); break;
+  switch (Nlo * 8 + Nm) {
+    DGMI_MORTAR_CASE(1, 2) DGMI_MORTAR_CASE(1, 3) DGMI_MORTAR_CASE(1, 4) DGMI_MORTAR_CASE(1, 5)
+    DGMI_MORTAR_CASE(1, 6) DGMI_MORTAR_CASE(1, 7) DGMI_MORTAR_CASE(2, 3) DGMI_MORTAR_CASE(2, 4)
+    DGMI_MORTAR_CASE(2, 5) DGMI_MORTAR_CASE(2, 6) DGMI_MORTAR_CASE(2, 7) DGMI_MORTAR_CASE(3, 4)
+    DGMI_MORTAR_CASE(3, 5) DGMI_MORTAR_CASE(3, 6) DGMI_MORTAR_CASE(3, 7) DGMI_MORTAR_CASE(4, 5)
+    DGMI_MORTAR_CASE(4, 6) DGMI_MORTAR_CASE(4, 7) DGMI_MORTAR_CASE(5, 6) DGMI_MORTAR_CASE(5, 7)
+    DGMI_MORTAR_CASE(6, 7)
+    default: break;  // the face list holds only pairs 1 <= Nlo < Nm <= 7
+  }
+#undef DGMI_MORTAR_CASE
 }
 
 // Node coordinates of a mixed-degree mesh: one workgroup per element.
