@@ -10,11 +10,14 @@ namespace dgmi {
 // Every degree of a mixed mesh in one launch: 512-thread workgroups, each
 // taking one group of elements of one degree from a block table ordered by
 // degree (highest first); per degree as many elements per workgroup as fit
-// 512 threads and the LDS budget of the largest degree.
+// 512 threads and the LDS budget.  The budget (52 KB) and, for SR hydro, at
+// most 80 VGPRs let three workgroups share a CU (24 waves); the degree-2 and
+// -3 tiles then leave a quarter and an eighth of their threads idle, which
+// costs far less than the occupancy gains.
 constexpr int kAllThreads = 512;
 template <int SYS>
-constexpr int all_budget() {  // doubles of LDS: 64 KB, or one degree-7 element with its flags if larger
-  return RhsCfg<SYS, 7, 1>::LDS + 512 > 8192 ? RhsCfg<SYS, 7, 1>::LDS + 512 : 8192;
+constexpr int all_budget() {  // doubles of LDS: 52 KB, or one degree-7 element with its flags if larger
+  return RhsCfg<SYS, 7, 1>::LDS + 512 > 6656 ? RhsCfg<SYS, 7, 1>::LDS + 512 : 6656;
 }
 // elements per workgroup: as many as fit 512 threads and the budget, with
 // room for the limited stage's recovery flags (one double per node)
@@ -30,14 +33,18 @@ constexpr int all_epb() {
 // does not depend on the flux)
 static_assert(RhsCfg<kMHD, 7, 1>::LDS + 512 <= all_budget<kMHD>(), "LDS budget");
 static_assert(RhsCfg<kSR, 7, 1>::LDS + 512 <= all_budget<kSR>(), "LDS budget");
+static_assert(3 * all_budget<kSR>() * 8 <= 160 * 1024, "three SR workgroups per CU");
 static_assert(RhsCfg<kNE, 7, 1>::LDS + 512 <= all_budget<kNE>(), "LDS budget");
 static_assert(RhsCfg<kSR, 7, 1, kHLL>::LDS == RhsCfg<kSR, 7, 1, kLLF>::LDS, "LDS layout");
 
 // MOM: the limited RK stage (every node of U^(s) recovered, the limiter's
 // element moments and unphysical-node flags written; limiter tables of
 // degree N at M.limtab + 24 N).
+// (SR hydro: six waves per SIMD, which its every degree body meets without
+// spilling; the others keep the compiler's choice)
 template <int SYS, int STAGE, bool MOM, int FLUX>
-__global__ void __launch_bounds__(kAllThreads) rhs_mixed_all_kernel(const RhsArgs A, const MixedAllArgs M) {
+__global__ void __launch_bounds__(kAllThreads) __attribute__((amdgpu_waves_per_eu(SYS == kSR ? 6 : 1)))
+rhs_mixed_all_kernel(const RhsArgs A, const MixedAllArgs M) {
   __shared__ double smem[all_budget<SYS>()];
   const int b = blockIdx.x;
   if (b >= M.nblocks) return;
