@@ -575,8 +575,8 @@ DG_HD bool fix_conserved(double *u, double g, double D_min, double tau_min) {
 
 // Recovery of one point.  p0: initial pressure (outside the bracket => the
 // bracket's upper end).  tol > 0: stop when the backward residual
-// |f| W^2 / ((g-1) E) <= tol at the evaluated pressure; tol <= 0: iterate
-// Newton until the step is below 1e-14 p (rounding level).
+// |f| W^2 / ((g-1) E) <= 0.99 tol at the evaluated pressure; tol <= 0:
+// iterate Newton until the step is below 1e-14 p (rounding level).
 template <int SYS>
 DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int maxit, bool poly = false) {
   C2PResult R;
@@ -668,7 +668,11 @@ DG_HD C2PResult recover(const double *u, double g, double p0, double tol, int ma
       // |f| <= 32 eps (g-1) (z + D / sqrt(1 - v^2)), without the division
       best_at_floor = f_best * sqw <= 7.105427357601002e-15 * gm1 * (z * sqw + D);
     }
-    if (tol > 0.0 && fabs(f) * W * W <= tol * gm1 * E) {
+    // |f| W^2 / ((g-1) E) is the backward residual |tau(P) - tau| / E of the
+    // primitives at p to first order (and bounds the momentum's); 1% of
+    // margin covers the rounding of the residual itself, a few 1e-14 of E
+    // for strongly magnetised states at large W
+    if (tol > 0.0 && fabs(f) * W * W <= 0.99 * tol * gm1 * E) {
       conv = 1;
       break;
     }

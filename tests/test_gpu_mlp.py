@@ -172,3 +172,45 @@ def test_recovery_seed_matches_network(ora, dg):
     d = np.abs(got - want)[inside]
     # FP32 arithmetic (features, 4,609 weights, the exponential of the seed)
     assert d.max() <= 1e-4 and d.mean() <= 1e-5, (d.max(), d.mean())
+
+
+def test_config5_full_size_recovery(ora, dg):
+    """The recovery workload at full size: 10^8 SRMHD states of the training
+    distribution (drawn on the host, conserved variables by the oracle),
+    residual target 1e-10, the call the benchmark times, with the plain,
+    f(0) and learned seeds (a network trained briefly on 10^5 states).  Every
+    point is recovered (the kernel's failure count), and on 10^6 points drawn
+    at random the oracle's backward residual of the returned primitives is
+    within 1e-10."""
+    import torch
+    n = 100_000_000
+    print("config 5 full size: drawing states", flush=True)
+    prim, mag = synth.srmhd_samples(n, seed=2)
+    U = ora.prim2cons(MHD, G43, prim, mag)
+    del prim, mag
+    Ud = to_dev(U)
+    sel = np.sort(np.random.default_rng(5).choice(n, size=1_000_000, replace=False))
+    Us = np.ascontiguousarray(U[:, sel])
+    del U
+    tp, tm = synth.srmhd_samples(100_000, seed=1)
+    Ut = ora.prim2cons(MHD, G43, tp, tm)
+    x, t = dg.mlp_features(MHD, G43, to_dev(Ut), prim=to_dev(tp))
+    net = dg.Mlp(seed=7)
+    dg.mlp_fit_normalization(net, x, t)
+    dg.mlp_train(net, x, t, batch=2048, epochs=4, lr0=3e-3, lr1=1e-5)
+    seld = torch.from_numpy(sel).to("cuda")
+    P = torch.empty((5, n), dtype=torch.float64, device="cuda")
+    it = torch.empty(n, dtype=torch.uint8, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for guess in (dg.GUESS_PLAIN, dg.GUESS_F0, dg.GUESS_LEARNED):
+        print("config 5 full size: guess", guess, flush=True)
+        P.zero_()
+        nf.zero_()
+        dg.con2prim(MHD, G43, Ud, P, guess=guess, mlp=net if guess == dg.GUESS_LEARNED else None, tol=1e-10,
+                    iters_out=it, n_failed=nf)
+        torch.cuda.synchronize()
+        assert int(nf.item()) == 0, guess
+        Ps = to_host(P[:, seld])
+        r = ora.backward_residual(MHD, G43, Us, Ps)
+        assert r.max() <= 1e-10, (guess, r.max())
+        assert int(it.max().item()) <= 40
