@@ -199,6 +199,9 @@ def mixed_degree_steps(dg, synth, torch, steps=50, warmup=3):
             ms = time_loop(torch, lambda i: dg.dg_step(G, U, prim, 2e-4), steps, warmup)
             out[name] = {"nodes": G.nnodes, "ms_per_step": ms, "dof_updates_per_s": G.nnodes * NV / (ms * 1e-3),
                          "failed_recoveries": dg.dgmi_failures(G, stream=s)}
+            mode = G.mixed_launch_mode()
+            if mode is not None:
+                out[name]["autotuned"] = {"single_launch": mode[0], "per_degree_tiles": mode[1]}
             del G, U, prim
     torch.cuda.synchronize()
     torch.cuda.empty_cache()

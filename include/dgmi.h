@@ -116,6 +116,12 @@ dgmi_status dgmi_destroy(dgmi_ctx *ctx);
 int64_t dgmi_num_nodes(const dgmi_ctx *ctx);    /* sum over elements of (N_e+1)^3 */
 int32_t dgmi_num_vars(const dgmi_ctx *ctx);     /* 5 or 9 */
 int64_t dgmi_num_elements(const dgmi_ctx *ctx);
+/* Mixed degrees: how the element kernels run, as DGMI_FLAG_AUTOTUNE chose
+ * (or the defaults without it): 1 = every degree in one launch, 0 = one
+ * launch per degree on the context's streams; -1 for a uniform mesh or a
+ * NULL context.  epb_out (int32[8], nullable): elements per workgroup of the
+ * per-degree launches, by degree (0 where no element has that degree). */
+int32_t dgmi_mixed_launch_mode(const dgmi_ctx *ctx, int32_t *epb_out);
 /* off_host[nelem+1]: first node of every element (host copy). */
 dgmi_status dgmi_elem_offsets(const dgmi_ctx *ctx, int64_t *off_host);
 /* The same nelem+1 offsets as a host array owned by the context (valid until

@@ -823,6 +823,13 @@ int64_t dgmi_num_nodes(const dgmi_ctx *ctx) { return ctx ? ctx->nnodes : -1; }
 int32_t dgmi_num_vars(const dgmi_ctx *ctx) { return ctx ? ctx->nv : -1; }
 int64_t dgmi_num_elements(const dgmi_ctx *ctx) { return ctx ? ctx->nelem : -1; }
 
+int32_t dgmi_mixed_launch_mode(const dgmi_ctx *ctx, int32_t *epb_out) {
+  if (!ctx || !ctx->mixed) return -1;
+  if (epb_out)
+    for (int N = 0; N < 8; ++N) epb_out[N] = (N >= 1 && ctx->lcount[N] > 0) ? ctx->epb[N] : 0;
+  return ctx->single_launch ? 1 : 0;
+}
+
 const int64_t *dgmi_elem_offsets_host(const dgmi_ctx *ctx) {
   if (!ctx) {
     fail(DGMI_EINVAL, "dgmi_elem_offsets_host: null context");

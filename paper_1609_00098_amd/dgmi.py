@@ -54,6 +54,7 @@ _SIGS = {
     "dgmi_num_elements": (_I64, [_P]),
     "dgmi_elem_offsets": (_I32, [_P, _P]),
     "dgmi_elem_offsets_host": (_P, [_P]),
+    "dgmi_mixed_launch_mode": (_I32, [_P, _P]),
     "dgmi_node_coords": (_I32, [_P, _P, _P]),
     "dgmi_prim2cons": (_I32, [_I32, _D, _P, _P, _P, _I64, _P]),
     "dg_rhs": (_I32, [_P, _P, _P, _P, _P]),
@@ -172,6 +173,16 @@ class Mesh:
         off = np.zeros(ne + 1, dtype=np.int64)
         _check(_lib.dgmi_elem_offsets(self.handle, off.ctypes.data_as(ctypes.c_void_p)), "dgmi_elem_offsets")
         return off
+
+    def mixed_launch_mode(self):
+        """(single launch?, {degree: elements per workgroup of the per-degree
+        launches}) as the autotuner chose them; None for a uniform mesh."""
+        import numpy as np
+        epb = np.zeros(8, dtype=np.int32)
+        m = int(_lib.dgmi_mixed_launch_mode(self.handle, epb.ctypes.data_as(ctypes.c_void_p)))
+        if m < 0:
+            return None
+        return bool(m), {N: int(epb[N]) for N in range(1, 8) if epb[N] > 0}
 
     def elem_offsets_host(self):
         """The context's own host array of element offsets (a copy of it)."""

@@ -270,6 +270,15 @@ def test_autotuned_tiles_give_identical_results(ora, dg):
     dg.dg_operator(plain, Ud, Pd, a)
     dg.dg_operator(tuned, Ud, Pd, b)
     assert np.array_equal(to_host(a), to_host(b))
+    # the choice is reported: one launch or per-degree launches, and per
+    # degree present one of its tile options
+    single, tiles = tuned.mixed_launch_mode()
+    assert isinstance(single, bool)
+    assert sorted(tiles) == sorted(set(int(x) for x in deg))
+    options = {1: (8, 4), 2: (9, 4), 3: (4, 2), 4: (2, 1), 5: (1,), 6: (1,), 7: (1,)}
+    assert all(tiles[N] in options[N] for N in tiles), tiles
+    assert plain.mixed_launch_mode()[0] is True
+    assert dg.Mesh(SR, (2, 2, 2), 3, G[SR]).mixed_launch_mode() is None
 
 
 def _cfg4(ora, dg, flags=0):
