@@ -181,7 +181,6 @@ struct dgmi_ctx {
   int32_t *d_elist = nullptr;     // elements grouped by degree, highest first
   int64_t lstart[9] = {0}, lcount[9] = {0};
   double *d_Itab = nullptr, *d_Ptab = nullptr;  // [8][8][8][8] mortar tables
-  int64_t *d_foff = nullptr;      // [nelem][6] lift-term offsets of non-conforming faces (-1: conforming)
   int64_t *d_mtab = nullptr;      // [nelem][7] per element-list slot: node block, exterior sources (RhsArgs::mtab)
   int64_t *d_fdesc = nullptr;     // [nfaces][5] descriptors of the non-conforming faces, each once
   int64_t nfaces = 0;
@@ -366,14 +365,12 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx, hipSt
     for (int f = 0; f < 6; ++f)
       mtab[7 * i + 1 + f] = foff[e * 6 + f] >= 0 ? -1 - foff[e * 6 + f] : c->off[nbr_of(c, e, f)];
   }
-  if (hipMalloc(&c->d_foff, sizeof(int64_t) * foff.size()) != hipSuccess ||
-      hipMalloc(&c->d_mtab, sizeof(int64_t) * mtab.size()) != hipSuccess ||
+  if (hipMalloc(&c->d_mtab, sizeof(int64_t) * mtab.size()) != hipSuccess ||
       hipMalloc(&c->d_fdesc, sizeof(int64_t) * (fdesc.size() + 5)) != hipSuccess ||
       hipMalloc(&c->d_facebuf, sizeof(double) * (cursor + 1)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the mortar buffers failed");
   }
-  HIP_TRY(hipMemcpyAsync(c->d_foff, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice, cs));
   HIP_TRY(hipMemcpyAsync(c->d_mtab, mtab.data(), sizeof(int64_t) * mtab.size(), hipMemcpyHostToDevice, cs));
   if (!fdesc.empty())
     HIP_TRY(hipMemcpyAsync(c->d_fdesc, fdesc.data(), sizeof(int64_t) * fdesc.size(), hipMemcpyHostToDevice, cs));
@@ -439,8 +436,6 @@ static dgmi::RhsArgs mix_args(dgmi_ctx *c, int N) {
   a.elist = c->d_elist + c->lstart[N];
   a.mtab = c->d_mtab + 7 * c->lstart[N];
   a.nlist = c->lcount[N];
-  a.off = c->d_off;
-  a.foff = c->d_foff;
   a.facebuf = c->d_facebuf;
   a.nbr = c->d_nbr;
   a.Dmat = c->d_D + 64 * N;
@@ -662,7 +657,6 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_elist);
   (void)hipFree(c->d_Itab);
   (void)hipFree(c->d_Ptab);
-  (void)hipFree(c->d_foff);
   (void)hipFree(c->d_mtab);
   (void)hipFree(c->d_blk);
   (void)hipFree(c->d_fdesc);

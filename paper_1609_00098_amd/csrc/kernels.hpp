@@ -41,16 +41,14 @@ struct RhsArgs {
   int full_prims;      // stage kernel: write all five primitive rows (else NE/SR write only p)
   const double *dtp;   // stage kernel: if set, dt is read from this device scalar
   // mixed degrees: the launch of degree N processes the nlist elements in
-  // elist; node blocks start at off[e]; a face with foff[e*6+f] >= 0 takes its
-  // lift terms facebuf[foff + v*(N+1)^2 + node] from the mortar kernel
+  // elist; per slot of elist, mtab holds [7] int64: the element's first
+  // node, then per face the neighbour's first node or, across a face between
+  // unequal degrees, -1 - o, where facebuf[o + v*(N+1)^2 + node] holds the
+  // lift terms the mortar kernel wrote (one table read per face, so that no
+  // load waits on another)
   const int32_t *elist;
   int64_t nlist;
-  const int64_t *off;
-  const int64_t *foff;
   const double *facebuf;
-  // the same per slot of elist, so that no load waits on another: [7] int64
-  // per slot, the element's first node, then per face the neighbour's first
-  // node or, across a face between unequal degrees, -1 - foff
   const int64_t *mtab;
   int nblocks;         // logical blocks (set at launch)
   // uniform meshes: a face whose neighbour index en is negative lies on box

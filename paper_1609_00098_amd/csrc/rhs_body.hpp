@@ -190,19 +190,21 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     int64_t en;
     if (A.periodic) {  // every direction periodic: the neighbour by arithmetic
       // (element indices are below 2^31: the neighbour table holds int32)
+      // (every index and stride below fits 32 bits)
       const uint32_t e32 = (uint32_t)fe, q1 = fastdiv(e32, A.div_nx);
-      int64_t n_d, st, c;
+      uint32_t n_d, st, c;
       if constexpr (d == 0) {
-        n_d = A.nx;
+        n_d = (uint32_t)A.nx;
         st = 1;
         c = e32 - q1 * (uint32_t)A.nx;
       } else {
         const uint32_t q2 = fastdiv(q1, A.div_ny);
-        n_d = d == 1 ? A.ny : A.nz;
-        st = d == 1 ? (int64_t)A.nx : (int64_t)A.nx * A.ny;
+        n_d = (uint32_t)(d == 1 ? A.ny : A.nz);
+        st = d == 1 ? (uint32_t)A.nx : (uint32_t)A.nx * (uint32_t)A.ny;
         c = d == 1 ? q1 - q2 * (uint32_t)A.ny : q2;
       }
-      en = side ? (c == n_d - 1 ? fe - (n_d - 1) * st : fe + st) : (c == 0 ? fe + (n_d - 1) * st : fe - st);
+      const uint32_t wrap = (n_d - 1) * st;
+      en = (int64_t)(side ? (c == n_d - 1 ? e32 - wrap : e32 + st) : (c == 0 ? e32 + wrap : e32 - st));
     } else {
       en = A.nbr[fe * 6 + f];
     }
