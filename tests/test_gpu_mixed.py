@@ -281,7 +281,7 @@ def test_autotuned_tiles_give_identical_results(ora, dg):
     assert dg.Mesh(SR, (2, 2, 2), 3, G[SR]).mixed_launch_mode() is None
 
 
-def _cfg4(ora, dg, flags=0):
+def _mixed_16x16x16_deg2to7(ora, dg, flags=0):
     """SR hydro, gamma 4/3, 16^3 elements on the unit box, degrees uniform in
     2..7 (seed 1610), the smooth random primitives (seed 1609) at every
     element's own nodes."""
@@ -309,7 +309,7 @@ def test_mixed_full_size_rhs_and_step(ora, dg):
     dg_rhs; the same mesh with the fields the step is timed on meets 1e-12
     itself (next test)."""
     import torch
-    m, mesh, U, prim, _, deg = _cfg4(ora, dg)
+    m, mesh, U, prim, _, deg = _mixed_16x16x16_deg2to7(ora, dg)
     assert mesh.nnodes == 879747
     L, Po, nf = ora.rhs_mixed(m, deg, U)
     assert nf == 0

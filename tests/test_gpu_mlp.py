@@ -174,7 +174,7 @@ def test_recovery_seed_matches_network(ora, dg):
     assert d.max() <= 1e-4 and d.mean() <= 1e-5, (d.max(), d.mean())
 
 
-def test_config5_full_size_recovery(ora, dg):
+def test_srmhd_recovery_1e8_states_full_size(ora, dg):
     """The recovery workload at full size: 10^8 SRMHD states of the training
     distribution (drawn on the host, conserved variables by the oracle),
     residual target 1e-10, the call the benchmark times, with the plain,
@@ -184,7 +184,7 @@ def test_config5_full_size_recovery(ora, dg):
     within 1e-10."""
     import torch
     n = 100_000_000
-    print("config 5 full size: drawing states", flush=True)
+    print("SRMHD recovery, 1e8 states: drawing states", flush=True)
     prim, mag = synth.srmhd_samples(n, seed=2)
     U = ora.prim2cons(MHD, G43, prim, mag)
     del prim, mag
@@ -203,7 +203,7 @@ def test_config5_full_size_recovery(ora, dg):
     it = torch.empty(n, dtype=torch.uint8, device="cuda")
     nf = torch.zeros(1, dtype=torch.int64, device="cuda")
     for guess in (dg.GUESS_PLAIN, dg.GUESS_F0, dg.GUESS_LEARNED):
-        print("config 5 full size: guess", guess, flush=True)
+        print("SRMHD recovery, 1e8 states: guess", guess, flush=True)
         P.zero_()
         nf.zero_()
         dg.con2prim(MHD, G43, Ud, P, guess=guess, mlp=net if guess == dg.GUESS_LEARNED else None, tol=1e-10,

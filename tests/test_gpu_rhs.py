@@ -199,7 +199,7 @@ def test_discrete_conservation_on_gpu(ora, dg, system):
     assert np.all(np.abs(tot) <= 1e-13 * absint.max())
 
 
-def test_config1_newtonian_rhs_and_step(ora, dg):
+def test_newtonian_8x8x8_deg3_rhs_and_step(ora, dg):
     """3D Newtonian Euler, gamma 5/3, periodic unit cube, 8^3 elements of
     degree 3 (32,768 nodes), rho = 1 + 0.2 sin(2 pi (x+y+z)), v = (0.5, 0.3,
     0.2), p = 1; one RHS and one SSP-RK3 step, full comparison."""
@@ -219,7 +219,7 @@ def test_config1_newtonian_rhs_and_step(ora, dg):
     assert np.all(np.abs(to_host(Ud) - Uo).max(axis=1) <= _step_tolerance(dUo, U, dt))
 
 
-def test_config2_sr_full_size_sampled(ora, dg):
+def test_sr_32x32x32_deg4_full_size_sampled(ora, dg):
     """3D SR hydro, Gamma 4/3, periodic, 32^3 elements of degree 4
     (4,096,000 nodes), seeded smooth random primitives (rho in [0.1, 10],
     p in [0.01, 100], W up to 10), dg_rhs in the benchmark's launch
@@ -294,7 +294,7 @@ def test_invalid_arguments_rejected(dg):
         dg.con2prim(SR, 4.0 / 3.0, torch.zeros((5, 4), dtype=torch.float64, device="cuda"), P, guess=7)
 
 
-def test_config3_srmhd_blast_full_size_sampled(ora, dg):
+def test_srmhd_blast_64x64x64_deg3_full_size_sampled(ora, dg):
     """SRMHD blast (64^3 elements of degree 3, 16,777,216 nodes, the smooth
     shell of the benchmark) through dg_rhs in the benchmark's launch
     configuration; the oracle recomputes 64 sampled elements (corners, the
@@ -365,7 +365,7 @@ def _face_ball(elems, n, r):
     return cur
 
 
-def test_config3_srmhd_blast_dg_step_full_size_sampled(ora, dg):
+def test_srmhd_blast_64x64x64_deg3_dg_step_sampled(ora, dg):
     """One SSP-RK3 step of the SRMHD blast (64^3 elements of degree 3,
     16,777,216 nodes, the benchmark's state, dt = 4e-4) through dg_step in the
     benchmark's launch configuration: stage kernels with their tail
@@ -388,7 +388,7 @@ def test_config3_srmhd_blast_dg_step_full_size_sampled(ora, dg):
     del mag
     Ud = to_dev(U)
     Pd = to_dev(prim)
-    print("config 3 dg_step full size: GPU step", flush=True)
+    print("SRMHD blast 64^3 deg 3 dg_step: GPU step", flush=True)
     dg.dg_step(G, Ud, Pd, dt)
     assert dg.dgmi_failures(G) == 0
     rng = np.random.default_rng(11)
