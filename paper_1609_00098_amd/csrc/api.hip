@@ -444,6 +444,7 @@ static dgmi::RhsArgs mix_args(dgmi_ctx *c, int N) {
   a.nelem = c->nelem;
   a.nnodes = c->nnodes;
   a.gamma = c->gamma;
+  a.gratio = c->gamma / (c->gamma - 1.0);
   a.kappa = c->kappa;
   for (int d = 0; d < 3; ++d) a.scale[d] = 2.0 / c->dx[d];
   a.inv_wend = 1.0 / c->wend[N];
@@ -516,6 +517,7 @@ static dgmi::MortarArgs mortar_args(dgmi_ctx *c, const double *U, const double *
   m.Ptab = c->d_Ptab;
   m.nnodes = c->nnodes;
   m.gamma = c->gamma;
+  m.gratio = c->gamma / (c->gamma - 1.0);
   return m;
 }
 
@@ -876,6 +878,7 @@ static dgmi::RhsArgs rhs_args(dgmi_ctx *c) {
   a.nelem = c->nelem;
   a.nnodes = c->nnodes;
   a.gamma = c->gamma;
+  a.gratio = c->gamma / (c->gamma - 1.0);
   a.kappa = c->kappa;
   for (int d = 0; d < 3; ++d) a.scale[d] = 2.0 / c->dx[d];
   a.inv_wend = 1.0 / c->wend[c->degree];

@@ -34,6 +34,7 @@ struct RhsArgs {
   unsigned long long *nfail;
   int64_t nelem, nnodes;
   double gamma, kappa;
+  double gratio;       // gamma / (gamma - 1), the enthalpy factor of the wave speeds
   double scale[3];     // 2/dx_d
   double inv_wend;     // 1/w_0 = N(N+1)/2
   double a, b, dt;     // Shu-Osher stage: out = a Un + b (U + dt L(U))
@@ -184,7 +185,7 @@ struct MortarArgs {
   const double *Itab;      // I[lo][m][ma][ia] = l^lo_ia(x^m_ma), [8][8][8][8]
   const double *Ptab;      // P[lo][m][a][ma] = w^m_ma l^lo_a(x^m_ma) / w^lo_a
   int64_t nnodes;
-  double gamma;
+  double gamma, gratio;    // gratio = gamma / (gamma - 1)
 };
 
 // All degrees of a mixed mesh in one launch: a table of workgroups (degree,

@@ -112,8 +112,8 @@ __device__ __forceinline__ void mortar_face(const MortarArgs &A, int64_t qhi, in
     Prim Ph;
     load_node<SYS>(A.U, A.P, nn, qhi + face_idx(nm, d, side_hi ? NMX : 0, l % nm, l / nm), A.gamma, uh, Ph);
     flux_normal<SYS>(d, uh, Ph, Fh);
-    if constexpr (FLUX == kHLL) wave_bounds<SYS>(d, uh, Ph, A.gamma, lmh, lph);
-    else ah = max_speed<SYS>(d, uh, Ph, A.gamma);
+    if constexpr (FLUX == kHLL) wave_bounds<SYS>(d, uh, Ph, A.gamma, A.gratio, lmh, lph);
+    else ah = max_speed<SYS>(d, uh, Ph, A.gamma, A.gratio);
   }
 
   // L: lower side's face nodes
@@ -187,7 +187,7 @@ __device__ __forceinline__ void mortar_face(const MortarArgs &A, int64_t qhi, in
       // s+ (U_l - U_h)], c = -s- / (s+ - s-), with the largest and smallest
       // speeds along its outward normal of either side, clipped by zero
       double lml, lpl;
-      wave_bounds<SYS>(d, ul, Pl, A.gamma, lml, lpl);
+      wave_bounds<SYS>(d, ul, Pl, A.gamma, A.gratio, lml, lpl);
       const double sp = fmax(0.0, side_hi ? fmax(lph, lpl) : -fmin(lmh, lml));
       const double sm = fmin(0.0, side_hi ? fmin(lmh, lml) : -fmax(lph, lpl));
       const double cf = -sm * fast_rcp(sp - sm);
@@ -204,7 +204,7 @@ __device__ __forceinline__ void mortar_face(const MortarArgs &A, int64_t qhi, in
         jr[v] = -(oh + sgn_hi * Fh[v]) - sgn_lo * s[NS + v];
       }
     } else {
-      const double alpha = fmax(ah, max_speed<SYS>(d, ul, Pl, A.gamma));
+      const double alpha = fmax(ah, max_speed<SYS>(d, ul, Pl, A.gamma, A.gratio));
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double al = alpha;

@@ -236,13 +236,15 @@ DG_HD void flux_all(const double *u, const Prim &P, double (*F)[SysTraits<SYS>::
 // whose larger modulus is (|v_n|(1 - c^2) + c sqrt(...)) / (1 - v^2 c^2);
 // MHD uses c^2 = v_A^2 + c_s^2 (1 - v_A^2), v_A^2 = b^2 / (rho h + b^2).
 // (B_n, Phi) of MHD travel at the speed of light, handled by the caller.
+// gr = gamma / (gamma - 1) (rho h = rho + gr p), passed in so that the
+// per-node work holds no division.
 template <int SYS>
-DG_HD double max_speed(int d, const double *u, const Prim P, double g) {
+DG_HD double max_speed(int d, const double *u, const Prim P, double g, double gr) {
   const double v0 = P.v[0], v1 = P.v[1], v2s = P.v[2];
   const double vn = (d == 0) ? v0 : ((d == 1) ? v1 : v2s);
   if (SYS == kNE) return fabs(vn) + fast_sqrt(g * P.p * fast_rcp(P.rho));
   const double v2 = v0 * v0 + v1 * v1 + v2s * v2s;
-  const double rhoh = P.rho + g / (g - 1.0) * P.p;
+  const double rhoh = P.rho + gr * P.p;
   double c2;
   if (SYS == kSR) {
     c2 = g * P.p * fast_rcp(rhoh);
@@ -260,7 +262,7 @@ DG_HD double max_speed(int d, const double *u, const Prim P, double g) {
 
 // Both fluid speed bounds along +e_d, lm <= lp (the pair above; NE: v_n -+ c_s).
 template <int SYS>
-DG_HD void wave_bounds(int d, const double *u, const Prim P, double g, double &lm, double &lp) {
+DG_HD void wave_bounds(int d, const double *u, const Prim P, double g, double gr, double &lm, double &lp) {
   const double v0 = P.v[0], v1 = P.v[1], v2s = P.v[2];
   const double vn = (d == 0) ? v0 : ((d == 1) ? v1 : v2s);
   if (SYS == kNE) {
@@ -270,7 +272,7 @@ DG_HD void wave_bounds(int d, const double *u, const Prim P, double g, double &l
     return;
   }
   const double v2 = v0 * v0 + v1 * v1 + v2s * v2s;
-  const double rhoh = P.rho + g / (g - 1.0) * P.p;
+  const double rhoh = P.rho + gr * P.p;
   double c2;
   if (SYS == kSR) {
     c2 = g * P.p * fast_rcp(rhoh);

@@ -265,8 +265,8 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       flux_normal<SYS>(d, ui, Pi, Fi);
 #pragma unroll
       for (int v = 0; v < NV; ++v) slot[v * 6 * NF] = Fi[v];
-      if constexpr (FLUX == kHLL) wave_bounds<SYS>(d, ui, Pi, A.gamma, lmi, lpi);
-      else if constexpr (FLUX == kLLF) si = max_speed<SYS>(d, ui, Pi, A.gamma);
+      if constexpr (FLUX == kHLL) wave_bounds<SYS>(d, ui, Pi, A.gamma, A.gratio, lmi, lpi);
+      else if constexpr (FLUX == kLLF) si = max_speed<SYS>(d, ui, Pi, A.gamma, A.gratio);
     }
     // the exterior state
     double ue[NV], Fe[NV];
@@ -320,7 +320,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       // c = -s- / (s+ - s-), the bounds (largest and smallest speed along the
       // outward normal of either side) clipped by zero
       double lm, lp;
-      wave_bounds<SYS>(d, ue, Pe, A.gamma, lm, lp);
+      wave_bounds<SYS>(d, ue, Pe, A.gamma, A.gratio, lm, lp);
       const double sp = fmax(0.0, side ? fmax(lpi, lp) : -fmin(lmi, lm));
       const double sm = fmin(0.0, side ? fmin(lmi, lm) : -fmax(lpi, lp));
       const double cf = -sm * fast_rcp(sp - sm);
@@ -335,7 +335,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       }
       return;
     }
-    const double alpha = fmax(si, max_speed<SYS>(d, ue, Pe, A.gamma));
+    const double alpha = fmax(si, max_speed<SYS>(d, ue, Pe, A.gamma, A.gratio));
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double al = alpha;
@@ -436,7 +436,12 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
     if (active) {
       const int idx = sel3i(d, ci, cj, ck);
       const int stride = sel3i(d, 1, NP, NF);
-      const int base = a - idx * stride;
+      int base = a - idx * stride;
+      // keep the pencil's first node opaque, so that every read below is
+      // one address plus a constant offset (the compiler would otherwise
+      // re-derive each node's address from idx)
+      asm volatile("" : "+v"(base));
+      const double *pen = mybuf + base;
       const double scale = sel3(d, A.scale[0], A.scale[1], A.scale[2]);
       double Drow[NP];
 #pragma unroll
@@ -445,7 +450,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       for (int v = 0; v < NV; ++v) {
         double s = 0.0;
 #pragma unroll
-        for (int l = 0; l < NP; ++l) s += Drow[l] * mybuf[v * NPE + base + l * stride];
+        for (int l = 0; l < NP; ++l) s += Drow[l] * pen[v * NPE + l * stride];
         acc[v] -= scale * s;
       }
     }
@@ -461,8 +466,11 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
       const int f = 2 * d + (idx == N ? 1 : 0);
       const int fn = sel3i(d, cj + NP * ck, ci + NP * ck, ci + NP * cj);
       const double sc = sel3(d, A.scale[0], A.scale[1], A.scale[2]) * A.inv_wend;
+      int off = f * NF + fn;
+      asm volatile("" : "+v"(off));  // one address, constant offsets per v
+      const double *sl = myslot + off;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] -= sc * myslot[(v * 6 + f) * NF + fn];
+      for (int v = 0; v < NV; ++v) acc[v] -= sc * sl[v * 6 * NF];
     }
   }
 

@@ -20,6 +20,7 @@ __global__ void __launch_bounds__(256) max_speed_kernel(const double *U, const d
   __shared__ double red[256];
   constexpr int NV = SysTraits<SYS>::nv;
   double lam = 0.0;
+  const double gr = g / (g - 1.0);
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nn; q += (int64_t)gridDim.x * 256) {
     double u[NV];
 #pragma unroll
@@ -35,7 +36,7 @@ __global__ void __launch_bounds__(256) max_speed_kernel(const double *U, const d
       P = prims_at_pressure<SYS>(u, g, SYS == kSR ? Pr[4 * nn + q] : 0.0, poly != 0);
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) lam = fmax(lam, max_speed<SYS>(d, u, P, g));
+    for (int d = 0; d < 3; ++d) lam = fmax(lam, max_speed<SYS>(d, u, P, g, gr));
     if (SYS == kMHD) lam = fmax(lam, 1.0);  // normal field and cleaning scalar
   }
   red[threadIdx.x] = lam;
