@@ -475,8 +475,10 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   }
 
   if (STAGE == 0) {
+    // dU/dt is streamed past L2 (no element group reads it), which leaves
+    // L2 to the neighbour states the next groups read across their faces
 #pragma unroll
-    for (int v = 0; v < NV; ++v) A.out[v * nn + q] = acc[v];
+    for (int v = 0; v < NV; ++v) __builtin_nontemporal_store(acc[v], &A.out[v * nn + q]);
     return;
   }
   // ---- Shu-Osher combination and tail recovery
