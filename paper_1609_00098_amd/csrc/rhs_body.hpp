@@ -54,24 +54,35 @@ __device__ __forceinline__ double sel3(int d, double a, double b, double c) {
 __device__ __forceinline__ int sel3i(int d, int a, int b, int c) { return d == 0 ? a : (d == 1 ? b : c); }
 
 // Processing order of element groups (EPB consecutive elements along x):
-// bricks of 8 x 8 x 8 elements one after another, lexicographic inside a
+// bricks of S x S x S elements one after another, lexicographic inside a
 // brick, so that the neighbours a group reads across its faces were loaded
 // shortly before by the same XCD and are still in its L2 (in plain
 // lexicographic order the z neighbour of an element is a whole plane of
-// elements away).  Used when the group grid tiles into bricks exactly;
-// otherwise the order stays lexicographic.
+// elements away).  S = 16 where the mesh tiles into such bricks: inside one
+// the z neighbour is 256 elements back, within what an XCD's L2 keeps of
+// the states read since (the operator's output bypasses L2), and a brick's
+// faces, whose neighbours were read long before or by another XCD, are half
+// as many per element as with S = 8, the next choice.  Otherwise the order
+// stays lexicographic.
+template <int EPB, int S>
+__device__ __forceinline__ bool bricks_tile(int nx, int ny, int nz) {
+  return S % EPB == 0 && nx % S == 0 && ny % S == 0 && nz % S == 0;
+}
+template <int EPB, int S>
+__device__ __forceinline__ int brick_map(int seq, int nx, int ny) {
+  constexpr int BX = S / EPB, V = BX * S * S;  // groups per brick row, per brick
+  const int ngx = nx / EPB;
+  const int b = seq / V, r = seq - b * V;
+  const int nbx = ngx / BX, nby = ny / S;
+  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+  const int gx = bx * BX + r % BX, gy = by * S + (r / BX) % S, gz = bz * S + r / (BX * S);
+  return gx + ngx * (gy + ny * gz);
+}
 template <int EPB>
 __device__ __forceinline__ int brick_order(int seq, int nx, int ny, int nz) {
-  constexpr int BX = EPB >= 8 ? 1 : 8 / EPB, BY = 8, BZ = 8;
-  if (nx % EPB != 0) return seq;
-  const int ngx = nx / EPB;
-  if (ngx % BX != 0 || ny % BY != 0 || nz % BZ != 0 || 8 % EPB != 0) return seq;
-  constexpr int V = BX * BY * BZ;
-  const int b = seq / V, r = seq - b * V;
-  const int nbx = ngx / BX, nby = ny / BY;
-  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-  const int gx = bx * BX + r % BX, gy = by * BY + (r / BX) % BY, gz = bz * BZ + r / (BX * BY);
-  return gx + ngx * (gy + ny * gz);
+  if (bricks_tile<EPB, 16>(nx, ny, nz)) return brick_map<EPB, 16>(seq, nx, ny);
+  if (bricks_tile<EPB, 8>(nx, ny, nz)) return brick_map<EPB, 8>(seq, nx, ny);
+  return seq;
 }
 
 template <int SYS, int N>
