@@ -52,10 +52,19 @@ __global__ void __launch_bounds__(256) con2prim_kernel(const C2PArgs A) {
     if (!valid) continue;
     C2PResult R = recover<SYS>(u, A.gamma, p0, A.tol, 100, A.poly);
     R.iters += extra;
-    A.prim[q] = R.P.rho;
-    A.prim[n + q] = R.P.v[0];
-    A.prim[2 * n + q] = R.P.v[1];
-    A.prim[3 * n + q] = R.P.v[2];
+    if (SYS == kMHD) {
+      A.prim[q] = R.P.rho;
+      A.prim[n + q] = R.P.v[0];
+      A.prim[2 * n + q] = R.P.v[1];
+      A.prim[3 * n + q] = R.P.v[2];
+    } else {
+      // NE / SR operators rebuild rho and v from U and p: these rows are
+      // streamed past the caches, which keeps them free for U and p
+      __builtin_nontemporal_store(R.P.rho, &A.prim[q]);
+      __builtin_nontemporal_store(R.P.v[0], &A.prim[n + q]);
+      __builtin_nontemporal_store(R.P.v[1], &A.prim[2 * n + q]);
+      __builtin_nontemporal_store(R.P.v[2], &A.prim[3 * n + q]);
+    }
     A.prim[4 * n + q] = R.P.p;
     if (A.iters) A.iters[q] = (uint8_t)(R.iters > 255 ? 255 : R.iters);
     if (A.fail) A.fail[q] = R.ok ? 0 : 1;

@@ -538,11 +538,16 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   const C2PResult R = recover<SYS>(us, A.gamma, P.p, 0.0, 100, A.poly);
   // intermediate stages of NE / SR keep only the pressure (the next stage
   // rebuilds the rest); SRMHD and the caller's buffers get all five rows
-  if (SYS == kMHD || A.full_prims) {
+  if (SYS == kMHD) {
     A.Pout[q] = R.P.rho;
     A.Pout[nn + q] = R.P.v[0];
     A.Pout[2 * nn + q] = R.P.v[1];
     A.Pout[3 * nn + q] = R.P.v[2];
+  } else if (A.full_prims) {  // rows the next stage does not read: streamed
+    __builtin_nontemporal_store(R.P.rho, &A.Pout[q]);
+    __builtin_nontemporal_store(R.P.v[0], &A.Pout[nn + q]);
+    __builtin_nontemporal_store(R.P.v[1], &A.Pout[2 * nn + q]);
+    __builtin_nontemporal_store(R.P.v[2], &A.Pout[3 * nn + q]);
   }
   A.Pout[4 * nn + q] = R.P.p;
   if (!R.ok) atomicAdd(A.nfail, 1ull);
