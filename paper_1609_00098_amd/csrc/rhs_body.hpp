@@ -144,6 +144,7 @@ __device__ __forceinline__ void load_node(const double *U, const double *Pr, int
 template <int SYS, int N, int STAGE, int EPB_, bool MIXED, int BT, int FLUX = kLLF, bool MOM = false>
 __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem) {
   using C = RhsCfg<SYS, N, EPB_, FLUX>;
+  static_assert(BT >= (N + 1) * (N + 1), "one thread per entry of D");
   constexpr int NP = C::NP, NPE = C::NPE, NF = C::NF, NV = C::NV, EPB = C::EPB, RS = C::RS;
   double *svol = smem;
   double *sslot = svol + C::VOL;
@@ -151,7 +152,9 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
   double *sflag = sD + NP * NP;  // the limited stage's recovery flags
 
   const int tid = threadIdx.x;
-  for (int t = tid; t < NP * NP; t += BT) sD[t] = A.Dmat[t];
+  // D for the volume term: loaded here, stored to LDS with the node states
+  // below, so that its wait does not hold back their loads (BT >= 64 >= (N+1)^2)
+  const double dval = tid < NP * NP ? A.Dmat[tid] : 0.0;
 
   const int le = tid / NPE;
   const int a = tid - le * NPE;
@@ -388,6 +391,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs &A, int grp, double *smem
 #pragma unroll
     for (int k = 0; k < C::NPR; ++k) mybuf[(NV + k) * NPE + a] = prr[k];
   }
+  if (tid < NP * NP) sD[tid] = dval;
   __syncthreads();
   // ---- face phase: the first round takes the exterior state loaded above
   if (has0) {
