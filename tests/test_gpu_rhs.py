@@ -199,6 +199,34 @@ def test_discrete_conservation_on_gpu(ora, dg, system):
     assert np.all(np.abs(tot) <= 1e-13 * absint.max())
 
 
+# meshes whose element groups are visited in 16^3-element bricks (degree 3:
+# four elements per group, degree 4: two), in 8^3 bricks (24 x 16 x 8 does
+# not tile into 16^3) and in plain lexicographic order (12^3 tiles into
+# neither)
+ORDER_CASES = [((16, 16, 16), 3), ((16, 16, 16), 4), ((24, 16, 8), 3), ((12, 12, 12), 3)]
+
+
+@pytest.mark.parametrize("nel,N", ORDER_CASES)
+def test_sr_processing_orders_full_parity(ora, dg, nel, N):
+    """SR dg_rhs and one dg_step over whole meshes in each processing order
+    of the element groups, every output compared with the oracle."""
+    m, G = _pair(ora, dg, SR, nel, N, flags=2)
+    U, prim = _state(ora, SR, m, seed=40 + N, wmax=3.0)
+    dUo, Po, nf = ora.rhs(m, U)
+    assert nf == 0
+    Pd = to_dev(prim * (1 + 1e-3))
+    dUd = G.empty_state()
+    dg.dg_rhs(G, to_dev(U), Pd, dUd)
+    assert np.all(normwise_err(to_host(dUd), dUo) <= RHS_TOL)
+    dt = 1e-3 / max(np.abs(dUo[0] / U[0]).max(), np.abs(dUo[4] / U[4]).max())
+    Uo, nf = ora.step(m, U, dt)
+    assert nf == 0
+    Ud = to_dev(U)
+    dg.dg_step(G, Ud, to_dev(prim), dt)
+    assert np.all(np.abs(to_host(Ud) - Uo).max(axis=1) <= _step_tolerance(dUo, U, dt))
+    assert dg.dgmi_failures(G) == 0
+
+
 def test_newtonian_8x8x8_deg3_rhs_and_step(ora, dg):
     """3D Newtonian Euler, gamma 5/3, periodic unit cube, 8^3 elements of
     degree 3 (32,768 nodes), rho = 1 + 0.2 sin(2 pi (x+y+z)), v = (0.5, 0.3,
