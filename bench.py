@@ -105,9 +105,10 @@ FP64_PEAK_TFLOPS = 78.6
 VALU_SIMDS, CLOCK_HZ = 1024, 2.4e9
 
 
-def alu_figures(c, ms):
+def alu_figures(c, ms, per_lane=1):
     """FP64 FLOP rate and VALU issue utilisation of one launch from its
-    counters and its measured duration."""
+    counters and its measured duration (per_lane: nodes or points each lane
+    of a wave handles)."""
     if not c:
         return None
     t = ms * 1e-3
@@ -116,7 +117,7 @@ def alu_figures(c, ms):
     return {"fp64_tflops": round(flops / t / 1e12, 2), "fp64_peak_tflops": FP64_PEAK_TFLOPS,
             "fp64_frac": round(flops / t / 1e12 / FP64_PEAK_TFLOPS, 4),
             "valu_issue_frac": round(cycles / (VALU_SIMDS * CLOCK_HZ * t), 4),
-            "valu_insts_per_node": round(c["valu_per_wave"], 1)}
+            "valu_insts_per_node": round(c["valu_per_wave"] / per_lane, 1)}
 
 
 def profiled_traffic():
@@ -560,7 +561,8 @@ def main():
             # counter-backed compute side (SQ_INSTS_VALU*, profiles/): FP64 FLOP rate against the
             # 78.6 TFLOP/s vector peak and VALU issue utilisation
             "alu": {"rhs_kernel": alu_figures(profiled_counters("rhs_kernel<1,4,0>"), ms_op),
-                    "con2prim_kernel": alu_figures(profiled_counters("con2prim_kernel<1,0>"), ms_c2p)}}
+                    # the NE / SR recovery takes two points per lane
+                    "con2prim_kernel": alu_figures(profiled_counters("con2prim2_kernel<1,0>"), ms_c2p, 2)}}
     value = nn * NV / (ms * 1e-3)
     out = {
         "metric": "DG RHS DOF-updates/s (FP64); con2prim pts/s, learned guess vs plain Newton",

@@ -80,11 +80,69 @@ __global__ void __launch_bounds__(256) con2prim_kernel(const C2PArgs A) {
   }
 }
 
+// NE and SR seeded from the input pressure (GUESS 0) or the bracket
+// (GUESS 1): two points per thread, both loaded before either is recovered,
+// so that the second point's loads overlap the first point's iteration (71
+// VGPRs, seven waves per SIMD; SRMHD's longer recovery keeps one point per
+// thread, where the second point's registers cost more occupancy than the
+// overlap gains).
+template <int SYS, int GUESS>
+__global__ void __launch_bounds__(256) con2prim2_kernel(const C2PArgs A) {
+  static_assert(SYS != kMHD && GUESS <= 1, "NE / SR, input or bracket seed");
+  constexpr int NV = SysTraits<SYS>::nv;
+  const int64_t n = A.n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long nbad = 0;
+  for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < n; q0 += 2 * stride) {
+    const int64_t qq[2] = {q0, q0 + stride};
+    double u[2][NV], p0[2] = {-1.0, -1.0};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (qq[j] < n) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[j][v] = A.U[v * n + qq[j]];
+        if (GUESS == 0) p0[j] = A.prim[4 * n + qq[j]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t q = qq[j];
+      if (q >= n) continue;
+      C2PResult R = recover<SYS>(u[j], A.gamma, p0[j], A.tol, 100, A.poly);
+      // (the operators rebuild rho and v from U and p: streamed, as above)
+      __builtin_nontemporal_store(R.P.rho, &A.prim[q]);
+      __builtin_nontemporal_store(R.P.v[0], &A.prim[n + q]);
+      __builtin_nontemporal_store(R.P.v[1], &A.prim[2 * n + q]);
+      __builtin_nontemporal_store(R.P.v[2], &A.prim[3 * n + q]);
+      A.prim[4 * n + q] = R.P.p;
+      if (A.iters) A.iters[q] = (uint8_t)(R.iters > 255 ? 255 : R.iters);
+      if (A.fail) A.fail[q] = R.ok ? 0 : 1;
+      nbad += R.ok ? 0 : 1;
+    }
+  }
+  if (A.nfail) {
+    const unsigned long long bad = __ballot(nbad != 0);
+    if (bad) {
+      for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off);
+      if ((threadIdx.x & 63) == 0) atomicAdd(A.nfail, nbad);
+    }
+  }
+}
+
 template <int SYS>
 static hipError_t c2p_sys(int guess, const C2PArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   const int64_t blocks_needed = (a.n + 255) / 256;
   const int grid = (int)(blocks_needed < 65536 ? blocks_needed : 65536);
+  const int64_t blocks2 = (a.n + 511) / 512;  // two points per thread
+  const int grid2 = (int)(blocks2 < 65536 ? blocks2 : 65536);
+  if constexpr (SYS != kMHD) {
+    if (guess == 0 || guess == 1) {
+      if (guess == 0) hipLaunchKernelGGL((con2prim2_kernel<SYS, 0>), dim3(grid2), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((con2prim2_kernel<SYS, 1>), dim3(grid2), dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   switch (guess) {
     case 0: hipLaunchKernelGGL((con2prim_kernel<SYS, 0>), dim3(grid), dim3(256), 0, s, a); break;
     case 1: hipLaunchKernelGGL((con2prim_kernel<SYS, 1>), dim3(grid), dim3(256), 0, s, a); break;
