@@ -99,6 +99,62 @@ def test_con2prim_tolerance_mode(ora, dg, system, guess):
     assert it.min() >= 1 and it.max() <= 40
 
 
+@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 511, 512, 513, 70001])
+@pytest.mark.parametrize("guess", [0, 1])
+def test_sr_con2prim_ragged_sizes(ora, dg, n, guess):
+    """The SR recovery takes two points per thread: every point of a ragged
+    batch (a single point, a lone first point of a pair, partial workgroups)
+    is recovered to the oracle's root, and nothing past the batch is
+    written."""
+    import torch
+    g = 4.0 / 3.0
+    prim = synth.sr_samples(n, seed=100 + n, w_max=10.0)
+    U = ora.prim2cons(SR, g, prim)
+    Po, fo, _ = ora.cons2prim(SR, g, U)
+    guard = 512
+    pbuf = torch.full((5 * n + guard,), 7.0, dtype=torch.float64, device="cuda")
+    P = pbuf[:5 * n].view(5, n)
+    if guess == 0:
+        P.copy_(to_dev(prim * (1 + 1e-3)))
+    else:
+        P.zero_()
+    ibuf = torch.full((n + guard,), 200, dtype=torch.uint8, device="cuda")
+    dg.con2prim(SR, g, to_dev(U), P, guess=guess, tol=0.0, iters_out=ibuf[:n])
+    Pg = to_host(P)
+    assert (np.abs(Pg[4] - Po[4]) / Po[4]).max() <= 2e-11
+    assert (np.abs(Pg[0] - Po[0]) / Po[0]).max() <= 2e-11
+    assert np.all(to_host(pbuf[5 * n:]) == 7.0)
+    it = to_host(ibuf)
+    assert it[:n].min() >= 1 and it[:n].max() <= 40 and np.all(it[n:] == 200)
+
+
+def test_sr_con2prim_beyond_one_grid(ora, dg):
+    """33.6M SR points, more than one launch grid holds at two points per
+    thread (65,536 workgroups of 256 threads), so threads loop: the oracle's
+    1,048,576 states tiled 33 times and cut at a ragged length; sampled
+    points across the batch, its tail included, against the oracle's roots
+    of their source states."""
+    import torch
+    g = 4.0 / 3.0
+    ns = 1 << 20
+    n = 65536 * 512 + 12345
+    prim = synth.sr_samples(ns, seed=77, w_max=10.0)
+    Us = ora.prim2cons(SR, g, prim)
+    U = to_dev(Us).repeat(1, 33)[:, :n].contiguous()
+    P = torch.zeros((5, n), dtype=torch.float64, device="cuda")
+    nfail = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dg.con2prim(SR, g, U, P, guess=1, tol=0.0, n_failed=nfail)
+    assert int(nfail.item()) == 0
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 3000), np.arange(n - 600, n),
+                                    np.arange(65536 * 512 - 300, 65536 * 512 + 300)]))
+    src = idx % ns
+    Po, fo, _ = ora.cons2prim(SR, g, np.ascontiguousarray(Us[:, src]))
+    Pg = to_host(P[:, torch.as_tensor(idx, device="cuda")])
+    assert (np.abs(Pg[4] - Po[4]) / Po[4]).max() <= 2e-11
+    assert (np.abs(Pg[0] - Po[0]) / Po[0]).max() <= 2e-11
+
+
 @pytest.mark.parametrize("system", [NE, SR, MHD])
 def test_con2prim_polish_matches_oracle_root(ora, dg, system):
     import torch
