@@ -26,17 +26,37 @@ hipError_t launch_rhs_mixed_all(int sys, int stage, bool mom, int flux, const Rh
 }
 
 // Tile options (elements per workgroup) of the mixed-degree element kernel.
+template <int SYS, int N>
+static int tile_options(int *epb_out) {
+  constexpr int E0 = default_epb<SYS, N>(), E1 = second_epb<SYS, N>();
+  epb_out[0] = E0;
+  if (E1 == E0) return 1;
+  epb_out[1] = E1;
+  return 2;
+}
+
+template <int SYS>
+static int tile_options_sys(int N, int *epb_out) {
+  switch (N) {
+    case 1: return tile_options<SYS, 1>(epb_out);
+    case 2: return tile_options<SYS, 2>(epb_out);
+    case 3: return tile_options<SYS, 3>(epb_out);
+    case 4: return tile_options<SYS, 4>(epb_out);
+    case 5: return tile_options<SYS, 5>(epb_out);
+    case 6: return tile_options<SYS, 6>(epb_out);
+    case 7: return tile_options<SYS, 7>(epb_out);
+  }
+  return 0;
+}
+
 int mixed_tile_options(int sys, int N, int *epb_out) {
   if (N < 1 || N > kMaxMixedDegree) return 0;
-  static const int sr[8][2] = {{0, 0}, {8, 4}, {9, 4}, {4, 2}, {2, 1}, {1, 0}, {1, 0}, {1, 0}};
-  if (sys == kSR) {
-    int n = 0;
-    for (int k = 0; k < 2 && sr[N][k]; ++k) epb_out[n++] = sr[N][k];
-    return n;
+  switch (sys) {
+    case kNE: return tile_options_sys<kNE>(N, epb_out);
+    case kSR: return tile_options_sys<kSR>(N, epb_out);
+    case kMHD: return tile_options_sys<kMHD>(N, epb_out);
   }
-  static const int dflt[3][8] = {{0, 8, 9, 4, 2, 1, 1, 1}, {0}, {0, 8, 9, 2, 2, 1, 1, 1}};
-  epb_out[0] = dflt[sys][N];
-  return 1;
+  return 0;
 }
 
 hipError_t launch_rhs_mixed(int sys, int N, int epb, int stage, int flux, const RhsArgs &a, hipStream_t s) {

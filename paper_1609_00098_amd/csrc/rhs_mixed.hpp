@@ -108,13 +108,20 @@ static hipError_t launch_mixed_one(int stage, const RhsArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The second tile option of SR hydro (mixed_tile_options in rhs.hip).
+// The second tile option of a degree's per-degree launch, timed against the
+// default by the autotuner (SR hydro only; the default where there is none).
+template <int SYS, int N>
+constexpr int second_epb() {
+  constexpr int E0 = default_epb<SYS, N>();
+  if (SYS != kSR) return E0;
+  return (N == 1) ? 4 : (N == 2) ? 4 : (N == 3) ? 2 : (N == 4) ? 2 : E0;
+}
+
 template <int SYS, int N, int FLUX>
 static hipError_t launch_mixed_deg(int epb, int stage, const RhsArgs &a, hipStream_t s) {
-  constexpr int E0 = default_epb<SYS, N>();
-  if constexpr (SYS == kSR) {
-    constexpr int E1 = (N == 1) ? 4 : (N == 2) ? 4 : (N == 3) ? 2 : (N == 4) ? 1 : E0;
-    if (epb == E1 && E1 != E0) return launch_mixed_one<SYS, N, E1, FLUX>(stage, a, s);
+  constexpr int E0 = default_epb<SYS, N>(), E1 = second_epb<SYS, N>();
+  if constexpr (E1 != E0) {
+    if (epb == E1) return launch_mixed_one<SYS, N, E1, FLUX>(stage, a, s);
   }
   return launch_mixed_one<SYS, N, E0, FLUX>(stage, a, s);
 }
