@@ -22,6 +22,19 @@ __device__ __forceinline__ uint32_t fastdiv(uint32_t n, FastDiv f) {
   return (uint32_t)(((uint64_t)n * f.m) >> f.s);
 }
 
+// Processing order of a uniform launch's element groups (EPB consecutive
+// elements along x): bricks of S x S x S elements one after another,
+// lexicographic inside a brick (S = 0: plain lexicographic order).  The
+// divisions by the brick sizes are multiply-shift pairs (make_brickmap in
+// rhs_body.hpp sets them up on the host).
+struct BrickMap {
+  int S;         // brick edge in elements, or 0
+  int bx, V;     // element groups per brick row and per brick
+  int ngx, ny;   // element groups per mesh row, elements along y
+  int nbx, nby;  // bricks along x and y
+  FastDiv dV, dbx, dS, dnbx, dnby;
+};
+
 // Arguments of the uniform-degree RHS / RK-stage kernel.
 struct RhsArgs {
   const double *U;     // state the operator is applied to, [nv][nnodes]
@@ -67,6 +80,7 @@ struct RhsArgs {
   int periodic;        // uniform meshes periodic in every direction: face
                        // neighbours by index arithmetic (else from nbr)
   FastDiv div_nx, div_ny;  // division by nx and ny (periodic neighbours)
+  BrickMap bm;         // uniform meshes: processing order of the element groups (set at launch)
 };
 
 // Numerical fluxes of the uniform-mesh element kernels.

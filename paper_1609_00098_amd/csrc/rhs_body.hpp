@@ -63,26 +63,38 @@ __device__ __forceinline__ int sel3i(int d, int a, int b, int c) { return d == 0
 // the states read since (the operator's output bypasses L2), and a brick's
 // faces, whose neighbours were read long before or by another XCD, are half
 // as many per element as with S = 8, the next choice.  Otherwise the order
-// stays lexicographic.
-template <int EPB, int S>
-__device__ __forceinline__ bool bricks_tile(int nx, int ny, int nz) {
-  return S % EPB == 0 && nx % S == 0 && ny % S == 0 && nz % S == 0;
+// stays lexicographic.  Host side: the brick sizes and their divisors.
+inline BrickMap make_brickmap(int epb, int nx, int ny, int nz) {
+  BrickMap m{};
+  for (int S = 16; S >= 8; S /= 2) {
+    if (S % epb != 0 || nx % S != 0 || ny % S != 0 || nz % S != 0) continue;
+    m.S = S;
+    m.bx = S / epb;
+    m.V = m.bx * S * S;
+    m.ngx = nx / epb;
+    m.ny = ny;
+    m.nbx = nx / S;
+    m.nby = ny / S;
+    m.dV = make_fastdiv((uint32_t)m.V);
+    m.dbx = make_fastdiv((uint32_t)m.bx);
+    m.dS = make_fastdiv((uint32_t)S);
+    m.dnbx = make_fastdiv((uint32_t)m.nbx);
+    m.dnby = make_fastdiv((uint32_t)m.nby);
+    return m;
+  }
+  return m;
 }
-template <int EPB, int S>
-__device__ __forceinline__ int brick_map(int seq, int nx, int ny) {
-  constexpr int BX = S / EPB, V = BX * S * S;  // groups per brick row, per brick
-  const int ngx = nx / EPB;
-  const int b = seq / V, r = seq - b * V;
-  const int nbx = ngx / BX, nby = ny / S;
-  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-  const int gx = bx * BX + r % BX, gy = by * S + (r / BX) % S, gz = bz * S + r / (BX * S);
-  return gx + ngx * (gy + ny * gz);
-}
-template <int EPB>
-__device__ __forceinline__ int brick_order(int seq, int nx, int ny, int nz) {
-  if (bricks_tile<EPB, 16>(nx, ny, nz)) return brick_map<EPB, 16>(seq, nx, ny);
-  if (bricks_tile<EPB, 8>(nx, ny, nz)) return brick_map<EPB, 8>(seq, nx, ny);
-  return seq;
+
+// The element group at position seq of that order (every index below 2^31).
+__device__ __forceinline__ int brick_map(int seq, const BrickMap &m) {
+  const uint32_t s = (uint32_t)seq;
+  const uint32_t b = fastdiv(s, m.dV), r = s - b * (uint32_t)m.V;  // brick, position inside
+  const uint32_t q = fastdiv(b, m.dnbx), bxi = b - q * (uint32_t)m.nbx;
+  const uint32_t bzi = fastdiv(q, m.dnby), byi = q - bzi * (uint32_t)m.nby;
+  const uint32_t r1 = fastdiv(r, m.dbx), rx = r - r1 * (uint32_t)m.bx;
+  const uint32_t r2 = fastdiv(r1, m.dS), ry = r1 - r2 * (uint32_t)m.S;
+  const uint32_t gx = bxi * (uint32_t)m.bx + rx, gy = byi * (uint32_t)m.S + ry, gz = bzi * (uint32_t)m.S + r2;
+  return (int)(gx + (uint32_t)m.ngx * (gy + (uint32_t)m.ny * gz));
 }
 
 // Elements per workgroup of the uniform kernels (measured: one element at
@@ -576,7 +588,7 @@ rhs_kernel(const RhsArgs A) {
   const int seq = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (seq >= A.nblocks) return;
   int grp = seq;
-  if constexpr (!MIXED) grp = brick_order<C::EPB>(seq, A.nx, A.ny, A.nz);
+  if constexpr (!MIXED) grp = A.bm.S ? brick_map(seq, A.bm) : seq;
   rhs_body<SYS, N, STAGE, EPB_, MIXED, C::THREADS, FLUX, MOM>(A, grp, smem);
 }
 
@@ -588,6 +600,7 @@ hipError_t launch_one_moments(const RhsArgs &a, hipStream_t s) {
   const int64_t nblocks = (a.nelem + C::EPB - 1) / C::EPB;
   if (nblocks > ((int64_t)1 << 30)) return hipErrorInvalidValue;
   b.nblocks = (int)nblocks;
+  b.bm = make_brickmap(C::EPB, a.nx, a.ny, a.nz);
   const int grid = ((b.nblocks + 7) / 8) * 8;
   hipLaunchKernelGGL((rhs_kernel<SYS, N, 1, C::EPB, false, FLUX, true>), dim3(grid), dim3(C::THREADS), 0, s, b);
   return hipGetLastError();
@@ -601,6 +614,7 @@ hipError_t launch_one(int stage, const RhsArgs &a, hipStream_t s) {
   const int64_t nblocks = (a.nelem + C::EPB - 1) / C::EPB;
   if (nblocks > ((int64_t)1 << 30)) return hipErrorInvalidValue;
   b.nblocks = (int)nblocks;
+  b.bm = make_brickmap(C::EPB, a.nx, a.ny, a.nz);
   const int grid = ((b.nblocks + 7) / 8) * 8;
   if (stage == 0)
     hipLaunchKernelGGL((rhs_kernel<SYS, N, 0, C::EPB, false, FLUX>), dim3(grid), dim3(C::THREADS), 0, s, b);
