@@ -192,8 +192,8 @@ struct dgmi_ctx {
   int ndeg = 0;
   double last_dt = NAN;           // dt held by d_dt
   bool single_launch = true;      // all degrees' element kernels in one launch
-  int32_t *d_blk = nullptr;       // [2][nblk] workgroup table of the single launch
-  int nblk = 0;
+  int nblk = 0;                   // workgroups of the single launch
+  int bbeg[8] = {0}, bend[8] = {0};  // per degree: its range of those workgroups
   hipStream_t side[8] = {nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[8] = {nullptr};
   hipGraph_t graph = nullptr;
@@ -402,28 +402,19 @@ static dgmi_status mixed_setup(dgmi_ctx *c, const std::vector<double> &hx, hipSt
     }
     c->ndeg = nd;
   }
-  // workgroup table of the single-launch element kernel: degrees highest
-  // first, each degree's element list cut into groups of mixed_all_epb
+  // workgroups of the single-launch element kernel: degrees highest first,
+  // each degree's element list cut into groups of mixed_all_epb
   {
-    std::vector<int32_t> bdeg, bgrp;
+    int64_t nb_total = 0;
     for (int N = dgmi::kMaxMixedDegree; N >= 1; --N) {
       const int e = dgmi::mixed_all_epb(c->sys, N);
       const int64_t nb = (c->lcount[N] + e - 1) / e;
-      for (int64_t g = 0; g < nb; ++g) {
-        bdeg.push_back(N);
-        bgrp.push_back((int32_t)g);
-      }
+      c->bbeg[N] = (int)nb_total;
+      nb_total += nb;
+      c->bend[N] = (int)nb_total;
     }
-    c->nblk = (int)bdeg.size();
-    if (hipMalloc(&c->d_blk, sizeof(int32_t) * 2 * (bdeg.size() + 1)) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(DGMI_ENOMEM, "dgmi_create: device allocation of the workgroup table failed");
-    }
-    if (c->nblk > 0) {
-      HIP_TRY(hipMemcpyAsync(c->d_blk, bdeg.data(), sizeof(int32_t) * bdeg.size(), hipMemcpyHostToDevice, cs));
-      HIP_TRY(hipMemcpyAsync(c->d_blk + c->nblk, bgrp.data(), sizeof(int32_t) * bgrp.size(), hipMemcpyHostToDevice,
-                             cs));
-    }
+    if (nb_total > ((int64_t)1 << 30)) return fail(DGMI_EINVAL, "dgmi_create: too many elements for one launch");
+    c->nblk = (int)nb_total;
     // the host tables above go out of scope here
     HIP_TRY(hipStreamSynchronize(cs));
   }
@@ -456,8 +447,10 @@ static dgmi::RhsArgs mix_args(dgmi_ctx *c, int N) {
 
 static dgmi::MixedAllArgs all_args(dgmi_ctx *c) {
   dgmi::MixedAllArgs m{};
-  m.blk_deg = c->d_blk;
-  m.blk_grp = c->d_blk + c->nblk;
+  for (int N = 0; N < 8; ++N) {
+    m.bbeg[N] = c->bbeg[N];
+    m.bend[N] = c->bend[N];
+  }
   m.nblocks = c->nblk;
   for (int N = 0; N < 8; ++N) {
     m.lstart[N] = c->lstart[N];
@@ -660,7 +653,6 @@ static void ctx_free(dgmi_ctx *c) {
   (void)hipFree(c->d_Itab);
   (void)hipFree(c->d_Ptab);
   (void)hipFree(c->d_mtab);
-  (void)hipFree(c->d_blk);
   (void)hipFree(c->d_fdesc);
   (void)hipFree(c->d_facebuf);
   (void)hipFree(c->d_dt);

@@ -202,10 +202,13 @@ struct MortarArgs {
   double gamma, gratio;    // gratio = gamma / (gamma - 1)
 };
 
-// All degrees of a mixed mesh in one launch: a table of workgroups (degree,
-// element group within that degree's list), highest degree first.
+// All degrees of a mixed mesh in one launch: one range of workgroups per
+// degree, highest degree first, each workgroup one element group of its
+// degree's list.
 struct MixedAllArgs {
-  const int32_t *blk_deg, *blk_grp;
+  // workgroups b in [bbeg[N], bend[N]) take the element groups b - bbeg[N]
+  // of degree N (degrees highest first, each range after the next higher's)
+  int bbeg[8], bend[8];
   int nblocks;
   int64_t lstart[8], lcount[8];  // per degree: start and length in the element list
   const double *D;               // [8][64] differentiation matrices

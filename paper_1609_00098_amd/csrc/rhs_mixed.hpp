@@ -8,8 +8,8 @@
 namespace dgmi {
 
 // Every degree of a mixed mesh in one launch: 512-thread workgroups, each
-// taking one group of elements of one degree from a block table ordered by
-// degree (highest first); per degree as many elements per workgroup as fit
+// taking one group of elements of one degree, the degrees' workgroup ranges
+// highest first; per degree as many elements per workgroup as fit
 // 512 threads and the LDS budget.  The budget (52 KB) and, for SR hydro, at
 // most 80 VGPRs let three workgroups share a CU (24 waves); the degree-2 and
 // -3 tiles then leave a quarter and an eighth of their threads idle, which
@@ -48,8 +48,13 @@ rhs_mixed_all_kernel(const RhsArgs A, const MixedAllArgs M) {
   __shared__ double smem[all_budget<SYS>()];
   const int b = blockIdx.x;
   if (b >= M.nblocks) return;
-  const int N = M.blk_deg[b];
-  const int grp = M.blk_grp[b];
+  // the degree from the block ranges (kernel arguments, no table read in
+  // front of the first loads)
+  int N = 7;
+#pragma unroll
+  for (int k = 7; k >= 2; --k)
+    if (b >= M.bend[k]) N = k - 1;
+  const int grp = b - M.bbeg[N];
   RhsArgs a = A;
   a.elist = A.elist + M.lstart[N];
   a.mtab = A.mtab + 7 * M.lstart[N];
