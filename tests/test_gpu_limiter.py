@@ -140,10 +140,14 @@ def test_boundary_rhs_parity(ora, dg, system, N, bc_dirs, flux):
     assert np.abs(dUp - dUo).max() > 1e-3 * np.abs(dUo).max()
 
 
-@pytest.mark.parametrize("system,N,lim,bc_dirs", [(NE, 1, "muscl", (0,)), (SR, 3, "minmod", ()),
-                                                  (MHD, 2, "minmod", (0,)), (SR, 2, "muscl", (0, 1))])
-def test_step_with_limiter_parity(ora, dg, system, N, lim, bc_dirs):
-    m, G = _pair(ora, dg, system, (6, 2, 2), N, lim, bc_dirs=bc_dirs)
+# (degree 4 of SR hydro and degree 3 of SRMHD run one element per workgroup;
+# the HLL cases take the limited stage's HLL instantiation)
+@pytest.mark.parametrize("system,N,lim,bc_dirs,flux", [(NE, 1, "muscl", (0,), "llf"), (SR, 3, "minmod", (), "llf"),
+                                                       (MHD, 2, "minmod", (0,), "llf"), (SR, 2, "muscl", (0, 1), "llf"),
+                                                       (SR, 4, "muscl", (), "llf"), (SR, 4, "minmod", (2,), "hll"),
+                                                       (MHD, 3, "muscl", (), "hll")])
+def test_step_with_limiter_parity(ora, dg, system, N, lim, bc_dirs, flux):
+    m, G = _pair(ora, dg, system, (6, 2, 2), N, lim, bc_dirs=bc_dirs, flux=flux)
     U, prim = _jump_state(ora, system, m, seed=80 + N)
     U, _ = ora.limit(m, U)
     Lo, Po, _ = ora.rhs(m, U)
